@@ -1,0 +1,209 @@
+"""Pins for the oracle's single-interaction terms (CPU only).
+
+Each check ties the oracle to something other than itself: hand-derived
+closed forms (tests/golden/closed_forms.json), a = -grad phi by central
+differences (Sec. 3 eq. 6), the order of accuracy of a second-order
+multipole expansion, and library special functions (scipy) for the split
+kernel.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import special
+
+from conftest import GOLDEN
+
+
+def _fixture():
+    with open(os.path.join(GOLDEN, "closed_forms.json")) as f:
+        return json.load(f)
+
+
+def test_two_body_closed_form(orc):
+    fx = _fixture()["two_body"]
+    x = np.array(fx["x"])
+    m = np.array(fx["m"])
+    a, phi = orc.direct(x, m, fx["eps"] ** 2)
+    np.testing.assert_allclose(a, np.array(fx["a"]), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(phi, np.array(fx["phi"]), rtol=1e-15)
+
+
+def test_axis_pair_moments_and_expansion(orc):
+    fx = _fixture()["axis_pair"]
+    s, mm, D = fx["s"], fx["m"], fx["D"]
+    x = np.array([[0.0, 0.0, s], [0.0, 0.0, -s]])
+    M, com, q, T = orc.moments(x, [mm, mm])
+    assert M == 2 * mm
+    np.testing.assert_allclose(com, 0.0, atol=1e-17)
+    np.testing.assert_allclose(q, fx["Q"], rtol=1e-14, atol=1e-17)
+    assert T == pytest.approx(fx["T"], rel=1e-14)
+    # on the axis: field point (0, 0, D), d = com - r_i
+    a, phi = orc.pc_quad(np.array([0.0, 0.0, -D]), M, q, 0.0)
+    assert phi == pytest.approx(fx["axis_phi"], rel=1e-14)
+    np.testing.assert_allclose(a, fx["axis_a"], rtol=1e-14, atol=1e-16)
+    # the residual against the exact two-body potential is the hexadecapole
+    exact = fx["axis_exact_phi"]
+    assert (exact - phi) == pytest.approx(fx["axis_residual_leading"], rel=0.05)
+    # in the plane: field point (D, 0, 0)
+    a, phi = orc.pc_quad(np.array([-D, 0.0, 0.0]), M, q, 0.0)
+    assert phi == pytest.approx(fx["plane_phi"], rel=1e-14)
+    np.testing.assert_allclose(a, fx["plane_a"], rtol=1e-14, atol=1e-16)
+    assert abs(fx["plane_exact_phi"] - phi) < 5e-6
+
+
+def test_monopole_cell_is_point_mass(orc):
+    d = np.array([0.3, -1.2, 0.7])
+    a1, p1 = orc.pc_mono(d, 2.5, 0.01)
+    a2, p2 = orc.pp_plummer(d, 2.5, 0.01)
+    assert np.array_equal(a1, a2) and p1 == p2
+    # a zero quadrupole reduces the quad term to the monopole term
+    a3, p3 = orc.pc_quad(d, 2.5, np.zeros(6), 0.01)
+    np.testing.assert_allclose(a3, a1, rtol=1e-15)
+    assert p3 == pytest.approx(p1, rel=1e-15)
+
+
+def _num_grad(f, x0, h):
+    g = np.zeros(3)
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        g[k] = (f(x0 + e) - f(x0 - e)) / (2 * h)
+    return g
+
+
+@pytest.mark.parametrize("eps2", [0.0, 0.04])
+def test_quad_force_is_minus_gradient(orc, eps2):
+    """a = -grad_i phi (eq. 6); the field point moves, d = com - x_i."""
+    g = np.random.default_rng(5)
+    for _ in range(20):
+        q = g.normal(size=6)
+        q[5] = -(q[0] + q[3])
+        com = g.normal(size=3) * 2.0
+        xi = g.normal(size=3) * 0.3
+        M = g.uniform(0.5, 2.0)
+
+        def phi_at(xp):
+            return orc.pc_quad(com - xp, M, q, eps2)[1]
+
+        a, _ = orc.pc_quad(com - xi, M, q, eps2)
+        np.testing.assert_allclose(a, -_num_grad(phi_at, xi, 1e-5),
+                                   rtol=1e-7, atol=1e-9 * np.abs(a).max())
+
+
+def _cluster(g, k, scale):
+    x = g.normal(size=(k, 3)) * scale * np.array([1.0, 0.6, 0.35])
+    m = g.uniform(0.5, 1.5, k)
+    return x, m
+
+
+def test_expansion_order(orc):
+    """Error of a second-order (quadrupole) cell expansion falls as (l/D)^3,
+    of a monopole as (l/D)^2, against summing the cell's particles
+    (direct pair terms, themselves pinned by the closed forms)."""
+    g = np.random.default_rng(11)
+    xc, mc = _cluster(g, 40, 1.0)
+    xi = np.array([7.0, 3.0, -5.0])
+    err_q, err_m = [], []
+    for scale in (0.4, 0.2, 0.1, 0.05):
+        x = xc * scale
+        M, com, q, _ = orc.moments(x, mc)
+        a_ex = np.zeros(3)
+        for p in range(len(mc)):
+            a_ex += orc.pp_plummer(x[p] - xi, mc[p], 0.0)[0]
+        aq, _ = orc.pc_quad(com - xi, M, q, 0.0)
+        am, _ = orc.pc_mono(com - xi, M, 0.0)
+        err_q.append(np.linalg.norm(aq - a_ex) / np.linalg.norm(a_ex))
+        err_m.append(np.linalg.norm(am - a_ex) / np.linalg.norm(a_ex))
+    rq = np.array(err_q[:-1]) / np.array(err_q[1:])
+    rm = np.array(err_m[:-1]) / np.array(err_m[1:])
+    assert np.all((rq > 6.5) & (rq < 10.0)), rq
+    assert np.all((rm > 3.3) & (rm < 4.8)), rm
+    assert np.all(np.array(err_q) < np.array(err_m))
+
+
+def test_split_kernel_library_values(orc):
+    """Phi(r) = -erfc(r/2rs)/r (scipy's erfc), and the radial derivative
+    functions against numerical derivatives of Phi."""
+    rs = 0.01
+    for r in (0.002, 0.01, 0.02, 0.04):
+        Phi, D1, D2, D3 = orc.split_derivs(r, rs)
+        assert Phi == pytest.approx(-special.erfc(r / (2 * rs)) / r, rel=1e-14)
+        h = r * 1e-4
+
+        def fPhi(t):
+            return orc.split_derivs(t, rs)[0]
+
+        def fD1(t):
+            return orc.split_derivs(t, rs)[1]
+
+        def fD2(t):
+            return orc.split_derivs(t, rs)[2]
+
+        assert D1 == pytest.approx((fPhi(r + h) - fPhi(r - h)) / (2 * h) / r,
+                                   rel=1e-6)
+        assert D2 == pytest.approx((fD1(r + h) - fD1(r - h)) / (2 * h) / r,
+                                   rel=1e-6)
+        assert D3 == pytest.approx((fD2(r + h) - fD2(r - h)) / (2 * h) / r,
+                                   rel=1e-6)
+
+
+def test_split_kernel_newtonian_limit(orc):
+    """rs -> infinity: Phi = -1/r, D1 = r^-3, D2 = -3 r^-5, D3 = 15 r^-7."""
+    r = 0.37
+    Phi, D1, D2, D3 = orc.split_derivs(r, 1e9)
+    assert Phi == pytest.approx(-1 / r, rel=1e-8)
+    assert D1 == pytest.approx(r ** -3, rel=1e-8)
+    assert D2 == pytest.approx(-3 * r ** -5, rel=1e-8)
+    assert D3 == pytest.approx(15 * r ** -7, rel=1e-8)
+    # g(0) = 1: the split pair force tends to the Newtonian one as r -> 0
+    r = 1e-6
+    _, D1, _, _ = orc.split_derivs(r, 1.0)
+    assert D1 * r ** 3 == pytest.approx(1.0, rel=1e-9)
+
+
+def test_split_cell_order_and_gradient(orc):
+    """Split cell term (with the trace T): force = -grad phi, third-order
+    accuracy against summing the cell's particles with the split pair
+    kernel, cutoff masking."""
+    g = np.random.default_rng(3)
+    rs, rcut = 0.02, 0.09
+    xc, mc = _cluster(g, 30, 1.0)
+    xi = np.array([0.05, -0.02, 0.03])
+    errs = []
+    for scale in (0.004, 0.002, 0.001):
+        x = xc * scale
+        M, com, q, T = orc.moments(x, mc)
+        a_ex = np.zeros(3)
+        for p in range(len(mc)):
+            a_ex += orc.pp_split(x[p] - xi, mc[p], rs, rcut)[0]
+        a, _ = orc.pc_split(com - xi, M, q, T, rs, rcut, True)
+        errs.append(np.linalg.norm(a - a_ex) / np.linalg.norm(a_ex))
+
+        def phi_at(xp):
+            return orc.pc_split(com - xp, M, q, T, rs, rcut, True)[1]
+
+        np.testing.assert_allclose(a, -_num_grad(phi_at, xi, 1e-6), rtol=1e-6)
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(ratios > 6.5), ratios
+    # beyond the cutoff, nothing
+    a, phi = orc.pc_split(np.array([rcut * 1.01, 0, 0]), 1.0, np.zeros(6), 0.0,
+                          rs, rcut, True)
+    assert phi == 0.0 and np.all(a == 0.0)
+    a, phi = orc.pp_split(np.zeros(3), 1.0, rs, rcut)
+    assert phi == 0.0 and np.all(a == 0.0)
+
+
+def test_split_pair_gradient(orc):
+    rs, rcut = 0.01, 0.045
+    d = np.array([0.011, -0.004, 0.006])
+    a, _ = orc.pp_split(d, 1.3, rs, rcut)
+
+    def phi_at(xp):
+        return orc.pp_split(d - xp, 1.3, rs, rcut)[1]
+
+    np.testing.assert_allclose(a, -_num_grad(phi_at, np.zeros(3), 1e-7),
+                               rtol=1e-6)
+    assert math.isfinite(a[0])
