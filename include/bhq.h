@@ -1,0 +1,208 @@
+/*
+ * bhq.h -- C ABI of libbhq: Barnes-Hut tree forces with monopole and
+ * traceless-quadrupole cell terms, evaluated over per-group interaction
+ * lists on an AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Kodama & Ishiyama, arXiv:1812.07313):
+ *   For every i-particle of group g, with d = r_j - r_i and
+ *   rhat^2 = |d|^2 + eps_i^2 (G = 1):
+ *     a_i   = sum_{j in P_g} m_j d / rhat^3
+ *           + sum_{c in C_g} [ (phi_m + 5 phi_q) / rhat^2 d - Q_c d / rhat^5 ]
+ *     phi_i = - sum_{j in P_g} m_j / rhat - sum_{c in C_g} (phi_m + phi_q)
+ *   with phi_m = M_c / rhat and phi_q = d.Q_c.d / (2 rhat^5)
+ *   (Sec. 3, eq. 1 for the potential, eqs. 4-7 for the acceleration;
+ *   a is returned attractive and phi negative).  P_g (j-particles) and C_g
+ *   (j-cells with mass, centre of mass and traceless quadrupole Q, eq. 2)
+ *   are the group's interaction list; all i-particles of a group share it
+ *   (the modified tree algorithm of Sec. 3.4).  The particle-particle part
+ *   is summed before the cell part (List 4: assign, then add).
+ *
+ * Kernels: BHQ_QUAD (above), BHQ_MONO (cells as point masses, Q ignored:
+ * the paper's "monopole" program), BHQ_SPLIT_QUAD / BHQ_SPLIT_MONO
+ * (short-range Gaussian-split kernel Phi = -erfc(r / 2 r_s) / r with a
+ * cutoff in a periodic box; not from the paper).
+ * Precisions: BHQ_FP32_OFS64 forms positions relative to the group centre
+ * in FP64 and does all interaction arithmetic and accumulation in FP32;
+ * BHQ_FP64 does everything in FP64.
+ *
+ * Conventions for every call:
+ *   - Return value: BHQ_OK (0) or a negative BHQ_E_* code; nothing aborts
+ *     or throws across the ABI.  bhq_last_error() describes the last
+ *     failure on a context.
+ *   - Host arrays passed to bhq_set_* are copied before the call returns
+ *     (as the paper's set calls copy into their own structures, Sec. 3.4);
+ *     the caller keeps ownership.  Device memory is owned by the context.
+ *   - Positions are FP64, AoS: double (*x)[3] = x[k][0..2].
+ *   - Quadrupoles are double (*q)[6] = (q00, q01, q02, q11, q12, q22), the
+ *     order of the paper's j-cell structure (List 1); q22 is stored, not
+ *     recomputed.
+ *   - i-particles are given in group order: group g owns i-particles
+ *     i_off[g] .. i_off[g+1]-1.
+ *   - Lists are materialised: group g's j-particles are entries
+ *     jp_off[g] .. jp_off[g+1]-1 of the j-particle arrays, its j-cells
+ *     entries jc_off[g] .. jc_off[g+1]-1 of the j-cell arrays.
+ *   - One context per host thread; calls on one context are not
+ *     thread-safe.
+ */
+#ifndef BHQ_H
+#define BHQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bhq_ctx bhq_ctx;
+typedef struct bhq_lists bhq_lists;
+
+/* return codes */
+#define BHQ_OK 0
+#define BHQ_E_ARG (-1)       /* invalid argument (null, negative, bad enum) */
+#define BHQ_E_RANGE (-2)     /* offsets not monotone, or past the end        */
+#define BHQ_E_NODEV (-3)     /* no usable GPU / device index out of range    */
+#define BHQ_E_HIP (-4)       /* a HIP runtime call failed                    */
+#define BHQ_E_NOMEM (-5)     /* host or device allocation failed             */
+#define BHQ_E_STATE (-6)     /* call out of order (e.g. compute before set)  */
+#define BHQ_E_NONFINITE (-7) /* NaN or infinity in an input                  */
+
+/* kernels */
+#define BHQ_MONO 0
+#define BHQ_QUAD 1
+#define BHQ_SPLIT_QUAD 2
+#define BHQ_SPLIT_MONO 3
+
+/* precisions */
+#define BHQ_FP32_OFS64 0
+#define BHQ_FP64 1
+
+/* Create a context on HIP device `device` for the given kernel and
+ * precision.  *out receives the context (NULL on failure).
+ * Errors: BHQ_E_ARG (null out, bad enum), BHQ_E_NODEV (no GPU, or device
+ * out of range), BHQ_E_HIP, BHQ_E_NOMEM. */
+int bhq_create(bhq_ctx **out, int device, int kernel, int precision);
+
+/* Wait for outstanding work, free all device and host memory of the
+ * context.  NULL is accepted and ignored. */
+int bhq_destroy(bhq_ctx *ctx);
+
+/* Switch kernel and/or precision for later computes on the same data. */
+int bhq_set_kernel(bhq_ctx *ctx, int kernel, int precision);
+
+/* One softening length for every i-particle: eps^2 = eps * eps (the
+ * paper's set-eps-to-all call, List 4).  eps >= 0.  Overrides earlier
+ * per-particle values. */
+int bhq_set_eps(bhq_ctx *ctx, double eps);
+
+/* Per-i-particle squared softening (the i-particle structure carries eps^2
+ * per particle, List 2), in group order; ni must equal i_off[ng] of the
+ * last bhq_set_groups.  Every value >= 0 and finite. */
+int bhq_set_eps2_i(bhq_ctx *ctx, int64_t ni, const double *eps2);
+
+/* Short-range split parameters for the SPLIT kernels: r_s > 0, cutoff
+ * rcut > 0; box > 0 selects a periodic cube of that side (minimum-image
+ * separations), box == 0 an open boundary. */
+int bhq_set_split(bhq_ctx *ctx, double rs, double rcut, double box);
+
+/* Define the groups and the list sizes; must precede set_i / set_jp /
+ * set_jc.  ng >= 1 groups.
+ *   i_off[ng+1]   i_off[0] == 0, non-decreasing; ni = i_off[ng]
+ *   center[ng]    FP64 reference point of each group (its cell centre);
+ *                 FP32 kernels form all positions relative to it
+ *   jp_off[ng+1]  jp_off[0] == 0, non-decreasing; njp = jp_off[ng]
+ *   jc_off[ng+1]  jc_off[0] == 0, non-decreasing; njc = jc_off[ng]
+ * Errors: BHQ_E_ARG, BHQ_E_RANGE (offsets), BHQ_E_NONFINITE (centres),
+ * BHQ_E_NOMEM. */
+int bhq_set_groups(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
+                   const double (*center)[3], const int64_t *jp_off,
+                   const int64_t *jc_off);
+
+/* i-particle positions, ni == i_off[ng], in group order. */
+int bhq_set_i(bhq_ctx *ctx, int64_t ni, const double (*x)[3]);
+
+/* j-particles: entries adr .. adr+n-1 of the materialised list arrays
+ * (chunked filling allowed; adr + n <= njp). */
+int bhq_set_jp(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
+               const double *m);
+
+/* j-cells: entries adr .. adr+n-1 (adr + n <= njc): centre of mass x,
+ * total mass m, quadrupole q (List 1 order), and the trace
+ * T = sum m |x - com|^2 used by the SPLIT_QUAD kernel (may be NULL for the
+ * other kernels; then T = 0). */
+int bhq_set_jc(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
+               const double *m, const double (*q)[6], const double *trace);
+
+/* Launch the force evaluation on HIP stream `stream` (NULL: the null
+ * stream).  Asynchronous.  Errors: BHQ_E_STATE if groups, i-particles or
+ * softening are missing; BHQ_E_HIP on a launch failure. */
+int bhq_compute(bhq_ctx *ctx, void *stream);
+
+/* Wait for the last compute and copy out a[ni][3] and pot[ni] (FP64, group
+ * order).  Either pointer may be NULL. */
+int bhq_get_result(bhq_ctx *ctx, double (*a)[3], double *pot);
+
+/* Interaction counts of the current lists: n_pp = sum_g ni_g * njp_g,
+ * n_pc = sum_g ni_g * njc_g. */
+int bhq_get_counts(const bhq_ctx *ctx, int64_t *n_pp, int64_t *n_pc);
+
+/* Duration in milliseconds of the force kernel(s) of the last compute,
+ * measured with HIP events on the compute stream.  Waits for it. */
+int bhq_get_kernel_ms(bhq_ctx *ctx, double *ms);
+
+/* Message for the last error on ctx (never NULL; "" when none).  With
+ * ctx == NULL: the message of the last failed bhq_create on this thread. */
+const char *bhq_last_error(const bhq_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Host-side tree and list construction (not the accelerated path; it
+ * produces the inputs).  Oct-tree over the particles (Sec. 1), cell
+ * moments M, centre of mass, Q (eq. 2) and trace, groups = the largest
+ * tree cells holding at most ncrit particles (Sec. 3.4), and for each
+ * group the list of j-cells accepted by l^2 < theta^2 d^2 (d: centre of
+ * mass to the nearest point of the group's cell) and of j-particles from
+ * the opened leaves.  The root is the cube on the bounding-box midpoint
+ * with side = largest extent * (1 + 2^-20) (or [0, box)^3 when box > 0,
+ * with minimum-image distances and cells farther than rcut pruned).
+ * Particles go to the upper half of a cell along an axis iff their
+ * coordinate is >= the cell centre; cells with more than nleaf particles
+ * are split, down to depth 21.
+ * ------------------------------------------------------------------------ */
+
+/* Build the lists.  n >= 1 particles x[n][3], m[n] (FP64); theta >= 0;
+ * ncrit >= 1; nleaf in [1, ncrit]; box >= 0; rcut >= 0 (0: no pruning).
+ * nthreads <= 0 uses all hardware threads.  *out owns the result. */
+int bhq_build_lists(int64_t n, const double (*x)[3], const double *m,
+                    double theta, int ncrit, int nleaf, double box,
+                    double rcut, int nthreads, bhq_lists **out);
+
+/* sizes[0..3] = ng, njp, njc, number of tree cells. */
+int bhq_lists_sizes(const bhq_lists *L, int64_t sizes[4]);
+
+/* Copy the lists out (any pointer may be NULL):
+ *   i_idx[n]          original index of the k-th i-particle (group order)
+ *   i_off[ng+1], center[ng][3] (group cell centre), side[ng]
+ *   jp_off[ng+1], jp_idx[njp]   (original particle indices)
+ *   jc_off[ng+1], jc_cell[njc]  (tree cell ids)                          */
+int bhq_lists_export(const bhq_lists *L, int64_t *i_idx, int64_t *i_off,
+                     double (*center)[3], double *side, int64_t *jp_off,
+                     int64_t *jp_idx, int64_t *jc_off, int32_t *jc_cell);
+
+/* Copy out cell moments for cells 0..ncell-1 (any pointer may be NULL):
+ * com[][3], mass[], q[][6], trace[]. */
+int bhq_lists_cells(const bhq_lists *L, double (*com)[3], double *mass,
+                    double (*q)[6], double *trace);
+
+/* Upload the lists into a context: groups, i-particles (x gathered into
+ * group order), the materialised j-particles and j-cells with their
+ * moments.  x, m are the arrays the lists were built from. */
+int bhq_set_lists(bhq_ctx *ctx, const bhq_lists *L, const double (*x)[3],
+                  const double *m);
+
+/* Free lists (NULL accepted). */
+int bhq_lists_free(bhq_lists *L);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BHQ_H */

@@ -1,0 +1,268 @@
+"""Thin ctypes binding of libbhq (include/bhq.h), same names as the C ABI.
+
+Argument marshalling only: every step of the force evaluation runs in the
+library's HIP kernels.  Non-zero return codes raise :class:`BhqError`.
+The library is built in-tree by ``paper_1812_07313_amd.build`` and loaded
+from this package directory; a missing or unloadable library is an error
+(there is no fallback path).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+MONO, QUAD, SPLIT_QUAD, SPLIT_MONO = 0, 1, 2, 3
+FP32_OFS64, FP64 = 0, 1
+
+OK = 0
+E_ARG, E_RANGE, E_NODEV, E_HIP, E_NOMEM, E_STATE, E_NONFINITE = (
+    -1, -2, -3, -4, -5, -6, -7)
+
+KERNEL_NAMES = {MONO: "mono", QUAD: "quad", SPLIT_QUAD: "split_quad",
+                SPLIT_MONO: "split_mono"}
+PRECISION_NAMES = {FP32_OFS64: "fp32_ofs64", FP64: "fp64"}
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbhq.so")
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_P = ctypes.c_void_p
+
+# name -> (restype, argtypes); every exported symbol of include/bhq.h
+SIGNATURES = {
+    "bhq_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int,
+                                  ctypes.c_int, ctypes.c_int]),
+    "bhq_destroy": (ctypes.c_int, [_P]),
+    "bhq_set_kernel": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+    "bhq_set_eps": (ctypes.c_int, [_P, ctypes.c_double]),
+    "bhq_set_eps2_i": (ctypes.c_int, [_P, ctypes.c_int64, _D]),
+    "bhq_set_split": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double]),
+    "bhq_set_groups": (ctypes.c_int, [_P, ctypes.c_int64, _I64, _D, _I64,
+                                      _I64]),
+    "bhq_set_i": (ctypes.c_int, [_P, ctypes.c_int64, _D]),
+    "bhq_set_jp": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _D,
+                                  _D]),
+    "bhq_set_jc": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _D, _D,
+                                  _D, _D]),
+    "bhq_compute": (ctypes.c_int, [_P, _P]),
+    "bhq_get_result": (ctypes.c_int, [_P, _D, _D]),
+    "bhq_get_counts": (ctypes.c_int, [_P, _I64, _I64]),
+    "bhq_get_kernel_ms": (ctypes.c_int, [_P, _D]),
+    "bhq_last_error": (ctypes.c_char_p, [_P]),
+    "bhq_build_lists": (ctypes.c_int, [ctypes.c_int64, _D, _D,
+                                       ctypes.c_double, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int,
+                                       ctypes.POINTER(_P)]),
+    "bhq_lists_sizes": (ctypes.c_int, [_P, _I64]),
+    "bhq_lists_export": (ctypes.c_int, [_P, _I64, _I64, _D, _D, _I64, _I64,
+                                        _I64, _I32]),
+    "bhq_lists_cells": (ctypes.c_int, [_P, _D, _D, _D, _D]),
+    "bhq_set_lists": (ctypes.c_int, [_P, _P, _D, _D]),
+    "bhq_lists_free": (ctypes.c_int, [_P]),
+}
+
+_lib = None
+
+
+class BhqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libbhq error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """Load libbhq.so; build it first only if it is not there."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _build
+            _build.build()
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, ctx=None):
+    if rc != OK:
+        msg = lib().bhq_last_error(ctx)
+        raise BhqError(rc, msg.decode() if msg else "")
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def _ip(a):
+    return None if a is None else a.ctypes.data_as(_I64)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+# --- contexts ---------------------------------------------------------------
+
+def bhq_create(device=0, kernel=QUAD, precision=FP32_OFS64):
+    h = _P()
+    _check(lib().bhq_create(ctypes.byref(h), int(device), int(kernel),
+                            int(precision)))
+    return h
+
+
+def bhq_destroy(ctx):
+    _check(lib().bhq_destroy(ctx), ctx)
+
+
+def bhq_set_kernel(ctx, kernel, precision):
+    _check(lib().bhq_set_kernel(ctx, int(kernel), int(precision)), ctx)
+
+
+def bhq_set_eps(ctx, eps):
+    _check(lib().bhq_set_eps(ctx, float(eps)), ctx)
+
+
+def bhq_set_eps2_i(ctx, eps2):
+    e = _f64(eps2)
+    _check(lib().bhq_set_eps2_i(ctx, e.shape[0], _dp(e)), ctx)
+
+
+def bhq_set_split(ctx, rs, rcut, box=0.0):
+    _check(lib().bhq_set_split(ctx, float(rs), float(rcut), float(box)), ctx)
+
+
+def bhq_set_groups(ctx, i_off, center, jp_off, jc_off):
+    i_off, jp_off, jc_off = _i64(i_off), _i64(jp_off), _i64(jc_off)
+    ng = i_off.shape[0] - 1
+    c = _f64(center, (-1, 3))
+    if not (c.shape[0] == ng == jp_off.shape[0] - 1 == jc_off.shape[0] - 1):
+        raise BhqError(E_ARG, "group array lengths disagree")
+    _check(lib().bhq_set_groups(ctx, ng, _ip(i_off), _dp(c), _ip(jp_off),
+                                _ip(jc_off)), ctx)
+
+
+def bhq_set_i(ctx, x):
+    x = _f64(x, (-1, 3))
+    _check(lib().bhq_set_i(ctx, x.shape[0], _dp(x)), ctx)
+
+
+def bhq_set_jp(ctx, adr, x, m):
+    x = _f64(x, (-1, 3))
+    m = _f64(m)
+    if m.shape[0] != x.shape[0]:
+        raise BhqError(E_ARG, "x and m lengths disagree")
+    _check(lib().bhq_set_jp(ctx, int(adr), x.shape[0], _dp(x), _dp(m)), ctx)
+
+
+def bhq_set_jc(ctx, adr, x, m, q, trace=None):
+    x = _f64(x, (-1, 3))
+    m = _f64(m)
+    q = _f64(q, (-1, 6))
+    t = None if trace is None else _f64(trace)
+    n = x.shape[0]
+    if m.shape[0] != n or q.shape[0] != n or (t is not None and t.shape[0] != n):
+        raise BhqError(E_ARG, "j-cell array lengths disagree")
+    _check(lib().bhq_set_jc(ctx, int(adr), n, _dp(x), _dp(m), _dp(q), _dp(t)),
+           ctx)
+
+
+def bhq_compute(ctx, stream=None):
+    _check(lib().bhq_compute(ctx, _stream_handle(stream)), ctx)
+
+
+def bhq_get_result(ctx, ni):
+    a = np.zeros((ni, 3))
+    pot = np.zeros(ni)
+    _check(lib().bhq_get_result(ctx, _dp(a), _dp(pot)), ctx)
+    return a, pot
+
+
+def bhq_get_counts(ctx):
+    pp, pc = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().bhq_get_counts(ctx, ctypes.byref(pp), ctypes.byref(pc)), ctx)
+    return pp.value, pc.value
+
+
+def bhq_get_kernel_ms(ctx):
+    ms = ctypes.c_double()
+    _check(lib().bhq_get_kernel_ms(ctx, ctypes.byref(ms)), ctx)
+    return ms.value
+
+
+def bhq_last_error(ctx=None):
+    msg = lib().bhq_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+# --- host list builder --------------------------------------------------------
+
+def bhq_build_lists(x, m, theta, ncrit, nleaf=8, box=0.0, rcut=0.0,
+                    nthreads=0):
+    x = _f64(x, (-1, 3))
+    m = _f64(m)
+    h = _P()
+    _check(lib().bhq_build_lists(x.shape[0], _dp(x), _dp(m), float(theta),
+                                 int(ncrit), int(nleaf), float(box),
+                                 float(rcut), int(nthreads), ctypes.byref(h)))
+    return h
+
+
+def bhq_lists_sizes(L):
+    s = np.zeros(4, np.int64)
+    _check(lib().bhq_lists_sizes(L, _ip(s)))
+    return tuple(int(v) for v in s)
+
+
+def bhq_lists_export(L, n):
+    ng, njp, njc, _ = bhq_lists_sizes(L)
+    out = dict(i_idx=np.zeros(n, np.int64), i_off=np.zeros(ng + 1, np.int64),
+               center=np.zeros((ng, 3)), side=np.zeros(ng),
+               jp_off=np.zeros(ng + 1, np.int64), jp_idx=np.zeros(njp, np.int64),
+               jc_off=np.zeros(ng + 1, np.int64),
+               jc_cell=np.zeros(njc, np.int32))
+    _check(lib().bhq_lists_export(
+        L, _ip(out["i_idx"]), _ip(out["i_off"]), _dp(out["center"]),
+        _dp(out["side"]), _ip(out["jp_off"]), _ip(out["jp_idx"]),
+        _ip(out["jc_off"]), out["jc_cell"].ctypes.data_as(_I32)))
+    return out
+
+
+def bhq_lists_cells(L):
+    nc = bhq_lists_sizes(L)[3]
+    out = dict(com=np.zeros((nc, 3)), mass=np.zeros(nc), q=np.zeros((nc, 6)),
+               trace=np.zeros(nc))
+    _check(lib().bhq_lists_cells(L, _dp(out["com"]), _dp(out["mass"]),
+                                 _dp(out["q"]), _dp(out["trace"])))
+    return out
+
+
+def bhq_set_lists(ctx, L, x, m):
+    x = _f64(x, (-1, 3))
+    m = _f64(m)
+    _check(lib().bhq_set_lists(ctx, L, _dp(x), _dp(m)), ctx)
+
+
+def bhq_lists_free(L):
+    _check(lib().bhq_lists_free(L))

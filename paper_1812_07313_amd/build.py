@@ -1,0 +1,63 @@
+"""Build libbhq.so in-tree with hipcc for gfx950.
+
+    python -m paper_1812_07313_amd.build
+
+Compiles the HIP kernels, the C-ABI layer and the host list builder into
+``paper_1812_07313_amd/libbhq.so``.  Packed FP32 instructions are disabled
+for all device code (``-packed-fp32-ops``); the compiler emits plain VALU
+FP32 operations.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(PKG, "libbhq.so")
+ARCH = os.environ.get("BHQ_OFFLOAD_ARCH", "gfx950")
+
+SOURCES = ["bhq_kernels.hip", "bhq_api.cpp", "bhq_lists.cpp"]
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def hipcc():
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc",
+                 shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def build(verbose=False, extra=()):
+    """Compile every source and link libbhq.so (always rebuilds)."""
+    cc = hipcc()
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
+        cmd = [cc, "-c", "-O3", "-std=c++17", "-fPIC", "-Wall",
+               "--offload-arch=" + ARCH, "-I", INCLUDE, "-I", CSRC]
+        if src.endswith(".hip"):
+            cmd += ["-x", "hip"] + DEVICE_FLAGS + ["-munsafe-fp-atomics"]
+        cmd += list(extra) + ["-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + [
+        "-lpthread"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)
+    print(LIB)

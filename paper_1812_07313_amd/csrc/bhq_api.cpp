@@ -1,0 +1,657 @@
+// bhq_api.cpp -- the C ABI declared in include/bhq.h: context, validation,
+// device memory, uploads, launch and results.  Every failure is reported
+// through a return code and a per-context message; nothing aborts.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "bhq.h"
+#include "bhq_internal.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// One device array with reusable capacity.
+struct DevArray {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t reserve(size_t bytes)
+    {
+        if (bytes <= cap && p) return hipSuccess;
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+            cap = 0;
+        }
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipSuccess) cap = bytes;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+enum Arr {
+    A_IOFF, A_JPOFF, A_JCOFF, A_ORDER, A_GCX, A_GCY, A_GCZ,
+    A_XI, A_YI, A_ZI, A_E2I,
+    A_JPX, A_JPY, A_JPZ, A_JPM,
+    A_JCX, A_JCY, A_JCZ, A_JCM, A_Q00, A_Q01, A_Q02, A_Q11, A_Q12, A_Q22,
+    A_JCT,
+    A_AX, A_AY, A_AZ, A_POT,
+    A_COUNT
+};
+
+bool finite_all(const double *v, int64_t n)
+{
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(v[k])) return false;
+    return true;
+}
+
+}  // namespace
+
+struct bhq_ctx {
+    int device = 0;
+    int kernel = BHQ_QUAD;
+    int precision = BHQ_FP32_OFS64;
+    std::string err;
+
+    int64_t ng = -1, ni = 0, njp = 0, njc = 0;
+    std::vector<int64_t> i_off, jp_off, jc_off;
+    DevArray arr[A_COUNT];
+
+    bool have_i = false, have_jp = false, have_jc = false, have_t = false;
+    int eps_mode = 0;  // 0 none, 1 uniform, 2 per-particle
+    double eps2_all = 0.0;
+    bool have_split = false;
+    double rs = 0.0, rcut = 0.0, box = 0.0;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool launched = false;
+    hipStream_t last_stream = nullptr;
+
+    std::vector<double> stage;  // host staging for SoA transposes
+
+    int fail(int code, const char *fmt, ...)
+    {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+    int hip_fail(hipError_t e, const char *what)
+    {
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+            return fail(BHQ_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+        return fail(BHQ_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    }
+    int select()
+    {
+        hipError_t e = hipSetDevice(device);
+        return e == hipSuccess ? BHQ_OK : hip_fail(e, "hipSetDevice");
+    }
+    // Upload n doubles to array a at element offset off.
+    int put(Arr a, int64_t off, const double *src, int64_t n)
+    {
+        if (n == 0) return BHQ_OK;
+        hipError_t e = hipMemcpy(arr[a].as<double>() + off, src,
+                                 (size_t)n * sizeof(double),
+                                 hipMemcpyHostToDevice);
+        return e == hipSuccess ? BHQ_OK : hip_fail(e, "hipMemcpy H2D");
+    }
+    // Upload component c of an AoS array v[n][w] into array a at offset off.
+    int put_component(Arr a, int64_t off, const double *v, int w, int c,
+                      int64_t n)
+    {
+        try {
+            stage.resize((size_t)n);
+        } catch (const std::bad_alloc &) {
+            return fail(BHQ_E_NOMEM, "host staging of %lld values",
+                        (long long)n);
+        }
+        for (int64_t k = 0; k < n; ++k) stage[(size_t)k] = v[k * w + c];
+        return put(a, off, stage.data(), n);
+    }
+    int fill_eps_uniform()
+    {
+        if (ni == 0) return BHQ_OK;
+        try {
+            stage.assign((size_t)ni, eps2_all);
+        } catch (const std::bad_alloc &) {
+            return fail(BHQ_E_NOMEM, "host staging");
+        }
+        return put(A_E2I, 0, stage.data(), ni);
+    }
+};
+
+#define CHECK_CTX(ctx)                                    \
+    do {                                                  \
+        if (!(ctx)) return BHQ_E_ARG;                     \
+    } while (0)
+
+#define TRY(expr)                                         \
+    do {                                                  \
+        int rc_ = (expr);                                 \
+        if (rc_ != BHQ_OK) return rc_;                    \
+    } while (0)
+
+static bool valid_kernel(int k) { return k >= BHQ_MONO && k <= BHQ_SPLIT_MONO; }
+static bool valid_prec(int p) { return p == BHQ_FP32_OFS64 || p == BHQ_FP64; }
+
+extern "C" {
+
+int bhq_create(bhq_ctx **out, int device, int kernel, int precision)
+{
+    if (!out) {
+        g_create_error = "bhq_create: out is NULL";
+        return BHQ_E_ARG;
+    }
+    *out = nullptr;
+    if (!valid_kernel(kernel) || !valid_prec(precision)) {
+        g_create_error = "bhq_create: unknown kernel or precision";
+        return BHQ_E_ARG;
+    }
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        g_create_error = std::string("bhq_create: no GPU available (") +
+                         hipGetErrorString(e) + ")";
+        return BHQ_E_NODEV;
+    }
+    if (device < 0 || device >= count) {
+        g_create_error = "bhq_create: device index out of range";
+        return BHQ_E_NODEV;
+    }
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("bhq_create: hipSetDevice: ") +
+                         hipGetErrorString(e);
+        return BHQ_E_HIP;
+    }
+    bhq_ctx *c = new (std::nothrow) bhq_ctx();
+    if (!c) {
+        g_create_error = "bhq_create: out of host memory";
+        return BHQ_E_NOMEM;
+    }
+    c->device = device;
+    c->kernel = kernel;
+    c->precision = precision;
+    if (hipEventCreate(&c->ev0) != hipSuccess ||
+        hipEventCreate(&c->ev1) != hipSuccess) {
+        g_create_error = "bhq_create: hipEventCreate failed";
+        if (c->ev0) (void)hipEventDestroy(c->ev0);
+        delete c;
+        return BHQ_E_HIP;
+    }
+    g_create_error.clear();
+    *out = c;
+    return BHQ_OK;
+}
+
+int bhq_destroy(bhq_ctx *ctx)
+{
+    if (!ctx) return BHQ_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
+    for (auto &a : ctx->arr) a.release();
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+    return BHQ_OK;
+}
+
+int bhq_set_kernel(bhq_ctx *ctx, int kernel, int precision)
+{
+    CHECK_CTX(ctx);
+    if (!valid_kernel(kernel) || !valid_prec(precision))
+        return ctx->fail(BHQ_E_ARG, "bhq_set_kernel: unknown kernel %d or "
+                                    "precision %d", kernel, precision);
+    ctx->kernel = kernel;
+    ctx->precision = precision;
+    return BHQ_OK;
+}
+
+int bhq_set_eps(bhq_ctx *ctx, double eps)
+{
+    CHECK_CTX(ctx);
+    if (!std::isfinite(eps)) return ctx->fail(BHQ_E_NONFINITE, "eps not finite");
+    if (eps < 0.0) return ctx->fail(BHQ_E_ARG, "eps must be >= 0");
+    ctx->eps2_all = eps * eps;
+    ctx->eps_mode = 1;
+    if (ctx->ng >= 0) {
+        TRY(ctx->select());
+        return ctx->fill_eps_uniform();
+    }
+    return BHQ_OK;
+}
+
+int bhq_set_eps2_i(bhq_ctx *ctx, int64_t ni, const double *eps2)
+{
+    CHECK_CTX(ctx);
+    if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "set_eps2_i before set_groups");
+    if (!eps2 && ni > 0) return ctx->fail(BHQ_E_ARG, "eps2 is NULL");
+    if (ni != ctx->ni)
+        return ctx->fail(BHQ_E_RANGE, "set_eps2_i: ni %lld != %lld",
+                         (long long)ni, (long long)ctx->ni);
+    for (int64_t k = 0; k < ni; ++k) {
+        if (!std::isfinite(eps2[k]))
+            return ctx->fail(BHQ_E_NONFINITE, "eps2[%lld] not finite",
+                             (long long)k);
+        if (eps2[k] < 0.0)
+            return ctx->fail(BHQ_E_ARG, "eps2[%lld] < 0", (long long)k);
+    }
+    TRY(ctx->select());
+    TRY(ctx->put(A_E2I, 0, eps2, ni));
+    ctx->eps_mode = 2;
+    return BHQ_OK;
+}
+
+int bhq_set_split(bhq_ctx *ctx, double rs, double rcut, double box)
+{
+    CHECK_CTX(ctx);
+    if (!std::isfinite(rs) || !std::isfinite(rcut) || !std::isfinite(box))
+        return ctx->fail(BHQ_E_NONFINITE, "split parameters not finite");
+    if (!(rs > 0.0) || !(rcut > 0.0) || box < 0.0)
+        return ctx->fail(BHQ_E_ARG, "need rs > 0, rcut > 0, box >= 0");
+    ctx->rs = rs;
+    ctx->rcut = rcut;
+    ctx->box = box;
+    ctx->have_split = true;
+    return BHQ_OK;
+}
+
+static int check_offsets(bhq_ctx *ctx, const char *name, const int64_t *off,
+                         int64_t ng)
+{
+    if (!off) return ctx->fail(BHQ_E_ARG, "%s is NULL", name);
+    if (off[0] != 0) return ctx->fail(BHQ_E_RANGE, "%s[0] != 0", name);
+    for (int64_t g = 0; g < ng; ++g)
+        if (off[g + 1] < off[g])
+            return ctx->fail(BHQ_E_RANGE, "%s not monotone at group %lld", name,
+                             (long long)g);
+    return BHQ_OK;
+}
+
+int bhq_set_groups(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
+                   const double (*center)[3], const int64_t *jp_off,
+                   const int64_t *jc_off)
+{
+    CHECK_CTX(ctx);
+    if (ng < 1) return ctx->fail(BHQ_E_ARG, "ng must be >= 1");
+    if (ng > 0x7fffffff) return ctx->fail(BHQ_E_RANGE, "too many groups");
+    if (!center) return ctx->fail(BHQ_E_ARG, "center is NULL");
+    TRY(check_offsets(ctx, "i_off", i_off, ng));
+    TRY(check_offsets(ctx, "jp_off", jp_off, ng));
+    TRY(check_offsets(ctx, "jc_off", jc_off, ng));
+    if (!finite_all(&center[0][0], 3 * ng))
+        return ctx->fail(BHQ_E_NONFINITE, "group centre not finite");
+    TRY(ctx->select());
+
+    const int64_t ni = i_off[ng], njp = jp_off[ng], njc = jc_off[ng];
+    const size_t D = sizeof(double);
+    struct { Arr a; size_t bytes; } need[] = {
+        {A_IOFF, (size_t)(ng + 1) * 8}, {A_JPOFF, (size_t)(ng + 1) * 8},
+        {A_JCOFF, (size_t)(ng + 1) * 8}, {A_ORDER, (size_t)ng * 4},
+        {A_GCX, (size_t)ng * D}, {A_GCY, (size_t)ng * D}, {A_GCZ, (size_t)ng * D},
+        {A_XI, (size_t)ni * D}, {A_YI, (size_t)ni * D}, {A_ZI, (size_t)ni * D},
+        {A_E2I, (size_t)ni * D},
+        {A_AX, (size_t)ni * D}, {A_AY, (size_t)ni * D}, {A_AZ, (size_t)ni * D},
+        {A_POT, (size_t)ni * D},
+        {A_JPX, (size_t)njp * D}, {A_JPY, (size_t)njp * D},
+        {A_JPZ, (size_t)njp * D}, {A_JPM, (size_t)njp * D},
+        {A_JCX, (size_t)njc * D}, {A_JCY, (size_t)njc * D},
+        {A_JCZ, (size_t)njc * D}, {A_JCM, (size_t)njc * D},
+        {A_Q00, (size_t)njc * D}, {A_Q01, (size_t)njc * D},
+        {A_Q02, (size_t)njc * D}, {A_Q11, (size_t)njc * D},
+        {A_Q12, (size_t)njc * D}, {A_Q22, (size_t)njc * D},
+        {A_JCT, (size_t)njc * D},
+    };
+    if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
+    for (auto &n : need) {
+        hipError_t e = ctx->arr[n.a].reserve(n.bytes);
+        if (e != hipSuccess) {
+            ctx->ng = -1;
+            return ctx->hip_fail(e, "hipMalloc");
+        }
+    }
+    try {
+        ctx->i_off.assign(i_off, i_off + ng + 1);
+        ctx->jp_off.assign(jp_off, jp_off + ng + 1);
+        ctx->jc_off.assign(jc_off, jc_off + ng + 1);
+    } catch (const std::bad_alloc &) {
+        ctx->ng = -1;
+        return ctx->fail(BHQ_E_NOMEM, "host copy of offsets");
+    }
+    ctx->ng = ng;
+    ctx->ni = ni;
+    ctx->njp = njp;
+    ctx->njc = njc;
+    ctx->have_i = ctx->have_jp = ctx->have_jc = ctx->have_t = false;
+    if (ctx->eps_mode == 2) ctx->eps_mode = 0;
+
+    auto up = [&](Arr a, const void *src, size_t bytes) -> int {
+        if (!bytes) return BHQ_OK;
+        hipError_t e = hipMemcpy(ctx->arr[a].p, src, bytes, hipMemcpyHostToDevice);
+        return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "hipMemcpy H2D");
+    };
+    TRY(up(A_IOFF, i_off, (size_t)(ng + 1) * 8));
+    TRY(up(A_JPOFF, jp_off, (size_t)(ng + 1) * 8));
+    TRY(up(A_JCOFF, jc_off, (size_t)(ng + 1) * 8));
+    for (int c = 0; c < 3; ++c)
+        TRY(ctx->put_component((Arr)(A_GCX + c), 0, &center[0][0], 3, c, ng));
+
+    // Longest-processing-time-first block order: cost ~ ni (njp + 2.65 njc)
+    // (a cell term costs about 53 / 20 of a particle term).
+    std::vector<double> cost((size_t)ng);
+    std::vector<int32_t> order((size_t)ng);
+    for (int64_t g = 0; g < ng; ++g) {
+        const double nig = (double)(i_off[g + 1] - i_off[g]);
+        cost[(size_t)g] = nig * ((double)(jp_off[g + 1] - jp_off[g]) +
+                                 2.65 * (double)(jc_off[g + 1] - jc_off[g]));
+        order[(size_t)g] = (int32_t)g;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return cost[(size_t)a] > cost[(size_t)b];
+    });
+    TRY(up(A_ORDER, order.data(), (size_t)ng * 4));
+    if (ctx->eps_mode == 1) TRY(ctx->fill_eps_uniform());
+    return BHQ_OK;
+}
+
+int bhq_set_i(bhq_ctx *ctx, int64_t ni, const double (*x)[3])
+{
+    CHECK_CTX(ctx);
+    if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "set_i before set_groups");
+    if (ni != ctx->ni)
+        return ctx->fail(BHQ_E_RANGE, "set_i: ni %lld != i_off[ng] %lld",
+                         (long long)ni, (long long)ctx->ni);
+    if (!x && ni > 0) return ctx->fail(BHQ_E_ARG, "x is NULL");
+    if (!finite_all(&x[0][0], 3 * ni))
+        return ctx->fail(BHQ_E_NONFINITE, "i position not finite");
+    TRY(ctx->select());
+    for (int c = 0; c < 3; ++c)
+        TRY(ctx->put_component((Arr)(A_XI + c), 0, &x[0][0], 3, c, ni));
+    ctx->have_i = true;
+    return BHQ_OK;
+}
+
+int bhq_set_jp(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
+               const double *m)
+{
+    CHECK_CTX(ctx);
+    if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "set_jp before set_groups");
+    if (adr < 0 || n < 0) return ctx->fail(BHQ_E_ARG, "negative adr or n");
+    if (adr + n > ctx->njp)
+        return ctx->fail(BHQ_E_RANGE, "set_jp: adr + n = %lld > njp = %lld",
+                         (long long)(adr + n), (long long)ctx->njp);
+    if (n > 0 && (!x || !m)) return ctx->fail(BHQ_E_ARG, "x or m is NULL");
+    if (!finite_all(&x[0][0], 3 * n) || !finite_all(m, n))
+        return ctx->fail(BHQ_E_NONFINITE, "j-particle data not finite");
+    TRY(ctx->select());
+    for (int c = 0; c < 3; ++c)
+        TRY(ctx->put_component((Arr)(A_JPX + c), adr, &x[0][0], 3, c, n));
+    TRY(ctx->put(A_JPM, adr, m, n));
+    ctx->have_jp = true;
+    return BHQ_OK;
+}
+
+int bhq_set_jc(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
+               const double *m, const double (*q)[6], const double *trace)
+{
+    CHECK_CTX(ctx);
+    if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "set_jc before set_groups");
+    if (adr < 0 || n < 0) return ctx->fail(BHQ_E_ARG, "negative adr or n");
+    if (adr + n > ctx->njc)
+        return ctx->fail(BHQ_E_RANGE, "set_jc: adr + n = %lld > njc = %lld",
+                         (long long)(adr + n), (long long)ctx->njc);
+    if (n > 0 && (!x || !m || !q))
+        return ctx->fail(BHQ_E_ARG, "x, m or q is NULL");
+    if (!finite_all(&x[0][0], 3 * n) || !finite_all(m, n) ||
+        !finite_all(&q[0][0], 6 * n) || (trace && !finite_all(trace, n)))
+        return ctx->fail(BHQ_E_NONFINITE, "j-cell data not finite");
+    TRY(ctx->select());
+    for (int c = 0; c < 3; ++c)
+        TRY(ctx->put_component((Arr)(A_JCX + c), adr, &x[0][0], 3, c, n));
+    TRY(ctx->put(A_JCM, adr, m, n));
+    for (int c = 0; c < 6; ++c)
+        TRY(ctx->put_component((Arr)(A_Q00 + c), adr, &q[0][0], 6, c, n));
+    if (trace) {
+        TRY(ctx->put(A_JCT, adr, trace, n));
+    } else if (n > 0) {
+        try {
+            ctx->stage.assign((size_t)n, 0.0);
+        } catch (const std::bad_alloc &) {
+            return ctx->fail(BHQ_E_NOMEM, "host staging");
+        }
+        TRY(ctx->put(A_JCT, adr, ctx->stage.data(), n));
+    }
+    ctx->have_jc = true;
+    return BHQ_OK;
+}
+
+int bhq_compute(bhq_ctx *ctx, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "compute before set_groups");
+    if (!ctx->have_i && ctx->ni > 0)
+        return ctx->fail(BHQ_E_STATE, "compute before set_i");
+    if (ctx->njp > 0 && !ctx->have_jp)
+        return ctx->fail(BHQ_E_STATE, "compute before set_jp");
+    if (ctx->njc > 0 && !ctx->have_jc)
+        return ctx->fail(BHQ_E_STATE, "compute before set_jc");
+    const bool split = ctx->kernel == BHQ_SPLIT_QUAD ||
+                       ctx->kernel == BHQ_SPLIT_MONO;
+    if (split && !ctx->have_split)
+        return ctx->fail(BHQ_E_STATE, "split kernel without bhq_set_split");
+    if (!split && ctx->eps_mode == 0)
+        return ctx->fail(BHQ_E_STATE, "compute before set_eps / set_eps2_i");
+    TRY(ctx->select());
+
+    bhq::ForceArgs A{};
+    auto D = [&](Arr a) { return ctx->arr[a].as<double>(); };
+    A.ng = ctx->ng;
+    A.order = ctx->arr[A_ORDER].as<int32_t>();
+    A.i_off = ctx->arr[A_IOFF].as<int64_t>();
+    A.jp_off = ctx->arr[A_JPOFF].as<int64_t>();
+    A.jc_off = ctx->arr[A_JCOFF].as<int64_t>();
+    A.gcx = D(A_GCX); A.gcy = D(A_GCY); A.gcz = D(A_GCZ);
+    A.xi = D(A_XI); A.yi = D(A_YI); A.zi = D(A_ZI); A.e2i = D(A_E2I);
+    A.jpx = D(A_JPX); A.jpy = D(A_JPY); A.jpz = D(A_JPZ); A.jpm = D(A_JPM);
+    A.jcx = D(A_JCX); A.jcy = D(A_JCY); A.jcz = D(A_JCZ); A.jcm = D(A_JCM);
+    A.q00 = D(A_Q00); A.q01 = D(A_Q01); A.q02 = D(A_Q02);
+    A.q11 = D(A_Q11); A.q12 = D(A_Q12); A.q22 = D(A_Q22);
+    A.jct = D(A_JCT);
+    A.ax = D(A_AX); A.ay = D(A_AY); A.az = D(A_AZ); A.pot = D(A_POT);
+    A.box = split ? ctx->box : 0.0;
+    A.rs = ctx->rs;
+    A.rcut = ctx->rcut;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipEventRecord(ctx->ev0, s);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipEventRecord");
+    e = bhq::launch_force(ctx->kernel, ctx->precision, A, s);
+    if (e != hipSuccess) return ctx->hip_fail(e, "force kernel launch");
+    e = hipEventRecord(ctx->ev1, s);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipEventRecord");
+    ctx->launched = true;
+    ctx->last_stream = s;
+    return BHQ_OK;
+}
+
+int bhq_get_result(bhq_ctx *ctx, double (*a)[3], double *pot)
+{
+    CHECK_CTX(ctx);
+    if (!ctx->launched) return ctx->fail(BHQ_E_STATE, "no compute launched");
+    TRY(ctx->select());
+    hipError_t e = hipEventSynchronize(ctx->ev1);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipEventSynchronize");
+    const int64_t ni = ctx->ni;
+    if (ni == 0) return BHQ_OK;
+    try {
+        ctx->stage.resize((size_t)ni);
+    } catch (const std::bad_alloc &) {
+        return ctx->fail(BHQ_E_NOMEM, "host staging");
+    }
+    if (a) {
+        for (int c = 0; c < 3; ++c) {
+            e = hipMemcpy(ctx->stage.data(), ctx->arr[A_AX + c].p,
+                          (size_t)ni * sizeof(double), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return ctx->hip_fail(e, "hipMemcpy D2H");
+            for (int64_t k = 0; k < ni; ++k) a[k][c] = ctx->stage[(size_t)k];
+        }
+    }
+    if (pot) {
+        e = hipMemcpy(pot, ctx->arr[A_POT].p, (size_t)ni * sizeof(double),
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return ctx->hip_fail(e, "hipMemcpy D2H");
+    }
+    return BHQ_OK;
+}
+
+int bhq_get_counts(const bhq_ctx *ctx, int64_t *n_pp, int64_t *n_pc)
+{
+    if (!ctx || !n_pp || !n_pc) return BHQ_E_ARG;
+    if (ctx->ng < 0) return BHQ_E_STATE;
+    int64_t pp = 0, pc = 0;
+    for (int64_t g = 0; g < ctx->ng; ++g) {
+        const int64_t nig = ctx->i_off[(size_t)g + 1] - ctx->i_off[(size_t)g];
+        pp += nig * (ctx->jp_off[(size_t)g + 1] - ctx->jp_off[(size_t)g]);
+        pc += nig * (ctx->jc_off[(size_t)g + 1] - ctx->jc_off[(size_t)g]);
+    }
+    *n_pp = pp;
+    *n_pc = pc;
+    return BHQ_OK;
+}
+
+int bhq_get_kernel_ms(bhq_ctx *ctx, double *ms)
+{
+    CHECK_CTX(ctx);
+    if (!ms) return ctx->fail(BHQ_E_ARG, "ms is NULL");
+    if (!ctx->launched) return ctx->fail(BHQ_E_STATE, "no compute launched");
+    TRY(ctx->select());
+    hipError_t e = hipEventSynchronize(ctx->ev1);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipEventSynchronize");
+    float f = 0.0f;
+    e = hipEventElapsedTime(&f, ctx->ev0, ctx->ev1);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipEventElapsedTime");
+    *ms = (double)f;
+    return BHQ_OK;
+}
+
+const char *bhq_last_error(const bhq_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+// Upload host-built lists: gathers i-particles into group order and
+// materialises the j-entries in chunks to bound host memory.
+int bhq_set_lists(bhq_ctx *ctx, const bhq_lists *L, const double (*x)[3],
+                  const double *m)
+{
+    CHECK_CTX(ctx);
+    if (!L || !x || !m) return ctx->fail(BHQ_E_ARG, "NULL lists, x or m");
+    int64_t sz[4];
+    TRY(bhq_lists_sizes(L, sz));
+    const int64_t ng = sz[0], njp = sz[1], njc = sz[2], ncell = sz[3];
+    try {
+        std::vector<int64_t> i_off((size_t)ng + 1), jp_off((size_t)ng + 1),
+            jc_off((size_t)ng + 1);
+        std::vector<double> center((size_t)ng * 3);
+        TRY(bhq_lists_export(L, nullptr, i_off.data(),
+                             reinterpret_cast<double(*)[3]>(center.data()),
+                             nullptr, jp_off.data(), nullptr, jc_off.data(),
+                             nullptr));
+        TRY(bhq_set_groups(ctx, ng, i_off.data(),
+                           reinterpret_cast<const double(*)[3]>(center.data()),
+                           jp_off.data(), jc_off.data()));
+        const int64_t n = i_off[(size_t)ng];
+        {
+            std::vector<int64_t> i_idx((size_t)n);
+            TRY(bhq_lists_export(L, i_idx.data(), nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, nullptr, nullptr));
+            std::vector<double> xi((size_t)n * 3);
+            for (int64_t k = 0; k < n; ++k)
+                for (int c = 0; c < 3; ++c)
+                    xi[(size_t)(3 * k + c)] = x[i_idx[(size_t)k]][c];
+            TRY(bhq_set_i(ctx, n, reinterpret_cast<const double(*)[3]>(xi.data())));
+        }
+        const int64_t chunk = 1 << 22;
+        {
+            std::vector<int64_t> jp_idx((size_t)njp);
+            TRY(bhq_lists_export(L, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                 jp_idx.data(), nullptr, nullptr));
+            std::vector<double> bx, bm;
+            for (int64_t a0 = 0; a0 < njp; a0 += chunk) {
+                const int64_t cn = std::min(chunk, njp - a0);
+                bx.resize((size_t)cn * 3);
+                bm.resize((size_t)cn);
+                for (int64_t k = 0; k < cn; ++k) {
+                    const int64_t p = jp_idx[(size_t)(a0 + k)];
+                    for (int c = 0; c < 3; ++c) bx[(size_t)(3 * k + c)] = x[p][c];
+                    bm[(size_t)k] = m[p];
+                }
+                TRY(bhq_set_jp(ctx, a0, cn,
+                               reinterpret_cast<const double(*)[3]>(bx.data()),
+                               bm.data()));
+            }
+            if (njp == 0) ctx->have_jp = true;
+        }
+        {
+            std::vector<int32_t> jc_cell((size_t)njc);
+            TRY(bhq_lists_export(L, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, jc_cell.data()));
+            std::vector<double> com((size_t)ncell * 3), mass((size_t)ncell),
+                q((size_t)ncell * 6), tr((size_t)ncell);
+            TRY(bhq_lists_cells(L, reinterpret_cast<double(*)[3]>(com.data()),
+                                mass.data(),
+                                reinterpret_cast<double(*)[6]>(q.data()),
+                                tr.data()));
+            std::vector<double> bx, bm, bq, bt;
+            for (int64_t a0 = 0; a0 < njc; a0 += chunk) {
+                const int64_t cn = std::min(chunk, njc - a0);
+                bx.resize((size_t)cn * 3);
+                bm.resize((size_t)cn);
+                bq.resize((size_t)cn * 6);
+                bt.resize((size_t)cn);
+                for (int64_t k = 0; k < cn; ++k) {
+                    const size_t c = (size_t)jc_cell[(size_t)(a0 + k)];
+                    for (int d = 0; d < 3; ++d)
+                        bx[(size_t)(3 * k + d)] = com[3 * c + d];
+                    for (int d = 0; d < 6; ++d)
+                        bq[(size_t)(6 * k + d)] = q[6 * c + d];
+                    bm[(size_t)k] = mass[c];
+                    bt[(size_t)k] = tr[c];
+                }
+                TRY(bhq_set_jc(ctx, a0, cn,
+                               reinterpret_cast<const double(*)[3]>(bx.data()),
+                               bm.data(),
+                               reinterpret_cast<const double(*)[6]>(bq.data()),
+                               bt.data()));
+            }
+            if (njc == 0) ctx->have_jc = true;
+        }
+    } catch (const std::bad_alloc &) {
+        return ctx->fail(BHQ_E_NOMEM, "host memory while materialising lists");
+    }
+    return BHQ_OK;
+}
+
+}  // extern "C"

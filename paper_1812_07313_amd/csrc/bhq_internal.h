@@ -1,0 +1,39 @@
+// bhq_internal.h -- shared between the C-ABI layer (bhq_api.cpp) and the
+// HIP kernels (bhq_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+namespace bhq {
+
+// Threads per block; also the depth of one LDS tile of j-entries.
+constexpr int kBlock = 256;
+
+// Device-side view of one force evaluation.  All arrays are SoA in device
+// memory; i-particles and outputs are in group order.
+struct ForceArgs {
+    int64_t ng;                     // groups
+    const int32_t *order;           // block b processes group order[b]
+    const int64_t *i_off;           // [ng+1]
+    const int64_t *jp_off;          // [ng+1]
+    const int64_t *jc_off;          // [ng+1]
+    const double *gcx, *gcy, *gcz;  // [ng] group reference points (FP64)
+    const double *xi, *yi, *zi;     // [ni] i positions (FP64)
+    const double *e2i;              // [ni] squared softening
+    const double *jpx, *jpy, *jpz, *jpm;           // [njp] j-particles
+    const double *jcx, *jcy, *jcz, *jcm;           // [njc] j-cell com, mass
+    const double *q00, *q01, *q02, *q11, *q12, *q22;  // [njc] quadrupole
+    const double *jct;              // [njc] trace (split kernel)
+    double *ax, *ay, *az, *pot;     // [ni] results (FP64)
+    double box;                     // > 0: periodic minimum image
+    double rs, rcut;                // split-kernel parameters
+};
+
+// Launch the force kernel for (kernel, precision) on `stream`.  Returns
+// the launch status.
+hipError_t launch_force(int kernel, int precision, const ForceArgs &args,
+                        hipStream_t stream);
+
+}  // namespace bhq

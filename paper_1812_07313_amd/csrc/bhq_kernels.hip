@@ -1,0 +1,370 @@
+// bhq_kernels.hip -- force kernels for gfx950 (CDNA4).
+//
+// One 256-thread block evaluates one group's interaction list (the modified
+// tree algorithm of Kodama & Ishiyama, Sec. 3.4: all i-particles of a group
+// share one list).  Each active thread owns one i-particle.  The list is
+// streamed through LDS in tiles of 256 entries: every thread loads one
+// entry with coalesced FP64 SoA reads, forms its position relative to the
+// group's FP64 reference point, converts it to the working precision and
+// stores it in LDS; the threads then read entries back as broadcasts.
+//
+// Small groups (ni < 256) split the tile between S = 256 / ni slices of ni
+// threads: slice s takes entries s, s + S, s + 2S, ...; the slices' partial
+// sums are combined in a fixed order at the end, so results are
+// deterministic run to run.
+//
+// Interaction arithmetic (per i-particle, per list entry, d = x_j - x_i):
+//   particle:  rinv = rsq(|d|^2 + eps^2); a += m rinv^3 d; -phi += m rinv
+//   cell (monopole + traceless quadrupole, Sec. 3 eqs. 1 and 7):
+//     Qd = Q d, dQd = d.Qd, rinv5 = rinv^5,
+//     -phi += M rinv + dQd rinv5 / 2,
+//     a += (M rinv + 2.5 dQd rinv5) rinv^2 d - rinv5 Qd
+//   This is the paper's per-cell sequence with the constant factors folded
+//   (0.5 and 5 phi_q become 0.5 and 2.5 on dQd rinv5), 34 VALU operations.
+// The particle-particle part is summed before the cell part (List 4).
+// Accumulation is tile-blocked: each tile is summed into fresh registers
+// that are then added to the running sums.
+#include <hip/hip_runtime.h>
+
+#include "bhq_internal.h"
+
+namespace bhq {
+
+namespace {
+
+template <typename R>
+struct alignas(4 * sizeof(R)) V4 {
+    R x, y, z, w;
+};
+
+__device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ double rsq(double v) { return ::rsqrt(v); }
+
+__device__ __forceinline__ float erfc_r(float v) { return ::erfcf(v); }
+__device__ __forceinline__ double erfc_r(double v) { return ::erfc(v); }
+__device__ __forceinline__ float exp_r(float v) { return ::expf(v); }
+__device__ __forceinline__ double exp_r(double v) { return ::exp(v); }
+
+__device__ __forceinline__ double wrap(double v, double box, double ibox)
+{
+    return box > 0.0 ? v - box * ::rint(v * ibox) : v;
+}
+
+constexpr int kMono = 0, kQuad = 1, kSplitQuad = 2, kSplitMono = 3;
+
+// Plummer-softened particle (also the monopole-only cell).
+template <typename R>
+__device__ __forceinline__ void pp_plummer(const V4<R> &j, R xi, R yi, R zi,
+                                           R e2, R &ax, R &ay, R &az, R &pt)
+{
+    const R dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
+    const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+    const R rinv = rsq(r2);
+    const R mr = j.w * rinv;
+    const R mr3 = mr * (rinv * rinv);
+    pt += mr;
+    ax = fma(mr3, dx, ax);
+    ay = fma(mr3, dy, ay);
+    az = fma(mr3, dz, az);
+}
+
+// Monopole + traceless quadrupole cell (Sec. 3, eqs. 1, 4-7).
+// a: (x, y, z, M), b: (q00, q01, q02, q11), c: (q12, q22, T, 0).
+template <typename R>
+__device__ __forceinline__ void pc_quad(const V4<R> &a, const V4<R> &b,
+                                        const V4<R> &c, R xi, R yi, R zi, R e2,
+                                        R &ax, R &ay, R &az, R &pt)
+{
+    const R dx = a.x - xi, dy = a.y - yi, dz = a.z - zi;
+    const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+    const R rinv = rsq(r2);
+    const R rinv2 = rinv * rinv;
+    const R phim = a.w * rinv;
+    const R qx = fma(b.z, dz, fma(b.y, dy, b.x * dx));
+    const R qy = fma(c.x, dz, fma(b.w, dy, b.y * dx));
+    const R qz = fma(c.y, dz, fma(c.x, dy, b.z * dx));
+    const R dqd = fma(dz, qz, fma(dy, qy, dx * qx));
+    const R rinv5 = (rinv2 * rinv2) * rinv;
+    const R pq = dqd * rinv5;  // 2 phi_quad
+    pt += phim;
+    pt = fma(R(0.5), pq, pt);
+    const R cf = fma(R(2.5), pq, phim) * rinv2;
+    ax = fma(cf, dx, ax);
+    ay = fma(cf, dy, ay);
+    az = fma(cf, dz, az);
+    ax = fma(-rinv5, qx, ax);
+    ay = fma(-rinv5, qy, ay);
+    az = fma(-rinv5, qz, az);
+}
+
+// Gaussian-split radial functions at r (with rinv = 1/r), u = r * i2rs:
+//   g = erfc(u) + (2u/sqrt(pi)) e^{-u^2}, h = (4u^3/sqrt(pi)) e^{-u^2}.
+template <typename R>
+struct SplitF {
+    R ec, g, h, k;  // k = (8 u^5 / sqrt(pi)) e^{-u^2}
+};
+
+template <typename R>
+__device__ __forceinline__ SplitF<R> split_f(R r, R i2rs)
+{
+    const R rsqpi = R(0.56418958354775628694807945156);
+    const R u = r * i2rs;
+    const R u2 = u * u;
+    const R e = exp_r(-u2) * rsqpi;
+    SplitF<R> f;
+    f.ec = erfc_r(u);
+    f.g = fma(R(2) * u, e, f.ec);
+    f.h = R(4) * u * u2 * e;
+    f.k = R(2) * u2 * f.h;
+    return f;
+}
+
+// Short-range particle: a += m g/r^3 d, -phi += m erfc(u)/r; masked at
+// r == 0 and r >= rcut.
+template <typename R>
+__device__ __forceinline__ void pp_split(const V4<R> &j, R xi, R yi, R zi,
+                                         R i2rs, R rcut2, R &ax, R &ay, R &az,
+                                         R &pt)
+{
+    const R dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
+    const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    if (r2 > R(0) && r2 < rcut2) {
+        const R rinv = rsq(r2);
+        const R r = r2 * rinv;
+        const SplitF<R> f = split_f(r, i2rs);
+        const R mr = j.w * rinv;
+        const R c = mr * f.g * (rinv * rinv);
+        pt = fma(mr, f.ec, pt);
+        ax = fma(c, dx, ax);
+        ay = fma(c, dy, ay);
+        az = fma(c, dz, az);
+    }
+}
+
+// Short-range cell expanded to second order about its centre of mass
+// (with the trace T):
+//   phi = M Phi + D2 dQd / 6 + T/6 (D2 r^2 + 3 D1)
+//   a   = [M D1 + D3 dQd / 6 + T/6 (D3 r^2 + 5 D2)] d + D2/3 Qd
+// with D1 = g/r^3, D2 = -(3g + h)/r^5, D3 = (15g + 5h + k)/r^7.
+template <typename R, bool QUAD>
+__device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b,
+                                         const V4<R> &c, R xi, R yi, R zi,
+                                         R i2rs, R rcut2, R &ax, R &ay, R &az,
+                                         R &pt)
+{
+    const R dx = a.x - xi, dy = a.y - yi, dz = a.z - zi;
+    const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    if (r2 > R(0) && r2 < rcut2) {
+        const R rinv = rsq(r2);
+        const R r = r2 * rinv;
+        const R rinv2 = rinv * rinv;
+        const SplitF<R> f = split_f(r, i2rs);
+        const R D1 = f.g * rinv2 * rinv;
+        R phi = -a.w * f.ec * rinv;  // M Phi
+        R coef = a.w * D1;
+        if (QUAD) {
+            const R rinv5 = rinv2 * rinv2 * rinv;
+            const R D2 = -fma(R(3), f.g, f.h) * rinv5;
+            const R D3 = fma(R(15), f.g, fma(R(5), f.h, f.k)) * rinv5 * rinv2;
+            const R qx = fma(b.z, dz, fma(b.y, dy, b.x * dx));
+            const R qy = fma(c.x, dz, fma(b.w, dy, b.y * dx));
+            const R qz = fma(c.y, dz, fma(c.x, dy, b.z * dx));
+            const R dqd = fma(dz, qz, fma(dy, qy, dx * qx));
+            const R t6 = c.z * R(1.0 / 6.0);
+            phi = fma(D2, dqd * R(1.0 / 6.0), phi);
+            phi = fma(t6, fma(D2, r2, R(3) * D1), phi);
+            coef = fma(D3, dqd * R(1.0 / 6.0), coef);
+            coef = fma(t6, fma(D3, r2, R(5) * D2), coef);
+            const R d23 = D2 * R(1.0 / 3.0);
+            ax = fma(d23, qx, ax);
+            ay = fma(d23, qy, ay);
+            az = fma(d23, qz, az);
+        }
+        pt -= phi;
+        ax = fma(coef, dx, ax);
+        ay = fma(coef, dy, ay);
+        az = fma(coef, dz, az);
+    }
+}
+
+template <typename R, int KIND>
+__global__ __launch_bounds__(kBlock) void force_kernel(const ForceArgs A)
+{
+    constexpr bool kSplit = (KIND == kSplitQuad || KIND == kSplitMono);
+    constexpr bool kCellQ = (KIND == kQuad || KIND == kSplitQuad);
+    __shared__ V4<R> sa[kBlock];
+    __shared__ V4<R> sb[kBlock];
+    __shared__ V4<R> sc[kBlock];
+
+    const int t = threadIdx.x;
+    const int64_t g = A.order ? A.order[blockIdx.x] : (int64_t)blockIdx.x;
+    const int64_t i0 = A.i_off[g];
+    const int64_t ni = A.i_off[g + 1] - i0;
+    const double cx = A.gcx[g], cy = A.gcy[g], cz = A.gcz[g];
+    const int64_t p0 = A.jp_off[g], np = A.jp_off[g + 1] - p0;
+    const int64_t c0 = A.jc_off[g], nc = A.jc_off[g + 1] - c0;
+    const double box = A.box;
+    const double ibox = box > 0.0 ? 1.0 / box : 0.0;
+    const R i2rs = kSplit ? R(0.5 / A.rs) : R(0);
+    const R rcut2 = kSplit ? R(A.rcut * A.rcut) : R(0);
+
+    for (int64_t ib = 0; ib < ni; ib += kBlock) {
+        const int nic = (int)(ni - ib < kBlock ? ni - ib : kBlock);
+        const int S = kBlock / nic;
+        const int slice = t / nic;
+        const int islot = t - slice * nic;
+        const bool active = slice < S;
+
+        R xi = R(0), yi = R(0), zi = R(0), e2 = R(1);
+        if (active) {
+            const int64_t i = i0 + ib + islot;
+            xi = R(wrap(A.xi[i] - cx, box, ibox));
+            yi = R(wrap(A.yi[i] - cy, box, ibox));
+            zi = R(wrap(A.zi[i] - cz, box, ibox));
+            e2 = R(A.e2i[i]);
+        }
+        R ax = R(0), ay = R(0), az = R(0), pt = R(0);
+
+        // j-particles
+        for (int64_t base = 0; base < np; base += kBlock) {
+            const int cnt = (int)(np - base < kBlock ? np - base : kBlock);
+            __syncthreads();
+            if (t < cnt) {
+                const int64_t j = p0 + base + t;
+                V4<R> v;
+                v.x = R(wrap(A.jpx[j] - cx, box, ibox));
+                v.y = R(wrap(A.jpy[j] - cy, box, ibox));
+                v.z = R(wrap(A.jpz[j] - cz, box, ibox));
+                v.w = R(A.jpm[j]);
+                sa[t] = v;
+            }
+            __syncthreads();
+            if (active) {
+                R bx = R(0), by = R(0), bz = R(0), bp = R(0);
+                for (int e = slice; e < cnt; e += S) {
+                    if (kSplit)
+                        pp_split(sa[e], xi, yi, zi, i2rs, rcut2, bx, by, bz, bp);
+                    else
+                        pp_plummer(sa[e], xi, yi, zi, e2, bx, by, bz, bp);
+                }
+                ax += bx;
+                ay += by;
+                az += bz;
+                pt += bp;
+            }
+        }
+
+        // j-cells
+        for (int64_t base = 0; base < nc; base += kBlock) {
+            const int cnt = (int)(nc - base < kBlock ? nc - base : kBlock);
+            __syncthreads();
+            if (t < cnt) {
+                const int64_t j = c0 + base + t;
+                V4<R> v;
+                v.x = R(wrap(A.jcx[j] - cx, box, ibox));
+                v.y = R(wrap(A.jcy[j] - cy, box, ibox));
+                v.z = R(wrap(A.jcz[j] - cz, box, ibox));
+                v.w = R(A.jcm[j]);
+                sa[t] = v;
+                if (kCellQ) {
+                    V4<R> w;
+                    w.x = R(A.q00[j]);
+                    w.y = R(A.q01[j]);
+                    w.z = R(A.q02[j]);
+                    w.w = R(A.q11[j]);
+                    sb[t] = w;
+                    V4<R> u;
+                    u.x = R(A.q12[j]);
+                    u.y = R(A.q22[j]);
+                    u.z = (KIND == kSplitQuad && A.jct) ? R(A.jct[j]) : R(0);
+                    u.w = R(0);
+                    sc[t] = u;
+                }
+            }
+            __syncthreads();
+            if (active) {
+                R bx = R(0), by = R(0), bz = R(0), bp = R(0);
+                for (int e = slice; e < cnt; e += S) {
+                    if (KIND == kQuad)
+                        pc_quad(sa[e], sb[e], sc[e], xi, yi, zi, e2, bx, by, bz,
+                                bp);
+                    else if (KIND == kMono)
+                        pp_plummer(sa[e], xi, yi, zi, e2, bx, by, bz, bp);
+                    else if (KIND == kSplitQuad)
+                        pc_split<R, true>(sa[e], sb[e], sc[e], xi, yi, zi, i2rs,
+                                          rcut2, bx, by, bz, bp);
+                    else
+                        pc_split<R, false>(sa[e], sb[e], sc[e], xi, yi, zi,
+                                           i2rs, rcut2, bx, by, bz, bp);
+                }
+                ax += bx;
+                ay += by;
+                az += bz;
+                pt += bp;
+            }
+        }
+
+        // combine the slices in a fixed order
+        __syncthreads();
+        if (active) {
+            V4<R> v;
+            v.x = ax;
+            v.y = ay;
+            v.z = az;
+            v.w = pt;
+            sa[t] = v;
+        }
+        __syncthreads();
+        if (t < nic) {
+            R sx = R(0), sy = R(0), sz = R(0), sp = R(0);
+            for (int s = 0; s < S; ++s) {
+                const V4<R> v = sa[s * nic + t];
+                sx += v.x;
+                sy += v.y;
+                sz += v.z;
+                sp += v.w;
+            }
+            const int64_t i = i0 + ib + t;
+            A.ax[i] = (double)sx;
+            A.ay[i] = (double)sy;
+            A.az[i] = (double)sz;
+            A.pot[i] = -(double)sp;
+        }
+    }
+}
+
+template <typename R>
+hipError_t launch_prec(int kernel, const ForceArgs &A, hipStream_t s)
+{
+    const dim3 grid((unsigned)A.ng), block(kBlock);
+    switch (kernel) {
+    case kMono:
+        hipLaunchKernelGGL((force_kernel<R, kMono>), grid, block, 0, s, A);
+        break;
+    case kQuad:
+        hipLaunchKernelGGL((force_kernel<R, kQuad>), grid, block, 0, s, A);
+        break;
+    case kSplitQuad:
+        hipLaunchKernelGGL((force_kernel<R, kSplitQuad>), grid, block, 0, s, A);
+        break;
+    case kSplitMono:
+        hipLaunchKernelGGL((force_kernel<R, kSplitMono>), grid, block, 0, s, A);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_force(int kernel, int precision, const ForceArgs &A,
+                        hipStream_t stream)
+{
+    if (A.ng <= 0) return hipSuccess;
+    if (A.ng > 0x7fffffff) return hipErrorInvalidValue;
+    return precision == 1 ? launch_prec<double>(kernel, A, stream)
+                          : launch_prec<float>(kernel, A, stream);
+}
+
+}  // namespace bhq

@@ -1,0 +1,230 @@
+"""GPU parity: libbhq's HIP kernels against the FP64 oracle on the same
+interaction lists, element by element, through the C ABI.
+
+Bars (per-particle relative error of the acceleration, and of the
+potential): FP32 with FP64 group offsets <= 2e-6 rms and <= 1e-4 max;
+FP64 <= 1e-12 rms and <= 1e-10 max (summation order only).
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from _parity import assert_parity, errors, log, run, upload
+from paper_1812_07313_amd import bhq, synth
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [(bhq.QUAD, orc.QUAD), (bhq.MONO, orc.MONO)]
+PRECS = [bhq.FP32_OFS64, bhq.FP64]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    yield c
+    bhq.bhq_destroy(c)
+
+
+def _check_case(ctx, name, x, m, eps, theta, ncrit, kinds=KINDS, precs=PRECS,
+                box=0.0):
+    log("case %s: n=%d theta=%g ncrit=%d" % (name, len(m), theta, ncrit))
+    T = orc.Tree(x, m, theta, ncrit)
+    mat = orc.materialise(T, x, m)
+    eps2 = np.broadcast_to(np.asarray(eps, np.float64) ** 2, (len(m),))
+    upload(ctx, mat, x, eps2=eps2)
+    out = {}
+    for bk, ok in kinds:
+        a_ref, p_ref = orc.eval_lists(ok, mat, x, eps2)
+        for prec in precs:
+            log("  kernel=%s precision=%s" % (bhq.KERNEL_NAMES[bk],
+                                               bhq.PRECISION_NAMES[prec]))
+            a, p = run(ctx, mat, len(m), bk, prec)
+            err = errors(a, p, a_ref, p_ref)
+            log("    %s" % err)
+            assert_parity(err, prec, "%s %s %s" % (name, bk, prec))
+            out[(bk, prec)] = (a, p)
+    return T, mat, out
+
+
+def test_plummer_16k(ctx):
+    c = synth.config_plummer_16k()
+    _check_case(ctx, "plummer16k", c["x"], c["m"], c["eps"], c["theta"],
+                c["ncrit"])
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.7])
+def test_uniform_cube_64k(ctx, theta):
+    x, m = synth.uniform_cube(1 << 16, synth.rng(1))
+    _check_case(ctx, "cube64k", x, m, 1e-3, theta, 256)
+
+
+def test_clustered_32k(ctx):
+    x, m = synth.clustered(1 << 15, synth.rng(2))
+    _check_case(ctx, "clustered32k", x, m, 2e-4, 0.5, 64)
+
+
+def test_large_groups_and_ragged_tiles(ctx):
+    """ncrit above the block size: groups of up to 600 i-particles are
+    processed in chunks of 256; list lengths are not tile multiples."""
+    x, m = synth.plummer(5000, synth.rng(5))
+    T, mat, _ = _check_case(ctx, "biggroups", x, m, 0.02, 0.6, 600)
+    assert np.diff(T.i_off).max() > 256
+
+
+def test_theta_zero_single_group_and_tiny(ctx):
+    # theta = 0: no cells, all particles direct; one group when n <= ncrit
+    x, m = synth.plummer(300, synth.rng(6))
+    _check_case(ctx, "theta0", x, m, 0.05, 0.0, 64)
+    _check_case(ctx, "onegroup", x, m, 0.05, 0.5, 512)
+    # a single particle: only the self term, phi = -m / eps, a = 0
+    x1 = np.array([[0.25, -0.5, 2.0]])
+    m1 = np.array([1.0])
+    _, _, out = _check_case(ctx, "single", x1, m1, 0.125, 0.5, 8)
+    for (bk, prec), (a, p) in out.items():
+        assert np.all(a == 0.0)
+        assert p[0] == pytest.approx(-8.0, rel=1e-6 if prec == 0 else 1e-15)
+
+
+def test_per_particle_softening(ctx):
+    """Several independent Plummer systems, each with its own eps, in one
+    launch (per-i eps^2; the batched configuration in miniature)."""
+    systems = synth.batched_plummer(6, lo=9.0, hi=11.0)
+    log("case batched: sizes %s" % [len(s[1]) for s in systems])
+    mats, xs, e2s, refs = [], [], [], []
+    base = 0
+    i_off, jp_off, jc_off, cen = [0], [0], [0], []
+    i_idx, jp_x, jp_m, jc_x, jc_m, jc_q, jc_t = [], [], [], [], [], [], []
+    for (x, m, eps) in systems:
+        T = orc.Tree(x, m, 0.6, 64)
+        mat = orc.materialise(T, x, m)
+        e2 = np.full(len(m), eps * eps)
+        refs.append(orc.eval_lists(orc.QUAD, mat, x, e2))
+        i_idx.append(mat["i_idx"] + base)
+        i_off += list(mat["i_off"][1:] + i_off[-1])
+        jp_off += list(mat["jp_off"][1:] + jp_off[-1])
+        jc_off += list(mat["jc_off"][1:] + jc_off[-1])
+        cen.append(mat["gcenter"])
+        jp_x.append(mat["jp_x"]); jp_m.append(mat["jp_m"])
+        jc_x.append(mat["jc_x"]); jc_m.append(mat["jc_m"])
+        jc_q.append(mat["jc_q"]); jc_t.append(mat["jc_t"])
+        xs.append(x)
+        e2s.append(e2)
+        base += len(m)
+    big = dict(i_idx=np.concatenate(i_idx), i_off=np.array(i_off),
+               gcenter=np.concatenate(cen), jp_off=np.array(jp_off),
+               jc_off=np.array(jc_off), jp_x=np.concatenate(jp_x),
+               jp_m=np.concatenate(jp_m), jc_x=np.concatenate(jc_x),
+               jc_m=np.concatenate(jc_m), jc_q=np.concatenate(jc_q),
+               jc_t=np.concatenate(jc_t))
+    X = np.concatenate(xs)
+    E2 = np.concatenate(e2s)
+    upload(ctx, big, X, eps2=E2)
+    a_ref = np.concatenate([r[0] for r in refs])
+    p_ref = np.concatenate([r[1] for r in refs])
+    for prec in PRECS:
+        a, p = run(ctx, big, len(X), bhq.QUAD, prec)
+        err = errors(a, p, a_ref, p_ref)
+        log("  precision=%s %s" % (bhq.PRECISION_NAMES[prec], err))
+        assert_parity(err, prec, "batched")
+
+
+def test_deterministic_and_zero_quadrupole(ctx):
+    """Bitwise identical results run to run; Q = 0 makes the quadrupole
+    kernel's cell terms the monopole ones (to rounding)."""
+    x, m = synth.uniform_cube(20000, synth.rng(8))
+    T = orc.Tree(x, m, 0.5, 128)
+    mat = orc.materialise(T, x, m)
+    upload(ctx, mat, x, eps2=1e-6)
+    for prec in PRECS:
+        log("case determinism precision=%s" % bhq.PRECISION_NAMES[prec])
+        a1, p1 = run(ctx, mat, len(m), bhq.QUAD, prec)
+        a2, p2 = run(ctx, mat, len(m), bhq.QUAD, prec)
+        assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+    mat0 = dict(mat)
+    mat0["jc_q"] = np.zeros_like(mat["jc_q"])
+    upload(ctx, mat0, x, eps2=1e-6)
+    aq, pq = run(ctx, mat0, len(m), bhq.QUAD, bhq.FP64)
+    am, pm = run(ctx, mat0, len(m), bhq.MONO, bhq.FP64)
+    np.testing.assert_allclose(aq, am, rtol=1e-12, atol=1e-12 * np.abs(am).max())
+    np.testing.assert_allclose(pq, pm, rtol=1e-13)
+
+
+def test_product_lists_path(ctx):
+    """bhq_build_lists + bhq_set_lists (the benchmark's input path) gives the
+    oracle's result on the oracle's lists."""
+    x, m = synth.uniform_cube(1 << 15, synth.rng(9))
+    T = orc.Tree(x, m, 0.5, 256)
+    mat = orc.materialise(T, x, m)
+    a_ref, p_ref = orc.eval_lists(orc.QUAD, mat, x, 1e-6)
+    log("case product lists n=%d" % len(m))
+    L = bhq.bhq_build_lists(x, m, 0.5, 256)
+    try:
+        bhq.bhq_set_lists(ctx, L, x, m)
+        idx = bhq.bhq_lists_export(L, len(m))["i_idx"]
+    finally:
+        bhq.bhq_lists_free(L)
+    bhq.bhq_set_eps(ctx, 1e-3)
+    for prec in PRECS:
+        bhq.bhq_set_kernel(ctx, bhq.QUAD, prec)
+        bhq.bhq_compute(ctx)
+        a_g, p_g = bhq.bhq_get_result(ctx, len(m))
+        a = np.zeros_like(a_g)
+        p = np.zeros_like(p_g)
+        a[idx] = a_g
+        p[idx] = p_g
+        err = errors(a, p, a_ref, p_ref)
+        log("  precision=%s %s" % (bhq.PRECISION_NAMES[prec], err))
+        assert_parity(err, prec, "product lists")
+
+
+def test_stream_and_timing(ctx):
+    torch = pytest.importorskip("torch")
+    x, m = synth.plummer(4096, synth.rng(10))
+    T = orc.Tree(x, m, 0.5, 64)
+    mat = orc.materialise(T, x, m)
+    upload(ctx, mat, x, eps2=1e-4)
+    s = torch.cuda.Stream()
+    a0, p0 = run(ctx, mat, len(m), bhq.QUAD, bhq.FP32_OFS64)
+    a1, p1 = run(ctx, mat, len(m), bhq.QUAD, bhq.FP32_OFS64, stream=s)
+    assert np.array_equal(a0, a1) and np.array_equal(p0, p1)
+    assert bhq.bhq_get_kernel_ms(ctx) > 0.0
+    n_pp, n_pc = bhq.bhq_get_counts(ctx)
+    assert (n_pp, n_pc) == T.interaction_counts()
+
+
+def test_state_errors(ctx):
+    c2 = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_compute(c2)
+        assert ei.value.code == bhq.E_STATE
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_set_i(c2, np.zeros((3, 3)))
+        assert ei.value.code == bhq.E_STATE
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_set_groups(c2, [0, 2, 1], np.zeros((2, 3)), [0, 0, 0],
+                               [0, 0, 0])
+        assert ei.value.code == bhq.E_RANGE
+        bhq.bhq_set_groups(c2, [0, 2], np.zeros((1, 3)), [0, 2], [0, 0])
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_set_i(c2, np.zeros((3, 3)))
+        assert ei.value.code == bhq.E_RANGE
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_set_i(c2, np.array([[0.0, np.nan, 0.0], [0, 0, 0]]))
+        assert ei.value.code == bhq.E_NONFINITE
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_set_jp(c2, 1, np.zeros((2, 3)), np.ones(2))
+        assert ei.value.code == bhq.E_RANGE
+        bhq.bhq_set_i(c2, np.array([[0.0, 0, 0], [1.0, 0, 0]]))
+        bhq.bhq_set_jp(c2, 0, np.array([[0.0, 0, 0], [1.0, 0, 0]]), np.ones(2))
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_compute(c2)  # no softening yet
+        assert ei.value.code == bhq.E_STATE
+        bhq.bhq_set_eps(c2, 0.0 + 1.0)
+        bhq.bhq_compute(c2)
+        a, p = bhq.bhq_get_result(c2, 2)
+        # two unit masses one apart with eps = 1: |a| = 1 / 2^1.5
+        assert a[0, 0] == pytest.approx(2 ** -1.5, rel=1e-6)
+        assert p[0] == pytest.approx(-1.0 - 2 ** -0.5, rel=1e-6)
+    finally:
+        bhq.bhq_destroy(c2)

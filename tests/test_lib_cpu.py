@@ -1,0 +1,78 @@
+"""CPU-side checks of libbhq: the library loads, exports every symbol that
+include/bhq.h declares, and reports the failures that can be forced without
+a GPU (no device, bad arguments)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from paper_1812_07313_amd import bhq
+
+
+def _declared_symbols():
+    with open(os.path.join(ROOT, "include", "bhq.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bhq_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = bhq.lib()
+    names = _declared_symbols()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in bhq.SIGNATURES, name
+
+
+def _have_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_have_gpu(), reason="checks the no-device path")
+def test_create_without_gpu_reports_nodev():
+    with pytest.raises(bhq.BhqError) as ei:
+        bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    assert ei.value.code == bhq.E_NODEV
+    assert "GPU" in bhq.bhq_last_error(None)
+
+
+def test_create_argument_errors():
+    L = bhq.lib()
+    assert L.bhq_create(None, 0, bhq.QUAD, bhq.FP32_OFS64) == bhq.E_ARG
+    h = ctypes.c_void_p()
+    assert L.bhq_create(ctypes.byref(h), 0, 9, bhq.FP32_OFS64) == bhq.E_ARG
+    assert L.bhq_create(ctypes.byref(h), 0, bhq.QUAD, 5) == bhq.E_ARG
+    assert h.value is None
+
+
+def test_null_context_calls_are_rejected():
+    L = bhq.lib()
+    assert L.bhq_set_eps(None, 0.1) == bhq.E_ARG
+    assert L.bhq_compute(None, None) == bhq.E_ARG
+    assert L.bhq_get_result(None, None, None) == bhq.E_ARG
+    assert L.bhq_destroy(None) == bhq.OK
+    assert L.bhq_lists_free(None) == bhq.OK
+
+
+def test_build_lists_argument_errors():
+    x = np.random.default_rng(0).random((100, 3))
+    m = np.full(100, 0.01)
+    for kw in (dict(theta=-0.1, ncrit=16), dict(theta=0.5, ncrit=0),
+               dict(theta=0.5, ncrit=16, nleaf=32),
+               dict(theta=0.5, ncrit=16, box=-1.0)):
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_build_lists(x, m, **kw)
+        assert ei.value.code == bhq.E_ARG
+    xb = x.copy()
+    xb[3, 1] = np.nan
+    with pytest.raises(bhq.BhqError) as ei:
+        bhq.bhq_build_lists(xb, m, 0.5, 16)
+    assert ei.value.code == bhq.E_NONFINITE
