@@ -88,6 +88,10 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before timing, copy a buffer of this many MiB "
+                         "device-to-device once (a plain copy kernel of known "
+                         "size, to calibrate HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build evaluates the force "
@@ -99,6 +103,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+
+    if args.copy_calibration_mib > 0:
+        nel = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB read + %d MiB written"
+            % (args.copy_calibration_mib, args.copy_calibration_mib))
+        del src, dst
 
     c = synth.config_uniform_cube(n=args.n, theta=args.theta)
     x, m, eps, theta, ncrit = c["x"], c["m"], c["eps"], c["theta"], c["ncrit"]

@@ -3,15 +3,17 @@
 // One 256-thread block evaluates one group's interaction list (the modified
 // tree algorithm of Kodama & Ishiyama, Sec. 3.4: all i-particles of a group
 // share one list).  Each active thread owns one i-particle.  The list is
-// streamed through LDS in tiles of 256 entries: every thread loads one
+// streamed through LDS in tiles of up to 256 entries: every thread loads one
 // entry with coalesced FP64 SoA reads, forms its position relative to the
 // group's FP64 reference point, converts it to the working precision and
 // stores it in LDS; the threads then read entries back as broadcasts.
 //
-// Small groups (ni < 256) split the tile between S = 256 / ni slices of ni
-// threads: slice s takes entries s, s + S, s + 2S, ...; the slices' partial
-// sums are combined in a fixed order at the end, so results are
-// deterministic run to run.
+// Small groups (ni < 256) split each tile between S = 256 / ni slices of
+// ni threads.  A tile then holds T = S * floor(256 / S) entries and slice s
+// takes the contiguous chunk [s * it, (s + 1) * it) of it; the last tile is
+// padded to a multiple of S with zero-mass entries, so every thread runs
+// the same trip count.  The slices' partial sums are combined in a fixed
+// order at the end, so results are deterministic run to run.
 //
 // Interaction arithmetic (per i-particle, per list entry, d = x_j - x_i):
 //   particle:  rinv = rsq(|d|^2 + eps^2); a += m rinv^3 d; -phi += m rinv
@@ -187,14 +189,18 @@ __device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b,
     }
 }
 
-template <typename R, int KIND>
+// Far position for padding entries: zero mass (and zero moments) at a
+// finite distance, so that a padded entry adds exactly +0 to every sum.
+constexpr float kPadPos = 1.0e15f;
+
+template <typename R, int KIND, bool PERIODIC>
 __global__ __launch_bounds__(kBlock) void force_kernel(const ForceArgs A)
 {
     constexpr bool kSplit = (KIND == kSplitQuad || KIND == kSplitMono);
     constexpr bool kCellQ = (KIND == kQuad || KIND == kSplitQuad);
     __shared__ V4<R> sa[kBlock];
-    __shared__ V4<R> sb[kBlock];
-    __shared__ V4<R> sc[kBlock];
+    __shared__ V4<R> sb[kCellQ ? kBlock : 1];
+    __shared__ V4<R> sc[kCellQ ? kBlock : 1];
 
     const int t = threadIdx.x;
     const int64_t g = A.order ? A.order[blockIdx.x] : (int64_t)blockIdx.x;
@@ -204,13 +210,19 @@ __global__ __launch_bounds__(kBlock) void force_kernel(const ForceArgs A)
     const int64_t p0 = A.jp_off[g], np = A.jp_off[g + 1] - p0;
     const int64_t c0 = A.jc_off[g], nc = A.jc_off[g + 1] - c0;
     const double box = A.box;
-    const double ibox = box > 0.0 ? 1.0 / box : 0.0;
+    const double ibox = PERIODIC ? 1.0 / box : 0.0;
     const R i2rs = kSplit ? R(0.5 / A.rs) : R(0);
     const R rcut2 = kSplit ? R(A.rcut * A.rcut) : R(0);
+    auto rel = [&](double v, double c) -> R {
+        return PERIODIC ? R(wrap(v - c, box, ibox)) : R(v - c);
+    };
 
     for (int64_t ib = 0; ib < ni; ib += kBlock) {
+        // Slices: S groups of nic threads; a tile holds T = S * floor(256/S)
+        // entries and slice s takes the contiguous chunk [s*it, (s+1)*it).
         const int nic = (int)(ni - ib < kBlock ? ni - ib : kBlock);
         const int S = kBlock / nic;
+        const int T = S * (kBlock / S);
         const int slice = t / nic;
         const int islot = t - slice * nic;
         const bool active = slice < S;
@@ -218,34 +230,42 @@ __global__ __launch_bounds__(kBlock) void force_kernel(const ForceArgs A)
         R xi = R(0), yi = R(0), zi = R(0), e2 = R(1);
         if (active) {
             const int64_t i = i0 + ib + islot;
-            xi = R(wrap(A.xi[i] - cx, box, ibox));
-            yi = R(wrap(A.yi[i] - cy, box, ibox));
-            zi = R(wrap(A.zi[i] - cz, box, ibox));
+            xi = rel(A.xi[i], cx);
+            yi = rel(A.yi[i], cy);
+            zi = rel(A.zi[i], cz);
             e2 = R(A.e2i[i]);
         }
         R ax = R(0), ay = R(0), az = R(0), pt = R(0);
 
         // j-particles
-        for (int64_t base = 0; base < np; base += kBlock) {
-            const int cnt = (int)(np - base < kBlock ? np - base : kBlock);
+        for (int64_t base = 0; base < np; base += T) {
+            const int cnt = (int)(np - base < T ? np - base : T);
+            const int it = (cnt + S - 1) / S;  // entries per slice
             __syncthreads();
-            if (t < cnt) {
-                const int64_t j = p0 + base + t;
+            if (t < it * S) {
                 V4<R> v;
-                v.x = R(wrap(A.jpx[j] - cx, box, ibox));
-                v.y = R(wrap(A.jpy[j] - cy, box, ibox));
-                v.z = R(wrap(A.jpz[j] - cz, box, ibox));
-                v.w = R(A.jpm[j]);
+                if (t < cnt) {
+                    const int64_t j = p0 + base + t;
+                    v.x = rel(A.jpx[j], cx);
+                    v.y = rel(A.jpy[j], cy);
+                    v.z = rel(A.jpz[j], cz);
+                    v.w = R(A.jpm[j]);
+                } else {
+                    v.x = v.y = v.z = R(kPadPos);
+                    v.w = R(0);
+                }
                 sa[t] = v;
             }
             __syncthreads();
             if (active) {
                 R bx = R(0), by = R(0), bz = R(0), bp = R(0);
-                for (int e = slice; e < cnt; e += S) {
+                const V4<R> *pa = sa + slice * it;
+#pragma unroll 4
+                for (int k = 0; k < it; ++k) {
                     if (kSplit)
-                        pp_split(sa[e], xi, yi, zi, i2rs, rcut2, bx, by, bz, bp);
+                        pp_split(pa[k], xi, yi, zi, i2rs, rcut2, bx, by, bz, bp);
                     else
-                        pp_plummer(sa[e], xi, yi, zi, e2, bx, by, bz, bp);
+                        pp_plummer(pa[k], xi, yi, zi, e2, bx, by, bz, bp);
                 }
                 ax += bx;
                 ay += by;
@@ -255,36 +275,47 @@ __global__ __launch_bounds__(kBlock) void force_kernel(const ForceArgs A)
         }
 
         // j-cells
-        for (int64_t base = 0; base < nc; base += kBlock) {
-            const int cnt = (int)(nc - base < kBlock ? nc - base : kBlock);
+        for (int64_t base = 0; base < nc; base += T) {
+            const int cnt = (int)(nc - base < T ? nc - base : T);
+            const int it = (cnt + S - 1) / S;
             __syncthreads();
-            if (t < cnt) {
-                const int64_t j = c0 + base + t;
-                V4<R> v;
-                v.x = R(wrap(A.jcx[j] - cx, box, ibox));
-                v.y = R(wrap(A.jcy[j] - cy, box, ibox));
-                v.z = R(wrap(A.jcz[j] - cz, box, ibox));
-                v.w = R(A.jcm[j]);
+            if (t < it * S) {
+                V4<R> v, w, u;
+                if (t < cnt) {
+                    const int64_t j = c0 + base + t;
+                    v.x = rel(A.jcx[j], cx);
+                    v.y = rel(A.jcy[j], cy);
+                    v.z = rel(A.jcz[j], cz);
+                    v.w = R(A.jcm[j]);
+                    if (kCellQ) {
+                        w.x = R(A.q00[j]);
+                        w.y = R(A.q01[j]);
+                        w.z = R(A.q02[j]);
+                        w.w = R(A.q11[j]);
+                        u.x = R(A.q12[j]);
+                        u.y = R(A.q22[j]);
+                        u.z = (KIND == kSplitQuad) ? R(A.jct[j]) : R(0);
+                        u.w = R(0);
+                    }
+                } else {
+                    v.x = v.y = v.z = R(kPadPos);
+                    v.w = R(0);
+                    w.x = w.y = w.z = w.w = R(0);
+                    u.x = u.y = u.z = u.w = R(0);
+                }
                 sa[t] = v;
                 if (kCellQ) {
-                    V4<R> w;
-                    w.x = R(A.q00[j]);
-                    w.y = R(A.q01[j]);
-                    w.z = R(A.q02[j]);
-                    w.w = R(A.q11[j]);
                     sb[t] = w;
-                    V4<R> u;
-                    u.x = R(A.q12[j]);
-                    u.y = R(A.q22[j]);
-                    u.z = (KIND == kSplitQuad && A.jct) ? R(A.jct[j]) : R(0);
-                    u.w = R(0);
                     sc[t] = u;
                 }
             }
             __syncthreads();
             if (active) {
                 R bx = R(0), by = R(0), bz = R(0), bp = R(0);
-                for (int e = slice; e < cnt; e += S) {
+                const int e0 = slice * it;
+#pragma unroll 4
+                for (int k = 0; k < it; ++k) {
+                    const int e = e0 + k;
                     if (KIND == kQuad)
                         pc_quad(sa[e], sb[e], sc[e], xi, yi, zi, e2, bx, by, bz,
                                 bp);
@@ -333,27 +364,38 @@ __global__ __launch_bounds__(kBlock) void force_kernel(const ForceArgs A)
     }
 }
 
-template <typename R>
-hipError_t launch_prec(int kernel, const ForceArgs &A, hipStream_t s)
+template <typename R, bool P>
+hipError_t launch_kind(int kernel, const ForceArgs &A, hipStream_t s)
 {
     const dim3 grid((unsigned)A.ng), block(kBlock);
     switch (kernel) {
     case kMono:
-        hipLaunchKernelGGL((force_kernel<R, kMono>), grid, block, 0, s, A);
+        hipLaunchKernelGGL((force_kernel<R, kMono, P>), grid, block, 0, s, A);
         break;
     case kQuad:
-        hipLaunchKernelGGL((force_kernel<R, kQuad>), grid, block, 0, s, A);
+        hipLaunchKernelGGL((force_kernel<R, kQuad, P>), grid, block, 0, s, A);
         break;
     case kSplitQuad:
-        hipLaunchKernelGGL((force_kernel<R, kSplitQuad>), grid, block, 0, s, A);
+        hipLaunchKernelGGL((force_kernel<R, kSplitQuad, P>), grid, block, 0, s,
+                           A);
         break;
     case kSplitMono:
-        hipLaunchKernelGGL((force_kernel<R, kSplitMono>), grid, block, 0, s, A);
+        hipLaunchKernelGGL((force_kernel<R, kSplitMono, P>), grid, block, 0, s,
+                           A);
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_prec(int kernel, const ForceArgs &A, hipStream_t s)
+{
+    // periodic minimum image only for the split kernels in a box
+    const bool periodic = A.box > 0.0 && (kernel == kSplitQuad || kernel == kSplitMono);
+    return periodic ? launch_kind<R, true>(kernel, A, s)
+                    : launch_kind<R, false>(kernel, A, s);
 }
 
 }  // namespace
