@@ -149,6 +149,24 @@ int bhq_get_counts(const bhq_ctx *ctx, int64_t *n_pp, int64_t *n_pc);
  * measured with HIP events on the compute stream.  Waits for it. */
 int bhq_get_kernel_ms(bhq_ctx *ctx, double *ms);
 
+/* Launch shape (an autotuner's knobs; results do not depend on them).
+ *   block          threads per block and LDS tile depth: 128 or 256 (0: 256)
+ *   blocks_per_cu  persistent grid size per compute unit (0: as many blocks
+ *                  as fit), ignored when persistent == 0
+ *   persistent     0: one block per group, groups dispatched longest first;
+ *                  1: a machine-sized grid pulls groups (longest first) from
+ *                  a device counter
+ *   use_graph      1: bhq_compute records its launches into a HIP graph once
+ *                  and replays it while kernel, precision, shape and data
+ *                  layout are unchanged (re-recorded otherwise)
+ * Errors: BHQ_E_ARG for values outside these sets. */
+int bhq_set_tuning(bhq_ctx *ctx, int block, int blocks_per_cu, int persistent,
+                   int use_graph);
+
+/* Current launch shape: out[0..3] = block, blocks_per_cu, persistent,
+ * use_graph. */
+int bhq_get_tuning(const bhq_ctx *ctx, int out[4]);
+
 /* Message for the last error on ctx (never NULL; "" when none).  With
  * ctx == NULL: the message of the last failed bhq_create on this thread. */
 const char *bhq_last_error(const bhq_ctx *ctx);
@@ -174,6 +192,17 @@ const char *bhq_last_error(const bhq_ctx *ctx);
 int bhq_build_lists(int64_t n, const double (*x)[3], const double *m,
                     double theta, int ncrit, int nleaf, double box,
                     double rcut, int nthreads, bhq_lists **out);
+
+/* Build lists for nsys independent systems in one object (for one batched
+ * launch): system s is particles sys_off[s] .. sys_off[s+1]-1 of x and m
+ * (sys_off[0] == 0, strictly increasing), open boundaries, one theta and
+ * ncrit for all.  Each system gets its own tree; groups, i-particles and
+ * list entries of system s follow those of system s-1, and every index in
+ * the exported lists refers to the concatenated arrays.  Per-system
+ * softening is given afterwards with bhq_set_eps2_i. */
+int bhq_build_lists_batch(int64_t nsys, const int64_t *sys_off,
+                          const double (*x)[3], const double *m, double theta,
+                          int ncrit, int nleaf, int nthreads, bhq_lists **out);
 
 /* sizes[0..3] = ng, njp, njc, number of tree cells. */
 int bhq_lists_sizes(const bhq_lists *L, int64_t sizes[4]);

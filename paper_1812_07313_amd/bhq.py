@@ -52,6 +52,13 @@ SIGNATURES = {
     "bhq_get_counts": (ctypes.c_int, [_P, _I64, _I64]),
     "bhq_get_kernel_ms": (ctypes.c_int, [_P, _D]),
     "bhq_last_error": (ctypes.c_char_p, [_P]),
+    "bhq_set_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int]),
+    "bhq_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
+    "bhq_build_lists_batch": (ctypes.c_int, [ctypes.c_int64, _I64, _D, _D,
+                                             ctypes.c_double, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(_P)]),
     "bhq_build_lists": (ctypes.c_int, [ctypes.c_int64, _D, _D,
                                        ctypes.c_double, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_double,
@@ -211,6 +218,19 @@ def bhq_get_kernel_ms(ctx):
     return ms.value
 
 
+def bhq_set_tuning(ctx, block=256, blocks_per_cu=0, persistent=0,
+                   use_graph=0):
+    _check(lib().bhq_set_tuning(ctx, int(block), int(blocks_per_cu),
+                                int(persistent), int(use_graph)), ctx)
+
+
+def bhq_get_tuning(ctx):
+    out = (ctypes.c_int * 4)()
+    _check(lib().bhq_get_tuning(ctx, out), ctx)
+    return dict(block=out[0], blocks_per_cu=out[1], persistent=out[2],
+                use_graph=out[3])
+
+
 def bhq_last_error(ctx=None):
     msg = lib().bhq_last_error(ctx)
     return msg.decode() if msg else ""
@@ -226,6 +246,18 @@ def bhq_build_lists(x, m, theta, ncrit, nleaf=8, box=0.0, rcut=0.0,
     _check(lib().bhq_build_lists(x.shape[0], _dp(x), _dp(m), float(theta),
                                  int(ncrit), int(nleaf), float(box),
                                  float(rcut), int(nthreads), ctypes.byref(h)))
+    return h
+
+
+def bhq_build_lists_batch(sys_off, x, m, theta, ncrit, nleaf=8, nthreads=0):
+    off = _i64(sys_off)
+    x = _f64(x, (-1, 3))
+    m = _f64(m)
+    h = _P()
+    _check(lib().bhq_build_lists_batch(off.shape[0] - 1, _ip(off), _dp(x),
+                                       _dp(m), float(theta), int(ncrit),
+                                       int(nleaf), int(nthreads),
+                                       ctypes.byref(h)))
     return h
 
 

@@ -53,6 +53,7 @@ enum Arr {
     A_JCX, A_JCY, A_JCZ, A_JCM, A_Q00, A_Q01, A_Q02, A_Q11, A_Q12, A_Q22,
     A_JCT,
     A_AX, A_AY, A_AZ, A_POT,
+    A_QUEUE,
     A_COUNT
 };
 
@@ -84,6 +85,25 @@ struct bhq_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool launched = false;
     hipStream_t last_stream = nullptr;
+
+    bhq::LaunchCfg cfg;
+    int use_graph = 0;
+    uint64_t args_version = 0;  // bumped when device pointers/params change
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    struct {
+        int kernel, precision, block, persistent, blocks_per_cu;
+        uint64_t version;
+    } graph_key{};
+
+    void drop_graph()
+    {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+    }
 
     std::vector<double> stage;  // host staging for SoA transposes
 
@@ -194,10 +214,19 @@ int bhq_create(bhq_ctx **out, int device, int kernel, int precision)
     c->device = device;
     c->kernel = kernel;
     c->precision = precision;
+    if (hipDeviceGetAttribute(&c->cfg.num_cu, hipDeviceAttributeMultiprocessorCount,
+                              device) != hipSuccess ||
+        c->cfg.num_cu <= 0 || c->arr[A_QUEUE].reserve(256) != hipSuccess) {
+        g_create_error = "bhq_create: device query or allocation failed";
+        c->arr[A_QUEUE].release();
+        delete c;
+        return BHQ_E_HIP;
+    }
     if (hipEventCreate(&c->ev0) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess) {
         g_create_error = "bhq_create: hipEventCreate failed";
         if (c->ev0) (void)hipEventDestroy(c->ev0);
+        c->arr[A_QUEUE].release();
         delete c;
         return BHQ_E_HIP;
     }
@@ -211,6 +240,8 @@ int bhq_destroy(bhq_ctx *ctx)
     if (!ctx) return BHQ_OK;
     (void)hipSetDevice(ctx->device);
     if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
+    ctx->drop_graph();
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto &a : ctx->arr) a.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -275,6 +306,7 @@ int bhq_set_split(bhq_ctx *ctx, double rs, double rcut, double box)
     ctx->rcut = rcut;
     ctx->box = box;
     ctx->have_split = true;
+    ++ctx->args_version;
     return BHQ_OK;
 }
 
@@ -344,6 +376,7 @@ int bhq_set_groups(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
     ctx->ni = ni;
     ctx->njp = njp;
     ctx->njc = njc;
+    ++ctx->args_version;
     ctx->have_i = ctx->have_jp = ctx->have_jc = ctx->have_t = false;
     if (ctx->eps_mode == 2) ctx->eps_mode = 0;
 
@@ -484,15 +517,90 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
     A.rs = ctx->rs;
     A.rcut = ctx->rcut;
 
+    A.queue = ctx->arr[A_QUEUE].as<unsigned int>();
+
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipEventRecord(ctx->ev0, s);
-    if (e != hipSuccess) return ctx->hip_fail(e, "hipEventRecord");
-    e = bhq::launch_force(ctx->kernel, ctx->precision, A, s);
-    if (e != hipSuccess) return ctx->hip_fail(e, "force kernel launch");
+    hipError_t e;
+    if (ctx->use_graph) {
+        const bool same =
+            ctx->graph_exec && ctx->graph_key.kernel == ctx->kernel &&
+            ctx->graph_key.precision == ctx->precision &&
+            ctx->graph_key.block == ctx->cfg.block &&
+            ctx->graph_key.persistent == ctx->cfg.persistent &&
+            ctx->graph_key.blocks_per_cu == ctx->cfg.blocks_per_cu &&
+            ctx->graph_key.version == ctx->args_version;
+        if (!same) {
+            if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
+            ctx->drop_graph();
+            if (!ctx->cap_stream) {
+                e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+                if (e != hipSuccess) return ctx->hip_fail(e, "hipStreamCreate");
+            }
+            e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return ctx->hip_fail(e, "hipStreamBeginCapture");
+            const hipError_t le =
+                bhq::launch_force(ctx->kernel, ctx->precision, A, ctx->cfg,
+                                  ctx->cap_stream);
+            e = hipStreamEndCapture(ctx->cap_stream, &ctx->graph);
+            if (le != hipSuccess) {
+                ctx->drop_graph();
+                return ctx->hip_fail(le, "force kernel capture");
+            }
+            if (e != hipSuccess) return ctx->hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                ctx->drop_graph();
+                return ctx->hip_fail(e, "hipGraphInstantiate");
+            }
+            ctx->graph_key.kernel = ctx->kernel;
+            ctx->graph_key.precision = ctx->precision;
+            ctx->graph_key.block = ctx->cfg.block;
+            ctx->graph_key.persistent = ctx->cfg.persistent;
+            ctx->graph_key.blocks_per_cu = ctx->cfg.blocks_per_cu;
+            ctx->graph_key.version = ctx->args_version;
+        }
+        e = hipEventRecord(ctx->ev0, s);
+        if (e != hipSuccess) return ctx->hip_fail(e, "hipEventRecord");
+        e = hipGraphLaunch(ctx->graph_exec, s);
+        if (e != hipSuccess) return ctx->hip_fail(e, "hipGraphLaunch");
+    } else {
+        e = hipEventRecord(ctx->ev0, s);
+        if (e != hipSuccess) return ctx->hip_fail(e, "hipEventRecord");
+        e = bhq::launch_force(ctx->kernel, ctx->precision, A, ctx->cfg, s);
+        if (e != hipSuccess) return ctx->hip_fail(e, "force kernel launch");
+    }
     e = hipEventRecord(ctx->ev1, s);
     if (e != hipSuccess) return ctx->hip_fail(e, "hipEventRecord");
     ctx->launched = true;
     ctx->last_stream = s;
+    return BHQ_OK;
+}
+
+int bhq_set_tuning(bhq_ctx *ctx, int block, int blocks_per_cu, int persistent,
+                   int use_graph)
+{
+    CHECK_CTX(ctx);
+    if (block == 0) block = 256;
+    if (block != 128 && block != 256)
+        return ctx->fail(BHQ_E_ARG, "block must be 128 or 256 (or 0)");
+    if (blocks_per_cu < 0 || blocks_per_cu > 64)
+        return ctx->fail(BHQ_E_ARG, "blocks_per_cu must be in [0, 64]");
+    if ((persistent != 0 && persistent != 1) || (use_graph != 0 && use_graph != 1))
+        return ctx->fail(BHQ_E_ARG, "persistent and use_graph are 0 or 1");
+    ctx->cfg.block = block;
+    ctx->cfg.blocks_per_cu = blocks_per_cu;
+    ctx->cfg.persistent = persistent;
+    ctx->use_graph = use_graph;
+    return BHQ_OK;
+}
+
+int bhq_get_tuning(const bhq_ctx *ctx, int out[4])
+{
+    if (!ctx || !out) return BHQ_E_ARG;
+    out[0] = ctx->cfg.block;
+    out[1] = ctx->cfg.blocks_per_cu;
+    out[2] = ctx->cfg.persistent;
+    out[3] = ctx->use_graph;
     return BHQ_OK;
 }
 

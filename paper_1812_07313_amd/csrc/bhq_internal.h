@@ -8,9 +8,6 @@
 
 namespace bhq {
 
-// Threads per block; also the depth of one LDS tile of j-entries.
-constexpr int kBlock = 256;
-
 // Device-side view of one force evaluation.  All arrays are SoA in device
 // memory; i-particles and outputs are in group order.
 struct ForceArgs {
@@ -29,11 +26,23 @@ struct ForceArgs {
     double *ax, *ay, *az, *pot;     // [ni] results (FP64)
     double box;                     // > 0: periodic minimum image
     double rs, rcut;                // split-kernel parameters
+    unsigned int *queue;            // group counter of the persistent kernel
+};
+
+// Launch shape.  block: threads per block (128 or 256), which is also the
+// depth of one LDS tile; persistent: one grid of blocks_per_cu * num_cu
+// blocks pulling groups from ForceArgs::queue (blocks_per_cu <= 0: as many
+// as fit), otherwise one block per group.
+struct LaunchCfg {
+    int block = 256;
+    int persistent = 0;
+    int blocks_per_cu = 0;
+    int num_cu = 0;
 };
 
 // Launch the force kernel for (kernel, precision) on `stream`.  Returns
 // the launch status.
 hipError_t launch_force(int kernel, int precision, const ForceArgs &args,
-                        hipStream_t stream);
+                        const LaunchCfg &cfg, hipStream_t stream);
 
 }  // namespace bhq

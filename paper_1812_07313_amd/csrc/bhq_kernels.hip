@@ -193,17 +193,21 @@ __device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b,
 // finite distance, so that a padded entry adds exactly +0 to every sum.
 constexpr float kPadPos = 1.0e15f;
 
-template <typename R, int KIND, bool PERIODIC>
-__global__ __launch_bounds__(kBlock) void force_kernel(const ForceArgs A)
-{
-    constexpr bool kSplit = (KIND == kSplitQuad || KIND == kSplitMono);
-    constexpr bool kCellQ = (KIND == kQuad || KIND == kSplitQuad);
-    __shared__ V4<R> sa[kBlock];
-    __shared__ V4<R> sb[kCellQ ? kBlock : 1];
-    __shared__ V4<R> sc[kCellQ ? kBlock : 1];
+template <typename R, int KIND>
+struct Smem {
+    static constexpr bool kCellQ = (KIND == kQuad || KIND == kSplitQuad);
+};
 
+// Evaluate group g with a block of BS threads; sa, sb, sc are LDS tiles of
+// BS entries (sb, sc only for the quadrupole kinds).
+template <typename R, int KIND, bool PERIODIC, int BS>
+__device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
+                                              V4<R> *sa, V4<R> *sb, V4<R> *sc)
+{
+    constexpr int kBlock = BS;
+    constexpr bool kSplit = (KIND == kSplitQuad || KIND == kSplitMono);
+    constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
     const int t = threadIdx.x;
-    const int64_t g = A.order ? A.order[blockIdx.x] : (int64_t)blockIdx.x;
     const int64_t i0 = A.i_off[g];
     const int64_t ni = A.i_off[g + 1] - i0;
     const double cx = A.gcx[g], cy = A.gcy[g], cz = A.gcz[g];
@@ -364,49 +368,110 @@ __global__ __launch_bounds__(kBlock) void force_kernel(const ForceArgs A)
     }
 }
 
-template <typename R, bool P>
-hipError_t launch_kind(int kernel, const ForceArgs &A, hipStream_t s)
+template <typename R, int KIND, bool PERIODIC, int BS>
+__global__ __launch_bounds__(BS) void force_kernel(const ForceArgs A)
 {
-    const dim3 grid((unsigned)A.ng), block(kBlock);
-    switch (kernel) {
-    case kMono:
-        hipLaunchKernelGGL((force_kernel<R, kMono, P>), grid, block, 0, s, A);
-        break;
-    case kQuad:
-        hipLaunchKernelGGL((force_kernel<R, kQuad, P>), grid, block, 0, s, A);
-        break;
-    case kSplitQuad:
-        hipLaunchKernelGGL((force_kernel<R, kSplitQuad, P>), grid, block, 0, s,
-                           A);
-        break;
-    case kSplitMono:
-        hipLaunchKernelGGL((force_kernel<R, kSplitMono, P>), grid, block, 0, s,
-                           A);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
+    __shared__ V4<R> sa[BS];
+    __shared__ V4<R> sb[kCellQ ? BS : 1];
+    __shared__ V4<R> sc[kCellQ ? BS : 1];
+    const int64_t g = A.order ? A.order[blockIdx.x] : (int64_t)blockIdx.x;
+    process_group<R, KIND, PERIODIC, BS>(A, g, sa, sb, sc);
+}
+
+// Persistent variant: a grid sized to the machine pulls groups, in the
+// order of A.order, from the counter A.queue (zeroed before the launch).
+// Every block leaves the loop once the counter has passed ng.
+template <typename R, int KIND, bool PERIODIC, int BS>
+__global__ __launch_bounds__(BS) void force_kernel_persistent(const ForceArgs A)
+{
+    constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
+    __shared__ V4<R> sa[BS];
+    __shared__ V4<R> sb[kCellQ ? BS : 1];
+    __shared__ V4<R> sc[kCellQ ? BS : 1];
+    __shared__ int64_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = (int64_t)atomicAdd(A.queue, 1u);
+        __syncthreads();
+        const int64_t k = next;
+        __syncthreads();
+        if (k >= A.ng) break;
+        const int64_t g = A.order ? A.order[k] : k;
+        process_group<R, KIND, PERIODIC, BS>(A, g, sa, sb, sc);
+    }
+}
+
+__global__ void reset_queue(unsigned int *q)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) q[0] = 0u;
+}
+
+template <typename R, int KIND, bool P, int BS>
+hipError_t launch_one(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
+{
+    if (cfg.persistent) {
+        hipLaunchKernelGGL(reset_queue, dim3(1), dim3(64), 0, s, A.queue);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        int per_cu = cfg.blocks_per_cu;
+        if (per_cu <= 0) {
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, force_kernel_persistent<R, KIND, P, BS>, BS, 0);
+            if (e != hipSuccess) return e;
+            if (per_cu < 1) per_cu = 1;
+        }
+        const int64_t want = (int64_t)per_cu * cfg.num_cu;
+        const unsigned grid = (unsigned)(want < A.ng ? want : A.ng);
+        hipLaunchKernelGGL((force_kernel_persistent<R, KIND, P, BS>), dim3(grid),
+                           dim3(BS), 0, s, A);
+    } else {
+        hipLaunchKernelGGL((force_kernel<R, KIND, P, BS>), dim3((unsigned)A.ng),
+                           dim3(BS), 0, s, A);
     }
     return hipGetLastError();
 }
 
+template <typename R, int KIND, bool P>
+hipError_t launch_bs(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
+{
+    return cfg.block == 128 ? launch_one<R, KIND, P, 128>(A, cfg, s)
+                            : launch_one<R, KIND, P, 256>(A, cfg, s);
+}
+
 template <typename R>
-hipError_t launch_prec(int kernel, const ForceArgs &A, hipStream_t s)
+hipError_t launch_prec(int kernel, const ForceArgs &A, const LaunchCfg &cfg,
+                       hipStream_t s)
 {
     // periodic minimum image only for the split kernels in a box
-    const bool periodic = A.box > 0.0 && (kernel == kSplitQuad || kernel == kSplitMono);
-    return periodic ? launch_kind<R, true>(kernel, A, s)
-                    : launch_kind<R, false>(kernel, A, s);
+    const bool periodic = A.box > 0.0;
+    switch (kernel) {
+    case kMono:
+        return launch_bs<R, kMono, false>(A, cfg, s);
+    case kQuad:
+        return launch_bs<R, kQuad, false>(A, cfg, s);
+    case kSplitQuad:
+        return periodic ? launch_bs<R, kSplitQuad, true>(A, cfg, s)
+                        : launch_bs<R, kSplitQuad, false>(A, cfg, s);
+    case kSplitMono:
+        return periodic ? launch_bs<R, kSplitMono, true>(A, cfg, s)
+                        : launch_bs<R, kSplitMono, false>(A, cfg, s);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
 hipError_t launch_force(int kernel, int precision, const ForceArgs &A,
-                        hipStream_t stream)
+                        const LaunchCfg &cfg, hipStream_t stream)
 {
     if (A.ng <= 0) return hipSuccess;
     if (A.ng > 0x7fffffff) return hipErrorInvalidValue;
-    return precision == 1 ? launch_prec<double>(kernel, A, stream)
-                          : launch_prec<float>(kernel, A, stream);
+    if (cfg.block != 128 && cfg.block != 256) return hipErrorInvalidValue;
+    if (cfg.persistent && (!A.queue || cfg.num_cu <= 0))
+        return hipErrorInvalidValue;
+    return precision == 1 ? launch_prec<double>(kernel, A, cfg, stream)
+                          : launch_prec<float>(kernel, A, cfg, stream);
 }
 
 }  // namespace bhq

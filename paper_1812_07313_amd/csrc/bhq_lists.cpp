@@ -163,14 +163,11 @@ void walk_group(const bhq_lists &L, int32_t gid, double theta2, double rcut,
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int bhq_build_lists(int64_t n, const double (*x)[3], const double *m,
-                    double theta, int ncrit, int nleaf, double box,
-                    double rcut, int nthreads, bhq_lists **out)
+int check_args(int64_t n, const double (*x)[3], const double *m, double theta,
+               int ncrit, int nleaf, double box, double rcut)
 {
-    if (!out) return BHQ_E_ARG;
-    *out = nullptr;
     if (n < 1 || !x || !m || !(theta >= 0.0) || ncrit < 1 || nleaf < 1 ||
         nleaf > ncrit || !(box >= 0.0) || !(rcut >= 0.0) || n > 0x7fffffffLL)
         return BHQ_E_ARG;
@@ -178,9 +175,14 @@ int bhq_build_lists(int64_t n, const double (*x)[3], const double *m,
         if (!std::isfinite(x[p][0]) || !std::isfinite(x[p][1]) ||
             !std::isfinite(x[p][2]) || !std::isfinite(m[p]))
             return BHQ_E_NONFINITE;
+    return BHQ_OK;
+}
 
-    bhq_lists *L = new (std::nothrow) bhq_lists();
-    if (!L) return BHQ_E_NOMEM;
+// Build the tree and lists of one particle set into *L (empty on entry).
+int build_one(int64_t n, const double (*x)[3], const double *m, double theta,
+              int ncrit, int nleaf, double box, double rcut, int nthreads,
+              bhq_lists *L)
+{
     try {
         L->n = n;
         L->box = box;
@@ -282,10 +284,7 @@ int bhq_build_lists(int64_t n, const double (*x)[3], const double *m,
             L->cells[id].nchild = nch;
         }
         const int64_t ncell = (int64_t)L->cells.size();
-        if (ncell > 0x7fffffffLL) {
-            delete L;
-            return BHQ_E_RANGE;
-        }
+        if (ncell > 0x7fffffffLL) return BHQ_E_RANGE;
         // leaves keep input order among their particles
         for (const Cell &c : L->cells)
             if (c.child0 < 0)
@@ -401,6 +400,99 @@ int bhq_build_lists(int64_t n, const double (*x)[3], const double *m,
                        [&](int64_t p) { *pp++ = p; },
                        [&](int32_t c) { *pc++ = c; });
         });
+    } catch (const std::bad_alloc &) {
+        return BHQ_E_NOMEM;
+    }
+    return BHQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bhq_build_lists(int64_t n, const double (*x)[3], const double *m,
+                    double theta, int ncrit, int nleaf, double box,
+                    double rcut, int nthreads, bhq_lists **out)
+{
+    if (!out) return BHQ_E_ARG;
+    *out = nullptr;
+    int rc = check_args(n, x, m, theta, ncrit, nleaf, box, rcut);
+    if (rc != BHQ_OK) return rc;
+    bhq_lists *L = new (std::nothrow) bhq_lists();
+    if (!L) return BHQ_E_NOMEM;
+    rc = build_one(n, x, m, theta, ncrit, nleaf, box, rcut, nthreads, L);
+    if (rc != BHQ_OK) {
+        delete L;
+        return rc;
+    }
+    *out = L;
+    return BHQ_OK;
+}
+
+int bhq_build_lists_batch(int64_t nsys, const int64_t *sys_off,
+                          const double (*x)[3], const double *m, double theta,
+                          int ncrit, int nleaf, int nthreads, bhq_lists **out)
+{
+    if (!out) return BHQ_E_ARG;
+    *out = nullptr;
+    if (nsys < 1 || !sys_off || sys_off[0] != 0) return BHQ_E_ARG;
+    for (int64_t s = 0; s < nsys; ++s)
+        if (sys_off[s + 1] <= sys_off[s]) return BHQ_E_RANGE;
+    const int64_t n = sys_off[nsys];
+    int rc = check_args(n, x, m, theta, ncrit, nleaf, 0.0, 0.0);
+    if (rc != BHQ_OK) return rc;
+    std::vector<bhq_lists> part;
+    try {
+        part.resize((size_t)nsys);
+    } catch (const std::bad_alloc &) {
+        return BHQ_E_NOMEM;
+    }
+    // independent systems are built concurrently, one thread each
+    std::vector<int> rcs((size_t)nsys, BHQ_OK);
+    parallel_for(nsys, nthreads, [&](int64_t s) {
+        const int64_t a = sys_off[s];
+        rcs[(size_t)s] = build_one(sys_off[s + 1] - a, x + a, m + a, theta,
+                                   ncrit, nleaf, 0.0, 0.0, 1, &part[(size_t)s]);
+    });
+    for (int r : rcs)
+        if (r != BHQ_OK) return r;
+    bhq_lists *L = new (std::nothrow) bhq_lists();
+    if (!L) return BHQ_E_NOMEM;
+    try {
+        L->n = n;
+        int64_t cell_base = 0, jp_base = 0, jc_base = 0;
+        L->jp_off.push_back(0);
+        L->jc_off.push_back(0);
+        for (int64_t s = 0; s < nsys; ++s) {
+            bhq_lists &P = part[(size_t)s];
+            const int64_t a = sys_off[s];
+            for (int64_t v : P.order) L->order.push_back(v + a);
+            for (Cell c : P.cells) {
+                c.first += a;
+                if (c.child0 >= 0) c.child0 += (int32_t)cell_base;
+                if (c.parent >= 0) c.parent += (int32_t)cell_base;
+                L->cells.push_back(c);
+            }
+            L->mass.insert(L->mass.end(), P.mass.begin(), P.mass.end());
+            L->com.insert(L->com.end(), P.com.begin(), P.com.end());
+            L->q.insert(L->q.end(), P.q.begin(), P.q.end());
+            L->tr.insert(L->tr.end(), P.tr.begin(), P.tr.end());
+            for (int32_t g : P.groups) L->groups.push_back(g + (int32_t)cell_base);
+            for (size_t g = 1; g < P.jp_off.size(); ++g) {
+                L->jp_off.push_back(P.jp_off[g] + jp_base);
+                L->jc_off.push_back(P.jc_off[g] + jc_base);
+            }
+            for (int64_t v : P.jp_idx) L->jp_idx.push_back(v + a);
+            for (int32_t v : P.jc_cell) L->jc_cell.push_back(v + (int32_t)cell_base);
+            cell_base += (int64_t)P.cells.size();
+            jp_base += (int64_t)P.jp_idx.size();
+            jc_base += (int64_t)P.jc_cell.size();
+            if (cell_base > 0x7fffffffLL) {
+                delete L;
+                return BHQ_E_RANGE;
+            }
+            bhq_lists().jp_idx.swap(P.jp_idx);
+        }
     } catch (const std::bad_alloc &) {
         delete L;
         return BHQ_E_NOMEM;

@@ -228,3 +228,28 @@ def test_state_errors(ctx):
         assert p[0] == pytest.approx(-1.0 - 2 ** -0.5, rel=1e-6)
     finally:
         bhq.bhq_destroy(c2)
+
+
+@pytest.mark.parametrize("nside", [24, 32])
+def test_split_kernel_periodic(ctx, nside):
+    """Short-range Gaussian-split kernel in the periodic unit box (perturbed
+    lattice, r_s = 1.25 mesh cells, cutoff 4.5 r_s, theta = 0.5): minimum
+    image offsets, cutoff masking, the trace term of the cells."""
+    x, m = synth.perturbed_lattice(nside, synth.rng(4))
+    rs = 1.25 / nside
+    rcut = 4.5 * rs
+    log("case split lattice %d^3 rs=%g rcut=%g" % (nside, rs, rcut))
+    T = orc.Tree(x, m, 0.5, 64, box=1.0, rcut=rcut)
+    mat = orc.materialise(T, x, m)
+    upload(ctx, mat, x, eps2=0.0, split=(rs, rcut, 1.0))
+    for bk, ok in ((bhq.SPLIT_QUAD, orc.SPLIT_QUAD),
+                   (bhq.SPLIT_MONO, orc.SPLIT_MONO)):
+        a_ref, p_ref = orc.eval_lists(ok, mat, x, 0.0, box=1.0, rs=rs,
+                                      rcut=rcut)
+        for prec in PRECS:
+            log("  kernel=%s precision=%s" % (bhq.KERNEL_NAMES[bk],
+                                               bhq.PRECISION_NAMES[prec]))
+            a, p = run(ctx, mat, len(m), bk, prec)
+            err = errors(a, p, a_ref, p_ref)
+            log("    %s" % err)
+            assert_parity(err, prec, "split %s %s" % (bk, prec))

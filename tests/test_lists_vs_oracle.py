@@ -59,3 +59,37 @@ def test_lists_match_oracle_periodic_cutoff(orc):
     x, m = synth.perturbed_lattice(24, synth.rng(4))
     rs = 1.25 / 24
     _compare(orc, x, m, 0.5, 32, box=1.0, rcut=4.5 * rs)
+
+
+def test_batch_builder_matches_per_system_oracle(orc):
+    """bhq_build_lists_batch: each system's groups and lists are the
+    oracle's lists of that system alone, shifted to the concatenated
+    indexing."""
+    systems = synth.batched_plummer(7, lo=8.0, hi=11.0)
+    sizes = [len(s[1]) for s in systems]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    X = np.concatenate([s[0] for s in systems])
+    M = np.concatenate([s[1] for s in systems])
+    L = bhq.bhq_build_lists_batch(off, X, M, 0.6, 64)
+    try:
+        P = bhq.bhq_lists_export(L, len(M))
+        C = bhq.bhq_lists_cells(L)
+    finally:
+        bhq.bhq_lists_free(L)
+    g0 = 0
+    for s, (x, m, _) in enumerate(systems):
+        T = orc.Tree(x, m, 0.6, 64)
+        a = off[s]
+        ng = T.ngroups
+        assert np.array_equal(P["i_idx"][a:off[s + 1]], T.perm + a)
+        assert np.array_equal(P["i_off"][g0:g0 + ng + 1] - a, T.i_off)
+        jp0, jc0 = P["jp_off"][g0], P["jc_off"][g0]
+        assert np.array_equal(P["jp_off"][g0:g0 + ng + 1] - jp0, T.jp_off)
+        assert np.array_equal(P["jc_off"][g0:g0 + ng + 1] - jc0, T.jc_off)
+        assert np.array_equal(P["jp_idx"][jp0:jp0 + T.n_jp] - a, T.jp_idx)
+        cp = P["jc_cell"][jc0:jc0 + T.n_jc]
+        np.testing.assert_allclose(C["mass"][cp], T.mass[T.jc_node], rtol=1e-13)
+        np.testing.assert_allclose(C["com"][cp], T.com[T.jc_node], rtol=1e-12,
+                                   atol=1e-14)
+        g0 += ng
+    assert g0 == len(P["i_off"]) - 1

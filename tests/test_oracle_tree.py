@@ -153,3 +153,33 @@ def test_error_scaling_with_theta(sphere_errors):
         le = np.log([err[(name, th)][1] for th in thetas])
         slope = np.polyfit(lt, le, 1)[0]
         assert abs(slope - claims[name]) <= claims["tolerance"], (name, slope)
+
+
+def test_split_tree_theta_zero_is_short_range_direct(orc):
+    """Periodic short-range kernel: with theta = 0 the tree lists (pruned at
+    the cutoff, minimum image) reproduce the direct short-range sum."""
+    x, m = synth.perturbed_lattice(16, synth.rng(4))
+    rs = 1.25 / 16
+    rcut = 4.5 * rs
+    T = orc.Tree(x, m, 0.0, 32, box=1.0, rcut=rcut)
+    mat = orc.materialise(T, x, m)
+    a, p = orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=1.0, rs=rs, rcut=rcut)
+    ad, pd = orc.direct(x, m, 0.0, split=True, box=1.0, rs=rs, rcut=rcut)
+    np.testing.assert_allclose(a, ad, rtol=1e-12, atol=1e-13 * np.abs(ad).max())
+    np.testing.assert_allclose(p, pd, rtol=1e-12)
+    # pruning really happened: lists are shorter than N
+    assert T.n_jp < T.ngroups * len(m)
+
+
+def test_split_tree_quad_beats_mono(orc):
+    x, m = synth.perturbed_lattice(16, synth.rng(4))
+    rs = 1.25 / 16
+    rcut = 4.5 * rs
+    ad, _ = orc.direct(x, m, 0.0, split=True, box=1.0, rs=rs, rcut=rcut)
+    T = orc.Tree(x, m, 0.5, 32, box=1.0, rcut=rcut)
+    mat = orc.materialise(T, x, m)
+    eq = orc.relative_errors(orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=1.0,
+                                            rs=rs, rcut=rcut)[0], ad)
+    em = orc.relative_errors(orc.eval_lists(orc.SPLIT_MONO, mat, x, 0.0, box=1.0,
+                                            rs=rs, rcut=rcut)[0], ad)
+    assert np.sqrt(np.mean(eq ** 2)) < 0.5 * np.sqrt(np.mean(em ** 2))
