@@ -2,18 +2,23 @@
 quadrupole cells, Plummer-softened particle terms) over per-group
 interaction lists on one MI355X.
 
-Workload (one "step" = one force evaluation of every particle):
+Default workload (one "step" = one force evaluation of every particle):
 uniform random cube [0,1)^3, N = 2^20 equal-mass particles drawn in FP32,
 eps = 1e-3, theta = 0.5, ncrit = 256; quadrupole kernel, FP32 arithmetic
 with FP64 group-relative offsets.  Lists are built on the host by the
-library's builder and resident in HBM before the timed region.
+library's builder and are resident in HBM before the timed region.
 
-Prints ONE JSON line: throughput in Ginteractions/s (particle-particle plus
-particle-cell interactions per second), the FP32 VALU roofline of the force
-kernel, the other variants (monopole, FP64) on the same workload, and the
-FP64 oracle timed on the host's cores.
+Prints ONE JSON line (logs go to stderr): throughput in Ginteractions/s
+(particle-particle plus particle-cell interactions per second), the FP32
+VALU roofline of the force kernel, the other variants on the same lists
+(monopole, FP64), the quadrupole-versus-monopole comparison at equal rms
+force error (the paper's Table 2 question), and the FP64 oracle timed on
+the host's cores.
 
-    python bench.py [--steps K] [--warmup W] [--theta T] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+        [--no-cpu-baseline] [--no-fixed-error] [--no-variants]
+
+Other workloads (--workload): plummer16k, clustered, batched, lattice.
 """
 import argparse
 import json
@@ -29,12 +34,14 @@ if ROOT not in sys.path:
 
 from paper_1812_07313_amd import bhq, synth  # noqa: E402
 
-# Hardware flops per interaction (FMA = 2, rsqrt = 1, others 1) of the
-# kernels' arithmetic: particle term 14 VALU ops / 20 flops, quadrupole
-# cell term 34 ops / 53 flops, monopole cell = particle term.
+# Algorithmic flops per interaction (FMA = 2, rsqrt = 1, other operations
+# 1) of the kernels' arithmetic: particle term 14 VALU operations and 20
+# flops; quadrupole cell term 34 operations and 53 flops; a monopole cell is
+# a particle term.  The split kernels add their radial-function evaluation
+# and are not priced here.
 FLOPS_PP = 20
 FLOPS_PC = {bhq.QUAD: 53, bhq.MONO: 20}
-PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (packed FP32)
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak
 METRIC = ("Ginteractions/s + s/force-eval at fixed rms error; quad vs mono, "
           "FP32 vs FP64")
@@ -44,11 +51,80 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# --- workloads ----------------------------------------------------------------
+
+def workload(name, n=None):
+    """Particles and parameters of a named configuration."""
+    if name == "cube":
+        c = synth.config_uniform_cube(n=n or (1 << 20))
+        return dict(name="uniform cube [0,1)^3, N=%d (FP32 draws), eps=1e-3, "
+                         "theta=0.5, ncrit=256" % len(c["m"]),
+                    x=c["x"], m=c["m"], eps=c["eps"], theta=0.5, ncrit=256,
+                    kernel=bhq.QUAD)
+    if name == "plummer16k":
+        c = synth.config_plummer_16k()
+        return dict(name="Plummer sphere N=16384, eps=1/64, theta=0.5, ncrit=64",
+                    x=c["x"], m=c["m"], eps=c["eps"], theta=0.5, ncrit=64,
+                    kernel=bhq.QUAD)
+    if name == "clustered":
+        c = synth.config_clustered(n=n or (1 << 22))
+        return dict(name="512 Plummer clusters + 10%% background, N=%d, "
+                         "eps=2e-4, theta=0.5, ncrit=256" % len(c["m"]),
+                    x=c["x"], m=c["m"], eps=c["eps"], theta=0.5, ncrit=256,
+                    kernel=bhq.QUAD)
+    if name == "batched":
+        systems = synth.batched_plummer(256)
+        sizes = np.array([len(s[1]) for s in systems])
+        off = np.concatenate([[0], np.cumsum(sizes)])
+        return dict(name="256 Plummer systems, N log-uniform in [2^10, 2^16] "
+                         "(total %d), eps=1/(4 N^(1/3)), theta=0.6, ncrit=64"
+                         % off[-1],
+                    x=np.concatenate([s[0] for s in systems]),
+                    m=np.concatenate([s[1] for s in systems]),
+                    eps2=np.concatenate([np.full(len(s[1]), s[2] ** 2)
+                                         for s in systems]),
+                    sys_off=off, theta=0.6, ncrit=64, kernel=bhq.QUAD)
+    if name == "lattice":
+        c = synth.config_lattice(nside=int(round((n or (1 << 24)) ** (1 / 3))))
+        return dict(name="perturbed lattice N=%d in the periodic unit box, "
+                         "Gaussian split r_s=1.25/256, cutoff 4.5 r_s, "
+                         "theta=0.5, ncrit=64" % len(c["m"]),
+                    x=c["x"], m=c["m"], theta=0.5, ncrit=64, box=1.0,
+                    rs=c["rs"], rcut=c["rcut"], kernel=bhq.SPLIT_QUAD)
+    raise SystemExit("unknown workload %r" % name)
+
+
+def build_lists(W, theta, ncrit):
+    t0 = time.perf_counter()
+    if W.get("sys_off") is not None:
+        L = bhq.bhq_build_lists_batch(W["sys_off"], W["x"], W["m"], theta, ncrit,
+                                      nleaf=min(8, ncrit))
+    else:
+        L = bhq.bhq_build_lists(W["x"], W["m"], theta, ncrit,
+                                nleaf=min(8, ncrit), box=W.get("box", 0.0),
+                                rcut=W.get("rcut", 0.0))
+    return L, time.perf_counter() - t0
+
+
+def upload(ctx, W, L):
+    t0 = time.perf_counter()
+    bhq.bhq_set_lists(ctx, L, W["x"], W["m"])
+    P = bhq.bhq_lists_export(L, len(W["m"]))
+    if W.get("eps2") is not None:
+        bhq.bhq_set_eps2_i(ctx, W["eps2"][P["i_idx"]])
+    elif W.get("eps") is not None:
+        bhq.bhq_set_eps(ctx, W["eps"])
+    if W.get("rs"):
+        bhq.bhq_set_split(ctx, W["rs"], W["rcut"], W.get("box", 0.0))
+    return P, time.perf_counter() - t0
+
+
 def time_variant(torch, ctx, kernel, precision, steps, warmup, stream):
+    """Wall time per step over `steps` back-to-back launches, and the mean
+    and median kernel duration from events recorded on the launch stream."""
     bhq.bhq_set_kernel(ctx, kernel, precision)
     for _ in range(warmup):
         bhq.bhq_compute(ctx, stream)
-    torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
@@ -63,31 +139,180 @@ def time_variant(torch, ctx, kernel, precision, steps, warmup, stream):
     return wall / steps * 1e3, float(np.mean(kern_ms)), float(np.median(kern_ms))
 
 
-def cpu_baseline(x, m, eps, theta, ncrit):
+def result_orig(ctx, P, n):
+    a_g, p_g = bhq.bhq_get_result(ctx, n)
+    a = np.zeros_like(a_g)
+    p = np.zeros_like(p_g)
+    a[P["i_idx"]] = a_g
+    p[P["i_idx"]] = p_g
+    return a, p
+
+
+# --- tree error against direct summation ---------------------------------------
+
+def direct_reference(W, P, nsample=4096, seed=7):
+    """FP64 direct-summation accelerations (Sec. 4, eq. 8 reference) for a
+    sample of whole groups, computed by the library's FP64 kernel with each
+    sampled group's list set to every particle of its system."""
+    n = len(W["m"])
+    ng = len(P["i_off"]) - 1
+    rng = np.random.default_rng(seed)
+    sel, tot = [], 0
+    for g in rng.permutation(ng):
+        sel.append(g)
+        tot += P["i_off"][g + 1] - P["i_off"][g]
+        if tot >= nsample:
+            break
+    sel = np.sort(np.array(sel))
+    sys_off = W.get("sys_off")
+    if sys_off is None:
+        sys_off = np.array([0, n])
+    x, m = W["x"], W["m"]
+    i_off, jp_off, centers, i_idx, jp_x, jp_m = [0], [0], [], [], [], []
+    for g in sel:
+        members = P["i_idx"][P["i_off"][g]:P["i_off"][g + 1]]
+        s = np.searchsorted(sys_off, members[0], side="right") - 1
+        a, b = sys_off[s], sys_off[s + 1]
+        xs, ms = x[a:b], m[a:b]
+        if W.get("rcut"):
+            # short-range kernel: only particles within the cutoff of the
+            # group's cell can contribute (minimum image in the box)
+            d = xs - P["center"][g]
+            box = W.get("box", 0.0)
+            if box > 0:
+                d -= box * np.rint(d / box)
+            v = np.maximum(np.abs(d) - 0.5 * P["side"][g], 0.0)
+            keep = np.einsum("ij,ij->i", v, v) <= W["rcut"] ** 2
+            xs, ms = xs[keep], ms[keep]
+        i_idx.append(members)
+        i_off.append(i_off[-1] + len(members))
+        jp_x.append(xs)
+        jp_m.append(ms)
+        jp_off.append(jp_off[-1] + len(ms))
+        centers.append(P["center"][g])
+    i_idx = np.concatenate(i_idx)
+    ctx = bhq.bhq_create(0, W["kernel"], bhq.FP64)
+    try:
+        bhq.bhq_set_groups(ctx, i_off, np.array(centers), jp_off,
+                           np.zeros(len(i_off), np.int64))
+        bhq.bhq_set_i(ctx, x[i_idx])
+        if W.get("eps2") is not None:
+            bhq.bhq_set_eps2_i(ctx, W["eps2"][i_idx])
+        elif W.get("eps") is not None:
+            bhq.bhq_set_eps(ctx, W["eps"])
+        if W.get("rs"):
+            bhq.bhq_set_split(ctx, W["rs"], W["rcut"], W.get("box", 0.0))
+        bhq.bhq_set_jp(ctx, 0, np.concatenate(jp_x), np.concatenate(jp_m))
+        bhq.bhq_set_jc(ctx, 0, np.zeros((0, 3)), np.zeros(0), np.zeros((0, 6)))
+        bhq.bhq_compute(ctx)
+        a, _ = bhq.bhq_get_result(ctx, len(i_idx))
+    finally:
+        bhq.bhq_destroy(ctx)
+    return i_idx, a
+
+
+def tree_error(a_tree, ref):
+    idx, a_dir = ref
+    e = (np.linalg.norm(a_tree[idx] - a_dir, axis=1) /
+         np.linalg.norm(a_dir, axis=1))
+    return dict(rms=float(np.sqrt(np.mean(e ** 2))),
+                p90=float(np.percentile(e, 90)), max=float(e.max()))
+
+
+def fixed_error_study(torch, ctx, W, ref, stream, steps):
+    """Quadrupole versus monopole at equal rms force error: for monopole
+    theta0 in {0.3, 0.5, 0.7} find the quadrupole theta with the same rms
+    tree error (log-log interpolation over a theta grid), rebuild the
+    lists there and time both kernels, in FP32 and FP64."""
+    def measure(kernel, theta, timing):
+        L, _ = build_lists(W, theta, W["ncrit"])
+        try:
+            P, _ = upload(ctx, W, L)
+        finally:
+            bhq.bhq_lists_free(L)
+        bhq.bhq_set_kernel(ctx, kernel, bhq.FP32_OFS64)
+        bhq.bhq_compute(ctx, stream)
+        a, _ = result_orig(ctx, P, len(W["m"]))
+        out = dict(theta=round(theta, 4), err=tree_error(a, ref))
+        if timing:
+            pp, pc = bhq.bhq_get_counts(ctx)
+            for prec in (bhq.FP32_OFS64, bhq.FP64):
+                _, km, _ = time_variant(torch, ctx, kernel, prec, steps, 1,
+                                        stream)
+                out["ms_" + bhq.PRECISION_NAMES[prec]] = round(km, 4)
+            out["n_pp"], out["n_pc"] = pp, pc
+        return out
+
+    quad_grid = [measure(bhq.QUAD, th, False)
+                 for th in (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0)]
+    lt = np.log([q["theta"] for q in quad_grid])
+    le = np.log([q["err"]["rms"] for q in quad_grid])
+    rows = []
+    for th0 in (0.3, 0.5, 0.7):
+        mono = measure(bhq.MONO, th0, True)
+        target = np.log(mono["err"]["rms"])
+        if target <= le[0]:
+            thq = float(np.exp(lt[0]))
+        elif target >= le[-1]:
+            thq = float(np.exp(lt[-1]))
+        else:
+            thq = float(np.exp(np.interp(target, le, lt)))
+        quad = measure(bhq.QUAD, thq, True)
+        rows.append(dict(mono=mono, quad=quad,
+                         quad_speedup_fp32=round(mono["ms_fp32_ofs64"] /
+                                                 quad["ms_fp32_ofs64"], 3),
+                         quad_speedup_fp64=round(mono["ms_fp64"] /
+                                                 quad["ms_fp64"], 3)))
+        log("fixed error %.3g: mono theta %.2f %.3f ms | quad theta %.3f "
+            "(err %.3g) %.3f ms" % (mono["err"]["rms"], th0,
+                                    mono["ms_fp32_ofs64"], thq,
+                                    quad["err"]["rms"], quad["ms_fp32_ofs64"]))
+    return dict(rows=rows, quad_theta_grid=[dict(theta=q["theta"],
+                                                 rms=q["err"]["rms"])
+                                            for q in quad_grid])
+
+
+# --- CPU baseline -----------------------------------------------------------------
+
+def cpu_baseline(W, a_gpu):
     """The FP64 oracle (test infrastructure) timed on this host's cores,
-    evaluating the whole workload's lists once."""
+    evaluating the whole workload's lists once; its result also gives the
+    GPU FP32 path's error against the oracle."""
     import oracle as orc
-    T = orc.Tree(x, m, theta, ncrit)
-    mat = orc.materialise(T, x, m)
+    T = orc.Tree(W["x"], W["m"], W["theta"], W["ncrit"])
+    mat = orc.materialise(T, W["x"], W["m"])
     n_pp, n_pc = T.interaction_counts()
     t0 = time.perf_counter()
-    orc.eval_lists(orc.QUAD, mat, x, eps * eps)
+    a_o, _ = orc.eval_lists(orc.QUAD, mat, W["x"], W["eps"] ** 2)
     dt = time.perf_counter() - t0
-    return {"value": (n_pp + n_pc) / dt / 1e9, "unit": "Ginteractions/s",
-            "cores": orc.num_threads(), "kind": "oracle",
+    e = orc.relative_errors(a_gpu, a_o)
+    return {"value": round((n_pp + n_pc) / dt / 1e9, 4),
+            "unit": "Ginteractions/s", "cores": orc.num_threads(),
+            "kind": "oracle",
             "sample": "one full FP64 evaluation of all %d particles' lists "
-                      "(%.3g interactions, %.2f s)" % (len(m), n_pp + n_pc, dt)}
+                      "(%.3g interactions, %.2f s)" % (len(W["m"]), n_pp + n_pc,
+                                                       dt),
+            "gpu_fp32_vs_oracle": {"rms": float(np.sqrt(np.mean(e ** 2))),
+                                   "max": float(e.max())}}
 
+
+# --- main -------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--theta", type=float, default=0.5)
-    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--workload", default="cube",
+                    choices=["cube", "plummer16k", "clustered", "batched",
+                             "lattice"])
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-fixed-error", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB "
                          "device-to-device once (a plain copy kernel of known "
@@ -114,68 +339,85 @@ def main():
             % (args.copy_calibration_mib, args.copy_calibration_mib))
         del src, dst
 
-    c = synth.config_uniform_cube(n=args.n, theta=args.theta)
-    x, m, eps, theta, ncrit = c["x"], c["m"], c["eps"], c["theta"], c["ncrit"]
-    t0 = time.perf_counter()
-    L = bhq.bhq_build_lists(x, m, theta, ncrit)
-    t_build = time.perf_counter() - t0
+    W = workload(args.workload, args.n)
+    kernel = W["kernel"]
+    n = len(W["m"])
+    L, t_build = build_lists(W, W["theta"], W["ncrit"])
     ng, njp, njc, _ = bhq.bhq_lists_sizes(L)
-    log("lists: %d groups, %d j-particles, %d j-cells, built in %.2f s"
-        % (ng, njp, njc, t_build))
+    log("%s: %d groups, %d j-particles, %d j-cells, lists built in %.2f s"
+        % (W["name"], ng, njp, njc, t_build))
 
-    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    stream = torch.cuda.current_stream()
+    ctx = bhq.bhq_create(0, kernel, bhq.FP32_OFS64)
+    out_extra = {}
     try:
-        t0 = time.perf_counter()
-        bhq.bhq_set_lists(ctx, L, x, m)
-        bhq.bhq_set_eps(ctx, eps)
-        t_upload = time.perf_counter() - t0
+        P, t_upload = upload(ctx, W, L)
         bhq.bhq_lists_free(L)
+        bhq.bhq_set_tuning(ctx, args.block, 0, args.persistent, args.graph)
         n_pp, n_pc = bhq.bhq_get_counts(ctx)
         n_int = n_pp + n_pc
-        stream = torch.cuda.current_stream()
 
         ms_step, ms_kern, ms_kern_med = time_variant(
-            torch, ctx, bhq.QUAD, bhq.FP32_OFS64, args.steps, args.warmup,
-            stream)
-        log("quad fp32: %.3f ms/step (kernel %.3f ms)" % (ms_step, ms_kern))
+            torch, ctx, kernel, bhq.FP32_OFS64, args.steps, args.warmup, stream)
+        log("%s fp32: %.3f ms/step (kernel %.3f ms)"
+            % (bhq.KERNEL_NAMES[kernel], ms_step, ms_kern))
         bhq.bhq_compute(ctx, stream)
-        a32, p32 = bhq.bhq_get_result(ctx, len(m))
+        a32, _ = result_orig(ctx, P, n)
 
         variants = {}
         if not args.no_variants:
-            for kern, prec in ((bhq.MONO, bhq.FP32_OFS64), (bhq.QUAD, bhq.FP64),
-                               (bhq.MONO, bhq.FP64)):
+            others = [(kernel, bhq.FP64)]
+            if kernel == bhq.QUAD:
+                others = [(bhq.MONO, bhq.FP32_OFS64), (bhq.QUAD, bhq.FP64),
+                          (bhq.MONO, bhq.FP64)]
+            elif kernel == bhq.SPLIT_QUAD:
+                others = [(bhq.SPLIT_MONO, bhq.FP32_OFS64),
+                          (bhq.SPLIT_QUAD, bhq.FP64)]
+            for kern, prec in others:
                 vs, vk, _ = time_variant(torch, ctx, kern, prec,
                                          max(3, args.steps // 4), 1, stream)
-                flops = FLOPS_PP * n_pp + FLOPS_PC[kern] * n_pc
-                peak = PEAK_FP64_TFLOPS if prec == bhq.FP64 else PEAK_FP32_TFLOPS
+                v = {"ms_per_eval": round(vs, 4), "kernel_ms": round(vk, 4),
+                     "Ginteractions_per_s": round(n_int / vk / 1e6, 2)}
+                if kern in FLOPS_PC:
+                    flops = FLOPS_PP * n_pp + FLOPS_PC[kern] * n_pc
+                    peak = (PEAK_FP64_TFLOPS if prec == bhq.FP64
+                            else PEAK_FP32_TFLOPS)
+                    v["tflops"] = round(flops / vk / 1e9, 2)
+                    v["frac_of_peak"] = round(flops / vk / 1e9 / peak, 4)
                 variants["%s_%s" % (bhq.KERNEL_NAMES[kern],
-                                    bhq.PRECISION_NAMES[prec])] = {
-                    "ms_per_eval": round(vs, 4), "kernel_ms": round(vk, 4),
-                    "Ginteractions_per_s": round(n_int / vk / 1e6, 2),
-                    "tflops": round(flops / vk / 1e9, 2),
-                    "frac_of_peak": round(flops / vk / 1e9 / peak, 4)}
+                                    bhq.PRECISION_NAMES[prec])] = v
                 log("%s_%s: kernel %.3f ms" % (bhq.KERNEL_NAMES[kern],
                                                 bhq.PRECISION_NAMES[prec], vk))
-            bhq.bhq_set_kernel(ctx, bhq.QUAD, bhq.FP64)
+            bhq.bhq_set_kernel(ctx, kernel, bhq.FP64)
             bhq.bhq_compute(ctx, stream)
-            a64, _ = bhq.bhq_get_result(ctx, len(m))
+            a64, _ = result_orig(ctx, P, n)
             e = np.linalg.norm(a32 - a64, axis=1) / np.linalg.norm(a64, axis=1)
-            variants["quad_fp32_vs_fp64_rel_err"] = {
+            variants["fp32_vs_fp64_rel_err"] = {
                 "rms": float(np.sqrt(np.mean(e ** 2))), "max": float(e.max())}
+
+        ref = direct_reference(W, P, nsample=4096 if n <= (1 << 20) else 1024)
+        out_extra["tree_error_vs_direct"] = dict(
+            sample=len(ref[0]), fp32=tree_error(a32, ref))
+        if not args.no_fixed_error and args.workload == "cube":
+            log("fixed-error study ...")
+            out_extra["fixed_error"] = fixed_error_study(
+                torch, ctx, W, ref, stream, max(5, args.steps // 4))
     finally:
         bhq.bhq_destroy(ctx)
 
-    flops = FLOPS_PP * n_pp + FLOPS_PC[bhq.QUAD] * n_pc
-    achieved = flops / (ms_kern * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3),
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None}
+    roofline = None
+    if kernel in FLOPS_PC:
+        flops = FLOPS_PP * n_pp + FLOPS_PC[kernel] * n_pc
+        achieved = flops / (ms_kern * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3),
+                    "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                    "traffic": None}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "cube":
         log("timing the oracle on the host ...")
-        cpu = cpu_baseline(x, m, eps, theta, ncrit)
+        cpu = cpu_baseline(W, a32)
 
     out = {
         "metric": METRIC,
@@ -185,11 +427,12 @@ def main():
         "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "uniform cube [0,1)^3, N=%d (FP32 draws), "
-                               "eps=1e-3, theta=%g, ncrit=%d; quadrupole, FP32 "
-                               "with FP64 group offsets" % (len(m), theta, ncrit),
-                   "n": len(m), "theta": theta, "ncrit": ncrit, "eps": eps,
-                   "groups": ng, "n_pp": n_pp, "n_pc": n_pc},
+        "config": {"workload": W["name"] + "; %s kernel, FP32 with FP64 group "
+                   "offsets" % bhq.KERNEL_NAMES[kernel],
+                   "n": n, "theta": W["theta"], "ncrit": W["ncrit"],
+                   "groups": ng, "n_pp": n_pp, "n_pc": n_pc,
+                   "launch": {"block": args.block, "persistent": args.persistent,
+                              "graph": args.graph}},
         "s_per_force_eval": round(ms_step * 1e-3, 6),
         "kernel_ms": round(ms_kern, 4), "kernel_ms_median": round(ms_kern_med, 4),
         "pc_Ginteractions_per_s": round(n_pc / (ms_kern * 1e-3) / 1e9, 3),
@@ -198,6 +441,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
     }
+    out.update(out_extra)
     print(json.dumps(out), flush=True)
 
 

@@ -6,4 +6,4 @@ host list builder), reached through the thin ctypes binding in
 ``paper_1812_07313_amd.bhq``.  Importing this package loads nothing; the
 library is loaded on first use of the binding.
 """
-__all__ = ["bhq", "synth"]
+__all__ = ["bhq", "synth", "tune"]

@@ -189,6 +189,20 @@ __device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b,
     }
 }
 
+// Compile-time tuning: unroll depth of the inner loops, and the occupancy
+// (waves per SIMD) the register allocator must allow.
+#ifndef BHQ_UNROLL
+#define BHQ_UNROLL 2
+#endif
+#ifndef BHQ_WAVES_PER_EU
+#define BHQ_WAVES_PER_EU 0
+#endif
+#if BHQ_WAVES_PER_EU > 0
+#define BHQ_OCCUPANCY __attribute__((amdgpu_waves_per_eu(BHQ_WAVES_PER_EU)))
+#else
+#define BHQ_OCCUPANCY
+#endif
+
 // Far position for padding entries: zero mass (and zero moments) at a
 // finite distance, so that a padded entry adds exactly +0 to every sum.
 constexpr float kPadPos = 1.0e15f;
@@ -264,7 +278,7 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
             if (active) {
                 R bx = R(0), by = R(0), bz = R(0), bp = R(0);
                 const V4<R> *pa = sa + slice * it;
-#pragma unroll 4
+#pragma unroll BHQ_UNROLL
                 for (int k = 0; k < it; ++k) {
                     if (kSplit)
                         pp_split(pa[k], xi, yi, zi, i2rs, rcut2, bx, by, bz, bp);
@@ -317,7 +331,7 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
             if (active) {
                 R bx = R(0), by = R(0), bz = R(0), bp = R(0);
                 const int e0 = slice * it;
-#pragma unroll 4
+#pragma unroll BHQ_UNROLL
                 for (int k = 0; k < it; ++k) {
                     const int e = e0 + k;
                     if (KIND == kQuad)
@@ -369,7 +383,7 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
 }
 
 template <typename R, int KIND, bool PERIODIC, int BS>
-__global__ __launch_bounds__(BS) void force_kernel(const ForceArgs A)
+__global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel(const ForceArgs A)
 {
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
     __shared__ V4<R> sa[BS];
@@ -383,7 +397,7 @@ __global__ __launch_bounds__(BS) void force_kernel(const ForceArgs A)
 // order of A.order, from the counter A.queue (zeroed before the launch).
 // Every block leaves the loop once the counter has passed ng.
 template <typename R, int KIND, bool PERIODIC, int BS>
-__global__ __launch_bounds__(BS) void force_kernel_persistent(const ForceArgs A)
+__global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(const ForceArgs A)
 {
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
     __shared__ V4<R> sa[BS];

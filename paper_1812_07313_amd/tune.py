@@ -1,0 +1,122 @@
+"""Autotuner for the force evaluation: chooses the group size bound ncrit
+(which changes the interaction lists) and the launch shape (block size,
+persistent queue, persistent grid size) that minimise the time of one force
+evaluation.  Interactions per second alone would reward larger ncrit (more,
+cheaper interactions), so the objective is seconds per evaluation.
+
+Results are cached in a JSON file keyed by device architecture, a caller
+supplied workload key, kernel, precision and theta, so that a repeated
+call returns the stored choice without measuring again.
+"""
+import json
+import os
+import time
+
+import numpy as np
+
+from . import bhq
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bhq",
+                             "tune.json")
+
+NCRITS = (64, 128, 256)
+SHAPES = ((256, 0, 0), (128, 0, 0), (256, 0, 1), (128, 0, 1), (256, 2, 1),
+          (128, 4, 1))
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, db):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def cache_key(arch, workload, kernel, precision, theta):
+    return "%s|%s|%s|%s|theta=%.4g" % (arch, workload,
+                                        bhq.KERNEL_NAMES[kernel],
+                                        bhq.PRECISION_NAMES[precision], theta)
+
+
+def search(measure, ncrits=NCRITS, shapes=SHAPES):
+    """Exhaustive search.  measure(ncrit, block, blocks_per_cu, persistent)
+    returns seconds per evaluation.  Returns (best, table)."""
+    table = []
+    for nc in ncrits:
+        for block, bpc, pers in shapes:
+            t = measure(nc, block, bpc, pers)
+            table.append(dict(ncrit=nc, block=block, blocks_per_cu=bpc,
+                              persistent=pers, seconds=t))
+    best = min(table, key=lambda r: r["seconds"])
+    return dict(best), table
+
+
+def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
+                eps=None, eps2_per_particle=None, sys_off=None, box=0.0,
+                rcut=0.0, repeats=5, stream=None):
+    """A measure() for search(): builds the lists for each ncrit once (host
+    builder), uploads them to ctx and times bhq_compute with HIP events
+    (median of `repeats` launches after one warm-up)."""
+    state = {"ncrit": None}
+
+    def measure(ncrit, block, bpc, pers):
+        if state["ncrit"] != ncrit:
+            if sys_off is not None:
+                L = bhq.bhq_build_lists_batch(sys_off, x, m, theta, ncrit,
+                                              nleaf=min(8, ncrit))
+            else:
+                L = bhq.bhq_build_lists(x, m, theta, ncrit,
+                                        nleaf=min(8, ncrit), box=box, rcut=rcut)
+            try:
+                bhq.bhq_set_lists(ctx, L, x, m)
+                idx = bhq.bhq_lists_export(L, len(m))["i_idx"]
+            finally:
+                bhq.bhq_lists_free(L)
+            if eps2_per_particle is not None:
+                bhq.bhq_set_eps2_i(ctx, np.asarray(eps2_per_particle)[idx])
+            elif eps is not None:
+                bhq.bhq_set_eps(ctx, eps)
+            state["ncrit"] = ncrit
+        bhq.bhq_set_kernel(ctx, kernel, precision)
+        bhq.bhq_set_tuning(ctx, block, bpc, pers, 0)
+        bhq.bhq_compute(ctx, stream)
+        bhq.bhq_get_kernel_ms(ctx)
+        ts = []
+        for _ in range(repeats):
+            bhq.bhq_compute(ctx, stream)
+            ts.append(bhq.bhq_get_kernel_ms(ctx))
+        return float(np.median(ts)) * 1e-3
+
+    return measure
+
+
+def autotune(ctx, x, m, theta, workload, arch="gfx950", kernel=bhq.QUAD,
+             precision=bhq.FP32_OFS64, cache=DEFAULT_CACHE, ncrits=NCRITS,
+             shapes=SHAPES, force=False, **kw):
+    """Tune (or read from the cache) and leave ctx holding the best lists
+    and launch shape.  Returns dict(best=..., table=..., cached=bool)."""
+    key = cache_key(arch, workload, kernel, precision, theta)
+    db = _load(cache)
+    measure = gpu_measure(ctx, x, m, theta, kernel=kernel, precision=precision,
+                          **kw)
+    if not force and key in db:
+        best = db[key]["best"]
+        measure(best["ncrit"], best["block"], best["blocks_per_cu"],
+                best["persistent"])
+        return dict(best=best, table=db[key]["table"], cached=True)
+    t0 = time.perf_counter()
+    best, table = search(measure, ncrits, shapes)
+    db = _load(cache)
+    db[key] = dict(best=best, table=table, seconds_spent=time.perf_counter() - t0)
+    _store(cache, db)
+    measure(best["ncrit"], best["block"], best["blocks_per_cu"],
+            best["persistent"])
+    return dict(best=best, table=table, cached=False)
