@@ -51,6 +51,28 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(profile="force_kernel_quad_fp32_cube1m.md"):
+    """HBM bytes per launch of the quadrupole FP32 kernel on the default
+    workload, from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated against a plain copy).  None when the kernel
+    source has changed since those counters were taken."""
+    import hashlib
+    try:
+        src = os.path.join(ROOT, "paper_1812_07313_amd", "csrc", "bhq_kernels.hip")
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+        with open(os.path.join(ROOT, "profiles", profile)) as f:
+            text = f.read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines()
+                  if line.startswith(("kernel_source_sha256:",
+                                      "traffic_bytes_per_launch:")))
+    if fields.get("kernel_source_sha256", "").strip() != digest:
+        return None
+    return int(fields["traffic_bytes_per_launch"].strip())
+
+
 # --- workloads ----------------------------------------------------------------
 
 def workload(name, n=None):
@@ -412,7 +434,8 @@ def main():
         roofline = {"bound": "alu", "achieved": round(achieved, 3),
                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                    "traffic": None}
+                    "traffic": (profiled_traffic() if args.workload == "cube"
+                                and kernel == bhq.QUAD else None)}
 
     cpu = None
     if not args.no_cpu_baseline and args.workload == "cube":
