@@ -128,9 +128,12 @@ def build_lists(W, theta, ncrit):
     return L, time.perf_counter() - t0
 
 
-def upload(ctx, W, L):
+def upload(ctx, W, L, indexed=False):
     t0 = time.perf_counter()
-    bhq.bhq_set_lists(ctx, L, W["x"], W["m"])
+    if indexed:
+        bhq.bhq_set_lists_indexed(ctx, L, W["x"], W["m"])
+    else:
+        bhq.bhq_set_lists(ctx, L, W["x"], W["m"])
     P = bhq.bhq_lists_export(L, len(W["m"]))
     if W.get("eps2") is not None:
         bhq.bhq_set_eps2_i(ctx, W["eps2"][P["i_idx"]])
@@ -249,7 +252,7 @@ def fixed_error_study(torch, ctx, W, ref, stream, steps):
     def measure(kernel, theta, timing):
         L, _ = build_lists(W, theta, W["ncrit"])
         try:
-            P, _ = upload(ctx, W, L)
+            P, _ = upload(ctx, W, L, indexed=W.get("indexed", False))
         finally:
             bhq.bhq_lists_free(L)
         bhq.bhq_set_kernel(ctx, kernel, bhq.FP32_OFS64)
@@ -332,6 +335,10 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--lists", default="indexed",
+                    choices=["materialised", "indexed"],
+                    help="list upload mode: index lists into shared particle "
+                         "and cell pools, or materialised copies")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-fixed-error", action="store_true")
@@ -373,7 +380,7 @@ def main():
     ctx = bhq.bhq_create(0, kernel, bhq.FP32_OFS64)
     out_extra = {}
     try:
-        P, t_upload = upload(ctx, W, L)
+        P, t_upload = upload(ctx, W, L, indexed=(args.lists == "indexed"))
         bhq.bhq_lists_free(L)
         bhq.bhq_set_tuning(ctx, args.block, 0, args.persistent, args.graph)
         n_pp, n_pc = bhq.bhq_get_counts(ctx)
@@ -420,7 +427,8 @@ def main():
         ref = direct_reference(W, P, nsample=4096 if n <= (1 << 20) else 1024)
         out_extra["tree_error_vs_direct"] = dict(
             sample=len(ref[0]), fp32=tree_error(a32, ref))
-        if not args.no_fixed_error and args.workload == "cube":
+        if not args.no_fixed_error and args.workload in ("cube", "sphere"):
+            W["indexed"] = args.lists == "indexed"
             log("fixed-error study ...")
             out_extra["fixed_error"] = fixed_error_study(
                 torch, ctx, W, ref, stream, max(5, args.steps // 4))
@@ -454,6 +462,7 @@ def main():
                    "offsets" % bhq.KERNEL_NAMES[kernel],
                    "n": n, "theta": W["theta"], "ncrit": W["ncrit"],
                    "groups": ng, "n_pp": n_pp, "n_pc": n_pc,
+                   "lists": args.lists,
                    "launch": {"block": args.block, "persistent": args.persistent,
                               "graph": args.graph}},
         "s_per_force_eval": round(ms_step * 1e-3, 6),

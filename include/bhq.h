@@ -132,6 +132,28 @@ int bhq_set_jp(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
 int bhq_set_jc(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
                const double *m, const double (*q)[6], const double *trace);
 
+/* Index-mode lists (alternative to bhq_set_jp / bhq_set_jc): the j-data
+ * live once in two pools and each list entry is an int32 index into them,
+ * so neighbouring groups share the data (4 bytes per entry instead of a
+ * copy).  After bhq_set_groups the lists are given either materialised or
+ * as indices; mixing the two returns BHQ_E_STATE.
+ *
+ * Particle pool: n particles, x[n][3], m[n].  Cell pool: n cells, centre of
+ * mass x, mass m, quadrupole q (List 1 order), trace (NULL: 0).  Setting a
+ * pool invalidates the indices given against it (set them again). */
+int bhq_set_pool_particles(bhq_ctx *ctx, int64_t n, const double (*x)[3],
+                           const double *m);
+int bhq_set_pool_cells(bhq_ctx *ctx, int64_t n, const double (*x)[3],
+                       const double *m, const double (*q)[6],
+                       const double *trace);
+
+/* Index lists: entries adr .. adr+n-1 of the j-particle (resp. j-cell)
+ * lists, each an index into the particle (resp. cell) pool.  The pool must
+ * be set first; every index is checked on the host (0 <= idx < pool size,
+ * else BHQ_E_RANGE), so the kernels never read outside the pools. */
+int bhq_set_jp_idx(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx);
+int bhq_set_jc_idx(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx);
+
 /* Launch the force evaluation on HIP stream `stream` (NULL: the null
  * stream).  Asynchronous.  Errors: BHQ_E_STATE if groups, i-particles or
  * softening are missing; BHQ_E_HIP on a launch failure. */
@@ -226,6 +248,11 @@ int bhq_lists_cells(const bhq_lists *L, double (*com)[3], double *mass,
  * moments.  x, m are the arrays the lists were built from. */
 int bhq_set_lists(bhq_ctx *ctx, const bhq_lists *L, const double (*x)[3],
                   const double *m);
+
+/* The same upload as index lists: the pools hold x, m (input order) and the
+ * tree cells; the list entries are indices. */
+int bhq_set_lists_indexed(bhq_ctx *ctx, const bhq_lists *L,
+                          const double (*x)[3], const double *m);
 
 /* Free lists (NULL accepted). */
 int bhq_lists_free(bhq_lists *L);

@@ -123,6 +123,67 @@ void orc_split_derivs(double r, double rs, double *Phi, double *D1, double *D2,
     *D3 = (15.0 * g + 5.0 * h + 8.0 * u * u * u * u * u * rsqpi * e) / r7;
 }
 
+/* The cutoff of the split kernel is a discrete decision: a term is kept iff
+ * its separation is non-zero and below rcut.  By definition that is decided
+ * on d = r_j - r_i in FP64 (mode ORC_MASK_ABS).  Where a pair or cell sits
+ * within rounding of rcut, an implementation that forms d differently may
+ * decide the other way; to compare such an implementation term by term the
+ * decision is taken as it takes it (the force values stay FP64):
+ *   ORC_MASK_F32_OFS: positions relative to the group centre c rounded to
+ *     FP32 (periodic: v - box * rint(v * (1/box)) first, in FP64), their
+ *     FP32 difference, r^2 = fma(dz, dz, fma(dy, dy, dx * dx)) in FP32,
+ *     kept iff 0 < r^2 < fl32(rcut * rcut);
+ *   ORC_MASK_F64_OFS: the same in FP64 without the rounding to FP32. */
+enum { ORC_MASK_ABS = 0, ORC_MASK_F32_OFS = 1, ORC_MASK_F64_OFS = 2 };
+
+static double wrap_ofs(double v, double box)
+{
+    return box > 0.0 ? v - box * nearbyint(v * (1.0 / box)) : v;
+}
+
+int orc_split_keep(int mode, const double xj[3], const double xi[3],
+                   const double c[3], double box, double rcut)
+{
+    if (mode == ORC_MASK_F32_OFS) {
+        float d[3];
+        for (int k = 0; k < 3; ++k) {
+            float pj = (float)wrap_ofs(xj[k] - c[k], box);
+            float pi = (float)wrap_ofs(xi[k] - c[k], box);
+            d[k] = pj - pi;
+        }
+        float r2 = fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
+        return r2 > 0.0f && r2 < (float)(rcut * rcut);
+    }
+    if (mode == ORC_MASK_F64_OFS) {
+        double d[3];
+        for (int k = 0; k < 3; ++k)
+            d[k] = wrap_ofs(xj[k] - c[k], box) - wrap_ofs(xi[k] - c[k], box);
+        double r2 = fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+        return r2 > 0.0 && r2 < rcut * rcut;
+    }
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+        d[k] = xj[k] - xi[k];
+        if (box > 0.0) d[k] -= box * nearbyint(d[k] / box);
+    }
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    return r2 > 0.0 && sqrt(r2) < rcut;
+}
+
+/* Short-range point mass without the cutoff test: a = m D1(r) d,
+ * phi = m Phi(r). */
+static void split_pair_value(const double d[3], double m, double rs,
+                             double a[3], double *phi)
+{
+    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double Phi, D1, D2, D3;
+    orc_split_derivs(r, rs, &Phi, &D1, &D2, &D3);
+    a[0] += m * D1 * d[0];
+    a[1] += m * D1 * d[1];
+    a[2] += m * D1 * d[2];
+    *phi += m * Phi;
+}
+
 /* Short-range point mass: a = m D1(r) d, phi = m Phi(r); zero for r >= rcut
  * and for r == 0 (the self pair; no softening in the split kernel). */
 void orc_pp_split(const double d[3], double m, double rs, double rcut,
@@ -146,14 +207,13 @@ void orc_pp_split(const double d[3], double m, double rs, double rcut,
  *   a   = M D1 d + (1/6)(D3 (d.Q.d) d + 2 D2 Q.d) + (T/6)(D3 r^2 + 5 D2) d
  * The cell contributes only when its centre of mass is closer than rcut.
  * With use_quad == 0 only the M terms are kept (split monopole). */
-void orc_pc_split(const double d[3], double M, const double q[6], double T,
-                  double rs, double rcut, int use_quad, double a[3],
-                  double *phi)
+/* The split cell term without the cutoff test. */
+static void split_cell_value(const double d[3], double M, const double q[6],
+                             double T, double rs, int use_quad, double a[3],
+                             double *phi)
 {
     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    if (r2 == 0.0) return;
     double r = sqrt(r2);
-    if (r >= rcut) return;
     double Phi, D1, D2, D3;
     orc_split_derivs(r, rs, &Phi, &D1, &D2, &D3);
     double pot = M * Phi;
@@ -172,6 +232,16 @@ void orc_pc_split(const double d[3], double M, const double q[6], double T,
     for (int k = 0; k < 3; ++k)
         a[k] += coef * d[k] + qterm * Qd[k];
     *phi += pot;
+}
+
+void orc_pc_split(const double d[3], double M, const double q[6], double T,
+                  double rs, double rcut, int use_quad, double a[3],
+                  double *phi)
+{
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 == 0.0) return;
+    if (sqrt(r2) >= rcut) return;
+    split_cell_value(d, M, q, T, rs, use_quad, a, phi);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -441,13 +511,16 @@ void orc_free(orc_tree *t)
  *   box             > 0: periodic cube [0, box)^3 as the root; 0: the root
  *                   is centred on the midpoint of the bounding box, with
  *                   side = largest extent * (1 + 2^-20)
- *   rcut            > 0: prune nodes farther than rcut (min-image) */
+ *   rcut            > 0: prune nodes farther than rcut (min-image)
+ *   walk_stride     >= 1: lists are built for groups g with g % walk_stride
+ *                   == 0 only (the others get empty lists), to sample very
+ *                   large inputs */
 int orc_build(int64_t n, const double *x, const double *m, double theta,
               int ncrit, int nleaf, int maxdepth, double box, double rcut,
-              orc_tree **out)
+              int walk_stride, orc_tree **out)
 {
     if (!out || n < 1 || !x || !m || ncrit < 1 || nleaf < 1 || theta < 0.0 ||
-        maxdepth < 0)
+        maxdepth < 0 || walk_stride < 1)
         return ORC_E_ARG;
     *out = NULL;
     orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
@@ -523,7 +596,8 @@ int orc_build(int64_t n, const double *x, const double *m, double theta,
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t g = 0; g < ng; ++g) {
         walk_state w = {theta2, rcut, 0, 0, NULL, NULL};
-        walk_node(t, root, &t->nodes[t->group_node[g]], &w);
+        if (g % walk_stride == 0)
+            walk_node(t, root, &t->nodes[t->group_node[g]], &w);
         t->jp_off[g + 1] = w.njp;
         t->jc_off[g + 1] = w.njc;
     }
@@ -541,7 +615,8 @@ int orc_build(int64_t n, const double *x, const double *m, double theta,
     for (int64_t g = 0; g < ng; ++g) {
         walk_state w = {theta2, rcut, 0, 0, &t->jp_idx[t->jp_off[g]],
                         &t->jc_node[t->jc_off[g]]};
-        walk_node(t, root, &t->nodes[t->group_node[g]], &w);
+        if (g % walk_stride == 0)
+            walk_node(t, root, &t->nodes[t->group_node[g]], &w);
     }
     *out = t;
     return ORC_OK;
@@ -629,13 +704,15 @@ void orc_export_nodes(const orc_tree *t, double *center, double *side,
  *   kind   ORC_MONO / ORC_QUAD / ORC_SPLIT_QUAD / ORC_SPLIT_MONO
  *   box    > 0: minimum image separations (periodic)
  *   rs, rcut  split-kernel parameters
+ *   mask_mode, gcenter[3 ng]  how the split kernel's cutoff is decided (see
+ *             orc_split_keep; gcenter may be NULL for ORC_MASK_ABS)
  * Writes a[3 i], phi[i] for every i listed. */
 void orc_eval(int kind, int64_t ng, const int64_t *i_idx, const int64_t *i_off,
               const double *x, const double *eps2, const int64_t *jp_off,
               const double *jp_x, const double *jp_m, const int64_t *jc_off,
               const double *jc_x, const double *jc_m, const double *jc_q,
               const double *jc_t, double box, double rs, double rcut,
-              double *a, double *phi)
+              int mask_mode, const double *gcenter, double *a, double *phi)
 {
     int split = (kind == ORC_SPLIT_QUAD || kind == ORC_SPLIT_MONO);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -648,10 +725,14 @@ void orc_eval(int kind, int64_t ng, const int64_t *i_idx, const int64_t *i_off,
                 double d[3];
                 for (int c = 0; c < 3; ++c)
                     d[c] = wrap(jp_x[3 * j + c] - xi[c], box);
-                if (split)
-                    orc_pp_split(d, jp_m[j], rs, rcut, acc, &pot);
-                else
+                if (split) {
+                    if (orc_split_keep(mask_mode, &jp_x[3 * j], xi,
+                                       gcenter ? &gcenter[3 * g] : xi, box,
+                                       rcut))
+                        split_pair_value(d, jp_m[j], rs, acc, &pot);
+                } else {
                     orc_pp_plummer(d, jp_m[j], eps2[i], acc, &pot);
+                }
             }
             for (int64_t j = jc_off[g]; j < jc_off[g + 1]; ++j) {
                 double d[3];
@@ -664,13 +745,14 @@ void orc_eval(int kind, int64_t ng, const int64_t *i_idx, const int64_t *i_off,
                 case ORC_QUAD:
                     orc_pc_quad(d, jc_m[j], &jc_q[6 * j], eps2[i], acc, &pot);
                     break;
-                case ORC_SPLIT_QUAD:
-                    orc_pc_split(d, jc_m[j], &jc_q[6 * j], jc_t ? jc_t[j] : 0.0,
-                                 rs, rcut, 1, acc, &pot);
-                    break;
                 default:
-                    orc_pc_split(d, jc_m[j], &jc_q[6 * j], 0.0, rs, rcut, 0,
-                                 acc, &pot);
+                    if (orc_split_keep(mask_mode, &jc_x[3 * j], xi,
+                                       gcenter ? &gcenter[3 * g] : xi, box,
+                                       rcut))
+                        split_cell_value(d, jc_m[j], &jc_q[6 * j],
+                                         (kind == ORC_SPLIT_QUAD && jc_t)
+                                             ? jc_t[j] : 0.0,
+                                         rs, kind == ORC_SPLIT_QUAD, acc, &pot);
                     break;
                 }
             }

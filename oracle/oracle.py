@@ -11,6 +11,8 @@ import subprocess
 import numpy as np
 
 MONO, QUAD, SPLIT_QUAD, SPLIT_MONO = 0, 1, 2, 3
+# how the split kernel's cutoff decision is taken (see orc_split_keep)
+MASK_ABS, MASK_F32_OFS, MASK_F64_OFS = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
@@ -41,7 +43,7 @@ def lib():
         L.orc_build.restype = ctypes.c_int
         L.orc_build.argtypes = [ctypes.c_int64, _D, _D, ctypes.c_double,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_void_p)]
         L.orc_free.argtypes = [ctypes.c_void_p]
         L.orc_sizes.argtypes = [ctypes.c_void_p, _I64]
@@ -52,7 +54,10 @@ def lib():
         L.orc_eval.argtypes = [ctypes.c_int, ctypes.c_int64, _I64, _I64, _D,
                                _D, _I64, _D, _D, _I64, _D, _D, _D, _D,
                                ctypes.c_double, ctypes.c_double,
-                               ctypes.c_double, _D, _D]
+                               ctypes.c_double, ctypes.c_int, _D, _D, _D]
+        L.orc_split_keep.restype = ctypes.c_int
+        L.orc_split_keep.argtypes = [ctypes.c_int, _D, _D, _D, ctypes.c_double,
+                                     ctypes.c_double]
         L.orc_direct.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_int64,
                                  _I64, ctypes.c_int, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, _D, _D]
@@ -94,14 +99,14 @@ class Tree:
     numpy arrays; the C object is freed on construction)."""
 
     def __init__(self, x, m, theta, ncrit, nleaf=8, maxdepth=21, box=0.0,
-                 rcut=0.0):
+                 rcut=0.0, walk_stride=1):
         x = _cd(x).reshape(-1, 3)
         m = _cd(m)
         n = x.shape[0]
         h = ctypes.c_void_p()
         rc = lib().orc_build(n, _dp(x), _dp(m), float(theta), int(ncrit),
                              int(nleaf), int(maxdepth), float(box), float(rcut),
-                             ctypes.byref(h))
+                             int(walk_stride), ctypes.byref(h))
         if rc != 0:
             raise RuntimeError("orc_build failed with code %d" % rc)
         try:
@@ -137,6 +142,30 @@ class Tree:
         finally:
             lib().orc_free(h)
         self.theta, self.ncrit, self.box, self.rcut = theta, ncrit, box, rcut
+        self.walk_stride = walk_stride
+
+    def sample_mat(self, x, m, groups):
+        """Materialised lists of the given groups only (their i-particles in
+        original indexing), e.g. the groups a strided walk visited."""
+        x = _cd(x).reshape(-1, 3)
+        m = _cd(m)
+        groups = np.asarray(groups, np.int64)
+        i_idx, i_off, jp_off, jc_off, jp, jc = [], [0], [0], [0], [], []
+        for g in groups:
+            i_idx.append(self.perm[self.i_off[g]:self.i_off[g + 1]])
+            i_off.append(i_off[-1] + self.i_off[g + 1] - self.i_off[g])
+            jp.append(self.jp_idx[self.jp_off[g]:self.jp_off[g + 1]])
+            jc.append(self.jc_node[self.jc_off[g]:self.jc_off[g + 1]].astype(np.int64))
+            jp_off.append(jp_off[-1] + len(jp[-1]))
+            jc_off.append(jc_off[-1] + len(jc[-1]))
+        jp = np.concatenate(jp)
+        jc = np.concatenate(jc)
+        return dict(i_idx=np.concatenate(i_idx), i_off=np.array(i_off),
+                    gcenter=self.center[self.gnode[groups]],
+                    gside=self.side[self.gnode[groups]],
+                    jp_off=np.array(jp_off), jp_x=x[jp], jp_m=m[jp],
+                    jc_off=np.array(jc_off), jc_x=self.com[jc],
+                    jc_m=self.mass[jc], jc_q=self.q[jc], jc_t=self.trace[jc])
 
     @property
     def n_jp(self):
@@ -173,10 +202,11 @@ def materialise(tree, x, m):
     )
 
 
-def eval_lists(kind, mat, x, eps2, box=0.0, rs=0.0, rcut=0.0):
+def eval_lists(kind, mat, x, eps2, box=0.0, rs=0.0, rcut=0.0,
+               mask=MASK_ABS):
     """Oracle evaluation of materialised lists (see orc_eval).  Returns
     (a[n,3], phi[n]) in original particle order; particles not in any group
-    are left at zero."""
+    are left at zero.  mask: how the split kernel's cutoff is decided."""
     x = _cd(x).reshape(-1, 3)
     eps2 = _cd(np.broadcast_to(eps2, (x.shape[0],)))
     n = x.shape[0]
@@ -190,10 +220,11 @@ def eval_lists(kind, mat, x, eps2, box=0.0, rs=0.0, rcut=0.0):
     jc_x, jc_m, jc_q = _cd(mat["jc_x"]), _cd(mat["jc_m"]), _cd(mat["jc_q"])
     jc_t = _cd(mat["jc_t"]) if mat.get("jc_t") is not None else None
     ng = i_off.shape[0] - 1
+    gc = _cd(mat["gcenter"]) if mask != MASK_ABS else None
     lib().orc_eval(int(kind), ng, _ip(i_idx), _ip(i_off), _dp(x), _dp(eps2),
                    _ip(jp_off), _dp(jp_x), _dp(jp_m), _ip(jc_off), _dp(jc_x),
                    _dp(jc_m), _dp(jc_q), _dp(jc_t), float(box), float(rs),
-                   float(rcut), _dp(a), _dp(phi))
+                   float(rcut), int(mask), _dp(gc), _dp(a), _dp(phi))
     return a, phi
 
 
@@ -258,6 +289,11 @@ def pc_split(d, M, q, T, rs, rcut, use_quad=True):
 
 def pp_split(d, m, rs, rcut):
     return _single(lib().orc_pp_split, d, float(m), float(rs), float(rcut))
+
+
+def split_keep(mode, xj, xi, c, box, rcut):
+    return bool(lib().orc_split_keep(int(mode), _dp(_cd(xj)), _dp(_cd(xi)),
+                                     _dp(_cd(c)), float(box), float(rcut)))
 
 
 def split_derivs(r, rs):

@@ -70,6 +70,11 @@ SIGNATURES = {
     "bhq_lists_cells": (ctypes.c_int, [_P, _D, _D, _D, _D]),
     "bhq_set_lists": (ctypes.c_int, [_P, _P, _D, _D]),
     "bhq_lists_free": (ctypes.c_int, [_P]),
+    "bhq_set_pool_particles": (ctypes.c_int, [_P, ctypes.c_int64, _D, _D]),
+    "bhq_set_pool_cells": (ctypes.c_int, [_P, ctypes.c_int64, _D, _D, _D, _D]),
+    "bhq_set_jp_idx": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _I32]),
+    "bhq_set_jc_idx": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _I32]),
+    "bhq_set_lists_indexed": (ctypes.c_int, [_P, _P, _D, _D]),
 }
 
 _lib = None
@@ -195,6 +200,41 @@ def bhq_set_jc(ctx, adr, x, m, q, trace=None):
            ctx)
 
 
+def bhq_set_pool_particles(ctx, x, m):
+    x = _f64(x, (-1, 3))
+    m = _f64(m)
+    if m.shape[0] != x.shape[0]:
+        raise BhqError(E_ARG, "x and m lengths disagree")
+    _check(lib().bhq_set_pool_particles(ctx, x.shape[0], _dp(x), _dp(m)), ctx)
+
+
+def bhq_set_pool_cells(ctx, x, m, q, trace=None):
+    x = _f64(x, (-1, 3))
+    m = _f64(m)
+    q = _f64(q, (-1, 6))
+    t = None if trace is None else _f64(trace)
+    n = x.shape[0]
+    if m.shape[0] != n or q.shape[0] != n or (t is not None and t.shape[0] != n):
+        raise BhqError(E_ARG, "cell pool array lengths disagree")
+    _check(lib().bhq_set_pool_cells(ctx, n, _dp(x), _dp(m), _dp(q), _dp(t)), ctx)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def bhq_set_jp_idx(ctx, adr, idx):
+    i = _i32(idx)
+    _check(lib().bhq_set_jp_idx(ctx, int(adr), i.shape[0],
+                                i.ctypes.data_as(_I32)), ctx)
+
+
+def bhq_set_jc_idx(ctx, adr, idx):
+    i = _i32(idx)
+    _check(lib().bhq_set_jc_idx(ctx, int(adr), i.shape[0],
+                                i.ctypes.data_as(_I32)), ctx)
+
+
 def bhq_compute(ctx, stream=None):
     _check(lib().bhq_compute(ctx, _stream_handle(stream)), ctx)
 
@@ -294,6 +334,12 @@ def bhq_set_lists(ctx, L, x, m):
     x = _f64(x, (-1, 3))
     m = _f64(m)
     _check(lib().bhq_set_lists(ctx, L, _dp(x), _dp(m)), ctx)
+
+
+def bhq_set_lists_indexed(ctx, L, x, m):
+    x = _f64(x, (-1, 3))
+    m = _f64(m)
+    _check(lib().bhq_set_lists_indexed(ctx, L, _dp(x), _dp(m)), ctx)
 
 
 def bhq_lists_free(L):

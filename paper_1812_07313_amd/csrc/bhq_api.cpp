@@ -54,6 +54,7 @@ enum Arr {
     A_JCT,
     A_AX, A_AY, A_AZ, A_POT,
     A_QUEUE,
+    A_POOLP, A_POOLC, A_JPIDX, A_JCIDX,
     A_COUNT
 };
 
@@ -77,6 +78,10 @@ struct bhq_ctx {
     DevArray arr[A_COUNT];
 
     bool have_i = false, have_jp = false, have_jc = false, have_t = false;
+    // list mode after bhq_set_groups: 0 undecided, 1 materialised, 2 indexed
+    int list_mode = 0;
+    int64_t npool_p = -1, npool_c = -1;
+    bool have_jp_idx = false, have_jc_idx = false;
     int eps_mode = 0;  // 0 none, 1 uniform, 2 per-particle
     double eps2_all = 0.0;
     bool have_split = false;
@@ -149,6 +154,43 @@ struct bhq_ctx {
         }
         for (int64_t k = 0; k < n; ++k) stage[(size_t)k] = v[k * w + c];
         return put(a, off, stage.data(), n);
+    }
+    // Allocate the materialised list arrays (first set_jp / set_jc after
+    // set_groups).
+    int use_materialised()
+    {
+        if (list_mode == 2)
+            return fail(BHQ_E_STATE, "lists already given as indices since "
+                                     "the last set_groups");
+        if (list_mode == 1) return BHQ_OK;
+        const size_t D = sizeof(double);
+        const Arr jp[] = {A_JPX, A_JPY, A_JPZ, A_JPM};
+        const Arr jc[] = {A_JCX, A_JCY, A_JCZ, A_JCM, A_Q00, A_Q01, A_Q02,
+                          A_Q11, A_Q12, A_Q22, A_JCT};
+        for (Arr a : jp) {
+            hipError_t e = arr[a].reserve((size_t)njp * D);
+            if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        }
+        for (Arr a : jc) {
+            hipError_t e = arr[a].reserve((size_t)njc * D);
+            if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        }
+        list_mode = 1;
+        ++args_version;
+        return BHQ_OK;
+    }
+    int use_indexed()
+    {
+        if (list_mode == 1)
+            return fail(BHQ_E_STATE, "lists already materialised since the "
+                                     "last set_groups");
+        if (list_mode == 2) return BHQ_OK;
+        hipError_t e = arr[A_JPIDX].reserve((size_t)njp * 4);
+        if (e == hipSuccess) e = arr[A_JCIDX].reserve((size_t)njc * 4);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        list_mode = 2;
+        ++args_version;
+        return BHQ_OK;
     }
     int fill_eps_uniform()
     {
@@ -347,14 +389,6 @@ int bhq_set_groups(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
         {A_E2I, (size_t)ni * D},
         {A_AX, (size_t)ni * D}, {A_AY, (size_t)ni * D}, {A_AZ, (size_t)ni * D},
         {A_POT, (size_t)ni * D},
-        {A_JPX, (size_t)njp * D}, {A_JPY, (size_t)njp * D},
-        {A_JPZ, (size_t)njp * D}, {A_JPM, (size_t)njp * D},
-        {A_JCX, (size_t)njc * D}, {A_JCY, (size_t)njc * D},
-        {A_JCZ, (size_t)njc * D}, {A_JCM, (size_t)njc * D},
-        {A_Q00, (size_t)njc * D}, {A_Q01, (size_t)njc * D},
-        {A_Q02, (size_t)njc * D}, {A_Q11, (size_t)njc * D},
-        {A_Q12, (size_t)njc * D}, {A_Q22, (size_t)njc * D},
-        {A_JCT, (size_t)njc * D},
     };
     if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
     for (auto &n : need) {
@@ -378,6 +412,8 @@ int bhq_set_groups(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
     ctx->njc = njc;
     ++ctx->args_version;
     ctx->have_i = ctx->have_jp = ctx->have_jc = ctx->have_t = false;
+    ctx->have_jp_idx = ctx->have_jc_idx = false;
+    ctx->list_mode = 0;
     if (ctx->eps_mode == 2) ctx->eps_mode = 0;
 
     auto up = [&](Arr a, const void *src, size_t bytes) -> int {
@@ -439,6 +475,7 @@ int bhq_set_jp(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
     if (!finite_all(&x[0][0], 3 * n) || !finite_all(m, n))
         return ctx->fail(BHQ_E_NONFINITE, "j-particle data not finite");
     TRY(ctx->select());
+    TRY(ctx->use_materialised());
     for (int c = 0; c < 3; ++c)
         TRY(ctx->put_component((Arr)(A_JPX + c), adr, &x[0][0], 3, c, n));
     TRY(ctx->put(A_JPM, adr, m, n));
@@ -461,6 +498,7 @@ int bhq_set_jc(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
         !finite_all(&q[0][0], 6 * n) || (trace && !finite_all(trace, n)))
         return ctx->fail(BHQ_E_NONFINITE, "j-cell data not finite");
     TRY(ctx->select());
+    TRY(ctx->use_materialised());
     for (int c = 0; c < 3; ++c)
         TRY(ctx->put_component((Arr)(A_JCX + c), adr, &x[0][0], 3, c, n));
     TRY(ctx->put(A_JCM, adr, m, n));
@@ -486,10 +524,19 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
     if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "compute before set_groups");
     if (!ctx->have_i && ctx->ni > 0)
         return ctx->fail(BHQ_E_STATE, "compute before set_i");
-    if (ctx->njp > 0 && !ctx->have_jp)
-        return ctx->fail(BHQ_E_STATE, "compute before set_jp");
-    if (ctx->njc > 0 && !ctx->have_jc)
-        return ctx->fail(BHQ_E_STATE, "compute before set_jc");
+    if (ctx->list_mode == 2) {
+        if (ctx->njp > 0 && !ctx->have_jp_idx)
+            return ctx->fail(BHQ_E_STATE, "compute before set_jp_idx");
+        if (ctx->njc > 0 && !ctx->have_jc_idx)
+            return ctx->fail(BHQ_E_STATE, "compute before set_jc_idx");
+    } else {
+        if (ctx->njp > 0 && !ctx->have_jp)
+            return ctx->fail(BHQ_E_STATE, "compute before set_jp");
+        if (ctx->njc > 0 && !ctx->have_jc)
+            return ctx->fail(BHQ_E_STATE, "compute before set_jc");
+        if (ctx->njp + ctx->njc > 0 && ctx->list_mode != 1)
+            return ctx->fail(BHQ_E_STATE, "compute before the lists are set");
+    }
     const bool split = ctx->kernel == BHQ_SPLIT_QUAD ||
                        ctx->kernel == BHQ_SPLIT_MONO;
     if (split && !ctx->have_split)
@@ -518,6 +565,12 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
     A.rcut = ctx->rcut;
 
     A.queue = ctx->arr[A_QUEUE].as<unsigned int>();
+    if (ctx->list_mode == 2) {
+        A.pool_p = ctx->arr[A_POOLP].as<bhq::PartRec>();
+        A.pool_c = ctx->arr[A_POOLC].as<bhq::CellRec>();
+        A.jp_idx = ctx->arr[A_JPIDX].as<int32_t>();
+        A.jc_idx = ctx->arr[A_JCIDX].as<int32_t>();
+    }
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
@@ -601,6 +654,107 @@ int bhq_get_tuning(const bhq_ctx *ctx, int out[4])
     out[1] = ctx->cfg.blocks_per_cu;
     out[2] = ctx->cfg.persistent;
     out[3] = ctx->use_graph;
+    return BHQ_OK;
+}
+
+int bhq_set_pool_particles(bhq_ctx *ctx, int64_t n, const double (*x)[3],
+                           const double *m)
+{
+    CHECK_CTX(ctx);
+    if (n < 0 || n > 0x7fffffffLL) return ctx->fail(BHQ_E_ARG, "bad pool size");
+    if (n > 0 && (!x || !m)) return ctx->fail(BHQ_E_ARG, "x or m is NULL");
+    if (n > 0 && (!finite_all(&x[0][0], 3 * n) || !finite_all(m, n)))
+        return ctx->fail(BHQ_E_NONFINITE, "particle pool not finite");
+    TRY(ctx->select());
+    std::vector<bhq::PartRec> rec;
+    try {
+        rec.resize((size_t)n);
+    } catch (const std::bad_alloc &) {
+        return ctx->fail(BHQ_E_NOMEM, "host staging");
+    }
+    for (int64_t k = 0; k < n; ++k)
+        rec[(size_t)k] = bhq::PartRec{x[k][0], x[k][1], x[k][2], m[k]};
+    hipError_t e = ctx->arr[A_POOLP].reserve((size_t)n * sizeof(bhq::PartRec));
+    if (e == hipSuccess && n > 0)
+        e = hipMemcpy(ctx->arr[A_POOLP].p, rec.data(),
+                      (size_t)n * sizeof(bhq::PartRec), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return ctx->hip_fail(e, "particle pool upload");
+    ctx->npool_p = n;
+    ctx->have_jp_idx = false;  // indices are validated against the pool
+    ++ctx->args_version;
+    return BHQ_OK;
+}
+
+int bhq_set_pool_cells(bhq_ctx *ctx, int64_t n, const double (*x)[3],
+                       const double *m, const double (*q)[6],
+                       const double *trace)
+{
+    CHECK_CTX(ctx);
+    if (n < 0 || n > 0x7fffffffLL) return ctx->fail(BHQ_E_ARG, "bad pool size");
+    if (n > 0 && (!x || !m || !q)) return ctx->fail(BHQ_E_ARG, "x, m or q is NULL");
+    if (n > 0 && (!finite_all(&x[0][0], 3 * n) || !finite_all(m, n) ||
+                  !finite_all(&q[0][0], 6 * n) || (trace && !finite_all(trace, n))))
+        return ctx->fail(BHQ_E_NONFINITE, "cell pool not finite");
+    TRY(ctx->select());
+    std::vector<bhq::CellRec> rec;
+    try {
+        rec.resize((size_t)n);
+    } catch (const std::bad_alloc &) {
+        return ctx->fail(BHQ_E_NOMEM, "host staging");
+    }
+    for (int64_t k = 0; k < n; ++k)
+        rec[(size_t)k] = bhq::CellRec{x[k][0], x[k][1], x[k][2], m[k],
+                                      q[k][0], q[k][1], q[k][2], q[k][3],
+                                      q[k][4], q[k][5], trace ? trace[k] : 0.0,
+                                      0.0};
+    hipError_t e = ctx->arr[A_POOLC].reserve((size_t)n * sizeof(bhq::CellRec));
+    if (e == hipSuccess && n > 0)
+        e = hipMemcpy(ctx->arr[A_POOLC].p, rec.data(),
+                      (size_t)n * sizeof(bhq::CellRec), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return ctx->hip_fail(e, "cell pool upload");
+    ctx->npool_c = n;
+    ctx->have_jc_idx = false;
+    ++ctx->args_version;
+    return BHQ_OK;
+}
+
+static int set_idx(bhq_ctx *ctx, Arr a, int64_t total, int64_t pool,
+                   int64_t adr, int64_t n, const int32_t *idx, const char *what)
+{
+    if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "%s before set_groups", what);
+    if (pool < 0)
+        return ctx->fail(BHQ_E_STATE, "%s before its pool is set", what);
+    if (adr < 0 || n < 0) return ctx->fail(BHQ_E_ARG, "negative adr or n");
+    if (adr + n > total)
+        return ctx->fail(BHQ_E_RANGE, "%s: adr + n = %lld > %lld", what,
+                         (long long)(adr + n), (long long)total);
+    if (n > 0 && !idx) return ctx->fail(BHQ_E_ARG, "idx is NULL");
+    for (int64_t k = 0; k < n; ++k)
+        if (idx[k] < 0 || idx[k] >= pool)
+            return ctx->fail(BHQ_E_RANGE, "%s: index %d at %lld outside the "
+                             "pool of %lld", what, (int)idx[k],
+                             (long long)(adr + k), (long long)pool);
+    TRY(ctx->select());
+    TRY(ctx->use_indexed());
+    if (n == 0) return BHQ_OK;
+    hipError_t e = hipMemcpy(ctx->arr[a].as<int32_t>() + adr, idx,
+                             (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice);
+    return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "hipMemcpy H2D");
+}
+
+int bhq_set_jp_idx(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx)
+{
+    CHECK_CTX(ctx);
+    TRY(set_idx(ctx, A_JPIDX, ctx->njp, ctx->npool_p, adr, n, idx, "set_jp_idx"));
+    ctx->have_jp_idx = true;
+    return BHQ_OK;
+}
+
+int bhq_set_jc_idx(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx)
+{
+    CHECK_CTX(ctx);
+    TRY(set_idx(ctx, A_JCIDX, ctx->njc, ctx->npool_c, adr, n, idx, "set_jc_idx"));
+    ctx->have_jc_idx = true;
     return BHQ_OK;
 }
 
@@ -758,6 +912,73 @@ int bhq_set_lists(bhq_ctx *ctx, const bhq_lists *L, const double (*x)[3],
         }
     } catch (const std::bad_alloc &) {
         return ctx->fail(BHQ_E_NOMEM, "host memory while materialising lists");
+    }
+    return BHQ_OK;
+}
+
+// Upload host-built lists as index lists into shared pools: the particles in
+// input order, the tree cells, and per-entry int32 indices.
+int bhq_set_lists_indexed(bhq_ctx *ctx, const bhq_lists *L,
+                          const double (*x)[3], const double *m)
+{
+    CHECK_CTX(ctx);
+    if (!L || !x || !m) return ctx->fail(BHQ_E_ARG, "NULL lists, x or m");
+    int64_t sz[4];
+    TRY(bhq_lists_sizes(L, sz));
+    const int64_t ng = sz[0], njp = sz[1], njc = sz[2], ncell = sz[3];
+    try {
+        std::vector<int64_t> i_off((size_t)ng + 1), jp_off((size_t)ng + 1),
+            jc_off((size_t)ng + 1);
+        std::vector<double> center((size_t)ng * 3);
+        TRY(bhq_lists_export(L, nullptr, i_off.data(),
+                             reinterpret_cast<double(*)[3]>(center.data()),
+                             nullptr, jp_off.data(), nullptr, jc_off.data(),
+                             nullptr));
+        TRY(bhq_set_groups(ctx, ng, i_off.data(),
+                           reinterpret_cast<const double(*)[3]>(center.data()),
+                           jp_off.data(), jc_off.data()));
+        const int64_t n = i_off[(size_t)ng];
+        {
+            std::vector<int64_t> i_idx((size_t)n);
+            TRY(bhq_lists_export(L, i_idx.data(), nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, nullptr, nullptr));
+            std::vector<double> xi((size_t)n * 3);
+            for (int64_t k = 0; k < n; ++k)
+                for (int c = 0; c < 3; ++c)
+                    xi[(size_t)(3 * k + c)] = x[i_idx[(size_t)k]][c];
+            TRY(bhq_set_i(ctx, n, reinterpret_cast<const double(*)[3]>(xi.data())));
+        }
+        TRY(bhq_set_pool_particles(ctx, n, x, m));
+        {
+            std::vector<double> com((size_t)ncell * 3), mass((size_t)ncell),
+                q((size_t)ncell * 6), tr((size_t)ncell);
+            TRY(bhq_lists_cells(L, reinterpret_cast<double(*)[3]>(com.data()),
+                                mass.data(),
+                                reinterpret_cast<double(*)[6]>(q.data()),
+                                tr.data()));
+            TRY(bhq_set_pool_cells(ctx, ncell,
+                                   reinterpret_cast<const double(*)[3]>(com.data()),
+                                   mass.data(),
+                                   reinterpret_cast<const double(*)[6]>(q.data()),
+                                   tr.data()));
+        }
+        {
+            std::vector<int64_t> jp64((size_t)njp);
+            TRY(bhq_lists_export(L, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                 jp64.data(), nullptr, nullptr));
+            std::vector<int32_t> jp32((size_t)njp);
+            for (int64_t k = 0; k < njp; ++k) jp32[(size_t)k] = (int32_t)jp64[(size_t)k];
+            std::vector<int64_t>().swap(jp64);
+            TRY(bhq_set_jp_idx(ctx, 0, njp, jp32.data()));
+        }
+        {
+            std::vector<int32_t> jc((size_t)njc);
+            TRY(bhq_lists_export(L, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, jc.data()));
+            TRY(bhq_set_jc_idx(ctx, 0, njc, jc.data()));
+        }
+    } catch (const std::bad_alloc &) {
+        return ctx->fail(BHQ_E_NOMEM, "host memory while uploading index lists");
     }
     return BHQ_OK;
 }

@@ -8,6 +8,16 @@
 
 namespace bhq {
 
+// Pool records for index-mode lists (AoS, FP64).
+struct alignas(32) PartRec {
+    double x, y, z, m;
+};
+struct alignas(32) CellRec {
+    double x, y, z, m;          // centre of mass, mass
+    double q00, q01, q02, q11;  // quadrupole (List 1 order)
+    double q12, q22, t, pad;    // ..., trace
+};
+
 // Device-side view of one force evaluation.  All arrays are SoA in device
 // memory; i-particles and outputs are in group order.
 struct ForceArgs {
@@ -27,6 +37,13 @@ struct ForceArgs {
     double box;                     // > 0: periodic minimum image
     double rs, rcut;                // split-kernel parameters
     unsigned int *queue;            // group counter of the persistent kernel
+    // Index-mode lists (all NULL for materialised lists): entry k of the
+    // j-particle list is pool_p[jp_idx[k]], of the j-cell list
+    // pool_c[jc_idx[k]].
+    const PartRec *pool_p;
+    const CellRec *pool_c;
+    const int32_t *jp_idx;
+    const int32_t *jc_idx;
 };
 
 // Launch shape.  block: threads per block (128 or 256), which is also the

@@ -15,6 +15,10 @@
 // the same trip count.  The slices' partial sums are combined in a fixed
 // order at the end, so results are deterministic run to run.
 //
+// Lists are either materialised (SoA FP64 copies of every entry) or
+// index lists into shared particle and cell pools (AoS FP64 records); the
+// staging step gathers either kind into the same LDS tile.
+//
 // Interaction arithmetic (per i-particle, per list entry, d = x_j - x_i):
 //   particle:  rinv = rsq(|d|^2 + eps^2); a += m rinv^3 d; -phi += m rinv
 //   cell (monopole + traceless quadrupole, Sec. 3 eqs. 1 and 7):
@@ -231,6 +235,7 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
     const double ibox = PERIODIC ? 1.0 / box : 0.0;
     const R i2rs = kSplit ? R(0.5 / A.rs) : R(0);
     const R rcut2 = kSplit ? R(A.rcut * A.rcut) : R(0);
+    const bool indexed = A.jp_idx != nullptr;
     auto rel = [&](double v, double c) -> R {
         return PERIODIC ? R(wrap(v - c, box, ibox)) : R(v - c);
     };
@@ -264,10 +269,18 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                 V4<R> v;
                 if (t < cnt) {
                     const int64_t j = p0 + base + t;
-                    v.x = rel(A.jpx[j], cx);
-                    v.y = rel(A.jpy[j], cy);
-                    v.z = rel(A.jpz[j], cz);
-                    v.w = R(A.jpm[j]);
+                    if (indexed) {
+                        const PartRec P = A.pool_p[A.jp_idx[j]];
+                        v.x = rel(P.x, cx);
+                        v.y = rel(P.y, cy);
+                        v.z = rel(P.z, cz);
+                        v.w = R(P.m);
+                    } else {
+                        v.x = rel(A.jpx[j], cx);
+                        v.y = rel(A.jpy[j], cy);
+                        v.z = rel(A.jpz[j], cz);
+                        v.w = R(A.jpm[j]);
+                    }
                 } else {
                     v.x = v.y = v.z = R(kPadPos);
                     v.w = R(0);
@@ -301,19 +314,37 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                 V4<R> v, w, u;
                 if (t < cnt) {
                     const int64_t j = c0 + base + t;
-                    v.x = rel(A.jcx[j], cx);
-                    v.y = rel(A.jcy[j], cy);
-                    v.z = rel(A.jcz[j], cz);
-                    v.w = R(A.jcm[j]);
-                    if (kCellQ) {
-                        w.x = R(A.q00[j]);
-                        w.y = R(A.q01[j]);
-                        w.z = R(A.q02[j]);
-                        w.w = R(A.q11[j]);
-                        u.x = R(A.q12[j]);
-                        u.y = R(A.q22[j]);
-                        u.z = (KIND == kSplitQuad) ? R(A.jct[j]) : R(0);
-                        u.w = R(0);
+                    if (indexed) {
+                        const CellRec *C = A.pool_c + A.jc_idx[j];
+                        v.x = rel(C->x, cx);
+                        v.y = rel(C->y, cy);
+                        v.z = rel(C->z, cz);
+                        v.w = R(C->m);
+                        if (kCellQ) {
+                            w.x = R(C->q00);
+                            w.y = R(C->q01);
+                            w.z = R(C->q02);
+                            w.w = R(C->q11);
+                            u.x = R(C->q12);
+                            u.y = R(C->q22);
+                            u.z = (KIND == kSplitQuad) ? R(C->t) : R(0);
+                            u.w = R(0);
+                        }
+                    } else {
+                        v.x = rel(A.jcx[j], cx);
+                        v.y = rel(A.jcy[j], cy);
+                        v.z = rel(A.jcz[j], cz);
+                        v.w = R(A.jcm[j]);
+                        if (kCellQ) {
+                            w.x = R(A.q00[j]);
+                            w.y = R(A.q01[j]);
+                            w.z = R(A.q02[j]);
+                            w.w = R(A.q11[j]);
+                            u.x = R(A.q12[j]);
+                            u.y = R(A.q22[j]);
+                            u.z = (KIND == kSplitQuad) ? R(A.jct[j]) : R(0);
+                            u.w = R(0);
+                        }
                     }
                 } else {
                     v.x = v.y = v.z = R(kPadPos);

@@ -16,6 +16,7 @@ pytestmark = pytest.mark.gpu
 
 KINDS = [(bhq.QUAD, orc.QUAD), (bhq.MONO, orc.MONO)]
 PRECS = [bhq.FP32_OFS64, bhq.FP64]
+SPLIT_MASK = {bhq.FP32_OFS64: orc.MASK_F32_OFS, bhq.FP64: orc.MASK_F64_OFS}
 
 
 @pytest.fixture(scope="module")
@@ -244,12 +245,124 @@ def test_split_kernel_periodic(ctx, nside):
     upload(ctx, mat, x, eps2=0.0, split=(rs, rcut, 1.0))
     for bk, ok in ((bhq.SPLIT_QUAD, orc.SPLIT_QUAD),
                    (bhq.SPLIT_MONO, orc.SPLIT_MONO)):
-        a_ref, p_ref = orc.eval_lists(ok, mat, x, 0.0, box=1.0, rs=rs,
-                                      rcut=rcut)
         for prec in PRECS:
+            # the cutoff is decided as the kernel decides it (a discrete
+            # choice made in floating point); the terms stay FP64
+            a_ref, p_ref = orc.eval_lists(ok, mat, x, 0.0, box=1.0, rs=rs,
+                                          rcut=rcut, mask=SPLIT_MASK[prec])
             log("  kernel=%s precision=%s" % (bhq.KERNEL_NAMES[bk],
                                                bhq.PRECISION_NAMES[prec]))
             a, p = run(ctx, mat, len(m), bk, prec)
             err = errors(a, p, a_ref, p_ref)
             log("    %s" % err)
             assert_parity(err, prec, "split %s %s" % (bk, prec))
+
+
+def _upload_indexed(ctx, T, mat, x, m, eps2=None, split=None):
+    x = np.asarray(x, np.float64).reshape(-1, 3)
+    bhq.bhq_set_groups(ctx, mat["i_off"], mat["gcenter"], mat["jp_off"],
+                       mat["jc_off"])
+    bhq.bhq_set_i(ctx, x[mat["i_idx"]])
+    if eps2 is not None:
+        e2 = np.broadcast_to(np.asarray(eps2, np.float64), (x.shape[0],))
+        bhq.bhq_set_eps2_i(ctx, np.ascontiguousarray(e2[mat["i_idx"]]))
+    if split is not None:
+        bhq.bhq_set_split(ctx, *split)
+    bhq.bhq_set_pool_particles(ctx, x, m)
+    bhq.bhq_set_pool_cells(ctx, T.com, T.mass, T.q, T.trace)
+    bhq.bhq_set_jp_idx(ctx, 0, T.jp_idx)
+    bhq.bhq_set_jc_idx(ctx, 0, T.jc_node)
+
+
+def test_index_lists_equal_materialised(ctx):
+    """Index-mode lists (pools + int32 indices) give bitwise the result of
+    materialised lists: the same FP64 data reach the same arithmetic."""
+    c = synth.config_plummer_16k()
+    x, m = c["x"], c["m"]
+    T = orc.Tree(x, m, 0.5, 64)
+    mat = orc.materialise(T, x, m)
+    e2 = c["eps"] ** 2
+    ref = {}
+    upload(ctx, mat, x, eps2=e2)
+    for bk in (bhq.QUAD, bhq.MONO):
+        for prec in PRECS:
+            ref[(bk, prec)] = run(ctx, mat, len(m), bk, prec)
+    log("case index lists plummer16k")
+    _upload_indexed(ctx, T, mat, x, m, eps2=e2)
+    for (bk, prec), (a0, p0) in ref.items():
+        a1, p1 = run(ctx, mat, len(m), bk, prec)
+        assert np.array_equal(a0, a1) and np.array_equal(p0, p1), (bk, prec)
+    a_ref, p_ref = orc.eval_lists(orc.QUAD, mat, x, e2)
+    a, p = run(ctx, mat, len(m), bhq.QUAD, bhq.FP32_OFS64)
+    assert_parity(errors(a, p, a_ref, p_ref), bhq.FP32_OFS64, "indexed")
+
+
+def test_index_lists_split_periodic(ctx):
+    x, m = synth.perturbed_lattice(24, synth.rng(4))
+    rs, box = 1.25 / 24, 1.0
+    rcut = 4.5 * rs
+    T = orc.Tree(x, m, 0.5, 64, box=box, rcut=rcut)
+    mat = orc.materialise(T, x, m)
+    log("case index lists split lattice 24^3")
+    _upload_indexed(ctx, T, mat, x, m, eps2=0.0, split=(rs, rcut, box))
+    for prec in PRECS:
+        a_ref, p_ref = orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=box,
+                                      rs=rs, rcut=rcut, mask=SPLIT_MASK[prec])
+        a, p = run(ctx, mat, len(m), bhq.SPLIT_QUAD, prec)
+        err = errors(a, p, a_ref, p_ref)
+        log("  precision=%s %s" % (bhq.PRECISION_NAMES[prec], err))
+        assert_parity(err, prec, "indexed split")
+
+
+def test_index_list_errors(ctx):
+    c2 = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        bhq.bhq_set_groups(c2, [0, 2], np.zeros((1, 3)), [0, 3], [0, 1])
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_set_jp_idx(c2, 0, [0, 1, 2])   # no pool yet
+        assert ei.value.code == bhq.E_STATE
+        bhq.bhq_set_pool_particles(c2, np.random.default_rng(0).random((3, 3)),
+                                   np.ones(3))
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_set_jp_idx(c2, 0, [0, 1, 3])   # 3 is outside the pool
+        assert ei.value.code == bhq.E_RANGE
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_set_jp_idx(c2, 0, [0, -1, 2])
+        assert ei.value.code == bhq.E_RANGE
+        bhq.bhq_set_jp_idx(c2, 0, [0, 1, 2])
+        with pytest.raises(bhq.BhqError) as ei:          # mixing modes
+            bhq.bhq_set_jc(c2, 0, np.zeros((1, 3)), [1.0], np.zeros((1, 6)))
+        assert ei.value.code == bhq.E_STATE
+        bhq.bhq_set_i(c2, np.random.default_rng(1).random((2, 3)))
+        bhq.bhq_set_eps(c2, 0.1)
+        with pytest.raises(bhq.BhqError) as ei:          # jc indices missing
+            bhq.bhq_compute(c2)
+        assert ei.value.code == bhq.E_STATE
+        bhq.bhq_set_pool_cells(c2, np.zeros((1, 3)), [0.5], np.zeros((1, 6)))
+        bhq.bhq_set_jc_idx(c2, 0, [0])
+        bhq.bhq_compute(c2)
+        a, p = bhq.bhq_get_result(c2, 2)
+        assert np.all(np.isfinite(a)) and np.all(p < 0)
+    finally:
+        bhq.bhq_destroy(c2)
+
+
+def test_product_index_lists_equal_materialised(ctx):
+    x, m = synth.clustered(1 << 15, synth.rng(2))
+    L = bhq.bhq_build_lists(x, m, 0.5, 128)
+    try:
+        bhq.bhq_set_lists(ctx, L, x, m)
+        bhq.bhq_set_eps(ctx, 2e-4)
+        out = []
+        for mode in ("materialised", "indexed"):
+            if mode == "indexed":
+                bhq.bhq_set_lists_indexed(ctx, L, x, m)
+                bhq.bhq_set_eps(ctx, 2e-4)
+            log("case product lists %s" % mode)
+            bhq.bhq_set_kernel(ctx, bhq.QUAD, bhq.FP32_OFS64)
+            bhq.bhq_compute(ctx)
+            out.append(bhq.bhq_get_result(ctx, len(m)))
+        assert np.array_equal(out[0][0], out[1][0])
+        assert np.array_equal(out[0][1], out[1][1])
+    finally:
+        bhq.bhq_lists_free(L)

@@ -207,3 +207,40 @@ def test_split_pair_gradient(orc):
     np.testing.assert_allclose(a, -_num_grad(phi_at, np.zeros(3), 1e-7),
                                rtol=1e-6)
     assert math.isfinite(a[0])
+
+
+def test_split_cutoff_decision_modes(orc):
+    """The cutoff decision taken as the FP32 / FP64 kernels take it agrees
+    with the definition (FP64, absolute separations) everywhere except
+    within rounding of r = rcut; the self pair is always excluded."""
+    g = np.random.default_rng(21)
+    rcut, box = 0.02, 1.0
+    c = np.array([0.51, 0.49, 0.502])
+    agree = 0
+    for _ in range(4000):
+        xi = c + g.uniform(-0.01, 0.01, 3)
+        xj = xi + g.normal(size=3) * 0.015
+        xj = np.mod(xj, 1.0)
+        d = xj - xi
+        d -= np.rint(d)
+        r = np.linalg.norm(d)
+        modes = [orc.split_keep(mm, xj, xi, c, box, rcut)
+                 for mm in (orc.MASK_ABS, orc.MASK_F32_OFS, orc.MASK_F64_OFS)]
+        assert modes[0] == (r < rcut)
+        if abs(r - rcut) > 1e-5 * rcut:
+            assert modes[0] == modes[1] == modes[2]
+            agree += 1
+    assert agree > 3900
+    for mm in (orc.MASK_ABS, orc.MASK_F32_OFS, orc.MASK_F64_OFS):
+        assert not orc.split_keep(mm, c, c, c, box, rcut)
+    # just inside / outside the cutoff along an axis, far from rounding
+    xi = c.copy()
+    for frac, keep in ((0.999, True), (1.001, False)):
+        xj = xi + np.array([rcut * frac, 0, 0])
+        for mm in (orc.MASK_ABS, orc.MASK_F32_OFS, orc.MASK_F64_OFS):
+            assert orc.split_keep(mm, xj, xi, c, box, rcut) == keep
+    # minimum image across the periodic boundary
+    xi = np.array([0.999, 0.5, 0.5])
+    xj = np.array([0.004, 0.5, 0.5])
+    for mm in (orc.MASK_ABS, orc.MASK_F32_OFS, orc.MASK_F64_OFS):
+        assert orc.split_keep(mm, xj, xi, np.array([0.995, 0.5, 0.5]), box, rcut)
