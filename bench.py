@@ -18,7 +18,8 @@ the host's cores.
     python bench.py [--steps K] [--warmup W] [--workload NAME]
         [--no-cpu-baseline] [--no-fixed-error] [--no-variants]
 
-Other workloads (--workload): plummer16k, clustered, batched, lattice.
+Other workloads (--workload): sphere (the paper's homogeneous sphere,
+N = 4,194,304), plummer16k, clustered, batched, lattice.
 """
 import argparse
 import json
@@ -80,18 +81,26 @@ def workload(name, n=None):
     if name == "cube":
         c = synth.config_uniform_cube(n=n or (1 << 20))
         return dict(name="uniform cube [0,1)^3, N=%d (FP32 draws), eps=1e-3, "
-                         "theta=0.5, ncrit=256" % len(c["m"]),
+                         "theta=0.5" % len(c["m"]),
                     x=c["x"], m=c["m"], eps=c["eps"], theta=0.5, ncrit=256,
+                    kernel=bhq.QUAD)
+    if name == "sphere":
+        # the paper's homogeneous sphere at its Table 2 size
+        nn = n or 4194304
+        x, m = synth.uniform_sphere(nn, synth.rng(5))
+        return dict(name="homogeneous sphere (radius 1) N=%d, eps=2^-8, "
+                         "theta=0.5" % nn,
+                    x=x, m=m, eps=2.0 ** -8, theta=0.5, ncrit=256,
                     kernel=bhq.QUAD)
     if name == "plummer16k":
         c = synth.config_plummer_16k()
-        return dict(name="Plummer sphere N=16384, eps=1/64, theta=0.5, ncrit=64",
+        return dict(name="Plummer sphere N=16384, eps=1/64, theta=0.5",
                     x=c["x"], m=c["m"], eps=c["eps"], theta=0.5, ncrit=64,
                     kernel=bhq.QUAD)
     if name == "clustered":
         c = synth.config_clustered(n=n or (1 << 22))
         return dict(name="512 Plummer clusters + 10%% background, N=%d, "
-                         "eps=2e-4, theta=0.5, ncrit=256" % len(c["m"]),
+                         "eps=2e-4, theta=0.5" % len(c["m"]),
                     x=c["x"], m=c["m"], eps=c["eps"], theta=0.5, ncrit=256,
                     kernel=bhq.QUAD)
     if name == "batched":
@@ -99,8 +108,7 @@ def workload(name, n=None):
         sizes = np.array([len(s[1]) for s in systems])
         off = np.concatenate([[0], np.cumsum(sizes)])
         return dict(name="256 Plummer systems, N log-uniform in [2^10, 2^16] "
-                         "(total %d), eps=1/(4 N^(1/3)), theta=0.6, ncrit=64"
-                         % off[-1],
+                         "(total %d), eps=1/(4 N^(1/3)), theta=0.6" % off[-1],
                     x=np.concatenate([s[0] for s in systems]),
                     m=np.concatenate([s[1] for s in systems]),
                     eps2=np.concatenate([np.full(len(s[1]), s[2] ** 2)
@@ -110,7 +118,7 @@ def workload(name, n=None):
         c = synth.config_lattice(nside=int(round((n or (1 << 24)) ** (1 / 3))))
         return dict(name="perturbed lattice N=%d in the periodic unit box, "
                          "Gaussian split r_s=1.25/256, cutoff 4.5 r_s, "
-                         "theta=0.5, ncrit=64" % len(c["m"]),
+                         "theta=0.5" % len(c["m"]),
                     x=c["x"], m=c["m"], theta=0.5, ncrit=64, box=1.0,
                     rs=c["rs"], rcut=c["rcut"], kernel=bhq.SPLIT_QUAD)
     raise SystemExit("unknown workload %r" % name)
@@ -329,8 +337,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cube",
-                    choices=["cube", "plummer16k", "clustered", "batched",
-                             "lattice"])
+                    choices=["cube", "sphere", "plummer16k", "clustered",
+                             "batched", "lattice"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--persistent", type=int, default=0)
@@ -339,6 +347,10 @@ def main():
                     choices=["materialised", "indexed"],
                     help="list upload mode: index lists into shared particle "
                          "and cell pools, or materialised copies")
+    ap.add_argument("--autotune", type=int, default=None,
+                    help="1: choose ncrit and the launch shape with the "
+                         "autotuner before timing (default: on for the "
+                         "batched workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-fixed-error", action="store_true")
@@ -371,6 +383,26 @@ def main():
     W = workload(args.workload, args.n)
     kernel = W["kernel"]
     n = len(W["m"])
+    tuned = None
+    if args.autotune is None:
+        args.autotune = 1 if args.workload == "batched" else 0
+    if args.autotune:
+        from paper_1812_07313_amd import tune
+        log("autotuning ncrit and launch shape ...")
+        tctx = bhq.bhq_create(0, kernel, bhq.FP32_OFS64)
+        try:
+            r = tune.autotune(tctx, W["x"], W["m"], W["theta"], args.workload,
+                              kernel=kernel, eps=W.get("eps"),
+                              eps2_per_particle=W.get("eps2"),
+                              sys_off=W.get("sys_off"), box=W.get("box", 0.0),
+                              rcut=W.get("rcut", 0.0), rs=W.get("rs", 0.0),
+                              force=True)
+        finally:
+            bhq.bhq_destroy(tctx)
+        tuned = r["best"]
+        W["ncrit"] = tuned["ncrit"]
+        args.block, args.persistent = tuned["block"], tuned["persistent"]
+        log("autotuned: %s" % tuned)
     L, t_build = build_lists(W, W["theta"], W["ncrit"])
     ng, njp, njc, _ = bhq.bhq_lists_sizes(L)
     log("%s: %d groups, %d j-particles, %d j-cells, lists built in %.2f s"
@@ -382,7 +414,9 @@ def main():
     try:
         P, t_upload = upload(ctx, W, L, indexed=(args.lists == "indexed"))
         bhq.bhq_lists_free(L)
-        bhq.bhq_set_tuning(ctx, args.block, 0, args.persistent, args.graph)
+        bhq.bhq_set_tuning(ctx, args.block,
+                           tuned["blocks_per_cu"] if tuned else 0,
+                           args.persistent, args.graph)
         n_pp, n_pc = bhq.bhq_get_counts(ctx)
         n_int = n_pp + n_pc
 
@@ -458,11 +492,11 @@ def main():
         "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": W["name"] + "; %s kernel, FP32 with FP64 group "
-                   "offsets" % bhq.KERNEL_NAMES[kernel],
+        "config": {"workload": W["name"] + ", ncrit=%d; %s kernel, FP32 with "
+                   "FP64 group offsets" % (W["ncrit"], bhq.KERNEL_NAMES[kernel]),
                    "n": n, "theta": W["theta"], "ncrit": W["ncrit"],
                    "groups": ng, "n_pp": n_pp, "n_pc": n_pc,
-                   "lists": args.lists,
+                   "lists": args.lists, "autotuned": tuned,
                    "launch": {"block": args.block, "persistent": args.persistent,
                               "graph": args.graph}},
         "s_per_force_eval": round(ms_step * 1e-3, 6),

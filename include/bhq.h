@@ -90,13 +90,16 @@ int bhq_destroy(bhq_ctx *ctx);
 int bhq_set_kernel(bhq_ctx *ctx, int kernel, int precision);
 
 /* One softening length for every i-particle: eps^2 = eps * eps (the
- * paper's set-eps-to-all call, List 4).  eps >= 0.  Overrides earlier
- * per-particle values. */
+ * paper's set-eps-to-all call, List 4).  eps > 0: the softened kernels
+ * include each particle's self pair (d = 0), which needs eps^2 > 0
+ * (BHQ_E_ARG otherwise).  Overrides earlier per-particle values.  The
+ * split kernels do not use eps. */
 int bhq_set_eps(bhq_ctx *ctx, double eps);
 
 /* Per-i-particle squared softening (the i-particle structure carries eps^2
  * per particle, List 2), in group order; ni must equal i_off[ng] of the
- * last bhq_set_groups.  Every value >= 0 and finite. */
+ * last bhq_set_groups.  Every value finite and > 0 (BHQ_E_ARG / 
+ * BHQ_E_NONFINITE otherwise). */
 int bhq_set_eps2_i(bhq_ctx *ctx, int64_t ni, const double *eps2);
 
 /* Short-range split parameters for the SPLIT kernels: r_s > 0, cutoff

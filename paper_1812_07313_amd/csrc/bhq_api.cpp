@@ -306,7 +306,9 @@ int bhq_set_eps(bhq_ctx *ctx, double eps)
 {
     CHECK_CTX(ctx);
     if (!std::isfinite(eps)) return ctx->fail(BHQ_E_NONFINITE, "eps not finite");
-    if (eps < 0.0) return ctx->fail(BHQ_E_ARG, "eps must be >= 0");
+    if (!(eps > 0.0))
+        return ctx->fail(BHQ_E_ARG, "eps must be > 0: the softened kernels "
+                                    "include each particle's self pair");
     ctx->eps2_all = eps * eps;
     ctx->eps_mode = 1;
     if (ctx->ng >= 0) {
@@ -328,8 +330,9 @@ int bhq_set_eps2_i(bhq_ctx *ctx, int64_t ni, const double *eps2)
         if (!std::isfinite(eps2[k]))
             return ctx->fail(BHQ_E_NONFINITE, "eps2[%lld] not finite",
                              (long long)k);
-        if (eps2[k] < 0.0)
-            return ctx->fail(BHQ_E_ARG, "eps2[%lld] < 0", (long long)k);
+        if (!(eps2[k] > 0.0))
+            return ctx->fail(BHQ_E_ARG, "eps2[%lld] must be > 0 (the softened "
+                             "kernels include the self pair)", (long long)k);
     }
     TRY(ctx->select());
     TRY(ctx->put(A_E2I, 0, eps2, ni));

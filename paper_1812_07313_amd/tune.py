@@ -61,7 +61,7 @@ def search(measure, ncrits=NCRITS, shapes=SHAPES):
 
 def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
                 eps=None, eps2_per_particle=None, sys_off=None, box=0.0,
-                rcut=0.0, repeats=5, stream=None):
+                rcut=0.0, rs=0.0, repeats=5, stream=None, indexed=True):
     """A measure() for search(): builds the lists for each ncrit once (host
     builder), uploads them to ctx and times bhq_compute with HIP events
     (median of `repeats` launches after one warm-up)."""
@@ -76,7 +76,10 @@ def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
                 L = bhq.bhq_build_lists(x, m, theta, ncrit,
                                         nleaf=min(8, ncrit), box=box, rcut=rcut)
             try:
-                bhq.bhq_set_lists(ctx, L, x, m)
+                if indexed:
+                    bhq.bhq_set_lists_indexed(ctx, L, x, m)
+                else:
+                    bhq.bhq_set_lists(ctx, L, x, m)
                 idx = bhq.bhq_lists_export(L, len(m))["i_idx"]
             finally:
                 bhq.bhq_lists_free(L)
@@ -84,6 +87,8 @@ def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
                 bhq.bhq_set_eps2_i(ctx, np.asarray(eps2_per_particle)[idx])
             elif eps is not None:
                 bhq.bhq_set_eps(ctx, eps)
+            if rs:
+                bhq.bhq_set_split(ctx, rs, rcut, box)
             state["ncrit"] = ncrit
         bhq.bhq_set_kernel(ctx, kernel, precision)
         bhq.bhq_set_tuning(ctx, block, bpc, pers, 0)

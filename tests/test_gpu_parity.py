@@ -221,7 +221,14 @@ def test_state_errors(ctx):
         with pytest.raises(bhq.BhqError) as ei:
             bhq.bhq_compute(c2)  # no softening yet
         assert ei.value.code == bhq.E_STATE
-        bhq.bhq_set_eps(c2, 0.0 + 1.0)
+        for bad in (0.0, -1.0):
+            with pytest.raises(bhq.BhqError) as ei:
+                bhq.bhq_set_eps(c2, bad)   # the self pair needs eps > 0
+            assert ei.value.code == bhq.E_ARG
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_set_eps2_i(c2, [1.0, 0.0])
+        assert ei.value.code == bhq.E_ARG
+        bhq.bhq_set_eps(c2, 1.0)
         bhq.bhq_compute(c2)
         a, p = bhq.bhq_get_result(c2, 2)
         # two unit masses one apart with eps = 1: |a| = 1 / 2^1.5
@@ -242,7 +249,7 @@ def test_split_kernel_periodic(ctx, nside):
     log("case split lattice %d^3 rs=%g rcut=%g" % (nside, rs, rcut))
     T = orc.Tree(x, m, 0.5, 64, box=1.0, rcut=rcut)
     mat = orc.materialise(T, x, m)
-    upload(ctx, mat, x, eps2=0.0, split=(rs, rcut, 1.0))
+    upload(ctx, mat, x, split=(rs, rcut, 1.0))
     for bk, ok in ((bhq.SPLIT_QUAD, orc.SPLIT_QUAD),
                    (bhq.SPLIT_MONO, orc.SPLIT_MONO)):
         for prec in PRECS:
@@ -304,7 +311,7 @@ def test_index_lists_split_periodic(ctx):
     T = orc.Tree(x, m, 0.5, 64, box=box, rcut=rcut)
     mat = orc.materialise(T, x, m)
     log("case index lists split lattice 24^3")
-    _upload_indexed(ctx, T, mat, x, m, eps2=0.0, split=(rs, rcut, box))
+    _upload_indexed(ctx, T, mat, x, m, split=(rs, rcut, box))
     for prec in PRECS:
         a_ref, p_ref = orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=box,
                                       rs=rs, rcut=rcut, mask=SPLIT_MASK[prec])
