@@ -341,6 +341,8 @@ def main():
                              "batched", "lattice"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--ipt", type=int, default=2,
+                    help="i-particles per thread (1 or 2)")
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--lists", default="indexed",
@@ -402,6 +404,7 @@ def main():
         tuned = r["best"]
         W["ncrit"] = tuned["ncrit"]
         args.block, args.persistent = tuned["block"], tuned["persistent"]
+        args.ipt = tuned["i_per_thread"]
         log("autotuned: %s" % tuned)
     L, t_build = build_lists(W, W["theta"], W["ncrit"])
     ng, njp, njc, _ = bhq.bhq_lists_sizes(L)
@@ -414,7 +417,7 @@ def main():
     try:
         P, t_upload = upload(ctx, W, L, indexed=(args.lists == "indexed"))
         bhq.bhq_lists_free(L)
-        bhq.bhq_set_tuning(ctx, args.block,
+        bhq.bhq_set_tuning(ctx, args.block, args.ipt,
                            tuned["blocks_per_cu"] if tuned else 0,
                            args.persistent, args.graph)
         n_pp, n_pc = bhq.bhq_get_counts(ctx)
@@ -497,7 +500,8 @@ def main():
                    "n": n, "theta": W["theta"], "ncrit": W["ncrit"],
                    "groups": ng, "n_pp": n_pp, "n_pc": n_pc,
                    "lists": args.lists, "autotuned": tuned,
-                   "launch": {"block": args.block, "persistent": args.persistent,
+                   "launch": {"block": args.block, "i_per_thread": args.ipt,
+                              "persistent": args.persistent,
                               "graph": args.graph}},
         "s_per_force_eval": round(ms_step * 1e-3, 6),
         "kernel_ms": round(ms_kern, 4), "kernel_ms_median": round(ms_kern_med, 4),

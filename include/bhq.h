@@ -104,7 +104,10 @@ int bhq_set_eps2_i(bhq_ctx *ctx, int64_t ni, const double *eps2);
 
 /* Short-range split parameters for the SPLIT kernels: r_s > 0, cutoff
  * rcut > 0; box > 0 selects a periodic cube of that side (minimum-image
- * separations), box == 0 an open boundary. */
+ * separations), box == 0 an open boundary.  The FP32 split kernels evaluate
+ * erfc for r / (2 r_s) <= 3 only, so bhq_compute returns BHQ_E_ARG for
+ * FP32 with rcut > 6 r_s (FP64 has no such limit).  In a periodic box every
+ * group cell plus 2 rcut must stay below half the box. */
 int bhq_set_split(bhq_ctx *ctx, double rs, double rcut, double box);
 
 /* Define the groups and the list sizes; must precede set_i / set_jp /
@@ -174,8 +177,9 @@ int bhq_get_counts(const bhq_ctx *ctx, int64_t *n_pp, int64_t *n_pc);
  * measured with HIP events on the compute stream.  Waits for it. */
 int bhq_get_kernel_ms(bhq_ctx *ctx, double *ms);
 
-/* Launch shape (an autotuner's knobs; results do not depend on them).
+/* Launch shape (an autotuner's knobs).
  *   block          threads per block and LDS tile depth: 128 or 256 (0: 256)
+ *   i_per_thread   i-particles owned by each thread: 1 or 2 (0: 2)
  *   blocks_per_cu  persistent grid size per compute unit (0: as many blocks
  *                  as fit), ignored when persistent == 0
  *   persistent     0: one block per group, groups dispatched longest first;
@@ -184,13 +188,16 @@ int bhq_get_kernel_ms(bhq_ctx *ctx, double *ms);
  *   use_graph      1: bhq_compute records its launches into a HIP graph once
  *                  and replays it while kernel, precision, shape and data
  *                  layout are unchanged (re-recorded otherwise)
- * Errors: BHQ_E_ARG for values outside these sets. */
-int bhq_set_tuning(bhq_ctx *ctx, int block, int blocks_per_cu, int persistent,
-                   int use_graph);
+ * The persistent queue and graph replay do not change results (bitwise).
+ * block and i_per_thread change how a group's list is split across
+ * threads and so the order of the FP32/FP64 sums (results agree to
+ * rounding).  Errors: BHQ_E_ARG for values outside these sets. */
+int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread,
+                   int blocks_per_cu, int persistent, int use_graph);
 
-/* Current launch shape: out[0..3] = block, blocks_per_cu, persistent,
- * use_graph. */
-int bhq_get_tuning(const bhq_ctx *ctx, int out[4]);
+/* Current launch shape: out[0..4] = block, i_per_thread, blocks_per_cu,
+ * persistent, use_graph. */
+int bhq_get_tuning(const bhq_ctx *ctx, int out[5]);
 
 /* Message for the last error on ctx (never NULL; "" when none).  With
  * ctx == NULL: the message of the last failed bhq_create on this thread. */

@@ -53,7 +53,7 @@ SIGNATURES = {
     "bhq_get_kernel_ms": (ctypes.c_int, [_P, _D]),
     "bhq_last_error": (ctypes.c_char_p, [_P]),
     "bhq_set_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int,
-                                      ctypes.c_int, ctypes.c_int]),
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "bhq_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
     "bhq_build_lists_batch": (ctypes.c_int, [ctypes.c_int64, _I64, _D, _D,
                                              ctypes.c_double, ctypes.c_int,
@@ -258,17 +258,18 @@ def bhq_get_kernel_ms(ctx):
     return ms.value
 
 
-def bhq_set_tuning(ctx, block=256, blocks_per_cu=0, persistent=0,
-                   use_graph=0):
-    _check(lib().bhq_set_tuning(ctx, int(block), int(blocks_per_cu),
-                                int(persistent), int(use_graph)), ctx)
+def bhq_set_tuning(ctx, block=256, i_per_thread=2, blocks_per_cu=0,
+                   persistent=0, use_graph=0):
+    _check(lib().bhq_set_tuning(ctx, int(block), int(i_per_thread),
+                                int(blocks_per_cu), int(persistent),
+                                int(use_graph)), ctx)
 
 
 def bhq_get_tuning(ctx):
-    out = (ctypes.c_int * 4)()
+    out = (ctypes.c_int * 5)()
     _check(lib().bhq_get_tuning(ctx, out), ctx)
-    return dict(block=out[0], blocks_per_cu=out[1], persistent=out[2],
-                use_graph=out[3])
+    return dict(block=out[0], i_per_thread=out[1], blocks_per_cu=out[2],
+                persistent=out[3], use_graph=out[4])
 
 
 def bhq_last_error(ctx=None):

@@ -14,6 +14,7 @@
 
 #include "bhq.h"
 #include "bhq_internal.h"
+#include "erfcx_fit.h"
 
 namespace {
 
@@ -98,7 +99,7 @@ struct bhq_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     struct {
-        int kernel, precision, block, persistent, blocks_per_cu;
+        int kernel, precision, block, i_per_thread, persistent, blocks_per_cu;
         uint64_t version;
     } graph_key{};
 
@@ -544,6 +545,11 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
                        ctx->kernel == BHQ_SPLIT_MONO;
     if (split && !ctx->have_split)
         return ctx->fail(BHQ_E_STATE, "split kernel without bhq_set_split");
+    if (split && ctx->precision == BHQ_FP32_OFS64 &&
+        ctx->rcut > 2.0 * (double)bhq::kErfcxDomain * ctx->rs)
+        return ctx->fail(BHQ_E_ARG, "FP32 split kernels need rcut <= %g rs "
+                         "(the range of their erfc evaluation); use BHQ_FP64",
+                         2.0 * (double)bhq::kErfcxDomain);
     if (!split && ctx->eps_mode == 0)
         return ctx->fail(BHQ_E_STATE, "compute before set_eps / set_eps2_i");
     TRY(ctx->select());
@@ -582,6 +588,7 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
             ctx->graph_exec && ctx->graph_key.kernel == ctx->kernel &&
             ctx->graph_key.precision == ctx->precision &&
             ctx->graph_key.block == ctx->cfg.block &&
+            ctx->graph_key.i_per_thread == ctx->cfg.i_per_thread &&
             ctx->graph_key.persistent == ctx->cfg.persistent &&
             ctx->graph_key.blocks_per_cu == ctx->cfg.blocks_per_cu &&
             ctx->graph_key.version == ctx->args_version;
@@ -611,6 +618,7 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
             ctx->graph_key.kernel = ctx->kernel;
             ctx->graph_key.precision = ctx->precision;
             ctx->graph_key.block = ctx->cfg.block;
+            ctx->graph_key.i_per_thread = ctx->cfg.i_per_thread;
             ctx->graph_key.persistent = ctx->cfg.persistent;
             ctx->graph_key.blocks_per_cu = ctx->cfg.blocks_per_cu;
             ctx->graph_key.version = ctx->args_version;
@@ -632,31 +640,36 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
     return BHQ_OK;
 }
 
-int bhq_set_tuning(bhq_ctx *ctx, int block, int blocks_per_cu, int persistent,
-                   int use_graph)
+int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread,
+                   int blocks_per_cu, int persistent, int use_graph)
 {
     CHECK_CTX(ctx);
     if (block == 0) block = 256;
+    if (i_per_thread == 0) i_per_thread = 2;
     if (block != 128 && block != 256)
         return ctx->fail(BHQ_E_ARG, "block must be 128 or 256 (or 0)");
+    if (i_per_thread != 1 && i_per_thread != 2)
+        return ctx->fail(BHQ_E_ARG, "i_per_thread must be 1 or 2 (or 0)");
     if (blocks_per_cu < 0 || blocks_per_cu > 64)
         return ctx->fail(BHQ_E_ARG, "blocks_per_cu must be in [0, 64]");
     if ((persistent != 0 && persistent != 1) || (use_graph != 0 && use_graph != 1))
         return ctx->fail(BHQ_E_ARG, "persistent and use_graph are 0 or 1");
     ctx->cfg.block = block;
+    ctx->cfg.i_per_thread = i_per_thread;
     ctx->cfg.blocks_per_cu = blocks_per_cu;
     ctx->cfg.persistent = persistent;
     ctx->use_graph = use_graph;
     return BHQ_OK;
 }
 
-int bhq_get_tuning(const bhq_ctx *ctx, int out[4])
+int bhq_get_tuning(const bhq_ctx *ctx, int out[5])
 {
     if (!ctx || !out) return BHQ_E_ARG;
     out[0] = ctx->cfg.block;
-    out[1] = ctx->cfg.blocks_per_cu;
-    out[2] = ctx->cfg.persistent;
-    out[3] = ctx->use_graph;
+    out[1] = ctx->cfg.i_per_thread;
+    out[2] = ctx->cfg.blocks_per_cu;
+    out[3] = ctx->cfg.persistent;
+    out[4] = ctx->use_graph;
     return BHQ_OK;
 }
 

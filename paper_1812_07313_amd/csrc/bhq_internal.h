@@ -47,11 +47,13 @@ struct ForceArgs {
 };
 
 // Launch shape.  block: threads per block (128 or 256), which is also the
-// depth of one LDS tile; persistent: one grid of blocks_per_cu * num_cu
+// depth of one LDS tile; i_per_thread: i-particles per thread (1 or 2);
+// persistent: one grid of blocks_per_cu * num_cu
 // blocks pulling groups from ForceArgs::queue (blocks_per_cu <= 0: as many
 // as fit), otherwise one block per group.
 struct LaunchCfg {
     int block = 256;
+    int i_per_thread = 2;  // i-particles owned by each thread: 1 or 2
     int persistent = 0;
     int blocks_per_cu = 0;
     int num_cu = 0;

@@ -1,8 +1,9 @@
 // bhq_kernels.hip -- force kernels for gfx950 (CDNA4).
 //
-// One 256-thread block evaluates one group's interaction list (the modified
-// tree algorithm of Kodama & Ishiyama, Sec. 3.4: all i-particles of a group
-// share one list).  Each active thread owns one i-particle.  The list is
+// One block (256 or 128 threads) evaluates one group's interaction list (the
+// modified tree algorithm of Kodama & Ishiyama, Sec. 3.4: all i-particles of
+// a group share one list).  Each active thread owns one or two i-particles
+// (two: every LDS broadcast feeds two interactions).  The list is
 // streamed through LDS in tiles of up to 256 entries: every thread loads one
 // entry with coalesced FP64 SoA reads, forms its position relative to the
 // group's FP64 reference point, converts it to the working precision and
@@ -33,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bhq_internal.h"
+#include "erfcx_fit.h"
 
 namespace bhq {
 
@@ -46,9 +48,7 @@ struct alignas(4 * sizeof(R)) V4 {
 __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ double rsq(double v) { return ::rsqrt(v); }
 
-__device__ __forceinline__ float erfc_r(float v) { return ::erfcf(v); }
 __device__ __forceinline__ double erfc_r(double v) { return ::erfc(v); }
-__device__ __forceinline__ float exp_r(float v) { return ::expf(v); }
 __device__ __forceinline__ double exp_r(double v) { return ::exp(v); }
 
 __device__ __forceinline__ double wrap(double v, double box, double ibox)
@@ -122,6 +122,35 @@ __device__ __forceinline__ SplitF<R> split_f(R r, R i2rs)
     f.g = fma(R(2) * u, e, f.ec);
     f.h = R(4) * u * u2 * e;
     f.k = R(2) * u2 * f.h;
+    return f;
+}
+
+// FP32: exp(-u^2) from the hardware base-2 exponential, with the rounding
+// error of the product u^2 * log2(e) fed back to first order, and
+// erfc(u) = exp(-u^2) erfcx(u) with erfcx from a fitted polynomial
+// (erfcx_fit.h, valid for u <= kErfcxDomain; the host refuses FP32 split
+// kernels whose cutoff reaches beyond it).
+template <>
+__device__ __forceinline__ SplitF<float> split_f<float>(float r, float i2rs)
+{
+    constexpr float kLog2e = 1.4426950408889634f;
+    constexpr float kLn2 = 0.6931471805599453f;
+    constexpr float k2rsqpi = 1.1283791670955126f;  // 2 / sqrt(pi)
+    const float u = r * i2rs;
+    const float u2 = u * u;
+    const float a = u2 * -kLog2e;
+    const float da = fmaf(u2, -kLog2e, -a);
+    float E = __builtin_amdgcn_exp2f(a);
+    E = fmaf(E, da * kLn2, E);
+    const float s = fmaf(u, 2.0f / kErfcxDomain, -1.0f);
+    float X = kErfcxCoef[kErfcxDegree];
+#pragma unroll
+    for (int k = kErfcxDegree - 1; k >= 0; --k) X = fmaf(X, s, kErfcxCoef[k]);
+    SplitF<float> f;
+    f.ec = E * X;
+    f.g = E * fmaf(u, k2rsqpi, X);
+    f.h = (2.0f * k2rsqpi) * u * u2 * E;
+    f.k = 2.0f * u2 * f.h;
     return f;
 }
 
@@ -216,13 +245,13 @@ struct Smem {
     static constexpr bool kCellQ = (KIND == kQuad || KIND == kSplitQuad);
 };
 
-// Evaluate group g with a block of BS threads; sa, sb, sc are LDS tiles of
-// BS entries (sb, sc only for the quadrupole kinds).
-template <typename R, int KIND, bool PERIODIC, int BS>
+// Evaluate group g with a block of BS threads, each owning IB i-particles;
+// sa, sb, sc are LDS tiles of BS entries (sb, sc only for the quadrupole
+// kinds).
+template <typename R, int KIND, bool PERIODIC, int BS, int IB>
 __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                                               V4<R> *sa, V4<R> *sb, V4<R> *sc)
 {
-    constexpr int kBlock = BS;
     constexpr bool kSplit = (KIND == kSplitQuad || KIND == kSplitMono);
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
     const int t = threadIdx.x;
@@ -240,25 +269,38 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
         return PERIODIC ? R(wrap(v - c, box, ibox)) : R(v - c);
     };
 
-    for (int64_t ib = 0; ib < ni; ib += kBlock) {
-        // Slices: S groups of nic threads; a tile holds T = S * floor(256/S)
-        // entries and slice s takes the contiguous chunk [s*it, (s+1)*it).
-        const int nic = (int)(ni - ib < kBlock ? ni - ib : kBlock);
-        const int S = kBlock / nic;
-        const int T = S * (kBlock / S);
-        const int slice = t / nic;
-        const int islot = t - slice * nic;
+    for (int64_t ib = 0; ib < ni; ib += (int64_t)BS * IB) {
+        // nic i-particles in this pass, P threads per slice owning IB each
+        // (thread islot owns islot, islot + P, ...).  S slices; a tile holds
+        // T = S * floor(BS / S) entries and slice s takes the contiguous
+        // chunk [s*it, (s+1)*it) of it.
+        const int nic = (int)(ni - ib < (int64_t)BS * IB ? ni - ib : BS * IB);
+        const int P = (nic + IB - 1) / IB;
+        const int S = BS / P;
+        const int T = S * (BS / S);
+        const int slice = t / P;
+        const int islot = t - slice * P;
         const bool active = slice < S;
 
-        R xi = R(0), yi = R(0), zi = R(0), e2 = R(1);
-        if (active) {
-            const int64_t i = i0 + ib + islot;
-            xi = rel(A.xi[i], cx);
-            yi = rel(A.yi[i], cy);
-            zi = rel(A.zi[i], cz);
-            e2 = R(A.e2i[i]);
+        R xi[IB], yi[IB], zi[IB], e2[IB];
+#pragma unroll
+        for (int u = 0; u < IB; ++u) {
+            // an i-slot past the end repeats a valid particle; its sums are
+            // computed but never written
+            const int li = islot + u * P < nic ? islot + u * P : islot;
+            xi[u] = yi[u] = zi[u] = R(0);
+            e2[u] = R(1);
+            if (active) {
+                const int64_t i = i0 + ib + li;
+                xi[u] = rel(A.xi[i], cx);
+                yi[u] = rel(A.yi[i], cy);
+                zi[u] = rel(A.zi[i], cz);
+                e2[u] = R(A.e2i[i]);
+            }
         }
-        R ax = R(0), ay = R(0), az = R(0), pt = R(0);
+        R ax[IB], ay[IB], az[IB], pt[IB];
+#pragma unroll
+        for (int u = 0; u < IB; ++u) ax[u] = ay[u] = az[u] = pt[u] = R(0);
 
         // j-particles
         for (int64_t base = 0; base < np; base += T) {
@@ -270,11 +312,11 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                 if (t < cnt) {
                     const int64_t j = p0 + base + t;
                     if (indexed) {
-                        const PartRec P = A.pool_p[A.jp_idx[j]];
-                        v.x = rel(P.x, cx);
-                        v.y = rel(P.y, cy);
-                        v.z = rel(P.z, cz);
-                        v.w = R(P.m);
+                        const PartRec Pj = A.pool_p[A.jp_idx[j]];
+                        v.x = rel(Pj.x, cx);
+                        v.y = rel(Pj.y, cy);
+                        v.z = rel(Pj.z, cz);
+                        v.w = R(Pj.m);
                     } else {
                         v.x = rel(A.jpx[j], cx);
                         v.y = rel(A.jpy[j], cy);
@@ -289,19 +331,30 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
             }
             __syncthreads();
             if (active) {
-                R bx = R(0), by = R(0), bz = R(0), bp = R(0);
+                R bx[IB], by[IB], bz[IB], bp[IB];
+#pragma unroll
+                for (int u = 0; u < IB; ++u) bx[u] = by[u] = bz[u] = bp[u] = R(0);
                 const V4<R> *pa = sa + slice * it;
 #pragma unroll BHQ_UNROLL
                 for (int k = 0; k < it; ++k) {
-                    if (kSplit)
-                        pp_split(pa[k], xi, yi, zi, i2rs, rcut2, bx, by, bz, bp);
-                    else
-                        pp_plummer(pa[k], xi, yi, zi, e2, bx, by, bz, bp);
+                    const V4<R> jv = pa[k];
+#pragma unroll
+                    for (int u = 0; u < IB; ++u) {
+                        if (kSplit)
+                            pp_split(jv, xi[u], yi[u], zi[u], i2rs, rcut2, bx[u],
+                                     by[u], bz[u], bp[u]);
+                        else
+                            pp_plummer(jv, xi[u], yi[u], zi[u], e2[u], bx[u],
+                                       by[u], bz[u], bp[u]);
+                    }
                 }
-                ax += bx;
-                ay += by;
-                az += bz;
-                pt += bp;
+#pragma unroll
+                for (int u = 0; u < IB; ++u) {
+                    ax[u] += bx[u];
+                    ay[u] += by[u];
+                    az[u] += bz[u];
+                    pt[u] += bp[u];
+                }
             }
         }
 
@@ -360,60 +413,81 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
             }
             __syncthreads();
             if (active) {
-                R bx = R(0), by = R(0), bz = R(0), bp = R(0);
+                R bx[IB], by[IB], bz[IB], bp[IB];
+#pragma unroll
+                for (int u = 0; u < IB; ++u) bx[u] = by[u] = bz[u] = bp[u] = R(0);
                 const int e0 = slice * it;
 #pragma unroll BHQ_UNROLL
                 for (int k = 0; k < it; ++k) {
                     const int e = e0 + k;
-                    if (KIND == kQuad)
-                        pc_quad(sa[e], sb[e], sc[e], xi, yi, zi, e2, bx, by, bz,
-                                bp);
-                    else if (KIND == kMono)
-                        pp_plummer(sa[e], xi, yi, zi, e2, bx, by, bz, bp);
-                    else if (KIND == kSplitQuad)
-                        pc_split<R, true>(sa[e], sb[e], sc[e], xi, yi, zi, i2rs,
-                                          rcut2, bx, by, bz, bp);
-                    else
-                        pc_split<R, false>(sa[e], sb[e], sc[e], xi, yi, zi,
-                                           i2rs, rcut2, bx, by, bz, bp);
+                    const V4<R> ja = sa[e];
+                    V4<R> jb, jc;
+                    if (kCellQ) {
+                        jb = sb[e];
+                        jc = sc[e];
+                    }
+#pragma unroll
+                    for (int u = 0; u < IB; ++u) {
+                        if (KIND == kQuad)
+                            pc_quad(ja, jb, jc, xi[u], yi[u], zi[u], e2[u], bx[u],
+                                    by[u], bz[u], bp[u]);
+                        else if (KIND == kMono)
+                            pp_plummer(ja, xi[u], yi[u], zi[u], e2[u], bx[u],
+                                       by[u], bz[u], bp[u]);
+                        else if (KIND == kSplitQuad)
+                            pc_split<R, true>(ja, jb, jc, xi[u], yi[u], zi[u],
+                                              i2rs, rcut2, bx[u], by[u], bz[u],
+                                              bp[u]);
+                        else
+                            pc_split<R, false>(ja, jb, jc, xi[u], yi[u], zi[u],
+                                               i2rs, rcut2, bx[u], by[u], bz[u],
+                                               bp[u]);
+                    }
                 }
-                ax += bx;
-                ay += by;
-                az += bz;
-                pt += bp;
+#pragma unroll
+                for (int u = 0; u < IB; ++u) {
+                    ax[u] += bx[u];
+                    ay[u] += by[u];
+                    az[u] += bz[u];
+                    pt[u] += bp[u];
+                }
             }
         }
 
-        // combine the slices in a fixed order
-        __syncthreads();
-        if (active) {
-            V4<R> v;
-            v.x = ax;
-            v.y = ay;
-            v.z = az;
-            v.w = pt;
-            sa[t] = v;
-        }
-        __syncthreads();
-        if (t < nic) {
-            R sx = R(0), sy = R(0), sz = R(0), sp = R(0);
-            for (int s = 0; s < S; ++s) {
-                const V4<R> v = sa[s * nic + t];
-                sx += v.x;
-                sy += v.y;
-                sz += v.z;
-                sp += v.w;
+        // combine the slices in a fixed order, one owned i-slot at a time
+#pragma unroll
+        for (int u = 0; u < IB; ++u) {
+            __syncthreads();
+            if (active) {
+                V4<R> v;
+                v.x = ax[u];
+                v.y = ay[u];
+                v.z = az[u];
+                v.w = pt[u];
+                sa[t] = v;
             }
-            const int64_t i = i0 + ib + t;
-            A.ax[i] = (double)sx;
-            A.ay[i] = (double)sy;
-            A.az[i] = (double)sz;
-            A.pot[i] = -(double)sp;
+            __syncthreads();
+            const int li = t + u * P;
+            if (t < P && li < nic) {
+                R sx = R(0), sy = R(0), sz = R(0), sp = R(0);
+                for (int s = 0; s < S; ++s) {
+                    const V4<R> v = sa[s * P + t];
+                    sx += v.x;
+                    sy += v.y;
+                    sz += v.z;
+                    sp += v.w;
+                }
+                const int64_t i = i0 + ib + li;
+                A.ax[i] = (double)sx;
+                A.ay[i] = (double)sy;
+                A.az[i] = (double)sz;
+                A.pot[i] = -(double)sp;
+            }
         }
     }
 }
 
-template <typename R, int KIND, bool PERIODIC, int BS>
+template <typename R, int KIND, bool PERIODIC, int BS, int IB>
 __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel(const ForceArgs A)
 {
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
@@ -421,13 +495,13 @@ __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel(const ForceArgs
     __shared__ V4<R> sb[kCellQ ? BS : 1];
     __shared__ V4<R> sc[kCellQ ? BS : 1];
     const int64_t g = A.order ? A.order[blockIdx.x] : (int64_t)blockIdx.x;
-    process_group<R, KIND, PERIODIC, BS>(A, g, sa, sb, sc);
+    process_group<R, KIND, PERIODIC, BS, IB>(A, g, sa, sb, sc);
 }
 
 // Persistent variant: a grid sized to the machine pulls groups, in the
 // order of A.order, from the counter A.queue (zeroed before the launch).
 // Every block leaves the loop once the counter has passed ng.
-template <typename R, int KIND, bool PERIODIC, int BS>
+template <typename R, int KIND, bool PERIODIC, int BS, int IB>
 __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(const ForceArgs A)
 {
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
@@ -442,7 +516,7 @@ __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(cons
         __syncthreads();
         if (k >= A.ng) break;
         const int64_t g = A.order ? A.order[k] : k;
-        process_group<R, KIND, PERIODIC, BS>(A, g, sa, sb, sc);
+        process_group<R, KIND, PERIODIC, BS, IB>(A, g, sa, sb, sc);
     }
 }
 
@@ -451,7 +525,7 @@ __global__ void reset_queue(unsigned int *q)
     if (threadIdx.x == 0 && blockIdx.x == 0) q[0] = 0u;
 }
 
-template <typename R, int KIND, bool P, int BS>
+template <typename R, int KIND, bool P, int BS, int IB>
 hipError_t launch_one(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
 {
     if (cfg.persistent) {
@@ -461,17 +535,17 @@ hipError_t launch_one(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
         int per_cu = cfg.blocks_per_cu;
         if (per_cu <= 0) {
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, force_kernel_persistent<R, KIND, P, BS>, BS, 0);
+                &per_cu, force_kernel_persistent<R, KIND, P, BS, IB>, BS, 0);
             if (e != hipSuccess) return e;
             if (per_cu < 1) per_cu = 1;
         }
         const int64_t want = (int64_t)per_cu * cfg.num_cu;
         const unsigned grid = (unsigned)(want < A.ng ? want : A.ng);
-        hipLaunchKernelGGL((force_kernel_persistent<R, KIND, P, BS>), dim3(grid),
-                           dim3(BS), 0, s, A);
+        hipLaunchKernelGGL((force_kernel_persistent<R, KIND, P, BS, IB>),
+                           dim3(grid), dim3(BS), 0, s, A);
     } else {
-        hipLaunchKernelGGL((force_kernel<R, KIND, P, BS>), dim3((unsigned)A.ng),
-                           dim3(BS), 0, s, A);
+        hipLaunchKernelGGL((force_kernel<R, KIND, P, BS, IB>),
+                           dim3((unsigned)A.ng), dim3(BS), 0, s, A);
     }
     return hipGetLastError();
 }
@@ -479,8 +553,11 @@ hipError_t launch_one(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
 template <typename R, int KIND, bool P>
 hipError_t launch_bs(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
 {
-    return cfg.block == 128 ? launch_one<R, KIND, P, 128>(A, cfg, s)
-                            : launch_one<R, KIND, P, 256>(A, cfg, s);
+    if (cfg.i_per_thread == 2)
+        return cfg.block == 128 ? launch_one<R, KIND, P, 128, 2>(A, cfg, s)
+                                : launch_one<R, KIND, P, 256, 2>(A, cfg, s);
+    return cfg.block == 128 ? launch_one<R, KIND, P, 128, 1>(A, cfg, s)
+                            : launch_one<R, KIND, P, 256, 1>(A, cfg, s);
 }
 
 template <typename R>
@@ -513,6 +590,7 @@ hipError_t launch_force(int kernel, int precision, const ForceArgs &A,
     if (A.ng <= 0) return hipSuccess;
     if (A.ng > 0x7fffffff) return hipErrorInvalidValue;
     if (cfg.block != 128 && cfg.block != 256) return hipErrorInvalidValue;
+    if (cfg.i_per_thread != 1 && cfg.i_per_thread != 2) return hipErrorInvalidValue;
     if (cfg.persistent && (!A.queue || cfg.num_cu <= 0))
         return hipErrorInvalidValue;
     return precision == 1 ? launch_prec<double>(kernel, A, cfg, stream)

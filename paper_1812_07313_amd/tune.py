@@ -20,8 +20,9 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bhq",
                              "tune.json")
 
 NCRITS = (64, 128, 256)
-SHAPES = ((256, 0, 0), (128, 0, 0), (256, 0, 1), (128, 0, 1), (256, 2, 1),
-          (128, 4, 1))
+# (block, i_per_thread, blocks_per_cu, persistent)
+SHAPES = ((256, 1, 0, 0), (256, 2, 0, 0), (128, 1, 0, 0), (128, 2, 0, 0),
+          (256, 1, 0, 1), (256, 2, 0, 1), (128, 2, 4, 1))
 
 
 def _load(path):
@@ -47,14 +48,15 @@ def cache_key(arch, workload, kernel, precision, theta):
 
 
 def search(measure, ncrits=NCRITS, shapes=SHAPES):
-    """Exhaustive search.  measure(ncrit, block, blocks_per_cu, persistent)
-    returns seconds per evaluation.  Returns (best, table)."""
+    """Exhaustive search.  measure(ncrit, block, i_per_thread,
+    blocks_per_cu, persistent) returns seconds per evaluation.  Returns
+    (best, table)."""
     table = []
     for nc in ncrits:
-        for block, bpc, pers in shapes:
-            t = measure(nc, block, bpc, pers)
-            table.append(dict(ncrit=nc, block=block, blocks_per_cu=bpc,
-                              persistent=pers, seconds=t))
+        for block, ipt, bpc, pers in shapes:
+            t = measure(nc, block, ipt, bpc, pers)
+            table.append(dict(ncrit=nc, block=block, i_per_thread=ipt,
+                              blocks_per_cu=bpc, persistent=pers, seconds=t))
     best = min(table, key=lambda r: r["seconds"])
     return dict(best), table
 
@@ -67,7 +69,7 @@ def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
     (median of `repeats` launches after one warm-up)."""
     state = {"ncrit": None}
 
-    def measure(ncrit, block, bpc, pers):
+    def measure(ncrit, block, ipt, bpc, pers):
         if state["ncrit"] != ncrit:
             if sys_off is not None:
                 L = bhq.bhq_build_lists_batch(sys_off, x, m, theta, ncrit,
@@ -91,7 +93,7 @@ def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
                 bhq.bhq_set_split(ctx, rs, rcut, box)
             state["ncrit"] = ncrit
         bhq.bhq_set_kernel(ctx, kernel, precision)
-        bhq.bhq_set_tuning(ctx, block, bpc, pers, 0)
+        bhq.bhq_set_tuning(ctx, block, ipt, bpc, pers, 0)
         bhq.bhq_compute(ctx, stream)
         bhq.bhq_get_kernel_ms(ctx)
         ts = []
@@ -114,14 +116,14 @@ def autotune(ctx, x, m, theta, workload, arch="gfx950", kernel=bhq.QUAD,
                           **kw)
     if not force and key in db:
         best = db[key]["best"]
-        measure(best["ncrit"], best["block"], best["blocks_per_cu"],
-                best["persistent"])
+        measure(best["ncrit"], best["block"], best["i_per_thread"],
+                best["blocks_per_cu"], best["persistent"])
         return dict(best=best, table=db[key]["table"], cached=True)
     t0 = time.perf_counter()
     best, table = search(measure, ncrits, shapes)
     db = _load(cache)
     db[key] = dict(best=best, table=table, seconds_spent=time.perf_counter() - t0)
     _store(cache, db)
-    measure(best["ncrit"], best["block"], best["blocks_per_cu"],
-            best["persistent"])
+    measure(best["ncrit"], best["block"], best["i_per_thread"],
+            best["blocks_per_cu"], best["persistent"])
     return dict(best=best, table=table, cached=False)

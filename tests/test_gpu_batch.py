@@ -34,25 +34,27 @@ def test_launch_shapes(ctx, cube_case):
     x, m, mat, (a_ref, p_ref) = cube_case
     upload(ctx, mat, x, eps2=1e-6)
     for prec in PRECS:
-        base = {}
         for block in (256, 128):
-            bhq.bhq_set_tuning(ctx, block, 0, 0, 0)
-            log("case shapes block=%d precision=%s" % (block,
-                                                      bhq.PRECISION_NAMES[prec]))
-            a0, p0 = run(ctx, mat, len(m), bhq.QUAD, prec)
-            assert_parity(errors(a0, p0, a_ref, p_ref), prec, "block %d" % block)
-            base[block] = (a0, p0)
-            for bpc in (0, 1, 3):
-                log("  persistent blocks_per_cu=%d" % bpc)
-                bhq.bhq_set_tuning(ctx, block, bpc, 1, 0)
-                a1, p1 = run(ctx, mat, len(m), bhq.QUAD, prec)
-                assert np.array_equal(a0, a1) and np.array_equal(p0, p1)
-        assert bhq.bhq_get_tuning(ctx)["persistent"] == 1
-    bhq.bhq_set_tuning(ctx, 256, 0, 0, 0)
+            for ipt in (1, 2):
+                bhq.bhq_set_tuning(ctx, block, ipt)
+                log("case shapes block=%d i_per_thread=%d precision=%s"
+                    % (block, ipt, bhq.PRECISION_NAMES[prec]))
+                a0, p0 = run(ctx, mat, len(m), bhq.QUAD, prec)
+                assert_parity(errors(a0, p0, a_ref, p_ref), prec,
+                              "block %d ipt %d" % (block, ipt))
+                for bpc in (0, 1, 3):
+                    log("  persistent blocks_per_cu=%d" % bpc)
+                    bhq.bhq_set_tuning(ctx, block, ipt, bpc, 1)
+                    a1, p1 = run(ctx, mat, len(m), bhq.QUAD, prec)
+                    assert np.array_equal(a0, a1) and np.array_equal(p0, p1)
+        t = bhq.bhq_get_tuning(ctx)
+        assert t["persistent"] == 1 and t["i_per_thread"] == 2
+    bhq.bhq_set_tuning(ctx)
 
 
 def test_tuning_argument_errors(ctx):
-    for args in ((64, 0, 0, 0), (256, -1, 0, 0), (256, 0, 2, 0), (256, 0, 0, 3)):
+    for args in ((64, 1, 0, 0, 0), (256, 3, 0, 0, 0), (256, 1, -1, 0, 0),
+                 (256, 1, 0, 2, 0), (256, 1, 0, 0, 3)):
         with pytest.raises(bhq.BhqError) as ei:
             bhq.bhq_set_tuning(ctx, *args)
         assert ei.value.code == bhq.E_ARG
@@ -65,9 +67,9 @@ def test_graph_replays_match_eager(ctx, cube_case):
     x, m, mat, (a_ref, p_ref) = cube_case
     upload(ctx, mat, x, eps2=1e-6)
     for persistent in (0, 1):
-        bhq.bhq_set_tuning(ctx, 256, 0, persistent, 0)
+        bhq.bhq_set_tuning(ctx, 256, 1, 0, persistent, 0)
         a_e, p_e = run(ctx, mat, len(m), bhq.QUAD, bhq.FP32_OFS64)
-        bhq.bhq_set_tuning(ctx, 256, 0, persistent, 1)
+        bhq.bhq_set_tuning(ctx, 256, 1, 0, persistent, 1)
         for rep in range(4):
             log("case graph persistent=%d replay %d" % (persistent, rep))
             a, p = run(ctx, mat, len(m), bhq.QUAD, bhq.FP32_OFS64)
@@ -84,7 +86,7 @@ def test_graph_replays_match_eager(ctx, cube_case):
     for rep in range(2):
         a, p = run(ctx, mat2, len(m2), bhq.QUAD, bhq.FP32_OFS64)
         assert_parity(errors(a, p, a_ref2, p_ref2), bhq.FP32_OFS64, "graph new data")
-    bhq.bhq_set_tuning(ctx, 256, 0, 0, 0)
+    bhq.bhq_set_tuning(ctx)
 
 
 @pytest.mark.parametrize("persistent", [0, 1])
@@ -115,7 +117,7 @@ def test_batched_systems_one_launch(ctx, persistent):
     finally:
         bhq.bhq_lists_free(L)
     bhq.bhq_set_eps2_i(ctx, E2[idx])
-    bhq.bhq_set_tuning(ctx, 256, 0, persistent, 1)
+    bhq.bhq_set_tuning(ctx, 256, 2, 0, persistent, 1)
     for prec in PRECS:
         bhq.bhq_set_kernel(ctx, bhq.QUAD, prec)
         bhq.bhq_compute(ctx)
@@ -127,4 +129,4 @@ def test_batched_systems_one_launch(ctx, persistent):
         err = errors(a, p, a_ref, p_ref)
         log("  precision=%s %s" % (bhq.PRECISION_NAMES[prec], err))
         assert_parity(err, prec, "batched")
-    bhq.bhq_set_tuning(ctx, 256, 0, 0, 0)
+    bhq.bhq_set_tuning(ctx)

@@ -304,6 +304,23 @@ def test_index_lists_equal_materialised(ctx):
     assert_parity(errors(a, p, a_ref, p_ref), bhq.FP32_OFS64, "indexed")
 
 
+def test_split_fp32_cutoff_range(ctx):
+    """FP32 split kernels evaluate erfc for r / 2r_s <= 3 only: a cutoff
+    beyond 6 r_s is refused for FP32 and accepted for FP64."""
+    x, m = synth.perturbed_lattice(8, synth.rng(4))
+    T = orc.Tree(x, m, 0.5, 64, box=1.0, rcut=0.3)
+    mat = orc.materialise(T, x, m)
+    upload(ctx, mat, x, split=(0.04, 0.3, 1.0))   # rcut = 7.5 rs
+    bhq.bhq_set_kernel(ctx, bhq.SPLIT_QUAD, bhq.FP32_OFS64)
+    with pytest.raises(bhq.BhqError) as ei:
+        bhq.bhq_compute(ctx)
+    assert ei.value.code == bhq.E_ARG
+    a_ref, p_ref = orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=1.0, rs=0.04,
+                                  rcut=0.3, mask=orc.MASK_F64_OFS)
+    a, p = run(ctx, mat, len(m), bhq.SPLIT_QUAD, bhq.FP64)
+    assert_parity(errors(a, p, a_ref, p_ref), bhq.FP64, "split fp64 wide cutoff")
+
+
 def test_index_lists_split_periodic(ctx):
     x, m = synth.perturbed_lattice(24, synth.rng(4))
     rs, box = 1.25 / 24, 1.0
