@@ -329,6 +329,9 @@ def cpu_baseline(W, a_gpu):
                                    "max": float(e.max())}}
 
 
+ORDERS = {"xcd": bhq.ORDER_XCD, "cost": bhq.ORDER_COST}
+
+
 # --- main -------------------------------------------------------------------------
 
 def main():
@@ -345,6 +348,15 @@ def main():
                     help="i-particles per thread (1 or 2)")
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--order", default="xcd", choices=["xcd", "cost"],
+                    help="group dispatch order: contiguous pieces of equal "
+                         "cost per XCD (windows sorted longest first), or "
+                         "every group longest first")
+    ap.add_argument("--order-window", type=int, default=bhq.ORDER_WINDOW,
+                    help="window of the xcd order")
+    ap.add_argument("--order-tail", type=int, default=bhq.ORDER_TAIL,
+                    help="groups at the end of each XCD's piece sorted as one "
+                         "window")
     ap.add_argument("--lists", default="indexed",
                     choices=["materialised", "indexed"],
                     help="list upload mode: index lists into shared particle "
@@ -405,6 +417,7 @@ def main():
         W["ncrit"] = tuned["ncrit"]
         args.block, args.persistent = tuned["block"], tuned["persistent"]
         args.ipt = tuned["i_per_thread"]
+        args.order = {v: k for k, v in ORDERS.items()}[tuned["order"]]
         log("autotuned: %s" % tuned)
     L, t_build = build_lists(W, W["theta"], W["ncrit"])
     ng, njp, njc, _ = bhq.bhq_lists_sizes(L)
@@ -420,6 +433,8 @@ def main():
         bhq.bhq_set_tuning(ctx, args.block, args.ipt,
                            tuned["blocks_per_cu"] if tuned else 0,
                            args.persistent, args.graph)
+        bhq.bhq_set_group_order(ctx, ORDERS[args.order], args.order_window,
+                                args.order_tail)
         n_pp, n_pc = bhq.bhq_get_counts(ctx)
         n_int = n_pp + n_pc
 
@@ -502,7 +517,9 @@ def main():
                    "lists": args.lists, "autotuned": tuned,
                    "launch": {"block": args.block, "i_per_thread": args.ipt,
                               "persistent": args.persistent,
-                              "graph": args.graph}},
+                              "graph": args.graph, "order": args.order,
+                              "order_window": args.order_window,
+                              "order_tail": args.order_tail}},
         "s_per_force_eval": round(ms_step * 1e-3, 6),
         "kernel_ms": round(ms_kern, 4), "kernel_ms_median": round(ms_kern_med, 4),
         "pc_Ginteractions_per_s": round(n_pc / (ms_kern * 1e-3) / 1e9, 3),

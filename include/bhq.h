@@ -76,6 +76,13 @@ typedef struct bhq_lists bhq_lists;
 #define BHQ_FP32_OFS64 0
 #define BHQ_FP64 1
 
+/* Group dispatch orders (bhq_set_group_order, bhq_plan_order). */
+#define BHQ_ORDER_COST 0   /* all groups, most expensive first            */
+#define BHQ_ORDER_XCD 1    /* pieces of space per XCD, see below          */
+#define BHQ_ORDER_WINDOW 256   /* default window of BHQ_ORDER_XCD          */
+#define BHQ_ORDER_TAIL 1024    /* default tail of BHQ_ORDER_XCD            */
+#define BHQ_XCDS 8 /* accelerator complex dies (own L2 each) of one gfx950 */
+
 /* Create a context on HIP device `device` for the given kernel and
  * precision.  *out receives the context (NULL on failure).
  * Errors: BHQ_E_ARG (null out, bad enum), BHQ_E_NODEV (no GPU, or device
@@ -182,9 +189,9 @@ int bhq_get_kernel_ms(bhq_ctx *ctx, double *ms);
  *   i_per_thread   i-particles owned by each thread: 1 or 2 (0: 2)
  *   blocks_per_cu  persistent grid size per compute unit (0: as many blocks
  *                  as fit), ignored when persistent == 0
- *   persistent     0: one block per group, groups dispatched longest first;
- *                  1: a machine-sized grid pulls groups (longest first) from
- *                  a device counter
+ *   persistent     0: one block per launch slot of the group order
+ *                  (bhq_set_group_order); 1: a machine-sized grid pulls
+ *                  groups in that order from device counters
  *   use_graph      1: bhq_compute records its launches into a HIP graph once
  *                  and replays it while kernel, precision, shape and data
  *                  layout are unchanged (re-recorded otherwise)
@@ -198,6 +205,50 @@ int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread,
 /* Current launch shape: out[0..4] = block, i_per_thread, blocks_per_cu,
  * persistent, use_graph. */
 int bhq_get_tuning(const bhq_ctx *ctx, int out[5]);
+
+/* Order in which groups are handed to blocks.  Group g costs
+ * c_g = ni_g (njp_g + 2.65 njc_g + 1) (a cell term costs about 53/20 of a
+ * particle term; the 1 stands for loading and storing the i-particles).
+ *   BHQ_ORDER_COST  every group sorted by c_g, largest first (longest
+ *                   processing time first: the last blocks are short).
+ *   BHQ_ORDER_XCD   the groups, in the order the lists give them (the host
+ *                   builder's depth-first order keeps neighbours in space
+ *                   together), are cut into BHQ_XCDS contiguous pieces of
+ *                   equal total cost.  The last `tail` groups of a piece
+ *                   form one window, the groups before them windows of
+ *                   `window` consecutive groups; each window is sorted by
+ *                   c_g, largest first.  Slot b of the launch takes entry
+ *                   b / BHQ_XCDS of piece b % BHQ_XCDS (shorter pieces are
+ *                   padded with empty slots): gfx950 hands the blocks of a
+ *                   grid to its XCDs round robin, so each piece runs on one
+ *                   XCD, and the groups resident together there are
+ *                   neighbours that share most list entries in that XCD's
+ *                   L2.  The persistent kernel reads its XCD id and drains
+ *                   that XCD's piece first, then the others'.  The sorted
+ *                   tail keeps the last blocks of each XCD short.
+ * The order never changes results (bitwise).  Default: BHQ_ORDER_XCD,
+ * window BHQ_ORDER_WINDOW, tail BHQ_ORDER_TAIL.  Applies to the current
+ * groups at once (when set) and to later bhq_set_groups calls.
+ * Errors: BHQ_E_ARG (mode not 0 or 1, window outside [1, 2^24], tail
+ * outside [0, 2^24]); BHQ_E_NOMEM / BHQ_E_HIP while uploading the table,
+ * after which the groups must be set again. */
+int bhq_set_group_order(bhq_ctx *ctx, int mode, int window, int tail);
+
+/* Current group order: out[0..2] = mode, window, tail. */
+int bhq_get_group_order(const bhq_ctx *ctx, int out[3]);
+
+/* The slot table of a dispatch order, computed on the host for offsets
+ * i_off, jp_off, jc_off of ng >= 1 groups (as bhq_set_groups takes them),
+ * with xcds in [1, 64] pieces: order[b] is the group of launch slot b, or
+ * -1 for an empty slot.  BHQ_ORDER_COST gives ng slots; BHQ_ORDER_XCD
+ * gives xcds * (the longest piece) slots, at most xcds * ng.  order may be
+ * NULL to query *nslots; otherwise it holds cap entries.
+ * Errors: BHQ_E_ARG (null pointer, ng, mode, window, tail or xcds out of
+ * range), BHQ_E_RANGE (offsets not starting at 0 or not monotone, cap too
+ * small), BHQ_E_NOMEM. */
+int bhq_plan_order(int64_t ng, const int64_t *i_off, const int64_t *jp_off,
+                   const int64_t *jc_off, int mode, int window, int tail,
+                   int xcds, int32_t *order, int64_t cap, int64_t *nslots);
 
 /* Message for the last error on ctx (never NULL; "" when none).  With
  * ctx == NULL: the message of the last failed bhq_create on this thread. */

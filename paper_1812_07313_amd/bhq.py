@@ -13,6 +13,9 @@ import numpy as np
 
 MONO, QUAD, SPLIT_QUAD, SPLIT_MONO = 0, 1, 2, 3
 FP32_OFS64, FP64 = 0, 1
+ORDER_COST, ORDER_XCD = 0, 1
+ORDER_WINDOW, ORDER_TAIL = 256, 1024
+XCDS = 8
 
 OK = 0
 E_ARG, E_RANGE, E_NODEV, E_HIP, E_NOMEM, E_STATE, E_NONFINITE = (
@@ -55,6 +58,13 @@ SIGNATURES = {
     "bhq_set_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "bhq_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
+    "bhq_set_group_order": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int]),
+    "bhq_get_group_order": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
+    "bhq_plan_order": (ctypes.c_int, [ctypes.c_int64, _I64, _I64, _I64,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, _I32, ctypes.c_int64,
+                                      _I64]),
     "bhq_build_lists_batch": (ctypes.c_int, [ctypes.c_int64, _I64, _D, _D,
                                              ctypes.c_double, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int,
@@ -270,6 +280,34 @@ def bhq_get_tuning(ctx):
     _check(lib().bhq_get_tuning(ctx, out), ctx)
     return dict(block=out[0], i_per_thread=out[1], blocks_per_cu=out[2],
                 persistent=out[3], use_graph=out[4])
+
+
+def bhq_set_group_order(ctx, mode=ORDER_XCD, window=ORDER_WINDOW,
+                        tail=ORDER_TAIL):
+    _check(lib().bhq_set_group_order(ctx, int(mode), int(window), int(tail)),
+           ctx)
+
+
+def bhq_get_group_order(ctx):
+    out = (ctypes.c_int * 3)()
+    _check(lib().bhq_get_group_order(ctx, out), ctx)
+    return dict(mode=out[0], window=out[1], tail=out[2])
+
+
+def bhq_plan_order(i_off, jp_off, jc_off, mode=ORDER_XCD, window=ORDER_WINDOW,
+                   tail=ORDER_TAIL, xcds=XCDS):
+    """Slot table of a group dispatch order: order[b] = group of launch
+    slot b, -1 for an empty slot."""
+    i_off, jp_off, jc_off = _i64(i_off), _i64(jp_off), _i64(jc_off)
+    ng = i_off.shape[0] - 1
+    n = ctypes.c_int64()
+    args = (ng, _ip(i_off), _ip(jp_off), _ip(jc_off), int(mode), int(window),
+            int(tail), int(xcds))
+    _check(lib().bhq_plan_order(*args, None, 0, ctypes.byref(n)))
+    out = np.empty(n.value, dtype=np.int32)
+    _check(lib().bhq_plan_order(*args, out.ctypes.data_as(_I32), out.shape[0],
+                                ctypes.byref(n)))
+    return out
 
 
 def bhq_last_error(ctx=None):

@@ -66,6 +66,67 @@ bool finite_all(const double *v, int64_t n)
     return true;
 }
 
+// Slot table of a group dispatch order (see bhq_plan_order).  Offsets are
+// already validated.  Throws std::bad_alloc.
+std::vector<int32_t> plan_order(int64_t ng, const int64_t *i_off,
+                                const int64_t *jp_off, const int64_t *jc_off,
+                                int mode, int window, int tail, int xcds)
+{
+    std::vector<double> cost((size_t)ng);
+    for (int64_t g = 0; g < ng; ++g) {
+        const double nig = (double)(i_off[g + 1] - i_off[g]);
+        cost[(size_t)g] = nig * ((double)(jp_off[g + 1] - jp_off[g]) +
+                                 2.65 * (double)(jc_off[g + 1] - jc_off[g]) + 1.0);
+    }
+    auto costly_first = [&](int32_t a, int32_t b) {
+        return cost[(size_t)a] > cost[(size_t)b];
+    };
+    if (mode == BHQ_ORDER_COST) {
+        std::vector<int32_t> order((size_t)ng);
+        for (int64_t g = 0; g < ng; ++g) order[(size_t)g] = (int32_t)g;
+        std::stable_sort(order.begin(), order.end(), costly_first);
+        return order;
+    }
+    // contiguous pieces of equal cost: group g goes to the piece holding the
+    // midpoint of its cost interval (monotone in g)
+    double total = 0.0;
+    for (double c : cost) total += c;
+    std::vector<std::vector<int32_t>> piece((size_t)xcds);
+    double before = 0.0;
+    for (int64_t g = 0; g < ng; ++g) {
+        const double mid = before + 0.5 * cost[(size_t)g];
+        before += cost[(size_t)g];
+        int x = total > 0.0 ? (int)(mid / total * xcds) : (int)(g * xcds / ng);
+        x = std::min(std::max(x, 0), xcds - 1);
+        piece[(size_t)x].push_back((int32_t)g);
+    }
+    // windows of `window` groups from the start of a piece, and its last
+    // `tail` groups as one more window; each sorted costly first
+    size_t longest = 0;
+    for (auto &pc : piece) {
+        const size_t n = pc.size();
+        const size_t body = n > (size_t)tail ? n - (size_t)tail : 0;
+        for (size_t w = 0; w < body; w += (size_t)window) {
+            const size_t e = std::min(body, w + (size_t)window);
+            std::stable_sort(pc.begin() + (ptrdiff_t)w, pc.begin() + (ptrdiff_t)e,
+                             costly_first);
+        }
+        std::stable_sort(pc.begin() + (ptrdiff_t)body, pc.end(), costly_first);
+        longest = std::max(longest, n);
+    }
+    std::vector<int32_t> order(longest * (size_t)xcds, -1);
+    for (int x = 0; x < xcds; ++x)
+        for (size_t k = 0; k < piece[(size_t)x].size(); ++k)
+            order[k * (size_t)xcds + (size_t)x] = piece[(size_t)x][k];
+    return order;
+}
+
+bool valid_order(int mode, int window, int tail)
+{
+    return (mode == BHQ_ORDER_COST || mode == BHQ_ORDER_XCD) && window >= 1 &&
+           window <= (1 << 24) && tail >= 0 && tail <= (1 << 24);
+}
+
 }  // namespace
 
 struct bhq_ctx {
@@ -94,6 +155,9 @@ struct bhq_ctx {
 
     bhq::LaunchCfg cfg;
     int use_graph = 0;
+    int order_mode = BHQ_ORDER_XCD, order_window = BHQ_ORDER_WINDOW,
+        order_tail = BHQ_ORDER_TAIL;
+    int64_t nslots = 0;
     uint64_t args_version = 0;  // bumped when device pointers/params change
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -190,6 +254,27 @@ struct bhq_ctx {
         if (e == hipSuccess) e = arr[A_JCIDX].reserve((size_t)njc * 4);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc");
         list_mode = 2;
+        ++args_version;
+        return BHQ_OK;
+    }
+    // Compute the slot table for the current groups and order mode and
+    // upload it.
+    int upload_order()
+    {
+        std::vector<int32_t> order;
+        try {
+            order = plan_order(ng, i_off.data(), jp_off.data(), jc_off.data(),
+                               order_mode, order_window, order_tail, BHQ_XCDS);
+        } catch (const std::bad_alloc &) {
+            return fail(BHQ_E_NOMEM, "host order table");
+        }
+        if (launched) (void)hipEventSynchronize(ev1);
+        hipError_t e = arr[A_ORDER].reserve(order.size() * 4);
+        if (e == hipSuccess)
+            e = hipMemcpy(arr[A_ORDER].p, order.data(), order.size() * 4,
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "order upload");
+        nslots = (int64_t)order.size();
         ++args_version;
         return BHQ_OK;
     }
@@ -387,7 +472,7 @@ int bhq_set_groups(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
     const size_t D = sizeof(double);
     struct { Arr a; size_t bytes; } need[] = {
         {A_IOFF, (size_t)(ng + 1) * 8}, {A_JPOFF, (size_t)(ng + 1) * 8},
-        {A_JCOFF, (size_t)(ng + 1) * 8}, {A_ORDER, (size_t)ng * 4},
+        {A_JCOFF, (size_t)(ng + 1) * 8},
         {A_GCX, (size_t)ng * D}, {A_GCY, (size_t)ng * D}, {A_GCZ, (size_t)ng * D},
         {A_XI, (size_t)ni * D}, {A_YI, (size_t)ni * D}, {A_ZI, (size_t)ni * D},
         {A_E2I, (size_t)ni * D},
@@ -431,20 +516,12 @@ int bhq_set_groups(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
     for (int c = 0; c < 3; ++c)
         TRY(ctx->put_component((Arr)(A_GCX + c), 0, &center[0][0], 3, c, ng));
 
-    // Longest-processing-time-first block order: cost ~ ni (njp + 2.65 njc)
-    // (a cell term costs about 53 / 20 of a particle term).
-    std::vector<double> cost((size_t)ng);
-    std::vector<int32_t> order((size_t)ng);
-    for (int64_t g = 0; g < ng; ++g) {
-        const double nig = (double)(i_off[g + 1] - i_off[g]);
-        cost[(size_t)g] = nig * ((double)(jp_off[g + 1] - jp_off[g]) +
-                                 2.65 * (double)(jc_off[g + 1] - jc_off[g]));
-        order[(size_t)g] = (int32_t)g;
+    ctx->nslots = 0;
+    const int rc = ctx->upload_order();
+    if (rc != BHQ_OK) {
+        ctx->ng = -1;
+        return rc;
     }
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return cost[(size_t)a] > cost[(size_t)b];
-    });
-    TRY(up(A_ORDER, order.data(), (size_t)ng * 4));
     if (ctx->eps_mode == 1) TRY(ctx->fill_eps_uniform());
     return BHQ_OK;
 }
@@ -557,7 +634,9 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
     bhq::ForceArgs A{};
     auto D = [&](Arr a) { return ctx->arr[a].as<double>(); };
     A.ng = ctx->ng;
+    A.nslots = ctx->nslots;
     A.order = ctx->arr[A_ORDER].as<int32_t>();
+    A.xcds = ctx->order_mode == BHQ_ORDER_XCD ? BHQ_XCDS : 0;
     A.i_off = ctx->arr[A_IOFF].as<int64_t>();
     A.jp_off = ctx->arr[A_JPOFF].as<int64_t>();
     A.jc_off = ctx->arr[A_JCOFF].as<int64_t>();
@@ -670,6 +749,58 @@ int bhq_get_tuning(const bhq_ctx *ctx, int out[5])
     out[2] = ctx->cfg.blocks_per_cu;
     out[3] = ctx->cfg.persistent;
     out[4] = ctx->use_graph;
+    return BHQ_OK;
+}
+
+int bhq_set_group_order(bhq_ctx *ctx, int mode, int window, int tail)
+{
+    CHECK_CTX(ctx);
+    if (!valid_order(mode, window, tail))
+        return ctx->fail(BHQ_E_ARG, "group order: mode %d window %d tail %d "
+                         "(mode 0 or 1, window in [1, 2^24], tail in [0, 2^24])",
+                         mode, window, tail);
+    ctx->order_mode = mode;
+    ctx->order_window = window;
+    ctx->order_tail = tail;
+    if (ctx->ng < 0) return BHQ_OK;
+    TRY(ctx->select());
+    const int rc = ctx->upload_order();
+    if (rc != BHQ_OK) ctx->ng = -1;  // no valid order table: set_groups again
+    return rc;
+}
+
+int bhq_get_group_order(const bhq_ctx *ctx, int out[3])
+{
+    if (!ctx || !out) return BHQ_E_ARG;
+    out[0] = ctx->order_mode;
+    out[1] = ctx->order_window;
+    out[2] = ctx->order_tail;
+    return BHQ_OK;
+}
+
+int bhq_plan_order(int64_t ng, const int64_t *i_off, const int64_t *jp_off,
+                   const int64_t *jc_off, int mode, int window, int tail,
+                   int xcds, int32_t *order, int64_t cap, int64_t *nslots)
+{
+    if (ng < 1 || ng > 0x7fffffff || !i_off || !jp_off || !jc_off || !nslots)
+        return BHQ_E_ARG;
+    if (!valid_order(mode, window, tail) || xcds < 1 || xcds > bhq::kQueueWords)
+        return BHQ_E_ARG;
+    for (const int64_t *off : {i_off, jp_off, jc_off}) {
+        if (off[0] != 0) return BHQ_E_RANGE;
+        for (int64_t g = 0; g < ng; ++g)
+            if (off[g + 1] < off[g]) return BHQ_E_RANGE;
+    }
+    std::vector<int32_t> o;
+    try {
+        o = plan_order(ng, i_off, jp_off, jc_off, mode, window, tail, xcds);
+    } catch (const std::bad_alloc &) {
+        return BHQ_E_NOMEM;
+    }
+    *nslots = (int64_t)o.size();
+    if (!order) return BHQ_OK;
+    if (cap < (int64_t)o.size()) return BHQ_E_RANGE;
+    std::copy(o.begin(), o.end(), order);
     return BHQ_OK;
 }
 

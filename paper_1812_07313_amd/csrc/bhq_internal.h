@@ -22,7 +22,13 @@ struct alignas(32) CellRec {
 // memory; i-particles and outputs are in group order.
 struct ForceArgs {
     int64_t ng;                     // groups
-    const int32_t *order;           // block b processes group order[b]
+    int64_t nslots;                 // entries of order (grid of one block
+                                    // per slot)
+    const int32_t *order;           // slot b holds group order[b], or -1
+                                    // (empty slot)
+    int xcds;                       // > 0: slot b belongs to XCD b % xcds
+                                    // and the persistent kernel keeps one
+                                    // counter per XCD in queue[0..xcds)
     const int64_t *i_off;           // [ng+1]
     const int64_t *jp_off;          // [ng+1]
     const int64_t *jc_off;          // [ng+1]
@@ -36,7 +42,8 @@ struct ForceArgs {
     double *ax, *ay, *az, *pot;     // [ni] results (FP64)
     double box;                     // > 0: periodic minimum image
     double rs, rcut;                // split-kernel parameters
-    unsigned int *queue;            // group counter of the persistent kernel
+    unsigned int *queue;            // slot counters of the persistent kernel
+                                    // (kQueueWords words, zeroed per launch)
     // Index-mode lists (all NULL for materialised lists): entry k of the
     // j-particle list is pool_p[jp_idx[k]], of the j-cell list
     // pool_c[jc_idx[k]].
@@ -45,6 +52,8 @@ struct ForceArgs {
     const int32_t *jp_idx;
     const int32_t *jc_idx;
 };
+
+constexpr int kQueueWords = 64;  // capacity of ForceArgs::queue
 
 // Launch shape.  block: threads per block (128 or 256), which is also the
 // depth of one LDS tile; i_per_thread: i-particles per thread (1 or 2);

@@ -495,12 +495,24 @@ __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel(const ForceArgs
     __shared__ V4<R> sb[kCellQ ? BS : 1];
     __shared__ V4<R> sc[kCellQ ? BS : 1];
     const int64_t g = A.order ? A.order[blockIdx.x] : (int64_t)blockIdx.x;
+    if (g < 0) return;  // empty slot (uniform over the block)
     process_group<R, KIND, PERIODIC, BS, IB>(A, g, sa, sb, sc);
 }
 
-// Persistent variant: a grid sized to the machine pulls groups, in the
-// order of A.order, from the counter A.queue (zeroed before the launch).
-// Every block leaves the loop once the counter has passed ng.
+// Id of the XCD this wave runs on (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ int xcd_id()
+{
+    constexpr int kHwRegXccId = 20;
+    return (int)(__builtin_amdgcn_s_getreg((3 << 11) | kHwRegXccId) & 0xfu);
+}
+
+// Persistent variant: a grid sized to the machine pulls slots of A.order
+// from the counters in A.queue (zeroed before the launch).  With xcds == 0
+// one counter runs over all slots; otherwise counter x runs over the slots
+// of XCD x (b % xcds == x) and a block drains its own XCD's counter first,
+// then the others' in turn.  Every counter only grows, and a block leaves a
+// counter once it has passed that counter's slot count, so every block
+// exits.
 template <typename R, int KIND, bool PERIODIC, int BS, int IB>
 __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(const ForceArgs A)
 {
@@ -509,27 +521,34 @@ __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(cons
     __shared__ V4<R> sb[kCellQ ? BS : 1];
     __shared__ V4<R> sc[kCellQ ? BS : 1];
     __shared__ int64_t next;
-    for (;;) {
-        if (threadIdx.x == 0) next = (int64_t)atomicAdd(A.queue, 1u);
-        __syncthreads();
-        const int64_t k = next;
-        __syncthreads();
-        if (k >= A.ng) break;
-        const int64_t g = A.order ? A.order[k] : k;
-        process_group<R, KIND, PERIODIC, BS, IB>(A, g, sa, sb, sc);
+    const int nq = A.xcds > 0 ? A.xcds : 1;
+    const int64_t per_q = A.nslots / nq;  // nslots is a multiple of nq
+    const int home = A.xcds > 0 ? xcd_id() % nq : 0;
+    for (int r = 0; r < nq; ++r) {
+        const int q = (home + r) % nq;
+        for (;;) {
+            if (threadIdx.x == 0) next = (int64_t)atomicAdd(A.queue + q, 1u);
+            __syncthreads();
+            const int64_t k = next;
+            __syncthreads();
+            if (k >= per_q) break;
+            const int64_t slot = k * nq + q;
+            const int64_t g = A.order ? A.order[slot] : slot;
+            if (g >= 0) process_group<R, KIND, PERIODIC, BS, IB>(A, g, sa, sb, sc);
+        }
     }
 }
 
 __global__ void reset_queue(unsigned int *q)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) q[0] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < kQueueWords) q[threadIdx.x] = 0u;
 }
 
 template <typename R, int KIND, bool P, int BS, int IB>
 hipError_t launch_one(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
 {
     if (cfg.persistent) {
-        hipLaunchKernelGGL(reset_queue, dim3(1), dim3(64), 0, s, A.queue);
+        hipLaunchKernelGGL(reset_queue, dim3(1), dim3(kQueueWords), 0, s, A.queue);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         int per_cu = cfg.blocks_per_cu;
@@ -540,12 +559,12 @@ hipError_t launch_one(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
             if (per_cu < 1) per_cu = 1;
         }
         const int64_t want = (int64_t)per_cu * cfg.num_cu;
-        const unsigned grid = (unsigned)(want < A.ng ? want : A.ng);
+        const unsigned grid = (unsigned)(want < A.nslots ? want : A.nslots);
         hipLaunchKernelGGL((force_kernel_persistent<R, KIND, P, BS, IB>),
                            dim3(grid), dim3(BS), 0, s, A);
     } else {
         hipLaunchKernelGGL((force_kernel<R, KIND, P, BS, IB>),
-                           dim3((unsigned)A.ng), dim3(BS), 0, s, A);
+                           dim3((unsigned)A.nslots), dim3(BS), 0, s, A);
     }
     return hipGetLastError();
 }
@@ -587,8 +606,10 @@ hipError_t launch_prec(int kernel, const ForceArgs &A, const LaunchCfg &cfg,
 hipError_t launch_force(int kernel, int precision, const ForceArgs &A,
                         const LaunchCfg &cfg, hipStream_t stream)
 {
-    if (A.ng <= 0) return hipSuccess;
-    if (A.ng > 0x7fffffff) return hipErrorInvalidValue;
+    if (A.ng <= 0 || A.nslots <= 0) return hipSuccess;
+    if (A.ng > 0x7fffffff || A.nslots > 0x7fffffff) return hipErrorInvalidValue;
+    if (A.xcds < 0 || A.xcds > kQueueWords) return hipErrorInvalidValue;
+    if (A.xcds > 0 && A.nslots % A.xcds != 0) return hipErrorInvalidValue;
     if (cfg.block != 128 && cfg.block != 256) return hipErrorInvalidValue;
     if (cfg.i_per_thread != 1 && cfg.i_per_thread != 2) return hipErrorInvalidValue;
     if (cfg.persistent && (!A.queue || cfg.num_cu <= 0))

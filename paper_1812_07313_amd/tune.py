@@ -1,7 +1,7 @@
 """Autotuner for the force evaluation: chooses the group size bound ncrit
-(which changes the interaction lists) and the launch shape (block size,
-persistent queue, persistent grid size) that minimise the time of one force
-evaluation.  Interactions per second alone would reward larger ncrit (more,
+(which changes the interaction lists), the launch shape (block size,
+i-particles per thread, persistent queue, persistent grid size) and the
+group dispatch order that minimise the time of one force evaluation.  Interactions per second alone would reward larger ncrit (more,
 cheaper interactions), so the objective is seconds per evaluation.
 
 Results are cached in a JSON file keyed by device architecture, a caller
@@ -23,6 +23,7 @@ NCRITS = (64, 128, 256)
 # (block, i_per_thread, blocks_per_cu, persistent)
 SHAPES = ((256, 1, 0, 0), (256, 2, 0, 0), (128, 1, 0, 0), (128, 2, 0, 0),
           (256, 1, 0, 1), (256, 2, 0, 1), (128, 2, 4, 1))
+ORDERS = (bhq.ORDER_XCD, bhq.ORDER_COST)
 
 
 def _load(path):
@@ -47,16 +48,18 @@ def cache_key(arch, workload, kernel, precision, theta):
                                         bhq.PRECISION_NAMES[precision], theta)
 
 
-def search(measure, ncrits=NCRITS, shapes=SHAPES):
+def search(measure, ncrits=NCRITS, shapes=SHAPES, orders=ORDERS):
     """Exhaustive search.  measure(ncrit, block, i_per_thread,
-    blocks_per_cu, persistent) returns seconds per evaluation.  Returns
-    (best, table)."""
+    blocks_per_cu, persistent, order) returns seconds per evaluation.
+    Returns (best, table)."""
     table = []
     for nc in ncrits:
         for block, ipt, bpc, pers in shapes:
-            t = measure(nc, block, ipt, bpc, pers)
-            table.append(dict(ncrit=nc, block=block, i_per_thread=ipt,
-                              blocks_per_cu=bpc, persistent=pers, seconds=t))
+            for order in orders:
+                t = measure(nc, block, ipt, bpc, pers, order)
+                table.append(dict(ncrit=nc, block=block, i_per_thread=ipt,
+                                  blocks_per_cu=bpc, persistent=pers,
+                                  order=order, seconds=t))
     best = min(table, key=lambda r: r["seconds"])
     return dict(best), table
 
@@ -69,7 +72,7 @@ def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
     (median of `repeats` launches after one warm-up)."""
     state = {"ncrit": None}
 
-    def measure(ncrit, block, ipt, bpc, pers):
+    def measure(ncrit, block, ipt, bpc, pers, order=bhq.ORDER_XCD):
         if state["ncrit"] != ncrit:
             if sys_off is not None:
                 L = bhq.bhq_build_lists_batch(sys_off, x, m, theta, ncrit,
@@ -94,6 +97,7 @@ def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
             state["ncrit"] = ncrit
         bhq.bhq_set_kernel(ctx, kernel, precision)
         bhq.bhq_set_tuning(ctx, block, ipt, bpc, pers, 0)
+        bhq.bhq_set_group_order(ctx, order)
         bhq.bhq_compute(ctx, stream)
         bhq.bhq_get_kernel_ms(ctx)
         ts = []
@@ -107,23 +111,23 @@ def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
 
 def autotune(ctx, x, m, theta, workload, arch="gfx950", kernel=bhq.QUAD,
              precision=bhq.FP32_OFS64, cache=DEFAULT_CACHE, ncrits=NCRITS,
-             shapes=SHAPES, force=False, **kw):
+             shapes=SHAPES, orders=ORDERS, force=False, **kw):
     """Tune (or read from the cache) and leave ctx holding the best lists
     and launch shape.  Returns dict(best=..., table=..., cached=bool)."""
     key = cache_key(arch, workload, kernel, precision, theta)
     db = _load(cache)
     measure = gpu_measure(ctx, x, m, theta, kernel=kernel, precision=precision,
                           **kw)
-    if not force and key in db:
+    if not force and key in db and "order" in db[key]["best"]:
         best = db[key]["best"]
         measure(best["ncrit"], best["block"], best["i_per_thread"],
-                best["blocks_per_cu"], best["persistent"])
+                best["blocks_per_cu"], best["persistent"], best["order"])
         return dict(best=best, table=db[key]["table"], cached=True)
     t0 = time.perf_counter()
-    best, table = search(measure, ncrits, shapes)
+    best, table = search(measure, ncrits, shapes, orders)
     db = _load(cache)
     db[key] = dict(best=best, table=table, seconds_spent=time.perf_counter() - t0)
     _store(cache, db)
     measure(best["ncrit"], best["block"], best["i_per_thread"],
-            best["blocks_per_cu"], best["persistent"])
+            best["blocks_per_cu"], best["persistent"], best["order"])
     return dict(best=best, table=table, cached=False)

@@ -52,12 +52,50 @@ def test_launch_shapes(ctx, cube_case):
     bhq.bhq_set_tuning(ctx)
 
 
+ORDERS = [(bhq.ORDER_COST, 256, 1024), (bhq.ORDER_XCD, 256, 1024),
+          (bhq.ORDER_XCD, 1, 0), (bhq.ORDER_XCD, 64, 3000),
+          (bhq.ORDER_XCD, 1 << 24, 0)]
+
+
+def test_group_orders_bitwise(ctx, cube_case):
+    """Every dispatch order, eager and persistent, gives the same bits (the
+    per-group arithmetic does not depend on which block runs a group), and
+    matches the oracle."""
+    x, m, mat, (a_ref, p_ref) = cube_case
+    upload(ctx, mat, x, eps2=1e-6)
+    for prec in PRECS:
+        first = None
+        for mode, window, tail in ORDERS:
+            bhq.bhq_set_group_order(ctx, mode, window, tail)
+            assert bhq.bhq_get_group_order(ctx) == dict(mode=mode, window=window,
+                                                        tail=tail)
+            for pers in (0, 1):
+                bhq.bhq_set_tuning(ctx, 256, 2, 0, pers, 0)
+                log("case order mode=%d window=%d tail=%d persistent=%d %s"
+                    % (mode, window, tail, pers, bhq.PRECISION_NAMES[prec]))
+                a, p = run(ctx, mat, len(m), bhq.QUAD, prec)
+                if first is None:
+                    first = (a, p)
+                    assert_parity(errors(a, p, a_ref, p_ref), prec, "orders")
+                else:
+                    assert np.array_equal(a, first[0]) and np.array_equal(p, first[1])
+    bhq.bhq_set_group_order(ctx)
+    bhq.bhq_set_tuning(ctx)
+
+
 def test_tuning_argument_errors(ctx):
     for args in ((64, 1, 0, 0, 0), (256, 3, 0, 0, 0), (256, 1, -1, 0, 0),
                  (256, 1, 0, 2, 0), (256, 1, 0, 0, 3)):
         with pytest.raises(bhq.BhqError) as ei:
             bhq.bhq_set_tuning(ctx, *args)
         assert ei.value.code == bhq.E_ARG
+    for args in ((2, 256, 0), (1, 0, 0), (1, 256, -1)):
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_set_group_order(ctx, *args)
+        assert ei.value.code == bhq.E_ARG
+    assert bhq.bhq_get_group_order(ctx) == dict(mode=bhq.ORDER_XCD,
+                                                window=bhq.ORDER_WINDOW,
+                                                tail=bhq.ORDER_TAIL)
 
 
 def test_graph_replays_match_eager(ctx, cube_case):
@@ -77,6 +115,15 @@ def test_graph_replays_match_eager(ctx, cube_case):
             y = torch.ones(1 << 20, device="cuda") * (rep + 1)
             torch.cuda.synchronize()
             assert float(y.sum()) == float((rep + 1) << 20)
+    # a new order re-records the graph; results unchanged
+    bhq.bhq_set_tuning(ctx, 256, 1, 0, 1, 1)
+    a0, p0 = run(ctx, mat, len(m), bhq.QUAD, bhq.FP32_OFS64)
+    for mode in (bhq.ORDER_COST, bhq.ORDER_XCD):
+        bhq.bhq_set_group_order(ctx, mode)
+        for rep in range(2):
+            log("case graph order=%d replay %d" % (mode, rep))
+            a, p = run(ctx, mat, len(m), bhq.QUAD, bhq.FP32_OFS64)
+            assert np.array_equal(a, a0) and np.array_equal(p, p0)
     # new data -> the graph is recorded again
     x2, m2 = synth.plummer(5000, synth.rng(12))
     T2 = orc.Tree(x2, m2, 0.5, 64)

@@ -12,13 +12,14 @@ from paper_1812_07313_amd import bhq, synth, tune
 def test_search_picks_minimum_and_cache_roundtrip(tmp_path):
     cost = {64: 3.0, 128: 2.0, 256: 2.5}
 
-    def measure(nc, block, ipt, bpc, pers):
-        return cost[nc] + (0.1 if block == 128 else 0.0) - 0.05 * pers - 0.01 * ipt
+    def measure(nc, block, ipt, bpc, pers, order):
+        return (cost[nc] + (0.1 if block == 128 else 0.0) - 0.05 * pers
+                - 0.01 * ipt - 0.001 * (order == bhq.ORDER_COST))
 
     best, table = tune.search(measure)
-    assert len(table) == len(tune.NCRITS) * len(tune.SHAPES)
+    assert len(table) == len(tune.NCRITS) * len(tune.SHAPES) * len(tune.ORDERS)
     assert best["ncrit"] == 128 and best["block"] == 256 and best["persistent"] == 1
-    assert best["i_per_thread"] == 2
+    assert best["i_per_thread"] == 2 and best["order"] == bhq.ORDER_COST
     assert best["seconds"] == min(r["seconds"] for r in table)
     path = str(tmp_path / "tune.json")
     key = tune.cache_key("gfx950", "w", bhq.QUAD, bhq.FP32_OFS64, 0.6)
