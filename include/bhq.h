@@ -310,13 +310,58 @@ int bhq_lists_cells(const bhq_lists *L, double (*com)[3], double *mass,
 int bhq_set_lists(bhq_ctx *ctx, const bhq_lists *L, const double (*x)[3],
                   const double *m);
 
-/* The same upload as index lists: the pools hold x, m (input order) and the
- * tree cells; the list entries are indices. */
+/* The same upload as index lists: the particle pool holds x, m in tree
+ * order (entry k is input particle i_idx[k], the order bhq_lists_export
+ * gives), the cell pool the tree cells; list entries are pool indices. */
 int bhq_set_lists_indexed(bhq_ctx *ctx, const bhq_lists *L,
                           const double (*x)[3], const double *m);
 
 /* Free lists (NULL accepted). */
 int bhq_lists_free(bhq_lists *L);
+
+/* ------------------------------------------------------------------------
+ * Device-side tree and list construction: the same tree, groups and lists
+ * as bhq_build_lists (same cells in the same breadth-first numbering, same
+ * moments bit for bit, same groups, same list entries in the same order),
+ * built on the GPU from particles already in device memory and left in
+ * the context as index lists, ready for bhq_compute.
+ * ------------------------------------------------------------------------ */
+
+/* Build on ctx's device: n in [1, 2^31) particles, x[n][3] and m[n] FP64 in
+ * device memory of that device (each range must lie inside one
+ * allocation); theta >= 0, ncrit >= 1, nleaf in [1, ncrit], box >= 0,
+ * rcut >= 0 as for bhq_build_lists.  Runs on `stream` (NULL: the default
+ * stream) and returns when the lists are complete; the context then holds
+ * the groups, i-particles, pools and lists (tree order) as
+ * bhq_set_lists_indexed would leave them, and keeps its softening if it
+ * was set with bhq_set_eps.  x and m are not kept.
+ * Errors: BHQ_E_ARG (arguments, pointers that are not device memory),
+ * BHQ_E_RANGE (a range outside its allocation, more than 2^31 cells),
+ * BHQ_E_NONFINITE (a non-finite position or mass), BHQ_E_NOMEM, BHQ_E_HIP.
+ * After a failure the context holds no lists. */
+int bhq_build_lists_device(bhq_ctx *ctx, int64_t n, const double *x,
+                           const double *m, double theta, int ncrit,
+                           int nleaf, double box, double rcut, void *stream);
+
+/* Sizes of the index lists a context holds: out[0..3] = groups, j-particle
+ * entries, j-cell entries, cells in the cell pool.  BHQ_E_STATE without
+ * index lists. */
+int bhq_get_lists_sizes(const bhq_ctx *ctx, int64_t out[4]);
+
+/* Copy a context's index lists to the host, in bhq_lists_export's layout:
+ * i_idx[n] (input index of the k-th i-particle; only for lists from
+ * bhq_set_lists_indexed or bhq_build_lists_device), i_off, jp_off, jc_off
+ * [ng + 1], jp_idx[njp] (input particle indices for those lists, pool
+ * indices otherwise), jc_idx[njc] (cell pool indices = cell ids).  Any
+ * pointer may be NULL.  Errors: BHQ_E_STATE, BHQ_E_HIP, BHQ_E_NOMEM. */
+int bhq_get_lists(bhq_ctx *ctx, int64_t *i_idx, int64_t *i_off,
+                  int64_t *jp_off, int64_t *jp_idx, int64_t *jc_off,
+                  int32_t *jc_idx);
+
+/* Copy the cell pool to the host, as bhq_lists_cells gives it (any pointer
+ * may be NULL).  Errors: BHQ_E_STATE (no cell pool), BHQ_E_HIP. */
+int bhq_get_cells(bhq_ctx *ctx, double (*com)[3], double *mass,
+                  double (*q)[6], double *trace);
 
 #ifdef __cplusplus
 }

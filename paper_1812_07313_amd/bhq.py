@@ -85,6 +85,13 @@ SIGNATURES = {
     "bhq_set_jp_idx": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _I32]),
     "bhq_set_jc_idx": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _I32]),
     "bhq_set_lists_indexed": (ctypes.c_int, [_P, _P, _D, _D]),
+    "bhq_build_lists_device": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P,
+                                              ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_double,
+                                              ctypes.c_double, _P]),
+    "bhq_get_lists_sizes": (ctypes.c_int, [_P, _I64]),
+    "bhq_get_lists": (ctypes.c_int, [_P, _I64, _I64, _I64, _I64, _I64, _I32]),
+    "bhq_get_cells": (ctypes.c_int, [_P, _D, _D, _D, _D]),
 }
 
 _lib = None
@@ -383,3 +390,58 @@ def bhq_set_lists_indexed(ctx, L, x, m):
 
 def bhq_lists_free(L):
     _check(lib().bhq_lists_free(L))
+
+
+# --- device list builder -------------------------------------------------------
+
+def _device_ptr(t, shape, name):
+    """Address of a contiguous float64 GPU tensor of the given shape."""
+    if not (hasattr(t, "is_cuda") and t.is_cuda):
+        raise TypeError("%s must be a GPU tensor" % name)
+    if str(t.dtype) != "torch.float64" or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous float64 tensor" % name)
+    if tuple(t.shape) != shape:
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), shape))
+    return t.data_ptr()
+
+
+def bhq_build_lists_device(ctx, x, m, theta, ncrit, nleaf=8, box=0.0, rcut=0.0,
+                           stream=None):
+    """x: (n, 3) and m: (n,) float64 torch tensors on the context's GPU."""
+    n = int(m.shape[0])
+    px = _device_ptr(x, (n, 3), "x")
+    pm = _device_ptr(m, (n,), "m")
+    _check(lib().bhq_build_lists_device(ctx, n, px, pm, float(theta), int(ncrit),
+                                        int(nleaf), float(box), float(rcut),
+                                        _stream_handle(stream)), ctx)
+
+
+def bhq_get_lists_sizes(ctx):
+    out = np.zeros(4, np.int64)
+    _check(lib().bhq_get_lists_sizes(ctx, _ip(out)), ctx)
+    return tuple(int(v) for v in out)
+
+
+def bhq_get_lists(ctx, n=None):
+    """The context's index lists on the host (bhq_lists_export's layout);
+    i_idx only when n (the particle count) is given."""
+    ng, njp, njc, _ = bhq_get_lists_sizes(ctx)
+    out = dict(i_off=np.zeros(ng + 1, np.int64), jp_off=np.zeros(ng + 1, np.int64),
+               jp_idx=np.zeros(njp, np.int64), jc_off=np.zeros(ng + 1, np.int64),
+               jc_cell=np.zeros(njc, np.int32))
+    if n is not None:
+        out["i_idx"] = np.zeros(n, np.int64)
+    _check(lib().bhq_get_lists(
+        ctx, _ip(out.get("i_idx")), _ip(out["i_off"]), _ip(out["jp_off"]),
+        _ip(out["jp_idx"]), _ip(out["jc_off"]),
+        out["jc_cell"].ctypes.data_as(_I32)), ctx)
+    return out
+
+
+def bhq_get_cells(ctx):
+    nc = bhq_get_lists_sizes(ctx)[3]
+    out = dict(com=np.zeros((nc, 3)), mass=np.zeros(nc), q=np.zeros((nc, 6)),
+               trace=np.zeros(nc))
+    _check(lib().bhq_get_cells(ctx, _dp(out["com"]), _dp(out["mass"]),
+                               _dp(out["q"]), _dp(out["trace"])), ctx)
+    return out

@@ -19,7 +19,10 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbhq.so")
 ARCH = os.environ.get("BHQ_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["bhq_kernels.hip", "bhq_api.cpp", "bhq_lists.cpp"]
+SOURCES = ["bhq_kernels.hip", "bhq_tree.hip", "bhq_api.cpp", "bhq_lists.cpp"]
+# the tree builders take their floating-point decisions with the same
+# operations on host and device: no fused multiply-adds there
+NO_CONTRACT = {"bhq_tree.hip", "bhq_lists.cpp"}
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
@@ -43,6 +46,8 @@ def build(verbose=False, extra=()):
                "--offload-arch=" + ARCH, "-I", INCLUDE, "-I", CSRC]
         if src.endswith(".hip"):
             cmd += ["-x", "hip"] + DEVICE_FLAGS + ["-munsafe-fp-atomics"]
+        if src in NO_CONTRACT:
+            cmd += ["-ffp-contract=off"]
         cmd += list(extra) + ["-o", obj, os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd), flush=True)

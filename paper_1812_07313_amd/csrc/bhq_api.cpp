@@ -16,36 +16,11 @@
 #include "bhq_internal.h"
 #include "erfcx_fit.h"
 
+using bhq::DevArray;
+
 namespace {
 
 thread_local std::string g_create_error;
-
-// One device array with reusable capacity.
-struct DevArray {
-    void *p = nullptr;
-    size_t cap = 0;
-    hipError_t reserve(size_t bytes)
-    {
-        if (bytes <= cap && p) return hipSuccess;
-        if (p) {
-            (void)hipFree(p);
-            p = nullptr;
-            cap = 0;
-        }
-        if (bytes == 0) bytes = 256;
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e == hipSuccess) cap = bytes;
-        return e;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-    }
-    template <typename T>
-    T *as() const { return static_cast<T *>(p); }
-};
 
 enum Arr {
     A_IOFF, A_JPOFF, A_JCOFF, A_ORDER, A_GCX, A_GCY, A_GCZ,
@@ -56,6 +31,7 @@ enum Arr {
     A_AX, A_AY, A_AZ, A_POT,
     A_QUEUE,
     A_POOLP, A_POOLC, A_JPIDX, A_JCIDX,
+    A_TORDER,
     A_COUNT
 };
 
@@ -143,6 +119,11 @@ struct bhq_ctx {
     // list mode after bhq_set_groups: 0 undecided, 1 materialised, 2 indexed
     int list_mode = 0;
     int64_t npool_p = -1, npool_c = -1;
+    // The particle pool is in tree order and A_TORDER[k] is the input index
+    // of pool entry k (lists from bhq_set_lists_indexed or
+    // bhq_build_lists_device).
+    bool tree_order = false;
+    DevArray tbuf[bhq::T_COUNT_];  // device list builder working memory
     bool have_jp_idx = false, have_jc_idx = false;
     int eps_mode = 0;  // 0 none, 1 uniform, 2 per-particle
     double eps2_all = 0.0;
@@ -371,6 +352,7 @@ int bhq_destroy(bhq_ctx *ctx)
     ctx->drop_graph();
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto &a : ctx->arr) a.release();
+    for (auto &a : ctx->tbuf) a.release();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
@@ -503,6 +485,7 @@ int bhq_set_groups(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
     ctx->have_i = ctx->have_jp = ctx->have_jc = ctx->have_t = false;
     ctx->have_jp_idx = ctx->have_jc_idx = false;
     ctx->list_mode = 0;
+    ctx->tree_order = false;
     if (ctx->eps_mode == 2) ctx->eps_mode = 0;
 
     auto up = [&](Arr a, const void *src, size_t bytes) -> int {
@@ -827,6 +810,7 @@ int bhq_set_pool_particles(bhq_ctx *ctx, int64_t n, const double (*x)[3],
                       (size_t)n * sizeof(bhq::PartRec), hipMemcpyHostToDevice);
     if (e != hipSuccess) return ctx->hip_fail(e, "particle pool upload");
     ctx->npool_p = n;
+    ctx->tree_order = false;
     ctx->have_jp_idx = false;  // indices are validated against the pool
     ++ctx->args_version;
     return BHQ_OK;
@@ -1085,17 +1069,21 @@ int bhq_set_lists_indexed(bhq_ctx *ctx, const bhq_lists *L,
                            reinterpret_cast<const double(*)[3]>(center.data()),
                            jp_off.data(), jc_off.data()));
         const int64_t n = i_off[(size_t)ng];
+        // particles in tree order: pool entry k is input particle i_idx[k]
+        std::vector<int64_t> i_idx((size_t)n);
+        TRY(bhq_lists_export(L, i_idx.data(), nullptr, nullptr, nullptr,
+                             nullptr, nullptr, nullptr, nullptr));
         {
-            std::vector<int64_t> i_idx((size_t)n);
-            TRY(bhq_lists_export(L, i_idx.data(), nullptr, nullptr, nullptr,
-                                 nullptr, nullptr, nullptr, nullptr));
-            std::vector<double> xi((size_t)n * 3);
-            for (int64_t k = 0; k < n; ++k)
+            std::vector<double> xs((size_t)n * 3), ms((size_t)n);
+            for (int64_t k = 0; k < n; ++k) {
                 for (int c = 0; c < 3; ++c)
-                    xi[(size_t)(3 * k + c)] = x[i_idx[(size_t)k]][c];
-            TRY(bhq_set_i(ctx, n, reinterpret_cast<const double(*)[3]>(xi.data())));
+                    xs[(size_t)(3 * k + c)] = x[i_idx[(size_t)k]][c];
+                ms[(size_t)k] = m[i_idx[(size_t)k]];
+            }
+            TRY(bhq_set_i(ctx, n, reinterpret_cast<const double(*)[3]>(xs.data())));
+            TRY(bhq_set_pool_particles(
+                ctx, n, reinterpret_cast<const double(*)[3]>(xs.data()), ms.data()));
         }
-        TRY(bhq_set_pool_particles(ctx, n, x, m));
         {
             std::vector<double> com((size_t)ncell * 3), mass((size_t)ncell),
                 q((size_t)ncell * 6), tr((size_t)ncell);
@@ -1109,12 +1097,14 @@ int bhq_set_lists_indexed(bhq_ctx *ctx, const bhq_lists *L,
                                    reinterpret_cast<const double(*)[6]>(q.data()),
                                    tr.data()));
         }
+        std::vector<int32_t> pos((size_t)n);
+        for (int64_t k = 0; k < n; ++k) pos[(size_t)i_idx[(size_t)k]] = (int32_t)k;
         {
             std::vector<int64_t> jp64((size_t)njp);
             TRY(bhq_lists_export(L, nullptr, nullptr, nullptr, nullptr, nullptr,
                                  jp64.data(), nullptr, nullptr));
             std::vector<int32_t> jp32((size_t)njp);
-            for (int64_t k = 0; k < njp; ++k) jp32[(size_t)k] = (int32_t)jp64[(size_t)k];
+            for (int64_t k = 0; k < njp; ++k) jp32[(size_t)k] = pos[(size_t)jp64[(size_t)k]];
             std::vector<int64_t>().swap(jp64);
             TRY(bhq_set_jp_idx(ctx, 0, njp, jp32.data()));
         }
@@ -1124,8 +1114,207 @@ int bhq_set_lists_indexed(bhq_ctx *ctx, const bhq_lists *L,
                                  nullptr, nullptr, jc.data()));
             TRY(bhq_set_jc_idx(ctx, 0, njc, jc.data()));
         }
+        {
+            std::vector<int32_t> o32((size_t)n);
+            for (int64_t k = 0; k < n; ++k) o32[(size_t)k] = (int32_t)i_idx[(size_t)k];
+            hipError_t e = ctx->arr[A_TORDER].reserve((size_t)n * 4);
+            if (e == hipSuccess)
+                e = hipMemcpy(ctx->arr[A_TORDER].p, o32.data(), (size_t)n * 4,
+                              hipMemcpyHostToDevice);
+            if (e != hipSuccess) return ctx->hip_fail(e, "order upload");
+            ctx->tree_order = true;
+        }
     } catch (const std::bad_alloc &) {
         return ctx->fail(BHQ_E_NOMEM, "host memory while uploading index lists");
+    }
+    return BHQ_OK;
+}
+
+// Device memory check: [p, p + bytes) inside one device allocation.
+static int check_device_range(bhq_ctx *ctx, const void *p, size_t bytes,
+                              const char *name)
+{
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    hipError_t e = hipMemGetAddressRange(&base, &size, const_cast<void *>(p));
+    if (e != hipSuccess || !base) {
+        (void)hipGetLastError();
+        return ctx->fail(BHQ_E_ARG, "%s is not device memory", name);
+    }
+    const char *b = static_cast<const char *>(base);
+    const char *q = static_cast<const char *>(p);
+    if (q < b || (size_t)(q - b) + bytes > size)
+        return ctx->fail(BHQ_E_RANGE, "%s: %zu bytes do not fit its allocation",
+                         name, bytes);
+    return BHQ_OK;
+}
+
+int bhq_build_lists_device(bhq_ctx *ctx, int64_t n, const double *x,
+                           const double *m, double theta, int ncrit, int nleaf,
+                           double box, double rcut, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (n < 1 || n > 0x7fffffffLL || !x || !m || !(theta >= 0.0) ||
+        !std::isfinite(theta) || ncrit < 1 || nleaf < 1 || nleaf > ncrit ||
+        !(box >= 0.0) || !std::isfinite(box) || !(rcut >= 0.0) ||
+        !std::isfinite(rcut))
+        return ctx->fail(BHQ_E_ARG, "build_lists_device: bad argument");
+    TRY(ctx->select());
+    TRY(check_device_range(ctx, x, (size_t)n * 3 * sizeof(double), "x"));
+    TRY(check_device_range(ctx, m, (size_t)n * sizeof(double), "m"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
+
+    bhq::TreeParams P{x, m, n, theta, ncrit, nleaf, box, rcut};
+    bhq::TreeOut O;
+    O.i_off = &ctx->arr[A_IOFF];
+    O.jp_off = &ctx->arr[A_JPOFF];
+    O.jc_off = &ctx->arr[A_JCOFF];
+    O.gcx = &ctx->arr[A_GCX];
+    O.gcy = &ctx->arr[A_GCY];
+    O.gcz = &ctx->arr[A_GCZ];
+    O.xi = &ctx->arr[A_XI];
+    O.yi = &ctx->arr[A_YI];
+    O.zi = &ctx->arr[A_ZI];
+    O.pool_p = &ctx->arr[A_POOLP];
+    O.pool_c = &ctx->arr[A_POOLC];
+    O.jp_idx = &ctx->arr[A_JPIDX];
+    O.jc_idx = &ctx->arr[A_JCIDX];
+    O.order = &ctx->arr[A_TORDER];
+    O.buf = ctx->tbuf;
+    ctx->ng = -1;  // no valid lists unless the build completes
+    ++ctx->args_version;
+    std::string msg;
+    const int rc = bhq::build_tree_lists(P, O, s, &msg);
+    if (rc != BHQ_OK) return ctx->fail(rc, "%s", msg.c_str());
+
+    const size_t D = sizeof(double);
+    const struct { Arr a; size_t bytes; } need[] = {
+        {A_E2I, (size_t)n * D}, {A_AX, (size_t)n * D}, {A_AY, (size_t)n * D},
+        {A_AZ, (size_t)n * D}, {A_POT, (size_t)n * D},
+    };
+    for (auto &q : need) {
+        hipError_t e = ctx->arr[q.a].reserve(q.bytes);
+        if (e != hipSuccess) return ctx->hip_fail(e, "hipMalloc");
+    }
+    ctx->i_off.swap(O.h_i_off);
+    ctx->jp_off.swap(O.h_jp_off);
+    ctx->jc_off.swap(O.h_jc_off);
+    ctx->ng = O.ng;
+    ctx->ni = n;
+    ctx->njp = O.njp;
+    ctx->njc = O.njc;
+    ctx->have_i = true;
+    ctx->have_jp = ctx->have_jc = ctx->have_t = false;
+    ctx->list_mode = 2;
+    ctx->npool_p = n;
+    ctx->npool_c = O.ncell;
+    ctx->have_jp_idx = ctx->have_jc_idx = true;
+    ctx->tree_order = true;
+    if (ctx->eps_mode == 2) ctx->eps_mode = 0;
+    ctx->nslots = 0;
+    const int orc = ctx->upload_order();
+    if (orc != BHQ_OK) {
+        ctx->ng = -1;
+        return orc;
+    }
+    if (ctx->eps_mode == 1) TRY(ctx->fill_eps_uniform());
+    return BHQ_OK;
+}
+
+int bhq_get_lists_sizes(const bhq_ctx *ctx, int64_t out[4])
+{
+    if (!ctx || !out) return BHQ_E_ARG;
+    if (ctx->ng < 0 || ctx->list_mode != 2) return BHQ_E_STATE;
+    out[0] = ctx->ng;
+    out[1] = ctx->njp;
+    out[2] = ctx->njc;
+    out[3] = ctx->npool_c;
+    return BHQ_OK;
+}
+
+int bhq_get_lists(bhq_ctx *ctx, int64_t *i_idx, int64_t *i_off,
+                  int64_t *jp_off, int64_t *jp_idx, int64_t *jc_off,
+                  int32_t *jc_idx)
+{
+    CHECK_CTX(ctx);
+    if (ctx->ng < 0 || ctx->list_mode != 2 ||
+        (ctx->njp > 0 && !ctx->have_jp_idx) || (ctx->njc > 0 && !ctx->have_jc_idx))
+        return ctx->fail(BHQ_E_STATE, "get_lists: no index lists set");
+    if (i_idx && !ctx->tree_order)
+        return ctx->fail(BHQ_E_STATE, "get_lists: the particle order is not "
+                                      "known for lists set entry by entry");
+    TRY(ctx->select());
+    if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
+    const size_t ng1 = (size_t)ctx->ng + 1;
+    if (i_off) std::memcpy(i_off, ctx->i_off.data(), ng1 * 8);
+    if (jp_off) std::memcpy(jp_off, ctx->jp_off.data(), ng1 * 8);
+    if (jc_off) std::memcpy(jc_off, ctx->jc_off.data(), ng1 * 8);
+    try {
+        std::vector<int32_t> ord;
+        if (ctx->tree_order && (i_idx || jp_idx)) {
+            ord.resize((size_t)ctx->ni);
+            hipError_t e = hipMemcpy(ord.data(), ctx->arr[A_TORDER].p,
+                                     (size_t)ctx->ni * 4, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return ctx->hip_fail(e, "hipMemcpy D2H");
+            if (i_idx)
+                for (int64_t k = 0; k < ctx->ni; ++k) i_idx[k] = ord[(size_t)k];
+        }
+        if (jp_idx && ctx->njp > 0) {
+            std::vector<int32_t> v((size_t)ctx->njp);
+            hipError_t e = hipMemcpy(v.data(), ctx->arr[A_JPIDX].p,
+                                     (size_t)ctx->njp * 4, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return ctx->hip_fail(e, "hipMemcpy D2H");
+            for (int64_t k = 0; k < ctx->njp; ++k)
+                jp_idx[k] = ctx->tree_order ? ord[(size_t)v[(size_t)k]] : v[(size_t)k];
+        }
+    } catch (const std::bad_alloc &) {
+        return ctx->fail(BHQ_E_NOMEM, "host staging");
+    }
+    if (jc_idx && ctx->njc > 0) {
+        hipError_t e = hipMemcpy(jc_idx, ctx->arr[A_JCIDX].p, (size_t)ctx->njc * 4,
+                                 hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return ctx->hip_fail(e, "hipMemcpy D2H");
+    }
+    return BHQ_OK;
+}
+
+int bhq_get_cells(bhq_ctx *ctx, double (*com)[3], double *mass, double (*q)[6],
+                  double *trace)
+{
+    CHECK_CTX(ctx);
+    if (ctx->npool_c < 0) return ctx->fail(BHQ_E_STATE, "get_cells: no cell pool");
+    TRY(ctx->select());
+    if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
+    const int64_t nc = ctx->npool_c;
+    std::vector<bhq::CellRec> rec;
+    try {
+        rec.resize((size_t)nc);
+    } catch (const std::bad_alloc &) {
+        return ctx->fail(BHQ_E_NOMEM, "host staging");
+    }
+    if (nc > 0) {
+        hipError_t e = hipMemcpy(rec.data(), ctx->arr[A_POOLC].p,
+                                 (size_t)nc * sizeof(bhq::CellRec), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return ctx->hip_fail(e, "hipMemcpy D2H");
+    }
+    for (int64_t c = 0; c < nc; ++c) {
+        const bhq::CellRec &r = rec[(size_t)c];
+        if (com) {
+            com[c][0] = r.x;
+            com[c][1] = r.y;
+            com[c][2] = r.z;
+        }
+        if (mass) mass[c] = r.m;
+        if (q) {
+            q[c][0] = r.q00;
+            q[c][1] = r.q01;
+            q[c][2] = r.q02;
+            q[c][3] = r.q11;
+            q[c][4] = r.q12;
+            q[c][5] = r.q22;
+        }
+        if (trace) trace[c] = r.t;
     }
     return BHQ_OK;
 }

@@ -4,9 +4,59 @@
 
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 #include <hip/hip_runtime_api.h>
 
 namespace bhq {
+
+// One device array with reusable capacity (host-side handle).
+struct DevArray {
+    void *p = nullptr;
+    size_t cap = 0;
+    // At least `bytes` of capacity; old contents are not kept.
+    hipError_t reserve(size_t bytes)
+    {
+        if (bytes <= cap && p) return hipSuccess;
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+            cap = 0;
+        }
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipSuccess) cap = bytes;
+        return e;
+    }
+    // At least `bytes` of capacity, keeping the first `used` bytes (the
+    // stream is synchronised before the old block is freed).
+    hipError_t grow(size_t bytes, size_t used, hipStream_t s)
+    {
+        if (bytes <= cap && p) return hipSuccess;
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, bytes ? bytes : 256);
+        if (e != hipSuccess) return e;
+        if (p && used) e = hipMemcpyAsync(q, p, used, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            (void)hipFree(q);
+            return e;
+        }
+        if (p) (void)hipFree(p);
+        p = q;
+        cap = bytes ? bytes : 256;
+        return hipSuccess;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
 
 // Pool records for index-mode lists (AoS, FP64).
 struct alignas(32) PartRec {
@@ -72,5 +122,45 @@ struct LaunchCfg {
 // the launch status.
 hipError_t launch_force(int kernel, int precision, const ForceArgs &args,
                         const LaunchCfg &cfg, hipStream_t stream);
+
+// Device construction of the tree, groups and index lists (bhq_tree.hip).
+// Inputs: n particles, positions x[n][3] and masses m[n] in device memory.
+struct TreeParams {
+    const double *x;
+    const double *m;
+    int64_t n;
+    double theta;
+    int ncrit, nleaf;
+    double box, rcut;
+};
+
+// Builder working memory, kept between builds of one context.
+enum TreeBuf {
+    T_KEY, T_KEY2, T_IDX0, T_SORT, T_BBOX, T_FLAG,
+    T_CX, T_CY, T_CZ, T_SIDE, T_FIRST, T_COUNT, T_CHILD0, T_NCHILD, T_PARENT,
+    T_DEPTH, T_CKEY, T_NCH, T_NOFF, T_GSTART, T_GROUPS, T_NSEL, T_WC, T_WL,
+    T_JPCNT, T_JCCNT, T_COUNT_
+};
+
+// Where the results go: arrays of the force context, filled in the layout
+// bhq_compute reads (i-particles, pools and lists in tree order).
+struct TreeOut {
+    DevArray *i_off, *jp_off, *jc_off;        // int64 [ng+1]
+    DevArray *gcx, *gcy, *gcz;                // FP64 [ng] group centres
+    DevArray *xi, *yi, *zi;                   // FP64 [n] i-particles
+    DevArray *pool_p;                         // PartRec [n], tree order
+    DevArray *pool_c;                         // CellRec [ncell]
+    DevArray *jp_idx, *jc_idx;                // int32 list entries
+    DevArray *order;                          // int32 [n]: input index of
+                                              // tree position k
+    DevArray *buf;                            // [T_COUNT_] working memory
+    // sizes and host copies of the offsets, set on success
+    int64_t ng = 0, njp = 0, njc = 0, ncell = 0;
+    std::vector<int64_t> h_i_off, h_jp_off, h_jc_off;
+};
+
+// Returns a BHQ_* code; on failure *err names the step.
+int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t stream,
+                     std::string *err);
 
 }  // namespace bhq

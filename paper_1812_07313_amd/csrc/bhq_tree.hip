@@ -1,0 +1,884 @@
+// bhq_tree.hip -- the oct-tree, its groups and the interaction lists built
+// on the GPU from particles already in device memory.
+//
+// The construction is the host builder's (Kodama & Ishiyama, Sec. 1 for
+// the tree, Sec. 3.4 for the groups and their shared lists), step by step,
+// so that cells, moments, groups and lists come out identical:
+//   1. root cube from the bounding box (or [0, box)^3);
+//   2. a 63-bit key per particle by descending 21 levels (upper half along
+//      an axis iff the coordinate is >= the cell centre), then a stable
+//      radix sort by key (ties keep input order);
+//   3. cells breadth-first, one level per pass: a cell with more than nleaf
+//      particles above depth 21 gets one child per non-empty octant, found
+//      by binary search in the sorted keys; children are numbered in the
+//      order of their parents, then octants (the host's breadth-first ids);
+//      particles inside a leaf return to input order;
+//   4. moments: leaves from their particles, parents from their children
+//      by the parallel-axis shift, deepest level first;
+//   5. groups: the largest cells with at most ncrit particles (or leaves),
+//      in depth-first order, which is the order of their first particle;
+//   6. lists: one thread per group walks the tree depth first (children in
+//      octant order), once to count and once to fill.  A cell that does not
+//      contain the group is accepted iff side^2 < theta^2 d^2 (d: its
+//      centre of mass to the group cube; minimum image in a periodic box,
+//      where cells farther than rcut from the group are skipped).
+// Every floating-point decision (key digits, acceptance) and every moment
+// is computed with the host builder's operations in the same order, with
+// no contraction into fused multiply-adds, so the results agree bit for
+// bit.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+
+#include "bhq.h"
+#include "bhq_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace bhq {
+
+namespace {
+
+constexpr int kMaxDepth = 21;
+constexpr int kFrames = kMaxDepth + 1;  // walk stack: root + one per depth
+constexpr int kWalkBlock = 64;
+constexpr int kBlock = 256;
+constexpr int kBboxBlocks = 1024;
+
+// What the walk reads of a cell: geometry and centre of mass (64 B), then
+// the links (16 B; nchild in bits 0-7 and depth in bits 8-15 of .w).
+struct alignas(64) WCell {
+    double cx, cy, cz, side;
+    double mx, my, mz;
+    uint64_t key;
+};
+struct alignas(16) WLink {
+    int32_t first, count, child0, nd;
+};
+
+struct Cells {
+    double *cx, *cy, *cz, *side;
+    int32_t *first, *count, *child0, *nchild, *parent, *depth;
+    uint64_t *key;
+};
+
+inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// ---- 1. bounding box ------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_bbox_partial(const double *x, int64_t n,
+                                                         double *part)
+{
+    __shared__ double s[6][kBlock];
+    double lo[3], hi[3];
+    const int64_t start = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t p0 = start < n ? start : 0;  // n >= 1
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = x[3 * p0 + a];
+    for (int64_t p = start; p < n; p += stride)
+        for (int a = 0; a < 3; ++a) {
+            const double v = x[3 * p + a];
+            lo[a] = v < lo[a] ? v : lo[a];
+            hi[a] = v > hi[a] ? v : hi[a];
+        }
+    for (int a = 0; a < 3; ++a) {
+        s[a][threadIdx.x] = lo[a];
+        s[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int a = 0; a < 3; ++a) {
+                const double l = s[a][threadIdx.x + h], u = s[3 + a][threadIdx.x + h];
+                if (l < s[a][threadIdx.x]) s[a][threadIdx.x] = l;
+                if (u > s[3 + a][threadIdx.x]) s[3 + a][threadIdx.x] = u;
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_bbox_final(double *part, int nb)
+{
+    __shared__ double s[6][kBlock];
+    for (int a = 0; a < 6; ++a) s[a][threadIdx.x] = part[a];  // block 0
+    for (int b = threadIdx.x; b < nb; b += kBlock)
+        for (int a = 0; a < 3; ++a) {
+            const double l = part[6 * b + a], u = part[6 * b + 3 + a];
+            if (l < s[a][threadIdx.x]) s[a][threadIdx.x] = l;
+            if (u > s[3 + a][threadIdx.x]) s[3 + a][threadIdx.x] = u;
+        }
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int a = 0; a < 3; ++a) {
+                const double l = s[a][threadIdx.x + h], u = s[3 + a][threadIdx.x + h];
+                if (l < s[a][threadIdx.x]) s[a][threadIdx.x] = l;
+                if (u > s[3 + a][threadIdx.x]) s[3 + a][threadIdx.x] = u;
+            }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) part[threadIdx.x] = s[threadIdx.x][0];
+}
+
+// Non-finite positions or masses set *flag (a vector store of 1).
+__global__ __launch_bounds__(kBlock) void k_check_finite(const double *x, const double *m,
+                                                         int64_t n, int *flag)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    if (!isfinite(x[3 * p]) || !isfinite(x[3 * p + 1]) || !isfinite(x[3 * p + 2]) ||
+        !isfinite(m[p]))
+        *flag = 1;
+}
+
+// ---- 2. keys ----------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_keys(const double *x, int64_t n, double r0,
+                                                 double r1, double r2, double rside,
+                                                 uint64_t *key, int32_t *idx)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
+    double c[3] = {r0, r1, r2};
+    double s = rside;
+    uint64_t k = 0;
+    for (int lev = 0; lev < kMaxDepth; ++lev) {
+        const double qd = s * 0.25;
+        unsigned o = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (xp[a] >= c[a]) {
+                o |= 1u << a;
+                c[a] = c[a] + qd;
+            } else {
+                c[a] = c[a] - qd;
+            }
+        }
+        k = (k << 3) | o;
+        s = s * 0.5;
+    }
+    key[p] = k;
+    idx[p] = (int32_t)p;
+}
+
+// ---- 3. cells ----------------------------------------------------------------
+
+__device__ __forceinline__ int32_t lower_bound(const uint64_t *v, int32_t lo, int32_t hi,
+                                               uint64_t x)
+{
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (v[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Octant boundaries of cell c: b[o] .. b[o+1] holds octant o.
+__device__ __forceinline__ void octant_bounds(const uint64_t *skey, const Cells &C,
+                                              int32_t c, int sh, int32_t b[9])
+{
+    const int32_t f = C.first[c], e = f + C.count[c];
+    const uint64_t k = C.key[c];
+    b[0] = f;
+    for (int o = 1; o < 8; ++o) b[o] = lower_bound(skey, b[o - 1], e, k | ((uint64_t)o << sh));
+    b[8] = e;
+}
+
+__global__ __launch_bounds__(kBlock) void k_level_count(Cells C, const uint64_t *skey,
+                                                        int32_t lo, int32_t hi, int nleaf,
+                                                        int32_t *nch)
+{
+    const int32_t c = lo + (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (c >= hi) return;
+    int32_t n = 0;
+    if (C.count[c] > nleaf && C.depth[c] < kMaxDepth) {
+        int32_t b[9];
+        octant_bounds(skey, C, c, 3 * (kMaxDepth - 1 - C.depth[c]), b);
+        for (int o = 0; o < 8; ++o) n += b[o + 1] > b[o];
+    }
+    nch[c - lo] = n;
+}
+
+__global__ __launch_bounds__(kBlock) void k_level_write(Cells C, const uint64_t *skey,
+                                                        int32_t lo, int32_t hi,
+                                                        const int32_t *nch,
+                                                        const int32_t *noff)
+{
+    const int32_t c = lo + (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (c >= hi) return;
+    if (nch[c - lo] == 0) return;
+    const int d = C.depth[c];
+    const int sh = 3 * (kMaxDepth - 1 - d);
+    int32_t b[9];
+    octant_bounds(skey, C, c, sh, b);
+    const int32_t child0 = hi + noff[c - lo];
+    const double qd = C.side[c] * 0.25;
+    const double pc[3] = {C.cx[c], C.cy[c], C.cz[c]};
+    int32_t j = 0;
+    for (int o = 0; o < 8; ++o) {
+        if (b[o + 1] <= b[o]) continue;
+        const int32_t ch = child0 + j++;
+        C.cx[ch] = pc[0] + (((o >> 0) & 1) ? qd : -qd);
+        C.cy[ch] = pc[1] + (((o >> 1) & 1) ? qd : -qd);
+        C.cz[ch] = pc[2] + (((o >> 2) & 1) ? qd : -qd);
+        C.side[ch] = C.side[c] * 0.5;
+        C.first[ch] = b[o];
+        C.count[ch] = b[o + 1] - b[o];
+        C.key[ch] = C.key[c] | ((uint64_t)o << sh);
+        C.depth[ch] = d + 1;
+        C.child0[ch] = -1;
+        C.nchild[ch] = 0;
+        C.parent[ch] = c;
+    }
+    C.child0[c] = child0;
+    C.nchild[c] = j;
+}
+
+// Leaves put their particles back in input order (insertion sort; a leaf
+// holds at most nleaf particles above depth 21, and at depth 21 its
+// particles share one key and are already in input order).
+__global__ __launch_bounds__(kBlock) void k_leaf_order(Cells C, int32_t ncell, int32_t *idx)
+{
+    const int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (c >= ncell || C.child0[c] >= 0) return;
+    const int32_t f = C.first[c], e = f + C.count[c];
+    for (int32_t i = f + 1; i < e; ++i) {
+        const int32_t v = idx[i];
+        int32_t j = i - 1;
+        while (j >= f && idx[j] > v) {
+            idx[j + 1] = idx[j];
+            --j;
+        }
+        idx[j + 1] = v;
+    }
+}
+
+// ---- 4. moments ---------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_moments_leaf(Cells C, int32_t ncell,
+                                                         const int32_t *idx, const double *x,
+                                                         const double *m, CellRec *pc)
+{
+    const int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (c >= ncell || C.child0[c] >= 0) return;
+    const int32_t f = C.first[c], e = f + C.count[c];
+    double M = 0.0, s[3] = {0.0, 0.0, 0.0};
+    for (int32_t k = f; k < e; ++k) {
+        const int64_t p = idx[k];
+        const double mp = m[p];
+        M += mp;
+        for (int a = 0; a < 3; ++a) s[a] += mp * x[3 * p + a];
+    }
+    const double ctr[3] = {C.cx[c], C.cy[c], C.cz[c]};
+    double cm[3];
+    for (int a = 0; a < 3; ++a) cm[a] = M > 0.0 ? s[a] / M : ctr[a];
+    double q6[6] = {0, 0, 0, 0, 0, 0}, T = 0.0;
+    for (int32_t k = f; k < e; ++k) {
+        const int64_t p = idx[k];
+        const double mp = m[p];
+        const double d0 = x[3 * p] - cm[0], d1 = x[3 * p + 1] - cm[1],
+                     d2 = x[3 * p + 2] - cm[2];
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        q6[0] += mp * (3.0 * d0 * d0 - r2);
+        q6[1] += mp * 3.0 * d0 * d1;
+        q6[2] += mp * 3.0 * d0 * d2;
+        q6[3] += mp * (3.0 * d1 * d1 - r2);
+        q6[4] += mp * 3.0 * d1 * d2;
+        q6[5] += mp * (3.0 * d2 * d2 - r2);
+        T += mp * r2;
+    }
+    CellRec r;
+    r.x = cm[0];
+    r.y = cm[1];
+    r.z = cm[2];
+    r.m = M;
+    r.q00 = q6[0];
+    r.q01 = q6[1];
+    r.q02 = q6[2];
+    r.q11 = q6[3];
+    r.q12 = q6[4];
+    r.q22 = q6[5];
+    r.t = T;
+    r.pad = 0.0;
+    pc[c] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_moments_level(Cells C, int32_t lo, int32_t hi,
+                                                          CellRec *pc)
+{
+    const int32_t c = lo + (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (c >= hi || C.child0[c] < 0) return;
+    const int32_t c0 = C.child0[c], nc = C.nchild[c];
+    double M = 0.0, s[3] = {0.0, 0.0, 0.0};
+    for (int32_t k = 0; k < nc; ++k) {
+        const CellRec &h = pc[c0 + k];
+        M += h.m;
+        s[0] += h.m * h.x;
+        s[1] += h.m * h.y;
+        s[2] += h.m * h.z;
+    }
+    const double ctr[3] = {C.cx[c], C.cy[c], C.cz[c]};
+    double cm[3];
+    for (int a = 0; a < 3; ++a) cm[a] = M > 0.0 ? s[a] / M : ctr[a];
+    double q6[6] = {0, 0, 0, 0, 0, 0}, T = 0.0;
+    for (int32_t k = 0; k < nc; ++k) {
+        const CellRec &h = pc[c0 + k];
+        const double Mc = h.m;
+        const double D[3] = {h.x - cm[0], h.y - cm[1], h.z - cm[2]};
+        const double D2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+        q6[0] += h.q00 + Mc * (3.0 * D[0] * D[0] - D2);
+        q6[1] += h.q01 + Mc * 3.0 * D[0] * D[1];
+        q6[2] += h.q02 + Mc * 3.0 * D[0] * D[2];
+        q6[3] += h.q11 + Mc * (3.0 * D[1] * D[1] - D2);
+        q6[4] += h.q12 + Mc * 3.0 * D[1] * D[2];
+        q6[5] += h.q22 + Mc * (3.0 * D[2] * D[2] - D2);
+        T += h.t + Mc * D2;
+    }
+    CellRec r;
+    r.x = cm[0];
+    r.y = cm[1];
+    r.z = cm[2];
+    r.m = M;
+    r.q00 = q6[0];
+    r.q01 = q6[1];
+    r.q02 = q6[2];
+    r.q11 = q6[3];
+    r.q12 = q6[4];
+    r.q22 = q6[5];
+    r.t = T;
+    r.pad = 0.0;
+    pc[c] = r;
+}
+
+// ---- 5. groups ----------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *v, int64_t n, int32_t val)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < n) v[k] = val;
+}
+
+// A cell is a group iff it has at most ncrit particles or is a leaf, and
+// its parent (if any) has more than ncrit.  gstart[first] = cell id.
+__global__ __launch_bounds__(kBlock) void k_group_mark(Cells C, int32_t ncell, int ncrit,
+                                                       int32_t *gstart)
+{
+    const int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (c >= ncell) return;
+    const bool cond = C.count[c] <= ncrit || C.child0[c] < 0;
+    const bool top = c == 0 || C.count[C.parent[c]] > ncrit;
+    if (cond && top) gstart[C.first[c]] = c;
+}
+
+struct NonNegative {
+    __host__ __device__ bool operator()(const int32_t &v) const { return v >= 0; }
+};
+
+// ---- 6. walk -----------------------------------------------------------------
+
+__device__ __forceinline__ double min_image(double v, double box)
+{
+    return box > 0.0 ? v - box * ::rint(v / box) : v;
+}
+
+__device__ __forceinline__ bool contains(uint64_t ckey, int cdepth, uint64_t gkey,
+                                         int gdepth)
+{
+    if (cdepth > gdepth) return false;
+    const int sh = 3 * (kMaxDepth - cdepth);
+    if (sh >= 64) return true;
+    return (ckey >> sh) == (gkey >> sh);
+}
+
+__global__ __launch_bounds__(kBlock) void k_walk_cells(Cells C, int32_t ncell,
+                                                       const CellRec *pc, WCell *wc,
+                                                       WLink *wl)
+{
+    const int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (c >= ncell) return;
+    WCell w;
+    w.cx = C.cx[c];
+    w.cy = C.cy[c];
+    w.cz = C.cz[c];
+    w.side = C.side[c];
+    w.mx = pc[c].x;
+    w.my = pc[c].y;
+    w.mz = pc[c].z;
+    w.key = C.key[c];
+    wc[c] = w;
+    WLink l;
+    l.first = C.first[c];
+    l.count = C.count[c];
+    l.child0 = C.child0[c];
+    l.nd = C.nchild[c] | (C.depth[c] << 8);
+    wl[c] = l;
+}
+
+struct WalkArgs {
+    const int32_t *groups;
+    int64_t ng;
+    const WCell *wc;
+    const WLink *wl;
+    double theta2, rcut, box;
+    int64_t *jp_cnt, *jc_cnt;          // count pass
+    const int64_t *jp_off, *jc_off;    // fill pass
+    int32_t *jp_idx, *jc_idx;
+    int *flag;                         // set if a stack would overflow
+};
+
+template <bool FILL>
+__global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
+{
+    __shared__ int32_t s_cur[kFrames][kWalkBlock];
+    __shared__ int32_t s_end[kFrames][kWalkBlock];
+    const int lane = threadIdx.x;
+    const int64_t gi = (int64_t)blockIdx.x * kWalkBlock + lane;
+    if (gi >= W.ng) return;  // no block-wide synchronisation below
+    const int32_t gid = W.groups[gi];
+    const WCell G = W.wc[gid];
+    const int gdepth = W.wl[gid].nd >> 8;
+    const double gc[3] = {G.cx, G.cy, G.cz};
+    const double box = W.box;
+    int64_t np = 0, nc = 0;
+    const int64_t pb = FILL ? W.jp_off[gi] : 0, cb = FILL ? W.jc_off[gi] : 0;
+    int sp = 0;
+    int32_t id = 0;  // the root first
+    for (;;) {
+        const WCell C = W.wc[id];
+        const WLink L = W.wl[id];
+        const int cdepth = L.nd >> 8;
+        bool done = false;
+        if (!contains(C.key, cdepth, G.key, gdepth)) {
+            bool skip = false;
+            if (W.rcut > 0.0) {
+                const double cc[3] = {C.cx, C.cy, C.cz};
+                double d2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const double v = ::fabs(min_image(cc[k] - gc[k], box)) -
+                                     0.5 * (C.side + G.side);
+                    if (v > 0.0) d2 += v * v;
+                }
+                skip = d2 > W.rcut * W.rcut;
+            }
+            if (skip) {
+                done = true;
+            } else {
+                const double cm[3] = {C.mx, C.my, C.mz};
+                double d2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const double v = ::fabs(min_image(cm[k] - gc[k], box)) - 0.5 * G.side;
+                    if (v > 0.0) d2 += v * v;
+                }
+                if (C.side * C.side < W.theta2 * d2) {
+                    if (L.count == 1) {
+                        if (FILL) W.jp_idx[pb + np] = L.first;
+                        ++np;
+                    } else {
+                        if (FILL) W.jc_idx[cb + nc] = id;
+                        ++nc;
+                    }
+                    done = true;
+                }
+            }
+        }
+        if (!done) {
+            if (L.child0 < 0) {
+                for (int32_t k = L.first; k < L.first + L.count; ++k) {
+                    if (FILL) W.jp_idx[pb + np] = k;
+                    ++np;
+                }
+            } else if (sp < kFrames) {
+                s_cur[sp][lane] = L.child0;
+                s_end[sp][lane] = L.child0 + (L.nd & 0xff);
+                ++sp;
+            } else {
+                *W.flag = 1;
+            }
+        }
+        // next cell: the next unvisited child of the deepest open frame
+        id = -1;
+        while (sp > 0) {
+            const int32_t cur = s_cur[sp - 1][lane];
+            if (cur < s_end[sp - 1][lane]) {
+                s_cur[sp - 1][lane] = cur + 1;
+                id = cur;
+                break;
+            }
+            --sp;
+        }
+        if (id < 0) break;
+    }
+    if (!FILL) {
+        W.jp_cnt[gi] = np;
+        W.jc_cnt[gi] = nc;
+    }
+}
+
+// ---- outputs -----------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_particles_out(const int32_t *idx, int64_t n,
+                                                          const double *x, const double *m,
+                                                          PartRec *pool, double *xi,
+                                                          double *yi, double *zi)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int64_t p = idx[k];
+    PartRec r;
+    r.x = x[3 * p];
+    r.y = x[3 * p + 1];
+    r.z = x[3 * p + 2];
+    r.m = m[p];
+    pool[k] = r;
+    xi[k] = r.x;
+    yi[k] = r.y;
+    zi[k] = r.z;
+}
+
+__global__ __launch_bounds__(kBlock) void k_groups_out(Cells C, const int32_t *groups,
+                                                       int64_t ng, int64_t n, int64_t *i_off,
+                                                       double *gcx, double *gcy, double *gcz)
+{
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g > ng) return;
+    if (g == ng) {
+        i_off[ng] = n;
+        return;
+    }
+    const int32_t c = groups[g];
+    i_off[g] = C.first[c];
+    gcx[g] = C.cx[c];
+    gcy[g] = C.cy[c];
+    gcz[g] = C.cz[c];
+}
+
+__global__ __launch_bounds__(kBlock) void k_set_cell(Cells C, double r0, double r1, double r2,
+                                                     double rside, int32_t n)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    C.cx[0] = r0;
+    C.cy[0] = r1;
+    C.cz[0] = r2;
+    C.side[0] = rside;
+    C.first[0] = 0;
+    C.count[0] = n;
+    C.key[0] = 0;
+    C.depth[0] = 0;
+    C.child0[0] = -1;
+    C.nchild[0] = 0;
+    C.parent[0] = -1;
+}
+
+}  // namespace
+
+// ---- host orchestration ---------------------------------------------------------
+
+int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string *err)
+{
+    DevArray *B = O.buf;
+    const int64_t n = P.n;
+    int code = BHQ_OK;
+    const char *what = "";
+    auto hip = [&](hipError_t e, const char *w) -> bool {
+        if (e == hipSuccess) return true;
+        code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? BHQ_E_NOMEM
+                                                                            : BHQ_E_HIP;
+        what = w;
+        return false;
+    };
+    auto fail = [&]() -> int {
+        if (err) {
+            *err = std::string("device list build: ") + what;
+            if (code == BHQ_E_HIP || code == BHQ_E_NOMEM)
+                *err += std::string(" (") + hipGetErrorString(hipGetLastError()) + ")";
+        }
+        return code;
+    };
+#define STEP(expr, w)              \
+    do {                           \
+        if (!hip((expr), (w))) return fail(); \
+    } while (0)
+#define LAUNCHED(w) STEP(hipGetLastError(), w)
+
+    // input check and root cube
+    STEP(B[T_FLAG].reserve(64), "allocation");
+    STEP(hipMemsetAsync(B[T_FLAG].p, 0, 64, s), "memset");
+    hipLaunchKernelGGL(k_check_finite, dim3(blocks(n, kBlock)), dim3(kBlock), 0, s, P.x, P.m,
+                       n, B[T_FLAG].as<int>());
+    LAUNCHED("finite check");
+    int hflag = 0;
+    STEP(hipMemcpyAsync(&hflag, B[T_FLAG].p, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    STEP(hipStreamSynchronize(s), "sync");
+    if (hflag) {
+        code = BHQ_E_NONFINITE;
+        what = "non-finite position or mass";
+        return fail();
+    }
+    double rc[3], rside;
+    if (P.box > 0.0) {
+        rc[0] = rc[1] = rc[2] = 0.5 * P.box;
+        rside = P.box;
+    } else {
+        const int nb = (int)std::min<int64_t>(kBboxBlocks, blocks(n, kBlock));
+        STEP(B[T_BBOX].reserve((size_t)nb * 6 * sizeof(double)), "allocation");
+        hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kBlock), 0, s, P.x, n,
+                           B[T_BBOX].as<double>());
+        LAUNCHED("bounding box");
+        hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBlock), 0, s, B[T_BBOX].as<double>(),
+                           nb);
+        LAUNCHED("bounding box");
+        double bb[6];
+        STEP(hipMemcpyAsync(bb, B[T_BBOX].p, sizeof(bb), hipMemcpyDeviceToHost, s), "copy");
+        STEP(hipStreamSynchronize(s), "sync");
+        double ext = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            rc[k] = 0.5 * (bb[k] + bb[3 + k]);
+            ext = std::max(ext, bb[3 + k] - bb[k]);
+        }
+        rside = ext > 0.0 ? ext * (1.0 + std::ldexp(1.0, -20)) : 1.0;
+    }
+
+    // keys, sort
+    STEP(B[T_KEY].reserve((size_t)n * 8), "allocation");
+    STEP(B[T_KEY2].reserve((size_t)n * 8), "allocation");
+    STEP(B[T_IDX0].reserve((size_t)n * 4), "allocation");
+    STEP(O.order->reserve((size_t)n * 4), "allocation");
+    hipLaunchKernelGGL(k_keys, dim3(blocks(n, kBlock)), dim3(kBlock), 0, s, P.x, n, rc[0],
+                       rc[1], rc[2], rside, B[T_KEY].as<uint64_t>(), B[T_IDX0].as<int32_t>());
+    LAUNCHED("keys");
+    size_t tmp = 0;
+    STEP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, B[T_KEY].as<uint64_t>(),
+                                            B[T_KEY2].as<uint64_t>(), B[T_IDX0].as<int32_t>(),
+                                            O.order->as<int32_t>(), (int)n, 0, 3 * kMaxDepth, s),
+         "sort size");
+    STEP(B[T_SORT].reserve(tmp), "allocation");
+    STEP(hipcub::DeviceRadixSort::SortPairs(B[T_SORT].p, tmp, B[T_KEY].as<uint64_t>(),
+                                            B[T_KEY2].as<uint64_t>(), B[T_IDX0].as<int32_t>(),
+                                            O.order->as<int32_t>(), (int)n, 0, 3 * kMaxDepth, s),
+         "sort");
+    const uint64_t *skey = B[T_KEY2].as<uint64_t>();
+    int32_t *idx = O.order->as<int32_t>();
+
+    // cells, level by level
+    size_t cap = B[T_CX].p ? B[T_CX].cap / 8 : 0;
+    const TreeBuf cbuf8[] = {T_CX, T_CY, T_CZ, T_SIDE, T_CKEY};
+    const TreeBuf cbuf4[] = {T_FIRST, T_COUNT, T_CHILD0, T_NCHILD, T_PARENT, T_DEPTH};
+    auto cells = [&]() {
+        Cells C;
+        C.cx = B[T_CX].as<double>();
+        C.cy = B[T_CY].as<double>();
+        C.cz = B[T_CZ].as<double>();
+        C.side = B[T_SIDE].as<double>();
+        C.key = B[T_CKEY].as<uint64_t>();
+        C.first = B[T_FIRST].as<int32_t>();
+        C.count = B[T_COUNT].as<int32_t>();
+        C.child0 = B[T_CHILD0].as<int32_t>();
+        C.nchild = B[T_NCHILD].as<int32_t>();
+        C.parent = B[T_PARENT].as<int32_t>();
+        C.depth = B[T_DEPTH].as<int32_t>();
+        return C;
+    };
+    auto ensure = [&](size_t need, size_t used) -> bool {
+        if (need <= cap) return true;
+        size_t nc = std::max(need, cap + cap / 2);
+        for (TreeBuf b : cbuf8)
+            if (!hip(B[b].grow(nc * 8, used * 8, s), "allocation")) return false;
+        for (TreeBuf b : cbuf4)
+            if (!hip(B[b].grow(nc * 4, used * 4, s), "allocation")) return false;
+        cap = nc;
+        return true;
+    };
+    if (!ensure((size_t)std::max<int64_t>(1024, n / 2), 0)) return fail();
+    hipLaunchKernelGGL(k_set_cell, dim3(1), dim3(64), 0, s, cells(), rc[0], rc[1], rc[2],
+                       rside, (int32_t)n);
+    LAUNCHED("root");
+    std::vector<int32_t> level{0, 1};  // level l is cells [level[l], level[l+1])
+    STEP(B[T_NCH].reserve((size_t)std::max<int64_t>(n, 1) * 4 + 4), "allocation");
+    STEP(B[T_NOFF].reserve((size_t)std::max<int64_t>(n, 1) * 4 + 4), "allocation");
+    for (int lev = 0; lev < kMaxDepth; ++lev) {
+        const int32_t lo = level[(size_t)lev], hi = level[(size_t)lev + 1];
+        const int32_t w = hi - lo;
+        if (w <= 0) break;
+        hipLaunchKernelGGL(k_level_count, dim3(blocks(w, kBlock)), dim3(kBlock), 0, s, cells(),
+                           skey, lo, hi, P.nleaf, B[T_NCH].as<int32_t>());
+        LAUNCHED("level count");
+        size_t st = 0;
+        STEP(hipcub::DeviceScan::ExclusiveSum(nullptr, st, B[T_NCH].as<int32_t>(),
+                                              B[T_NOFF].as<int32_t>(), w, s),
+             "scan size");
+        STEP(B[T_SORT].reserve(std::max(st, B[T_SORT].cap)), "allocation");
+        STEP(hipcub::DeviceScan::ExclusiveSum(B[T_SORT].p, st, B[T_NCH].as<int32_t>(),
+                                              B[T_NOFF].as<int32_t>(), w, s),
+             "scan");
+        int32_t tail[2];
+        STEP(hipMemcpyAsync(&tail[0], B[T_NOFF].as<int32_t>() + (w - 1), 4,
+                            hipMemcpyDeviceToHost, s),
+             "copy");
+        STEP(hipMemcpyAsync(&tail[1], B[T_NCH].as<int32_t>() + (w - 1), 4,
+                            hipMemcpyDeviceToHost, s),
+             "copy");
+        STEP(hipStreamSynchronize(s), "sync");
+        const int64_t total = (int64_t)tail[0] + tail[1];
+        if (total == 0) break;
+        if ((int64_t)hi + total > 0x7fffffffLL) {
+            code = BHQ_E_RANGE;
+            what = "more than 2^31 cells";
+            return fail();
+        }
+        if (!ensure((size_t)(hi + total), (size_t)hi)) return fail();
+        hipLaunchKernelGGL(k_level_write, dim3(blocks(w, kBlock)), dim3(kBlock), 0, s, cells(),
+                           skey, lo, hi, B[T_NCH].as<int32_t>(), B[T_NOFF].as<int32_t>());
+        LAUNCHED("level write");
+        level.push_back((int32_t)(hi + total));
+    }
+    const int32_t ncell = level.back();
+    hipLaunchKernelGGL(k_leaf_order, dim3(blocks(ncell, kBlock)), dim3(kBlock), 0, s, cells(),
+                       ncell, idx);
+    LAUNCHED("leaf order");
+
+    // moments straight into the cell pool
+    STEP(O.pool_c->reserve((size_t)ncell * sizeof(CellRec)), "allocation");
+    CellRec *pc = O.pool_c->as<CellRec>();
+    hipLaunchKernelGGL(k_moments_leaf, dim3(blocks(ncell, kBlock)), dim3(kBlock), 0, s,
+                       cells(), ncell, idx, P.x, P.m, pc);
+    LAUNCHED("leaf moments");
+    for (int l = (int)level.size() - 2; l >= 0; --l) {
+        const int32_t lo = level[(size_t)l], hi = level[(size_t)l + 1];
+        hipLaunchKernelGGL(k_moments_level, dim3(blocks(hi - lo, kBlock)), dim3(kBlock), 0, s,
+                           cells(), lo, hi, pc);
+        LAUNCHED("cell moments");
+    }
+
+    // groups in depth-first order
+    STEP(B[T_GSTART].reserve((size_t)n * 4), "allocation");
+    STEP(B[T_GROUPS].reserve((size_t)n * 4), "allocation");
+    STEP(B[T_NSEL].reserve(64), "allocation");
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(n, kBlock)), dim3(kBlock), 0, s,
+                       B[T_GSTART].as<int32_t>(), n, -1);
+    LAUNCHED("fill");
+    hipLaunchKernelGGL(k_group_mark, dim3(blocks(ncell, kBlock)), dim3(kBlock), 0, s, cells(),
+                       ncell, P.ncrit, B[T_GSTART].as<int32_t>());
+    LAUNCHED("groups");
+    {
+        size_t st = 0;
+        STEP(hipcub::DeviceSelect::If(nullptr, st, B[T_GSTART].as<int32_t>(),
+                                      B[T_GROUPS].as<int32_t>(), B[T_NSEL].as<int32_t>(),
+                                      (int)n, NonNegative(), s),
+             "select size");
+        STEP(B[T_SORT].reserve(std::max(st, B[T_SORT].cap)), "allocation");
+        STEP(hipcub::DeviceSelect::If(B[T_SORT].p, st, B[T_GSTART].as<int32_t>(),
+                                      B[T_GROUPS].as<int32_t>(), B[T_NSEL].as<int32_t>(),
+                                      (int)n, NonNegative(), s),
+             "select");
+    }
+    int32_t ng32 = 0;
+    STEP(hipMemcpyAsync(&ng32, B[T_NSEL].p, 4, hipMemcpyDeviceToHost, s), "copy");
+    STEP(hipStreamSynchronize(s), "sync");
+    const int64_t ng = ng32;
+    const int32_t *groups = B[T_GROUPS].as<int32_t>();
+
+    // walk: count, offsets, fill
+    STEP(B[T_WC].reserve((size_t)ncell * sizeof(WCell)), "allocation");
+    STEP(B[T_WL].reserve((size_t)ncell * sizeof(WLink)), "allocation");
+    hipLaunchKernelGGL(k_walk_cells, dim3(blocks(ncell, kBlock)), dim3(kBlock), 0, s, cells(),
+                       ncell, pc, B[T_WC].as<WCell>(), B[T_WL].as<WLink>());
+    LAUNCHED("walk cells");
+    STEP(B[T_JPCNT].reserve((size_t)(ng + 1) * 8), "allocation");
+    STEP(B[T_JCCNT].reserve((size_t)(ng + 1) * 8), "allocation");
+    STEP(O.jp_off->reserve((size_t)(ng + 1) * 8), "allocation");
+    STEP(O.jc_off->reserve((size_t)(ng + 1) * 8), "allocation");
+    STEP(hipMemsetAsync(B[T_JPCNT].as<int64_t>() + ng, 0, 8, s), "memset");
+    STEP(hipMemsetAsync(B[T_JCCNT].as<int64_t>() + ng, 0, 8, s), "memset");
+    WalkArgs W{};
+    W.groups = groups;
+    W.ng = ng;
+    W.wc = B[T_WC].as<WCell>();
+    W.wl = B[T_WL].as<WLink>();
+    W.theta2 = P.theta * P.theta;
+    W.rcut = P.rcut;
+    W.box = P.box;
+    W.jp_cnt = B[T_JPCNT].as<int64_t>();
+    W.jc_cnt = B[T_JCCNT].as<int64_t>();
+    W.flag = B[T_FLAG].as<int>();
+    hipLaunchKernelGGL(k_walk<false>, dim3(blocks(ng, kWalkBlock)), dim3(kWalkBlock), 0, s, W);
+    LAUNCHED("walk (count)");
+    for (int pass = 0; pass < 2; ++pass) {
+        int64_t *cnt = pass ? B[T_JCCNT].as<int64_t>() : B[T_JPCNT].as<int64_t>();
+        int64_t *off = pass ? O.jc_off->as<int64_t>() : O.jp_off->as<int64_t>();
+        size_t st = 0;
+        STEP(hipcub::DeviceScan::ExclusiveSum(nullptr, st, cnt, off, (int)(ng + 1), s),
+             "scan size");
+        STEP(B[T_SORT].reserve(std::max(st, B[T_SORT].cap)), "allocation");
+        STEP(hipcub::DeviceScan::ExclusiveSum(B[T_SORT].p, st, cnt, off, (int)(ng + 1), s),
+             "scan");
+    }
+    try {
+        O.h_jp_off.resize((size_t)ng + 1);
+        O.h_jc_off.resize((size_t)ng + 1);
+        O.h_i_off.resize((size_t)ng + 1);
+    } catch (const std::bad_alloc &) {
+        code = BHQ_E_NOMEM;
+        what = "host offsets";
+        return fail();
+    }
+    STEP(hipMemcpyAsync(O.h_jp_off.data(), O.jp_off->p, (size_t)(ng + 1) * 8,
+                        hipMemcpyDeviceToHost, s),
+         "copy");
+    STEP(hipMemcpyAsync(O.h_jc_off.data(), O.jc_off->p, (size_t)(ng + 1) * 8,
+                        hipMemcpyDeviceToHost, s),
+         "copy");
+    STEP(hipMemcpyAsync(&hflag, B[T_FLAG].p, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    STEP(hipStreamSynchronize(s), "sync");
+    if (hflag) {
+        code = BHQ_E_RANGE;
+        what = "walk stack overflow";
+        return fail();
+    }
+    const int64_t njp = O.h_jp_off[(size_t)ng], njc = O.h_jc_off[(size_t)ng];
+    STEP(O.jp_idx->reserve((size_t)std::max<int64_t>(njp, 1) * 4), "allocation");
+    STEP(O.jc_idx->reserve((size_t)std::max<int64_t>(njc, 1) * 4), "allocation");
+    W.jp_off = O.jp_off->as<int64_t>();
+    W.jc_off = O.jc_off->as<int64_t>();
+    W.jp_idx = O.jp_idx->as<int32_t>();
+    W.jc_idx = O.jc_idx->as<int32_t>();
+    hipLaunchKernelGGL(k_walk<true>, dim3(blocks(ng, kWalkBlock)), dim3(kWalkBlock), 0, s, W);
+    LAUNCHED("walk (fill)");
+
+    // particles and groups in the layout of the force context
+    STEP(O.pool_p->reserve((size_t)n * sizeof(PartRec)), "allocation");
+    STEP(O.xi->reserve((size_t)n * 8), "allocation");
+    STEP(O.yi->reserve((size_t)n * 8), "allocation");
+    STEP(O.zi->reserve((size_t)n * 8), "allocation");
+    STEP(O.i_off->reserve((size_t)(ng + 1) * 8), "allocation");
+    STEP(O.gcx->reserve((size_t)ng * 8), "allocation");
+    STEP(O.gcy->reserve((size_t)ng * 8), "allocation");
+    STEP(O.gcz->reserve((size_t)ng * 8), "allocation");
+    hipLaunchKernelGGL(k_particles_out, dim3(blocks(n, kBlock)), dim3(kBlock), 0, s, idx, n,
+                       P.x, P.m, O.pool_p->as<PartRec>(), O.xi->as<double>(),
+                       O.yi->as<double>(), O.zi->as<double>());
+    LAUNCHED("particle pool");
+    hipLaunchKernelGGL(k_groups_out, dim3(blocks(ng + 1, kBlock)), dim3(kBlock), 0, s, cells(),
+                       groups, ng, n, O.i_off->as<int64_t>(), O.gcx->as<double>(),
+                       O.gcy->as<double>(), O.gcz->as<double>());
+    LAUNCHED("groups");
+    STEP(hipMemcpyAsync(O.h_i_off.data(), O.i_off->p, (size_t)(ng + 1) * 8,
+                        hipMemcpyDeviceToHost, s),
+         "copy");
+    STEP(hipStreamSynchronize(s), "sync");
+    O.ng = ng;
+    O.njp = njp;
+    O.njc = njc;
+    O.ncell = ncell;
+#undef STEP
+#undef LAUNCHED
+    return BHQ_OK;
+}
+
+}  // namespace bhq

@@ -1,0 +1,226 @@
+"""GPU: tree, groups and interaction lists built on the device
+(bhq_build_lists_device) against the host builder (bhq_build_lists), whose
+lists the CPU tests tie to the oracle's tree walk.  Index work is compared
+bit for bit: particle order, group offsets, every list entry in order, and
+the cell moments (the device computes them with the host's operations in
+the host's order).  Forces from device-built lists then equal, bit for bit,
+forces from the host-built lists, and match the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from _parity import assert_parity, errors, log
+from paper_1812_07313_amd import bhq, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(x, m):
+    xt = torch.from_numpy(np.ascontiguousarray(x, np.float64)).cuda()
+    mt = torch.from_numpy(np.ascontiguousarray(m, np.float64)).cuda()
+    return xt, mt
+
+
+def _host(x, m, theta, ncrit, nleaf=8, box=0.0, rcut=0.0):
+    L = bhq.bhq_build_lists(x, m, theta, ncrit, nleaf=nleaf, box=box, rcut=rcut)
+    try:
+        out = bhq.bhq_lists_export(L, len(m))
+        out["cells"] = bhq.bhq_lists_cells(L)
+        out["sizes"] = bhq.bhq_lists_sizes(L)
+    finally:
+        bhq.bhq_lists_free(L)
+    return out
+
+
+def _device(ctx, x, m, theta, ncrit, nleaf=8, box=0.0, rcut=0.0):
+    xt, mt = _dev(x, m)
+    bhq.bhq_build_lists_device(ctx, xt, mt, theta, ncrit, nleaf, box, rcut)
+    torch.cuda.synchronize()
+    out = bhq.bhq_get_lists(ctx, len(m))
+    out["cells"] = bhq.bhq_get_cells(ctx)
+    out["sizes"] = bhq.bhq_get_lists_sizes(ctx)
+    return out
+
+
+def _same(h, d, name):
+    assert h["sizes"] == d["sizes"], (name, h["sizes"], d["sizes"])
+    for k in ("i_idx", "i_off", "jp_off", "jp_idx", "jc_off"):
+        assert np.array_equal(h[k], d[k]), (name, k)
+    assert np.array_equal(h["jc_cell"], d["jc_cell"]), (name, "jc_cell")
+    for k in ("com", "mass", "q", "trace"):
+        a, b = h["cells"][k], d["cells"][k]
+        assert np.array_equal(a.view(np.int64), b.view(np.int64)), (name, k)
+
+
+CASES = [
+    ("cube 65536", lambda: synth.uniform_cube(1 << 16, synth.rng(1)), 0.5, 256, 8, 0.0, 0.0),
+    ("plummer 16384", lambda: synth.plummer(16384, synth.rng(0)), 0.5, 64, 8, 0.0, 0.0),
+    ("clustered 32768", lambda: synth.clustered(1 << 15, synth.rng(2)), 0.6, 128, 8, 0.0, 0.0),
+    ("cube theta 0", lambda: synth.uniform_cube(3000, synth.rng(5)), 0.0, 64, 8, 0.0, 0.0),
+    ("cube ncrit=nleaf=1", lambda: synth.uniform_cube(2000, synth.rng(6)), 0.7, 1, 1, 0.0, 0.0),
+    ("lattice 32^3 periodic", lambda: synth.perturbed_lattice(32, synth.rng(4)), 0.5, 64, 8,
+     1.0, 4.5 * 1.25 / 32),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_device_lists_equal_host(case):
+    name, gen, theta, ncrit, nleaf, box, rcut = case
+    x, m = gen()
+    log("case device lists %s (n=%d)" % (name, len(m)))
+    h = _host(x, m, theta, ncrit, nleaf, box, rcut)
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        d = _device(ctx, x, m, theta, ncrit, nleaf, box, rcut)
+    finally:
+        bhq.bhq_destroy(ctx)
+    log("  sizes %s" % (d["sizes"],))
+    _same(h, d, name)
+
+
+def test_degenerate_inputs():
+    """One particle; two; coincident particles (a chain of cells down to
+    depth 21 holding more than nleaf); a flat (2-d) distribution."""
+    g = np.random.default_rng(9)
+    cases = [
+        ("one", np.array([[0.3, 0.2, 0.1]]), np.array([1.0])),
+        ("two", np.array([[0.0, 0.0, 0.0], [1.0, 2.0, 3.0]]), np.array([1.0, 2.0])),
+        ("coincident", np.vstack([np.full((20, 3), 0.25), g.random((50, 3))]),
+         np.full(70, 1.0 / 70)),
+        ("flat", np.column_stack([g.random(500), g.random(500), np.zeros(500)]),
+         np.full(500, 0.002)),
+    ]
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        for name, x, m in cases:
+            log("case device lists degenerate %s" % name)
+            for ncrit, nleaf in ((8, 8), (16, 2)):
+                h = _host(x, m, 0.5, ncrit, nleaf)
+                d = _device(ctx, x, m, 0.5, ncrit, nleaf)
+                _same(h, d, name)
+    finally:
+        bhq.bhq_destroy(ctx)
+
+
+@pytest.mark.parametrize("prec", [bhq.FP32_OFS64, bhq.FP64])
+def test_forces_from_device_lists(prec):
+    """Device-built lists: the same force bits as host-built index lists,
+    and parity with the FP64 oracle's own tree and lists."""
+    x, m = synth.plummer(16384, synth.rng(0))
+    eps = 1.0 / 64.0
+    ctx_d = bhq.bhq_create(0, bhq.QUAD, prec)
+    ctx_h = bhq.bhq_create(0, bhq.QUAD, prec)
+    try:
+        xt, mt = _dev(x, m)
+        bhq.bhq_build_lists_device(ctx_d, xt, mt, 0.5, 64)
+        bhq.bhq_set_eps(ctx_d, eps)
+        L = bhq.bhq_build_lists(x, m, 0.5, 64)
+        bhq.bhq_set_lists_indexed(ctx_h, L, x, m)
+        bhq.bhq_lists_free(L)
+        bhq.bhq_set_eps(ctx_h, eps)
+        res = []
+        for ctx in (ctx_d, ctx_h):
+            bhq.bhq_compute(ctx)
+            res.append(bhq.bhq_get_result(ctx, len(m)))
+        assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+        idx = bhq.bhq_get_lists(ctx_d, len(m))["i_idx"]
+        a = np.zeros_like(res[0][0])
+        p = np.zeros_like(res[0][1])
+        a[idx] = res[0][0]
+        p[idx] = res[0][1]
+        T = orc.Tree(x, m, 0.5, 64)
+        a_ref, p_ref = orc.eval_lists(orc.QUAD, orc.materialise(T, x, m), x, eps * eps)
+        err = errors(a, p, a_ref, p_ref)
+        log("case device-list forces %s: %s" % (bhq.PRECISION_NAMES[prec], err))
+        assert_parity(err, prec, "device lists")
+    finally:
+        bhq.bhq_destroy(ctx_d)
+        bhq.bhq_destroy(ctx_h)
+
+
+def test_split_forces_from_device_lists():
+    """Periodic split kernel on device-built lists equals host-built."""
+    x, m = synth.perturbed_lattice(24, synth.rng(4))
+    rs = 1.25 / 24
+    rcut = 4.5 * rs
+    ctx_d = bhq.bhq_create(0, bhq.SPLIT_QUAD, bhq.FP32_OFS64)
+    ctx_h = bhq.bhq_create(0, bhq.SPLIT_QUAD, bhq.FP32_OFS64)
+    try:
+        xt, mt = _dev(x, m)
+        bhq.bhq_build_lists_device(ctx_d, xt, mt, 0.5, 64, 8, 1.0, rcut)
+        L = bhq.bhq_build_lists(x, m, 0.5, 64, box=1.0, rcut=rcut)
+        bhq.bhq_set_lists_indexed(ctx_h, L, x, m)
+        bhq.bhq_lists_free(L)
+        res = []
+        for ctx in (ctx_d, ctx_h):
+            bhq.bhq_set_split(ctx, rs, rcut, 1.0)
+            bhq.bhq_compute(ctx)
+            res.append(bhq.bhq_get_result(ctx, len(m)))
+        assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    finally:
+        bhq.bhq_destroy(ctx_d)
+        bhq.bhq_destroy(ctx_h)
+
+
+def test_device_build_errors():
+    x, m = synth.uniform_cube(1000, synth.rng(3))
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        xt, mt = _dev(x, m)
+        lib = bhq.lib()
+        # host memory instead of device memory
+        rc = lib.bhq_build_lists_device(ctx, len(m), x.ctypes.data, m.ctypes.data, 0.5, 64,
+                                        8, 0.0, 0.0, None)
+        assert rc == bhq.E_ARG, rc
+        # a count far beyond the allocation
+        rc = lib.bhq_build_lists_device(ctx, 1 << 30, xt.data_ptr(), mt.data_ptr(), 0.5, 64,
+                                        8, 0.0, 0.0, None)
+        assert rc == bhq.E_RANGE, rc
+        for args in ((-0.1, 64, 8, 0.0, 0.0), (0.5, 0, 8, 0.0, 0.0), (0.5, 8, 16, 0.0, 0.0),
+                     (0.5, 64, 8, -1.0, 0.0), (0.5, 64, 8, 0.0, -1.0)):
+            with pytest.raises(bhq.BhqError) as ei:
+                bhq.bhq_build_lists_device(ctx, xt, mt, *args)
+            assert ei.value.code == bhq.E_ARG
+        # a non-finite position: error, and no lists left in the context
+        bhq.bhq_build_lists_device(ctx, xt, mt, 0.5, 64)
+        bhq.bhq_set_eps(ctx, 0.01)
+        bhq.bhq_compute(ctx)
+        xt[17, 1] = float("nan")
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_build_lists_device(ctx, xt, mt, 0.5, 64)
+        assert ei.value.code == bhq.E_NONFINITE
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_compute(ctx)
+        assert ei.value.code == bhq.E_STATE
+        with pytest.raises(TypeError):
+            bhq.bhq_build_lists_device(ctx, torch.from_numpy(x), torch.from_numpy(m), 0.5, 64)
+    finally:
+        bhq.bhq_destroy(ctx)
+
+
+def test_rebuild_reuses_context():
+    """Two builds of different sizes in a row on one context, each equal
+    to the host builder's lists; the second evaluates correctly."""
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        for n, seed in ((40000, 11), (7000, 12)):
+            x, m = synth.plummer(n, synth.rng(seed))
+            log("case device rebuild n=%d" % n)
+            h = _host(x, m, 0.6, 64)
+            d = _device(ctx, x, m, 0.6, 64)
+            _same(h, d, "rebuild %d" % n)
+        bhq.bhq_set_eps(ctx, 0.01)
+        bhq.bhq_compute(ctx)
+        a, p = bhq.bhq_get_result(ctx, len(m))
+        idx = bhq.bhq_get_lists(ctx, len(m))["i_idx"]
+        aa = np.zeros_like(a)
+        pp = np.zeros_like(p)
+        aa[idx] = a
+        pp[idx] = p
+        T = orc.Tree(x, m, 0.6, 64)
+        a_ref, p_ref = orc.eval_lists(orc.QUAD, orc.materialise(T, x, m), x, 1e-4)
+        assert_parity(errors(aa, pp, a_ref, p_ref), bhq.FP32_OFS64, "rebuild")
+    finally:
+        bhq.bhq_destroy(ctx)
