@@ -136,6 +136,30 @@ def build_lists(W, theta, ncrit):
     return L, time.perf_counter() - t0
 
 
+def device_list_build(torch, W, theta, ncrit, sizes, repeats=3):
+    """Time bhq_build_lists_device on the workload (particles already in
+    device memory; the call returns when the lists are complete) and check
+    that it gives the host builder's list sizes."""
+    if W.get("sys_off") is not None:
+        return None
+    xt = torch.from_numpy(np.ascontiguousarray(W["x"])).cuda()
+    mt = torch.from_numpy(np.ascontiguousarray(W["m"])).cuda()
+    ctx = bhq.bhq_create(0, W["kernel"], bhq.FP32_OFS64)
+    try:
+        ts = []
+        for _ in range(repeats + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bhq.bhq_build_lists_device(ctx, xt, mt, theta, ncrit, min(8, ncrit),
+                                       W.get("box", 0.0), W.get("rcut", 0.0))
+            ts.append(time.perf_counter() - t0)
+        same = bhq.bhq_get_lists_sizes(ctx) == tuple(sizes)
+    finally:
+        bhq.bhq_destroy(ctx)
+    return {"ms": round(float(np.median(ts[1:])) * 1e3, 3),
+            "first_call_ms": round(ts[0] * 1e3, 3), "sizes_equal_host": bool(same)}
+
+
 def upload(ctx, W, L, indexed=False):
     t0 = time.perf_counter()
     if indexed:
@@ -420,7 +444,7 @@ def main():
         args.order = {v: k for k, v in ORDERS.items()}[tuned["order"]]
         log("autotuned: %s" % tuned)
     L, t_build = build_lists(W, W["theta"], W["ncrit"])
-    ng, njp, njc, _ = bhq.bhq_lists_sizes(L)
+    ng, njp, njc, ncell = bhq.bhq_lists_sizes(L)
     log("%s: %d groups, %d j-particles, %d j-cells, lists built in %.2f s"
         % (W["name"], ng, njp, njc, t_build))
 
@@ -487,6 +511,11 @@ def main():
     finally:
         bhq.bhq_destroy(ctx)
 
+    dev_build = device_list_build(torch, W, W["theta"], W["ncrit"],
+                                  (ng, njp, njc, ncell))
+    if dev_build:
+        log("device list build: %.2f ms (host %.3f s)" % (dev_build["ms"], t_build))
+
     roofline = None
     if kernel in FLOPS_PC:
         flops = FLOPS_PP * n_pp + FLOPS_PC[kernel] * n_pc
@@ -524,6 +553,7 @@ def main():
         "kernel_ms": round(ms_kern, 4), "kernel_ms_median": round(ms_kern_med, 4),
         "pc_Ginteractions_per_s": round(n_pc / (ms_kern * 1e-3) / 1e9, 3),
         "host_list_build_s": round(t_build, 3), "upload_s": round(t_upload, 3),
+        "device_list_build": dev_build,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,

@@ -8,6 +8,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include <hip/hip_runtime_api.h>
@@ -78,8 +80,8 @@ std::vector<int32_t> plan_order(int64_t ng, const int64_t *i_off,
     }
     // windows of `window` groups from the start of a piece, and its last
     // `tail` groups as one more window; each sorted costly first
-    size_t longest = 0;
-    for (auto &pc : piece) {
+    // (pieces are independent: one host thread each when there is work)
+    auto sort_piece = [&](std::vector<int32_t> &pc) {
         const size_t n = pc.size();
         const size_t body = n > (size_t)tail ? n - (size_t)tail : 0;
         for (size_t w = 0; w < body; w += (size_t)window) {
@@ -88,8 +90,21 @@ std::vector<int32_t> plan_order(int64_t ng, const int64_t *i_off,
                              costly_first);
         }
         std::stable_sort(pc.begin() + (ptrdiff_t)body, pc.end(), costly_first);
-        longest = std::max(longest, n);
+    };
+    if (ng >= (int64_t)1 << 16) {
+        std::vector<std::thread> pool;
+        try {
+            for (auto &pc : piece) pool.emplace_back(sort_piece, std::ref(pc));
+        } catch (const std::system_error &) {
+            // no threads: the pieces not started are sorted below
+        }
+        for (auto &t : pool) t.join();
+        for (size_t x = pool.size(); x < piece.size(); ++x) sort_piece(piece[x]);
+    } else {
+        for (auto &pc : piece) sort_piece(pc);
     }
+    size_t longest = 0;
+    for (auto &pc : piece) longest = std::max(longest, pc.size());
     std::vector<int32_t> order(longest * (size_t)xcds, -1);
     for (int x = 0; x < xcds; ++x)
         for (size_t k = 0; k < piece[(size_t)x].size(); ++k)

@@ -137,3 +137,47 @@ def test_periodic_lattice_16m_sampled():
                               rcut=rcut, mask=SPLIT_MASK[prec])
 
     _check("lattice", gpu, ref, mat["i_idx"])
+
+
+@pytest.mark.parametrize("which", ["cube", "clustered", "lattice"])
+def test_device_lists_full_size(which):
+    """Device-built lists at the benchmark sizes equal the host builder's
+    entry for entry (particle order, offsets, every list entry in order)
+    and the cell moments bit for bit."""
+    torch = pytest.importorskip("torch")
+    if which == "cube":
+        c = synth.config_uniform_cube()
+        box = rcut = 0.0
+    elif which == "clustered":
+        c = synth.config_clustered()
+        box = rcut = 0.0
+    else:
+        c = synth.config_lattice()
+        box, rcut = 1.0, c["rcut"]
+    x, m = c["x"], c["m"]
+    ncrit = 64 if which == "lattice" else 256
+    log("case device lists full size %s (n=%d)" % (which, len(m)))
+    L = bhq.bhq_build_lists(x, m, c["theta"], ncrit, box=box, rcut=rcut)
+    try:
+        h = bhq.bhq_lists_export(L, len(m))
+        hc = bhq.bhq_lists_cells(L)
+        hs = bhq.bhq_lists_sizes(L)
+    finally:
+        bhq.bhq_lists_free(L)
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        xt = torch.from_numpy(x).cuda()
+        mt = torch.from_numpy(m).cuda()
+        bhq.bhq_build_lists_device(ctx, xt, mt, c["theta"], ncrit, 8, box, rcut)
+        del xt, mt
+        assert bhq.bhq_get_lists_sizes(ctx) == hs
+        d = bhq.bhq_get_lists(ctx, len(m))
+        for k in ("i_idx", "i_off", "jp_off", "jc_off", "jc_cell", "jp_idx"):
+            assert np.array_equal(h[k], d[k]), k
+            del d[k]
+        dc = bhq.bhq_get_cells(ctx)
+        for k in ("com", "mass", "q", "trace"):
+            assert np.array_equal(hc[k].view(np.int64), dc[k].view(np.int64)), k
+        log("  %d groups, %d + %d entries, %d cells: identical" % hs)
+    finally:
+        bhq.bhq_destroy(ctx)

@@ -43,7 +43,7 @@ def _windows(k, window, tail):
 @pytest.mark.parametrize("ng,window,tail,xcds", [
     (1, 256, 1024, 8), (5, 256, 1024, 8), (1000, 256, 0, 8),
     (17914, 256, 1024, 8), (17914, 100, 333, 8), (3001, 7, 50, 3),
-    (64, 1, 0, 1), (40000, 256, 1024, 8)])
+    (64, 1, 0, 1), (40000, 256, 1024, 8), (70000, 256, 1024, 8)])
 def test_xcd_order_pieces_and_windows(ng, window, tail, xcds):
     rng = np.random.default_rng(ng + window)
     i_off, jp_off, jc_off, cost = _offsets(rng, ng, empty_frac=0.05)
