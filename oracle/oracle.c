@@ -40,7 +40,8 @@
 #define ORC_E_ARG (-1)
 #define ORC_E_NOMEM (-5)
 
-enum { ORC_MONO = 0, ORC_QUAD = 1, ORC_SPLIT_QUAD = 2, ORC_SPLIT_MONO = 3 };
+enum { ORC_MONO = 0, ORC_QUAD = 1, ORC_SPLIT_QUAD = 2, ORC_SPLIT_MONO = 3,
+       ORC_QUAD_SOFT = 4 };
 
 /* ------------------------------------------------------------------------ */
 /* Pair and cell interaction terms                                           */
@@ -86,6 +87,42 @@ void orc_pc_quad(const double d[3], double M, const double q[6], double eps2,
     for (int k = 0; k < 3; ++k)
         a[k] += c * d[k] - Qd[k] / rhat5;
     *phi -= phi_mono + phi_quad;
+}
+
+/* One j-cell on one i-particle, the complete second-order expansion of the
+ * Plummer-softened potential -1/rhat about the cell's centre of mass.
+ * Because the softened potential is not harmonic, the second moment
+ * contributes through its trace T = sum m |x - com|^2 as well as through
+ * the traceless Q.  With the radial derivative functions of
+ * Phi(r) = -1/rhat, rhat^2 = r^2 + eps^2:
+ *   D1 = Phi'/r = rhat^-3,  D2 = D1'/r = -3 rhat^-5,  D3 = D2'/r = 15 rhat^-7,
+ * the expansion of sum_p m_p Phi(|r_p - r_i|) to second order in r_p - com
+ * (Taylor's theorem, second moment (Q + T 1)/3) is
+ *   phi = M Phi + D2 (d.Q.d) / 6 + T (D2 r^2 + 3 D1) / 6
+ *   a   = -grad_i phi
+ *       = M D1 d + [D3 (d.Q.d) d + 2 D2 Q d] / 6 + T (D3 r^2 + 5 D2) d / 6
+ * with d = com - r_i, r = |d|.  With T = 0 this is orc_pc_quad; the T part
+ * is T eps^2 / (2 rhat^5) in phi, the term eq. (1) leaves out. */
+void orc_pc_quad_soft(const double d[3], double M, const double q[6], double T,
+                      double eps2, double a[3], double *phi)
+{
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double rhat = sqrt(r2 + eps2);
+    double Phi = -1.0 / rhat;
+    double D1 = 1.0 / (rhat * rhat * rhat);
+    double D2 = -3.0 * D1 / (rhat * rhat);
+    double D3 = -5.0 * D2 / (rhat * rhat);
+    double Qd[3];
+    Qd[0] = q[0] * d[0] + q[1] * d[1] + q[2] * d[2];
+    Qd[1] = q[1] * d[0] + q[3] * d[1] + q[4] * d[2];
+    Qd[2] = q[2] * d[0] + q[4] * d[1] + q[5] * d[2];
+    double dQd = d[0] * Qd[0] + d[1] * Qd[1] + d[2] * Qd[2];
+    double pot = M * Phi + D2 * dQd / 6.0 + T / 6.0 * (D2 * r2 + 3.0 * D1);
+    double coef = M * D1 + D3 * dQd / 6.0 + T / 6.0 * (D3 * r2 + 5.0 * D2);
+    double qterm = 2.0 * D2 / 6.0;
+    for (int k = 0; k < 3; ++k)
+        a[k] += coef * d[k] + qterm * Qd[k];
+    *phi += pot;
 }
 
 /* Monopole-only cell: the cell is a point of mass M at its centre of mass
@@ -701,7 +738,8 @@ void orc_export_nodes(const orc_tree *t, double *center, double *side,
  *   ng, i_idx[], i_off[ng+1]          group g owns i_idx[i_off[g]..)
  *   jp_off[ng+1]; jp_x[3*], jp_m[]    materialised j-particles
  *   jc_off[ng+1]; jc_x[3*], jc_m[], jc_q[6*], jc_t[]  j-cells
- *   kind   ORC_MONO / ORC_QUAD / ORC_SPLIT_QUAD / ORC_SPLIT_MONO
+ *   kind   ORC_MONO / ORC_QUAD / ORC_SPLIT_QUAD / ORC_SPLIT_MONO /
+ *          ORC_QUAD_SOFT (Plummer cells with the trace term; needs jc_t)
  *   box    > 0: minimum image separations (periodic)
  *   rs, rcut  split-kernel parameters
  *   mask_mode, gcenter[3 ng]  how the split kernel's cutoff is decided (see
@@ -744,6 +782,10 @@ void orc_eval(int kind, int64_t ng, const int64_t *i_idx, const int64_t *i_off,
                     break;
                 case ORC_QUAD:
                     orc_pc_quad(d, jc_m[j], &jc_q[6 * j], eps2[i], acc, &pot);
+                    break;
+                case ORC_QUAD_SOFT:
+                    orc_pc_quad_soft(d, jc_m[j], &jc_q[6 * j], jc_t ? jc_t[j] : 0.0,
+                                     eps2[i], acc, &pot);
                     break;
                 default:
                     if (orc_split_keep(mask_mode, &jc_x[3 * j], xi,

@@ -10,7 +10,7 @@ import subprocess
 
 import numpy as np
 
-MONO, QUAD, SPLIT_QUAD, SPLIT_MONO = 0, 1, 2, 3
+MONO, QUAD, SPLIT_QUAD, SPLIT_MONO, QUAD_SOFT = 0, 1, 2, 3, 4
 # how the split kernel's cutoff decision is taken (see orc_split_keep)
 MASK_ABS, MASK_F32_OFS, MASK_F64_OFS = 0, 1, 2
 
@@ -66,6 +66,8 @@ def lib():
         L.orc_pc_quad.argtypes = [_D, ctypes.c_double, _D, ctypes.c_double,
                                   _D, _D]
         L.orc_pc_mono.argtypes = [_D, ctypes.c_double, ctypes.c_double, _D, _D]
+        L.orc_pc_quad_soft.argtypes = [_D, ctypes.c_double, _D, ctypes.c_double,
+                                       ctypes.c_double, _D, _D]
         L.orc_pc_split.argtypes = [_D, ctypes.c_double, _D, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int, _D, _D]
@@ -275,6 +277,13 @@ def pp_plummer(d, m, eps2):
 def pc_quad(d, M, q, eps2):
     q = _cd(q)
     return _single(lib().orc_pc_quad, d, float(M), _dp(q), float(eps2))
+
+
+def pc_quad_soft(d, M, q, T, eps2):
+    """Plummer cell, complete second-order expansion (with the trace T)."""
+    q = _cd(q)
+    return _single(lib().orc_pc_quad_soft, d, float(M), _dp(q), float(T),
+                   float(eps2))
 
 
 def pc_mono(d, M, eps2):

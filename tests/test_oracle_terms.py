@@ -244,3 +244,101 @@ def test_split_cutoff_decision_modes(orc):
     xj = np.array([0.004, 0.5, 0.5])
     for mm in (orc.MASK_ABS, orc.MASK_F32_OFS, orc.MASK_F64_OFS):
         assert orc.split_keep(mm, xj, xi, np.array([0.995, 0.5, 0.5]), box, rcut)
+
+
+# --- the complete softened quadrupole (with the trace term) ---------------------
+
+def test_soft_quad_limits(orc):
+    """T = 0 gives eq. (1) exactly (orc_pc_quad); eps = 0 makes the trace
+    term vanish for any T (the unsoftened potential is harmonic)."""
+    g = np.random.default_rng(31)
+    for _ in range(20):
+        d = g.normal(size=3)
+        q = g.normal(size=6)
+        q[5] = -(q[0] + q[3])
+        M, T, e2 = g.uniform(0.5, 2), g.uniform(0.1, 1), g.uniform(0.01, 0.5)
+        a1, p1 = orc.pc_quad_soft(d, M, q, 0.0, e2)
+        a2, p2 = orc.pc_quad(d, M, q, e2)
+        np.testing.assert_allclose(a1, a2, rtol=1e-14, atol=1e-16)
+        assert p1 == pytest.approx(p2, rel=1e-14)
+        a1, p1 = orc.pc_quad_soft(d, M, q, T, 0.0)
+        a2, p2 = orc.pc_quad(d, M, q, 0.0)
+        np.testing.assert_allclose(a1, a2, rtol=1e-12, atol=1e-14)
+        assert p1 == pytest.approx(p2, rel=1e-12)
+
+
+def test_soft_quad_minus_gradient(orc):
+    g = np.random.default_rng(32)
+    for _ in range(20):
+        q = g.normal(size=6)
+        q[5] = -(q[0] + q[3])
+        com = g.normal(size=3) * 2.0
+        xi = g.normal(size=3) * 0.3
+        M, T, e2 = g.uniform(0.5, 2.0), g.uniform(0.1, 1.0), g.uniform(0.05, 1.0)
+
+        def phi_at(xp):
+            return orc.pc_quad_soft(com - xp, M, q, T, e2)[1]
+
+        a, _ = orc.pc_quad_soft(com - xi, M, q, T, e2)
+        np.testing.assert_allclose(a, -_num_grad(phi_at, xi, 1e-5), rtol=1e-7,
+                                   atol=1e-9 * np.abs(a).max())
+
+
+@pytest.mark.parametrize("where", ["plane", "axis"])
+def test_soft_quad_axis_pair_closed_form(orc, where):
+    """Two masses m at +-s on the z axis, softening eps, field point at
+    distance D in the plane or on the axis.  The exact softened two-body
+    potential expands as -2m/rhat + m s^2 (eps^2 - 2 D^2)/rhat^5 on the axis
+    and -2m/rhat + m s^2/rhat^3 in the plane (hand Taylor expansion in s,
+    rhat^2 = D^2 + eps^2), so the complete expansion leaves an O(s^4)
+    residual, while the traceless one misses m s^2 eps^2 / rhat^5."""
+    m, D, eps = 0.7, 1.0, 0.5
+    rhat = math.sqrt(D * D + eps * eps)
+    res_soft, res_tl = [], []
+    for s in (0.1, 0.05, 0.025):
+        x = np.array([[0.0, 0.0, s], [0.0, 0.0, -s]])
+        M, com, q, T = orc.moments(x, [m, m])
+        if where == "plane":
+            xi = np.array([D, 0.0, 0.0])
+            closed = -2 * m / rhat + m * s * s / rhat ** 3
+        else:
+            xi = np.array([0.0, 0.0, D])
+            closed = -2 * m / rhat + m * s * s * (eps * eps - 2 * D * D) / rhat ** 5
+        exact = -m / np.linalg.norm(np.append(x[0] - xi, eps)) \
+            - m / np.linalg.norm(np.append(x[1] - xi, eps))
+        _, p_soft = orc.pc_quad_soft(com - xi, M, q, T, eps * eps)
+        _, p_tl = orc.pc_quad(com - xi, M, q, eps * eps)
+        assert p_soft == pytest.approx(closed, rel=1e-13)
+        assert (p_soft - p_tl) == pytest.approx(m * s * s * eps * eps / rhat ** 5, rel=1e-9)
+        res_soft.append(abs(exact - p_soft))
+        res_tl.append(abs(exact - p_tl))
+    r_soft = np.array(res_soft[:-1]) / np.array(res_soft[1:])
+    r_tl = np.array(res_tl[:-1]) / np.array(res_tl[1:])
+    assert np.all((r_soft > 14) & (r_soft < 18)), r_soft      # O(s^4)
+    assert np.all((r_tl > 3.5) & (r_tl < 4.5)), r_tl          # O(s^2)
+
+
+def test_soft_quad_expansion_order(orc):
+    """Against summing a cluster's particles with the softened pair kernel
+    at eps comparable to the distance: the complete expansion's error falls
+    as (l/D)^3, the traceless one's as (l/D)^2."""
+    g = np.random.default_rng(33)
+    xc, mc = _cluster(g, 40, 1.0)
+    xi = np.array([2.0, 1.0, -1.5])
+    eps2 = 1.5
+    err_s, err_t = [], []
+    for scale in (0.2, 0.1, 0.05, 0.025):
+        x = xc * scale
+        M, com, q, T = orc.moments(x, mc)
+        a_ex = np.zeros(3)
+        for p in range(len(mc)):
+            a_ex += orc.pp_plummer(x[p] - xi, mc[p], eps2)[0]
+        a_s, _ = orc.pc_quad_soft(com - xi, M, q, T, eps2)
+        a_t, _ = orc.pc_quad(com - xi, M, q, eps2)
+        err_s.append(np.linalg.norm(a_s - a_ex) / np.linalg.norm(a_ex))
+        err_t.append(np.linalg.norm(a_t - a_ex) / np.linalg.norm(a_ex))
+    rs = np.array(err_s[:-1]) / np.array(err_s[1:])
+    rt = np.array(err_t[:-1]) / np.array(err_t[1:])
+    assert np.all((rs > 6.5) & (rs < 10.0)), rs
+    assert np.all((rt > 3.3) & (rt < 4.8)), rt
+    assert np.all(np.array(err_s) < np.array(err_t))
