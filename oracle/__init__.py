@@ -12,5 +12,5 @@ from .oracle import (  # noqa: F401
     split_keep,
     build, lib, Tree, build_tree, eval_lists, direct, moments, pp_plummer,
     pc_quad, pc_quad_soft, pc_mono, pc_split, pp_split, split_derivs, num_threads,
-    materialise, relative_errors,
+    materialise, relative_errors, leapfrog,
 )

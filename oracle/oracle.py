@@ -317,3 +317,26 @@ def relative_errors(a_test, a_ref):
     a_ref = np.asarray(a_ref, np.float64).reshape(-1, 3)
     return (np.linalg.norm(a_test - a_ref, axis=1) /
             np.linalg.norm(a_ref, axis=1))
+
+
+def leapfrog(x, v, m, eps, dt, nsteps, theta, ncrit, kind=QUAD, nleaf=8):
+    """Kick-drift-kick leapfrog (second order, time reversible; the
+    integrator of the paper's cold-collapse runs), forces from the oracle's
+    own tree and lists, rebuilt after every drift:
+        v += dt/2 a(x);  x += dt v;  v += dt/2 a(x).
+    Returns (x, v, a, phi) after nsteps, FP64."""
+    x = np.array(x, np.float64).reshape(-1, 3)
+    v = np.array(v, np.float64).reshape(-1, 3)
+    m = np.asarray(m, np.float64)
+
+    def force(xx):
+        T = Tree(xx, m, theta, ncrit, nleaf)
+        return eval_lists(kind, materialise(T, xx, m), xx, eps * eps)
+
+    a, phi = force(x)
+    for _ in range(nsteps):
+        v = v + (0.5 * dt) * a
+        x = x + dt * v
+        a, phi = force(x)
+        v = v + (0.5 * dt) * a
+    return x, v, a, phi
