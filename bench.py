@@ -38,10 +38,11 @@ from paper_1812_07313_amd import bhq, synth  # noqa: E402
 # Algorithmic flops per interaction (FMA = 2, rsqrt = 1, other operations
 # 1) of the kernels' arithmetic: particle term 14 VALU operations and 20
 # flops; quadrupole cell term 34 operations and 53 flops; a monopole cell is
-# a particle term.  The split kernels add their radial-function evaluation
-# and are not priced here.
+# a particle term; the complete softened quadrupole adds one FMA to the
+# cell term (35 operations, 55 flops).  The split kernels add their
+# radial-function evaluation and are not priced here.
 FLOPS_PP = 20
-FLOPS_PC = {bhq.QUAD: 53, bhq.MONO: 20}
+FLOPS_PC = {bhq.QUAD: 53, bhq.MONO: 20, bhq.QUAD_SOFT: 55}
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak
 METRIC = ("Ginteractions/s + s/force-eval at fixed rms error; quad vs mono, "
@@ -474,7 +475,7 @@ def main():
             others = [(kernel, bhq.FP64)]
             if kernel == bhq.QUAD:
                 others = [(bhq.MONO, bhq.FP32_OFS64), (bhq.QUAD, bhq.FP64),
-                          (bhq.MONO, bhq.FP64)]
+                          (bhq.MONO, bhq.FP64), (bhq.QUAD_SOFT, bhq.FP32_OFS64)]
             elif kernel == bhq.SPLIT_QUAD:
                 others = [(bhq.SPLIT_MONO, bhq.FP32_OFS64),
                           (bhq.SPLIT_QUAD, bhq.FP64)]
@@ -503,6 +504,13 @@ def main():
         ref = direct_reference(W, P, nsample=4096 if n <= (1 << 20) else 1024)
         out_extra["tree_error_vs_direct"] = dict(
             sample=len(ref[0]), fp32=tree_error(a32, ref))
+        if kernel == bhq.QUAD and not args.no_variants:
+            # the complete softened quadrupole (with the cells' trace term)
+            bhq.bhq_set_kernel(ctx, bhq.QUAD_SOFT, bhq.FP32_OFS64)
+            bhq.bhq_compute(ctx, stream)
+            a_soft, _ = result_orig(ctx, P, n)
+            out_extra["tree_error_vs_direct"]["fp32_quad_soft"] = tree_error(a_soft, ref)
+            bhq.bhq_set_kernel(ctx, kernel, bhq.FP32_OFS64)
         if not args.no_fixed_error and args.workload in ("cube", "sphere"):
             W["indexed"] = args.lists == "indexed"
             log("fixed-error study ...")

@@ -20,7 +20,12 @@
  * Kernels: BHQ_QUAD (above), BHQ_MONO (cells as point masses, Q ignored:
  * the paper's "monopole" program), BHQ_SPLIT_QUAD / BHQ_SPLIT_MONO
  * (short-range Gaussian-split kernel Phi = -erfc(r / 2 r_s) / r with a
- * cutoff in a periodic box; not from the paper).
+ * cutoff in a periodic box; not from the paper), BHQ_QUAD_SOFT (the
+ * complete second-order expansion of the softened potential: eq. 1 plus the
+ * trace term T_c eps^2 / (2 rhat^5) that eq. 1 leaves out, T_c = sum m
+ * |x - com|^2, i.e. d.Q_c.d replaced by d.Q_c.d - T_c eps^2 in phi_q; the
+ * traces come from set_jc's trace argument or the cell pool, and a NULL
+ * trace in set_jc means T_c = 0, which makes it BHQ_QUAD).
  * Precisions: BHQ_FP32_OFS64 forms positions relative to the group centre
  * in FP64 and does all interaction arithmetic and accumulation in FP32;
  * BHQ_FP64 does everything in FP64.
@@ -71,6 +76,7 @@ typedef struct bhq_lists bhq_lists;
 #define BHQ_QUAD 1
 #define BHQ_SPLIT_QUAD 2
 #define BHQ_SPLIT_MONO 3
+#define BHQ_QUAD_SOFT 4
 
 /* precisions */
 #define BHQ_FP32_OFS64 0
@@ -362,6 +368,38 @@ int bhq_get_lists(bhq_ctx *ctx, int64_t *i_idx, int64_t *i_off,
  * may be NULL).  Errors: BHQ_E_STATE (no cell pool), BHQ_E_HIP. */
 int bhq_get_cells(bhq_ctx *ctx, double (*com)[3], double *mass,
                   double (*q)[6], double *trace);
+
+/* ------------------------------------------------------------------------
+ * Around the force evaluation in a time step (leapfrog, as the paper's
+ * cold-collapse runs integrate, Sec. 5.2).  Arrays are FP64 in device
+ * memory of ctx's device, particles in input order, x and v as [n][3].
+ * ------------------------------------------------------------------------ */
+
+/* Copy the last compute's accelerations a[ni][3] and potentials pot[ni]
+ * (pot may be NULL) to device arrays in the particles' input order (for
+ * lists from bhq_set_lists_indexed or bhq_build_lists_device; in group order
+ * otherwise).  Runs on `stream` after the compute (it waits for it).
+ * Errors: BHQ_E_STATE (no compute yet), BHQ_E_ARG / BHQ_E_RANGE (pointers),
+ * BHQ_E_HIP. */
+int bhq_get_result_device(bhq_ctx *ctx, double *a, double *pot, void *stream);
+
+/* Leapfrog step pieces on n particles: v += dt_kick * a, then, unless
+ * dt_drift == 0, x += dt_drift * v (x may be NULL then).  A kick-drift-kick
+ * step is kick_drift(dt/2, dt), forces, kick_drift(dt/2, 0); consecutive
+ * steps merge the two half kicks into kick_drift(dt, dt).  Asynchronous on
+ * `stream`.  Errors: BHQ_E_ARG, BHQ_E_RANGE, BHQ_E_NONFINITE, BHQ_E_HIP. */
+int bhq_kick_drift(bhq_ctx *ctx, int64_t n, double *x, double *v,
+                   const double *a, double dt_kick, double dt_drift,
+                   void *stream);
+
+/* Energies of n particles: out[0] = K = 1/2 sum m |v|^2 and, when pot is
+ * given (the potentials of the softened kernels, which include each
+ * particle's self pair -m/eps), out[1] = W = 1/2 sum m (pot + m / eps);
+ * out[1] = 0 without pot.  eps >= 0 (0: nothing removed).  Deterministic
+ * (fixed-order reduction); waits for the result.
+ * Errors: BHQ_E_ARG, BHQ_E_RANGE, BHQ_E_HIP. */
+int bhq_energies(bhq_ctx *ctx, int64_t n, const double *m, const double *v,
+                 const double *pot, double eps, double out[2], void *stream);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,7 @@ import os
 
 import numpy as np
 
-MONO, QUAD, SPLIT_QUAD, SPLIT_MONO = 0, 1, 2, 3
+MONO, QUAD, SPLIT_QUAD, SPLIT_MONO, QUAD_SOFT = 0, 1, 2, 3, 4
 FP32_OFS64, FP64 = 0, 1
 ORDER_COST, ORDER_XCD = 0, 1
 ORDER_WINDOW, ORDER_TAIL = 256, 1024
@@ -22,7 +22,7 @@ E_ARG, E_RANGE, E_NODEV, E_HIP, E_NOMEM, E_STATE, E_NONFINITE = (
     -1, -2, -3, -4, -5, -6, -7)
 
 KERNEL_NAMES = {MONO: "mono", QUAD: "quad", SPLIT_QUAD: "split_quad",
-                SPLIT_MONO: "split_mono"}
+                SPLIT_MONO: "split_mono", QUAD_SOFT: "quad_soft"}
 PRECISION_NAMES = {FP32_OFS64: "fp32_ofs64", FP64: "fp64"}
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -92,6 +92,11 @@ SIGNATURES = {
     "bhq_get_lists_sizes": (ctypes.c_int, [_P, _I64]),
     "bhq_get_lists": (ctypes.c_int, [_P, _I64, _I64, _I64, _I64, _I64, _I32]),
     "bhq_get_cells": (ctypes.c_int, [_P, _D, _D, _D, _D]),
+    "bhq_get_result_device": (ctypes.c_int, [_P, _P, _P, _P]),
+    "bhq_kick_drift": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P,
+                                      ctypes.c_double, ctypes.c_double, _P]),
+    "bhq_energies": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P,
+                                    ctypes.c_double, _D, _P]),
 }
 
 _lib = None
@@ -110,6 +115,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             from . import build as _build
             _build.build()
+        # PyTorch ships its own HIP runtime.  Importing it first lets libbhq
+        # bind to that runtime, so the process runs one HIP runtime; a
+        # second one started by libbhq before torch leaves torch without a
+        # device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -445,3 +458,35 @@ def bhq_get_cells(ctx):
     _check(lib().bhq_get_cells(ctx, _dp(out["com"]), _dp(out["mass"]),
                                _dp(out["q"]), _dp(out["trace"])), ctx)
     return out
+
+
+# --- time-step helpers (device arrays as torch tensors) ------------------------
+
+def _dptr(t, shape, name):
+    return None if t is None else _device_ptr(t, shape, name)
+
+
+def bhq_get_result_device(ctx, a, pot=None, stream=None):
+    """a: (n, 3) float64 GPU tensor, pot: (n,) or None; input order."""
+    n = int(a.shape[0])
+    _check(lib().bhq_get_result_device(ctx, _dptr(a, (n, 3), "a"),
+                                       _dptr(pot, (n,), "pot"),
+                                       _stream_handle(stream)), ctx)
+
+
+def bhq_kick_drift(ctx, x, v, a, dt_kick, dt_drift, stream=None):
+    n = int(v.shape[0])
+    _check(lib().bhq_kick_drift(ctx, n, _dptr(x, (n, 3), "x"),
+                                _dptr(v, (n, 3), "v"), _dptr(a, (n, 3), "a"),
+                                float(dt_kick), float(dt_drift),
+                                _stream_handle(stream)), ctx)
+
+
+def bhq_energies(ctx, m, v, pot=None, eps=0.0, stream=None):
+    """(K, W) with W = 1/2 sum m (pot + m/eps); W = 0 without pot."""
+    n = int(m.shape[0])
+    out = np.zeros(2)
+    _check(lib().bhq_energies(ctx, n, _dptr(m, (n,), "m"), _dptr(v, (n, 3), "v"),
+                              _dptr(pot, (n,), "pot"), float(eps), _dp(out),
+                              _stream_handle(stream)), ctx)
+    return float(out[0]), float(out[1])

@@ -33,7 +33,7 @@ enum Arr {
     A_AX, A_AY, A_AZ, A_POT,
     A_QUEUE,
     A_POOLP, A_POOLC, A_JPIDX, A_JCIDX,
-    A_TORDER,
+    A_TORDER, A_ENERGY,
     A_COUNT
 };
 
@@ -297,7 +297,7 @@ struct bhq_ctx {
         if (rc_ != BHQ_OK) return rc_;                    \
     } while (0)
 
-static bool valid_kernel(int k) { return k >= BHQ_MONO && k <= BHQ_SPLIT_MONO; }
+static bool valid_kernel(int k) { return k >= BHQ_MONO && k <= BHQ_QUAD_SOFT; }
 static bool valid_prec(int p) { return p == BHQ_FP32_OFS64 || p == BHQ_FP64; }
 
 extern "C" {
@@ -1332,6 +1332,67 @@ int bhq_get_cells(bhq_ctx *ctx, double (*com)[3], double *mass, double (*q)[6],
         if (trace) trace[c] = r.t;
     }
     return BHQ_OK;
+}
+
+int bhq_get_result_device(bhq_ctx *ctx, double *a, double *pot, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (!ctx->launched || ctx->ng < 0)
+        return ctx->fail(BHQ_E_STATE, "get_result_device before compute");
+    if (!a) return ctx->fail(BHQ_E_ARG, "a is NULL");
+    TRY(ctx->select());
+    const int64_t n = ctx->ni;
+    TRY(check_device_range(ctx, a, (size_t)n * 3 * sizeof(double), "a"));
+    if (pot) TRY(check_device_range(ctx, pot, (size_t)n * sizeof(double), "pot"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamWaitEvent(s, ctx->ev1, 0);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipStreamWaitEvent");
+    e = bhq::launch_scatter(ctx->tree_order ? ctx->arr[A_TORDER].as<int32_t>() : nullptr, n,
+                            ctx->arr[A_AX].as<double>(), ctx->arr[A_AY].as<double>(),
+                            ctx->arr[A_AZ].as<double>(), ctx->arr[A_POT].as<double>(), a,
+                            pot, s);
+    return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "scatter launch");
+}
+
+int bhq_kick_drift(bhq_ctx *ctx, int64_t n, double *x, double *v, const double *a,
+                   double dt_kick, double dt_drift, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (!std::isfinite(dt_kick) || !std::isfinite(dt_drift))
+        return ctx->fail(BHQ_E_NONFINITE, "kick_drift: time step not finite");
+    if (n < 0 || !v || !a || (dt_drift != 0.0 && !x))
+        return ctx->fail(BHQ_E_ARG, "kick_drift: bad argument");
+    if (n == 0) return BHQ_OK;
+    TRY(ctx->select());
+    const size_t b = (size_t)n * 3 * sizeof(double);
+    TRY(check_device_range(ctx, v, b, "v"));
+    TRY(check_device_range(ctx, a, b, "a"));
+    if (dt_drift != 0.0) TRY(check_device_range(ctx, x, b, "x"));
+    hipError_t e = bhq::launch_kick_drift(n, x, v, a, dt_kick, dt_drift,
+                                          static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "kick_drift launch");
+}
+
+int bhq_energies(bhq_ctx *ctx, int64_t n, const double *m, const double *v,
+                 const double *pot, double eps, double out[2], void *stream)
+{
+    CHECK_CTX(ctx);
+    if (n < 1 || !m || !v || !out || !(eps >= 0.0) || !std::isfinite(eps))
+        return ctx->fail(BHQ_E_ARG, "energies: bad argument");
+    TRY(ctx->select());
+    TRY(check_device_range(ctx, m, (size_t)n * sizeof(double), "m"));
+    TRY(check_device_range(ctx, v, (size_t)n * 3 * sizeof(double), "v"));
+    if (pot) TRY(check_device_range(ctx, pot, (size_t)n * sizeof(double), "pot"));
+    const int nb = bhq::energy_partials();
+    hipError_t e = ctx->arr[A_ENERGY].reserve((size_t)(2 * nb + 2) * sizeof(double));
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipMalloc");
+    double *part = ctx->arr[A_ENERGY].as<double>();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    e = bhq::launch_energies(n, m, v, pot, eps, part, part + 2 * nb, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, part + 2 * nb, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "energies");
 }
 
 }  // extern "C"

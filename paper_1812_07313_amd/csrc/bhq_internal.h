@@ -123,6 +123,17 @@ struct LaunchCfg {
 hipError_t launch_force(int kernel, int precision, const ForceArgs &args,
                         const LaunchCfg &cfg, hipStream_t stream);
 
+// Time-step helpers (bhq_integrate.hip).  order == NULL: identity.
+hipError_t launch_scatter(const int32_t *order, int64_t n, const double *ax,
+                          const double *ay, const double *az, const double *pot,
+                          double *a_out, double *pot_out, hipStream_t s);
+hipError_t launch_kick_drift(int64_t n, double *x, double *v, const double *a,
+                             double dtk, double dtd, hipStream_t s);
+int energy_partials();  // partial-sum slots (pairs) used by launch_energies
+hipError_t launch_energies(int64_t n, const double *m, const double *v,
+                           const double *pot, double eps, double *part,
+                           double *out, hipStream_t s);
+
 // Device construction of the tree, groups and index lists (bhq_tree.hip).
 // Inputs: n particles, positions x[n][3] and masses m[n] in device memory.
 struct TreeParams {

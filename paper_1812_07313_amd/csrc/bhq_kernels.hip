@@ -28,6 +28,8 @@
 //     a += (M rinv + 2.5 dQd rinv5) rinv^2 d - rinv5 Qd
 //   This is the paper's per-cell sequence with the constant factors folded
 //   (0.5 and 5 phi_q become 0.5 and 2.5 on dQd rinv5), 34 VALU operations.
+//   The complete softened expansion (cells carry their trace T) replaces
+//   dQd by dQd - T eps^2 in both terms: 35 operations.
 // The particle-particle part is summed before the cell part (List 4).
 // Accumulation is tile-blocked: each tile is summed into fresh registers
 // that are then added to the running sums.
@@ -56,7 +58,7 @@ __device__ __forceinline__ double wrap(double v, double box, double ibox)
     return box > 0.0 ? v - box * ::rint(v * ibox) : v;
 }
 
-constexpr int kMono = 0, kQuad = 1, kSplitQuad = 2, kSplitMono = 3;
+constexpr int kMono = 0, kQuad = 1, kSplitQuad = 2, kSplitMono = 3, kQuadSoft = 4;
 
 // Plummer-softened particle (also the monopole-only cell).
 template <typename R>
@@ -76,7 +78,10 @@ __device__ __forceinline__ void pp_plummer(const V4<R> &j, R xi, R yi, R zi,
 
 // Monopole + traceless quadrupole cell (Sec. 3, eqs. 1, 4-7).
 // a: (x, y, z, M), b: (q00, q01, q02, q11), c: (q12, q22, T, 0).
-template <typename R>
+// SOFT: the complete second-order expansion of the softened potential,
+// which adds T eps^2 / (2 rhat^5) to -phi's quadrupole part with the sign
+// of -d.Q.d: d.Q.d becomes d.Q.d - T eps^2 in both terms (one more FMA).
+template <typename R, bool SOFT>
 __device__ __forceinline__ void pc_quad(const V4<R> &a, const V4<R> &b,
                                         const V4<R> &c, R xi, R yi, R zi, R e2,
                                         R &ax, R &ay, R &az, R &pt)
@@ -89,7 +94,8 @@ __device__ __forceinline__ void pc_quad(const V4<R> &a, const V4<R> &b,
     const R qx = fma(b.z, dz, fma(b.y, dy, b.x * dx));
     const R qy = fma(c.x, dz, fma(b.w, dy, b.y * dx));
     const R qz = fma(c.y, dz, fma(c.x, dy, b.z * dx));
-    const R dqd = fma(dz, qz, fma(dy, qy, dx * qx));
+    R dqd = fma(dz, qz, fma(dy, qy, dx * qx));
+    if (SOFT) dqd = fma(-e2, c.z, dqd);
     const R rinv5 = (rinv2 * rinv2) * rinv;
     const R pq = dqd * rinv5;  // 2 phi_quad
     pt += phim;
@@ -242,7 +248,7 @@ constexpr float kPadPos = 1.0e15f;
 
 template <typename R, int KIND>
 struct Smem {
-    static constexpr bool kCellQ = (KIND == kQuad || KIND == kSplitQuad);
+    static constexpr bool kCellQ = (KIND == kQuad || KIND == kSplitQuad || KIND == kQuadSoft);
 };
 
 // Evaluate group g with a block of BS threads, each owning IB i-particles;
@@ -380,7 +386,8 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                             w.w = R(C->q11);
                             u.x = R(C->q12);
                             u.y = R(C->q22);
-                            u.z = (KIND == kSplitQuad) ? R(C->t) : R(0);
+                            u.z = (KIND == kSplitQuad || KIND == kQuadSoft) ? R(C->t)
+                                                                            : R(0);
                             u.w = R(0);
                         }
                     } else {
@@ -395,7 +402,9 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                             w.w = R(A.q11[j]);
                             u.x = R(A.q12[j]);
                             u.y = R(A.q22[j]);
-                            u.z = (KIND == kSplitQuad) ? R(A.jct[j]) : R(0);
+                            u.z = (KIND == kSplitQuad || KIND == kQuadSoft)
+                                      ? R(A.jct[j])
+                                      : R(0);
                             u.w = R(0);
                         }
                     }
@@ -428,9 +437,10 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                     }
 #pragma unroll
                     for (int u = 0; u < IB; ++u) {
-                        if (KIND == kQuad)
-                            pc_quad(ja, jb, jc, xi[u], yi[u], zi[u], e2[u], bx[u],
-                                    by[u], bz[u], bp[u]);
+                        if (KIND == kQuad || KIND == kQuadSoft)
+                            pc_quad<R, KIND == kQuadSoft>(ja, jb, jc, xi[u], yi[u],
+                                                          zi[u], e2[u], bx[u], by[u],
+                                                          bz[u], bp[u]);
                         else if (KIND == kMono)
                             pp_plummer(ja, xi[u], yi[u], zi[u], e2[u], bx[u],
                                        by[u], bz[u], bp[u]);
@@ -590,6 +600,8 @@ hipError_t launch_prec(int kernel, const ForceArgs &A, const LaunchCfg &cfg,
         return launch_bs<R, kMono, false>(A, cfg, s);
     case kQuad:
         return launch_bs<R, kQuad, false>(A, cfg, s);
+    case kQuadSoft:
+        return launch_bs<R, kQuadSoft, false>(A, cfg, s);
     case kSplitQuad:
         return periodic ? launch_bs<R, kSplitQuad, true>(A, cfg, s)
                         : launch_bs<R, kSplitQuad, false>(A, cfg, s);

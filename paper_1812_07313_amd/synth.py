@@ -58,6 +58,19 @@ def uniform_sphere(n, g, radius=1.0):
     return x, np.full(n, 1.0 / n)
 
 
+def cold_sphere(n, g, virial=0.1):
+    """Homogeneous sphere of radius 1 and mass 1 (G = 1) with isotropic
+    Gaussian velocities (zero mean) scaled to the virial ratio
+    2K/|W| = virial, |W| = 3/5 being the homogeneous sphere's potential
+    energy: the initial state of the cold-collapse runs."""
+    x, m = uniform_sphere(n, g)
+    v = g.normal(size=(n, 3))
+    v -= v.mean(axis=0)
+    k = 0.5 * np.sum(m * (v * v).sum(axis=1))
+    v *= np.sqrt(virial * 0.6 / (2.0 * k))
+    return x, v, m
+
+
 def clustered(n, g, nclusters=512, slope=1.9, mratio=1000.0, a_max=0.02,
               background=0.1):
     n_bg = int(round(background * n))

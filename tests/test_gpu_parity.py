@@ -14,7 +14,8 @@ from paper_1812_07313_amd import bhq, synth
 
 pytestmark = pytest.mark.gpu
 
-KINDS = [(bhq.QUAD, orc.QUAD), (bhq.MONO, orc.MONO)]
+KINDS = [(bhq.QUAD, orc.QUAD), (bhq.MONO, orc.MONO),
+         (bhq.QUAD_SOFT, orc.QUAD_SOFT)]
 PRECS = [bhq.FP32_OFS64, bhq.FP64]
 SPLIT_MASK = {bhq.FP32_OFS64: orc.MASK_F32_OFS, bhq.FP64: orc.MASK_F64_OFS}
 
@@ -99,7 +100,8 @@ def test_per_particle_softening(ctx):
         T = orc.Tree(x, m, 0.6, 64)
         mat = orc.materialise(T, x, m)
         e2 = np.full(len(m), eps * eps)
-        refs.append(orc.eval_lists(orc.QUAD, mat, x, e2))
+        refs.append((orc.eval_lists(orc.QUAD, mat, x, e2),
+                     orc.eval_lists(orc.QUAD_SOFT, mat, x, e2)))
         i_idx.append(mat["i_idx"] + base)
         i_off += list(mat["i_off"][1:] + i_off[-1])
         jp_off += list(mat["jp_off"][1:] + jp_off[-1])
@@ -120,13 +122,15 @@ def test_per_particle_softening(ctx):
     X = np.concatenate(xs)
     E2 = np.concatenate(e2s)
     upload(ctx, big, X, eps2=E2)
-    a_ref = np.concatenate([r[0] for r in refs])
-    p_ref = np.concatenate([r[1] for r in refs])
-    for prec in PRECS:
-        a, p = run(ctx, big, len(X), bhq.QUAD, prec)
-        err = errors(a, p, a_ref, p_ref)
-        log("  precision=%s %s" % (bhq.PRECISION_NAMES[prec], err))
-        assert_parity(err, prec, "batched")
+    for which, kern in ((0, bhq.QUAD), (1, bhq.QUAD_SOFT)):
+        a_ref = np.concatenate([r[which][0] for r in refs])
+        p_ref = np.concatenate([r[which][1] for r in refs])
+        for prec in PRECS:
+            a, p = run(ctx, big, len(X), kern, prec)
+            err = errors(a, p, a_ref, p_ref)
+            log("  kernel=%s precision=%s %s" % (bhq.KERNEL_NAMES[kern],
+                                                 bhq.PRECISION_NAMES[prec], err))
+            assert_parity(err, prec, "batched")
 
 
 def test_deterministic_and_zero_quadrupole(ctx):
@@ -390,3 +394,39 @@ def test_product_index_lists_equal_materialised(ctx):
         assert np.array_equal(out[0][1], out[1][1])
     finally:
         bhq.bhq_lists_free(L)
+
+
+def test_quad_soft_index_lists_and_trace_effect():
+    """The complete softened quadrupole on index lists from the host
+    builder (cell traces from the cell pool) against the oracle's own tree;
+    with a large softening the trace term moves the result well beyond the
+    FP64 bar, so the comparison shows the kernel uses it."""
+    x, m = synth.plummer(12000, synth.rng(14))
+    eps = 0.08
+    T = orc.Tree(x, m, 0.6, 64)
+    mat = orc.materialise(T, x, m)
+    ref_soft = orc.eval_lists(orc.QUAD_SOFT, mat, x, eps * eps)
+    ref_quad = orc.eval_lists(orc.QUAD, mat, x, eps * eps)
+    diff = errors(ref_soft[0], ref_soft[1], ref_quad[0], ref_quad[1])
+    log("case quad_soft: oracle soft vs traceless %s" % diff)
+    assert diff["rms"] > 1e-6
+    L = bhq.bhq_build_lists(x, m, 0.6, 64)
+    c = bhq.bhq_create(0, bhq.QUAD_SOFT, bhq.FP32_OFS64)
+    try:
+        bhq.bhq_set_lists_indexed(c, L, x, m)
+        idx = bhq.bhq_lists_export(L, len(m))["i_idx"]
+        bhq.bhq_set_eps(c, eps)
+        for prec in PRECS:
+            bhq.bhq_set_kernel(c, bhq.QUAD_SOFT, prec)
+            bhq.bhq_compute(c)
+            a_g, p_g = bhq.bhq_get_result(c, len(m))
+            a = np.zeros_like(a_g)
+            p = np.zeros_like(p_g)
+            a[idx] = a_g
+            p[idx] = p_g
+            err = errors(a, p, *ref_soft)
+            log("  precision=%s %s" % (bhq.PRECISION_NAMES[prec], err))
+            assert_parity(err, prec, "quad_soft index lists")
+    finally:
+        bhq.bhq_lists_free(L)
+        bhq.bhq_destroy(c)
