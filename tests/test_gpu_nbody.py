@@ -127,3 +127,18 @@ def test_step_helper_errors():
         assert rc == bhq.E_ARG
     finally:
         bhq.bhq_destroy(ctx)
+
+
+@pytest.mark.slow
+def test_cold_collapse_small():
+    """The cold-collapse driver on 2^14 particles through the collapse
+    (t = 0 .. 2, 512 steps): energy is conserved to 1 % and a dense core
+    forms (central density far above the initial 3/(4 pi))."""
+    from paper_1812_07313_amd import coldcollapse as cc
+    r = cc.run("C", n=1 << 14, t_end=2.0, eps=2.0 ** -6, ncrit=64)
+    log("case cold collapse small: %.2f ms/step, dE/E %.3g"
+        % (1e3 * r["s_per_step"], r["rel_energy_change"]))
+    assert abs(r["rel_energy_change"]) < 1e-2
+    p = r["profile"]
+    core = [rho for rr, rho, c in zip(p["r"], p["rho"], p["count"]) if rr < 0.1 and c >= 50]
+    assert core and max(core) > 20 * 3.0 / (4.0 * np.pi)
