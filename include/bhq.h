@@ -401,6 +401,46 @@ int bhq_kick_drift(bhq_ctx *ctx, int64_t n, double *x, double *v,
 int bhq_energies(bhq_ctx *ctx, int64_t n, const double *m, const double *v,
                  const double *pot, double eps, double out[2], void *stream);
 
+/* ------------------------------------------------------------------------
+ * Particle-mesh long-range force: with the short-range split kernels
+ * (pair potential -erfc(r / 2 r_s) / r) it makes a TreePM force (the
+ * TreePM context of Sec. 1).  The long-range pair potential is
+ * -erf(r / 2 r_s) / r, in the periodic box of side L with the mean density
+ * removed (G = 1).  Method: triangular-shaped-cloud (TSC) assignment to an
+ * n^3 mesh (mesh points at multiples of L / n), FFT, multiplication by
+ * -4 pi exp(-k^2 r_s^2) / k^2 divided by the squared TSC window
+ * prod sinc(k_a L / 2n)^6, gradient -i k (zero on the Nyquist planes),
+ * inverse FFTs, TSC interpolation.  FP64 throughout; hipFFT for the FFTs.
+ * The potential includes each particle's own smoothed long-range term
+ * (about -m / (r_s sqrt(pi))).
+ * ------------------------------------------------------------------------ */
+typedef struct bhq_pm bhq_pm;
+
+/* n: even mesh size in [4, 2048]; box > 0; rs > 0 (the split scale of
+ * bhq_set_split).  Allocates 5 real and 5 complex meshes and the FFT plans
+ * on `device`.  Errors: BHQ_E_ARG, BHQ_E_NODEV, BHQ_E_NOMEM, BHQ_E_HIP;
+ * bhq_pm_last_error(NULL) describes a failed create. */
+int bhq_pm_create(bhq_pm **out, int device, int nmesh, double box, double rs);
+
+/* Waits for outstanding work and frees everything (NULL accepted). */
+int bhq_pm_destroy(bhq_pm *pm);
+
+/* Long-range acceleration and potential of n particles, x[n][3] (in
+ * [0, box) or any periodic image) and m[n] in device memory: writes, or
+ * with accumulate = 1 adds to, a[n][3] and pot[n] (pot may be NULL), in
+ * the order of x.  Asynchronous on `stream`.  Errors: BHQ_E_ARG,
+ * BHQ_E_RANGE (pointers), BHQ_E_HIP. */
+int bhq_pm_compute(bhq_pm *pm, int64_t n, const double *x, const double *m,
+                   double *a, double *pot, int accumulate, void *stream);
+
+/* Duration of the last bhq_pm_compute in milliseconds (HIP events on its
+ * stream); waits for it.  Errors: BHQ_E_STATE before any compute. */
+int bhq_pm_get_ms(bhq_pm *pm, double *ms);
+
+/* Message of the last error on pm (never NULL; with pm == NULL: the last
+ * failed bhq_pm_create on this thread). */
+const char *bhq_pm_last_error(const bhq_pm *pm);
+
 #ifdef __cplusplus
 }
 #endif

@@ -97,6 +97,13 @@ SIGNATURES = {
                                       ctypes.c_double, ctypes.c_double, _P]),
     "bhq_energies": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P,
                                     ctypes.c_double, _D, _P]),
+    "bhq_pm_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_double]),
+    "bhq_pm_destroy": (ctypes.c_int, [_P]),
+    "bhq_pm_compute": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int,
+                                      _P]),
+    "bhq_pm_get_ms": (ctypes.c_int, [_P, _D]),
+    "bhq_pm_last_error": (ctypes.c_char_p, [_P]),
 }
 
 _lib = None
@@ -490,3 +497,36 @@ def bhq_energies(ctx, m, v, pot=None, eps=0.0, stream=None):
                               _dptr(pot, (n,), "pot"), float(eps), _dp(out),
                               _stream_handle(stream)), ctx)
     return float(out[0]), float(out[1])
+
+
+# --- particle-mesh long-range force ----------------------------------------------
+
+def _pm_check(rc, pm=None):
+    if rc != OK:
+        msg = lib().bhq_pm_last_error(pm)
+        raise BhqError(rc, msg.decode() if msg else "")
+
+
+def bhq_pm_create(nmesh, box, rs, device=0):
+    h = _P()
+    _pm_check(lib().bhq_pm_create(ctypes.byref(h), int(device), int(nmesh), float(box),
+                                  float(rs)))
+    return h
+
+
+def bhq_pm_destroy(pm):
+    _pm_check(lib().bhq_pm_destroy(pm), pm)
+
+
+def bhq_pm_compute(pm, x, m, a, pot=None, accumulate=False, stream=None):
+    """x, a: (n, 3), m, pot: (n,) float64 GPU tensors."""
+    n = int(m.shape[0])
+    _pm_check(lib().bhq_pm_compute(pm, n, _dptr(x, (n, 3), "x"), _dptr(m, (n,), "m"),
+                                   _dptr(a, (n, 3), "a"), _dptr(pot, (n,), "pot"),
+                                   int(bool(accumulate)), _stream_handle(stream)), pm)
+
+
+def bhq_pm_get_ms(pm):
+    ms = ctypes.c_double()
+    _pm_check(lib().bhq_pm_get_ms(pm, ctypes.byref(ms)), pm)
+    return ms.value

@@ -19,8 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbhq.so")
 ARCH = os.environ.get("BHQ_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["bhq_kernels.hip", "bhq_tree.hip", "bhq_integrate.hip", "bhq_api.cpp",
-           "bhq_lists.cpp"]
+SOURCES = ["bhq_kernels.hip", "bhq_tree.hip", "bhq_integrate.hip", "bhq_pm.hip",
+           "bhq_api.cpp", "bhq_lists.cpp"]
 # the tree builders take their floating-point decisions with the same
 # operations on host and device, and the leapfrog updates round like plain
 # FP64 arithmetic: no fused multiply-adds there
@@ -57,7 +57,7 @@ def build(verbose=False, extra=()):
         objs.append(obj)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + [
-        "-lpthread"]
+        "-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib", "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
