@@ -161,6 +161,30 @@ def device_list_build(torch, W, theta, ncrit, sizes, repeats=3):
             "first_call_ms": round(ts[0] * 1e3, 3), "sizes_equal_host": bool(same)}
 
 
+def pm_long_range(torch, W, short_ms, repeats):
+    """Time the particle-mesh long-range part that completes the split
+    kernel into a TreePM force: a mesh of spacing r_s / 1.25 (256^3 for the
+    2^24 lattice), particles already in device memory."""
+    nmesh = int(round(1.25 * W["box"] / W["rs"]))
+    nmesh += nmesh & 1
+    xt = torch.from_numpy(np.ascontiguousarray(W["x"])).cuda()
+    mt = torch.from_numpy(np.ascontiguousarray(W["m"])).cuda()
+    a = torch.zeros((len(W["m"]), 3), dtype=torch.float64, device="cuda")
+    p = torch.zeros(len(W["m"]), dtype=torch.float64, device="cuda")
+    pm = bhq.bhq_pm_create(nmesh, W["box"], W["rs"])
+    try:
+        ms = []
+        for _ in range(repeats + 1):
+            bhq.bhq_pm_compute(pm, xt, mt, a, p)
+            ms.append(bhq.bhq_pm_get_ms(pm))
+    finally:
+        bhq.bhq_pm_destroy(pm)
+    pm_ms = float(np.median(ms[1:]))
+    return {"nmesh": nmesh, "pm_ms": round(pm_ms, 3),
+            "short_range_kernel_ms": round(short_ms, 3),
+            "treepm_force_ms": round(pm_ms + short_ms, 3)}
+
+
 def upload(ctx, W, L, indexed=False):
     t0 = time.perf_counter()
     if indexed:
@@ -519,6 +543,10 @@ def main():
     finally:
         bhq.bhq_destroy(ctx)
 
+    treepm = None
+    if W.get("rs") and W.get("box"):
+        treepm = pm_long_range(torch, W, ms_kern, max(3, args.steps // 4))
+        log("PM long range (mesh %d): %.3f ms" % (treepm["nmesh"], treepm["pm_ms"]))
     dev_build = device_list_build(torch, W, W["theta"], W["ncrit"],
                                   (ng, njp, njc, ncell))
     if dev_build:
@@ -562,6 +590,7 @@ def main():
         "pc_Ginteractions_per_s": round(n_pc / (ms_kern * 1e-3) / 1e9, 3),
         "host_list_build_s": round(t_build, 3), "upload_s": round(t_upload, 3),
         "device_list_build": dev_build,
+        "treepm": treepm,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,

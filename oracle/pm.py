@@ -15,7 +15,8 @@ removed, G = 1):
 `direct_k_sum` evaluates this definition mode by mode (no mesh).  `pm`
 evaluates it the particle-mesh way, step by step:
   1. triangular-shaped-cloud (TSC) assignment of the masses to an n^3 mesh
-     (mesh points at integer multiples of h = L / n, periodic);
+     (mesh points at integer multiples of h = L / n, periodic), one of the
+     27 stencil offsets at a time (a weighted histogram per offset);
   2. forward FFT of the density;
   3. multiplication by -4 pi exp(-k^2 r_s^2) / k^2 (k = 0 set to zero)
      and division by the squared TSC window prod_a sinc(k_a h / 2)^6
@@ -51,13 +52,15 @@ def pm(x, m, L, n, rs, deconvolve=True):
     m = np.asarray(m, np.float64)
     h = L / n
     i0, w = tsc_weights(x, h, n)
-    rho = np.zeros((n, n, n))
+    rho = np.zeros(n * n * n)
     for a in range(3):
         for b in range(3):
             for c in range(3):
-                idx = ((i0[:, 0] + a - 1) % n, (i0[:, 1] + b - 1) % n, (i0[:, 2] + c - 1) % n)
-                np.add.at(rho, idx, m * w[a, :, 0] * w[b, :, 1] * w[c, :, 2])
-    rho /= h ** 3
+                flat = (((i0[:, 0] + a - 1) % n) * n + (i0[:, 1] + b - 1) % n) * n \
+                    + (i0[:, 2] + c - 1) % n
+                rho += np.bincount(flat, weights=m * w[a, :, 0] * w[b, :, 1] * w[c, :, 2],
+                                   minlength=n * n * n)
+    rho = rho.reshape(n, n, n) / h ** 3
     rk = np.fft.rfftn(rho)
     kx, ky, kz = _k_vectors(n, L)
     KX, KY, KZ = np.meshgrid(kx, ky, kz, indexing="ij")
@@ -84,13 +87,15 @@ def pm(x, m, L, n, rs, deconvolve=True):
     phim = np.fft.irfftn(phik, s=(n, n, n), axes=(0, 1, 2))
     meshes = out + [phim]
     res = np.zeros((x.shape[0], 4))
+    flat_meshes = [q.ravel() for q in meshes]
     for a in range(3):
         for b in range(3):
             for c in range(3):
-                idx = ((i0[:, 0] + a - 1) % n, (i0[:, 1] + b - 1) % n, (i0[:, 2] + c - 1) % n)
+                flat = (((i0[:, 0] + a - 1) % n) * n + (i0[:, 1] + b - 1) % n) * n \
+                    + (i0[:, 2] + c - 1) % n
                 wt = w[a, :, 0] * w[b, :, 1] * w[c, :, 2]
                 for q in range(4):
-                    res[:, q] += wt * meshes[q][idx]
+                    res[:, q] += wt * flat_meshes[q][flat]
     return res[:, :3], res[:, 3]
 
 

@@ -181,3 +181,30 @@ def test_device_lists_full_size(which):
         log("  %d groups, %d + %d entries, %d cells: identical" % hs)
     finally:
         bhq.bhq_destroy(ctx)
+
+
+def test_pm_lattice_16m():
+    """The particle-mesh long-range force on the 2^24 lattice with the
+    benchmark's mesh (256^3, r_s = 1.25 mesh spacings) against the FP64 PM
+    reference, every particle."""
+    torch = pytest.importorskip("torch")
+    from oracle import pm as opm
+    c = synth.config_lattice()
+    x, m, rs = c["x"], c["m"], c["rs"]
+    log("case pm lattice 2^24, mesh 256")
+    a_ref, p_ref = opm.pm(x, m, 1.0, 256, rs)
+    pm = bhq.bhq_pm_create(256, 1.0, rs)
+    try:
+        xt = torch.from_numpy(x).cuda()
+        mt = torch.from_numpy(m).cuda()
+        a = torch.zeros((len(m), 3), dtype=torch.float64, device="cuda")
+        p = torch.zeros(len(m), dtype=torch.float64, device="cuda")
+        bhq.bhq_pm_compute(pm, xt, mt, a, p)
+        ag, pg = a.cpu().numpy(), p.cpu().numpy()
+    finally:
+        bhq.bhq_pm_destroy(pm)
+    sa = np.sqrt((a_ref ** 2).sum(1).mean())
+    ea = np.abs(ag - a_ref).max() / sa
+    ep = np.abs(pg - p_ref).max() / np.sqrt((p_ref ** 2).mean())
+    log("  force %.3g, potential %.3g (max error / rms)" % (ea, ep))
+    assert ea < 1e-10 and ep < 1e-10
