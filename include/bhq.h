@@ -416,9 +416,9 @@ int bhq_energies(bhq_ctx *ctx, int64_t n, const double *m, const double *v,
  * ------------------------------------------------------------------------ */
 typedef struct bhq_pm bhq_pm;
 
-/* n: even mesh size in [4, 2048]; box > 0; rs > 0 (the split scale of
- * bhq_set_split).  Allocates 5 real and 5 complex meshes and the FFT plans
- * on `device`.  Errors: BHQ_E_ARG, BHQ_E_NODEV, BHQ_E_NOMEM, BHQ_E_HIP;
+/* n: even mesh size in [4, 1024]; box > 0; rs > 0 (the split scale of
+ * bhq_set_split).  Allocates the real, complex and interleaved meshes and
+ * the FFT plans on `device`.  Errors: BHQ_E_ARG, BHQ_E_NODEV, BHQ_E_NOMEM, BHQ_E_HIP;
  * bhq_pm_last_error(NULL) describes a failed create. */
 int bhq_pm_create(bhq_pm **out, int device, int nmesh, double box, double rs);
 
@@ -428,7 +428,9 @@ int bhq_pm_destroy(bhq_pm *pm);
 /* Long-range acceleration and potential of n particles, x[n][3] (in
  * [0, box) or any periodic image) and m[n] in device memory: writes, or
  * with accumulate = 1 adds to, a[n][3] and pot[n] (pot may be NULL), in
- * the order of x.  Asynchronous on `stream`.  Errors: BHQ_E_ARG,
+ * the order of x.  The mass assignment gathers particles sorted by their
+ * nearest mesh point in a fixed order, so results are bitwise reproducible.
+ * Asynchronous on `stream`.  Errors: BHQ_E_ARG,
  * BHQ_E_RANGE (pointers), BHQ_E_HIP. */
 int bhq_pm_compute(bhq_pm *pm, int64_t n, const double *x, const double *m,
                    double *a, double *pot, int accumulate, void *stream);

@@ -7,19 +7,23 @@
 // -4 pi exp(-k^2 r_s^2) / k^2.  In the periodic box of side L (mean density
 // removed, G = 1) on an n^3 mesh of spacing h = L / n:
 //   1. triangular-shaped-cloud (TSC) assignment of the masses (mesh points
-//      at integer multiples of h), one thread per particle with FP64 atomic
-//      adds;
+//      at integer multiples of h): the particles are radix-sorted by their
+//      nearest mesh point, and one thread per mesh point sums, in a fixed
+//      order, the particles of the 27 cells around it (no atomics: the
+//      result is the same bits every run);
 //   2. forward real-to-complex FFT (hipFFT);
 //   3. one thread per complex mode: phi(k) = G(k) rho(k) with
 //      G = -4 pi exp(-k^2 r_s^2) / k^2 / W(k)^2, W = prod_a sinc(k_a h/2)^3
 //      (TSC window, assignment and interpolation), G(0) = 0, and the three
 //      components -i k_a phi(k) (zero on the Nyquist planes);
 //   4. four inverse complex-to-real FFTs (potential and acceleration);
-//   5. one thread per particle interpolates the four meshes with the same
-//      TSC weights.
-// All FP64.  The atomic adds of step 1 make the last bits of the mesh
-// depend on the order in which particles arrive.
+//   5. the four meshes are interleaved into one (a_x, a_y, a_z, phi) record
+//      per mesh point, and one thread per particle, in the sorted order,
+//      interpolates them with the same TSC weights and writes its result
+//      at the particle's input position.
+// All FP64.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 #include <hipfft/hipfft.h>
 
 #include <cmath>
@@ -62,24 +66,61 @@ __device__ __forceinline__ Tsc tsc(const double *x, double ih, int n)
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-__global__ __launch_bounds__(kBlock) void k_assign(int64_t np, const double *x, const double *m,
-                                                   double ih, int n, double *rho)
+// Cell of the nearest mesh point of each particle, and the identity order.
+__global__ __launch_bounds__(kBlock) void k_cell_keys(int64_t np, const double *x, double ih,
+                                                      int n, uint32_t *key, int32_t *idx)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= np) return;
     const Tsc t = tsc(x + 3 * p, ih, n);
-    const double mp = m[p];
-    for (int a = 0; a < 3; ++a) {
-        const int ix = wrap(t.i[0] + a - 1, n);
-        for (int b = 0; b < 3; ++b) {
-            const int iy = wrap(t.i[1] + b - 1, n);
-            const double wab = mp * t.w[a][0] * t.w[b][1];
-            for (int c = 0; c < 3; ++c) {
-                const int iz = wrap(t.i[2] + c - 1, n);
-                atomicAdd(rho + ((int64_t)ix * n + iy) * n + iz, wab * t.w[c][2]);
+    key[p] = (uint32_t)(((int64_t)t.i[0] * n + t.i[1]) * n + t.i[2]);
+    idx[p] = (int32_t)p;
+}
+
+// Sorted particle records (x, y, z, m) and each cell's range [start, end).
+__global__ __launch_bounds__(kBlock) void k_sorted(int64_t np, const uint32_t *key,
+                                                   const int32_t *idx, const double *x,
+                                                   const double *m, double4 *xs,
+                                                   int32_t *start, int32_t *end)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= np) return;
+    const int64_t p = idx[k];
+    xs[k] = make_double4(x[3 * p], x[3 * p + 1], x[3 * p + 2], m[p]);
+    const uint32_t c = key[k];
+    if (k == 0 || key[k - 1] != c) start[c] = (int32_t)k;
+    if (k == np - 1 || key[k + 1] != c) end[c] = (int32_t)(k + 1);
+}
+
+// rho at mesh point q: the particles whose nearest point is q - o,
+// o in {-1, 0, 1}^3, each with its TSC weight for offset o.
+__global__ __launch_bounds__(kBlock) void k_gather_rho(int n, double ih, const double4 *xs,
+                                                       const int32_t *start,
+                                                       const int32_t *end, double *rho)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t n3 = (int64_t)n * n * n;
+    if (q >= n3) return;
+    const int qz = (int)(q % n), qy = (int)((q / n) % n), qx = (int)(q / ((int64_t)n * n));
+    double sum = 0.0;
+    for (int ox = -1; ox <= 1; ++ox) {
+        const int cx = wrap(qx - ox, n);
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int cy = wrap(qy - oy, n);
+            for (int oz = -1; oz <= 1; ++oz) {
+                const int cz = wrap(qz - oz, n);
+                const int64_t c = ((int64_t)cx * n + cy) * n + cz;
+                const int32_t e = end[c];
+                for (int32_t k = start[c]; k < e; ++k) {
+                    const double4 r = xs[k];
+                    const double xp[3] = {r.x, r.y, r.z};
+                    const Tsc t = tsc(xp, ih, n);
+                    sum += r.w * t.w[ox + 1][0] * t.w[oy + 1][1] * t.w[oz + 1][2];
+                }
             }
         }
     }
+    rho[q] = sum;
 }
 
 __device__ __forceinline__ double sinc_half(double kh)
@@ -127,31 +168,44 @@ __global__ __launch_bounds__(kBlock) void k_green(const hipfftDoubleComplex *rk,
     azk[e] = make_hipDoubleComplex(gz * pi, -gz * pr);
 }
 
-__global__ __launch_bounds__(kBlock) void k_interp(int64_t np, const double *x, double ih,
-                                                   int n, const double *phim,
-                                                   const double *axm, const double *aym,
-                                                   const double *azm, double *a, double *pot,
+__global__ __launch_bounds__(kBlock) void k_interleave(int64_t n3, const double *axm,
+                                                       const double *aym, const double *azm,
+                                                       const double *phim, double4 *m4)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n3) return;
+    m4[q] = make_double4(axm[q], aym[q], azm[q], phim[q]);
+}
+
+// Particle k of the sorted order: 27-point TSC interpolation of the
+// interleaved mesh; the result goes to the particle's input index.
+__global__ __launch_bounds__(kBlock) void k_interp(int64_t np, const double4 *xs,
+                                                   const int32_t *idx, double ih, int n,
+                                                   const double4 *m4, double *a, double *pot,
                                                    int accumulate)
 {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= np) return;
-    const Tsc t = tsc(x + 3 * p, ih, n);
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= np) return;
+    const double4 r = xs[k];
+    const double xp[3] = {r.x, r.y, r.z};
+    const Tsc t = tsc(xp, ih, n);
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int a = 0; a < 3; ++a) {
-        const int ix = wrap(t.i[0] + a - 1, n);
+    for (int a0 = 0; a0 < 3; ++a0) {
+        const int ix = wrap(t.i[0] + a0 - 1, n);
         for (int b = 0; b < 3; ++b) {
             const int iy = wrap(t.i[1] + b - 1, n);
             for (int c = 0; c < 3; ++c) {
                 const int iz = wrap(t.i[2] + c - 1, n);
-                const int64_t q = ((int64_t)ix * n + iy) * n + iz;
-                const double w = t.w[a][0] * t.w[b][1] * t.w[c][2];
-                s[0] += w * axm[q];
-                s[1] += w * aym[q];
-                s[2] += w * azm[q];
-                s[3] += w * phim[q];
+                const double4 v = m4[((int64_t)ix * n + iy) * n + iz];
+                const double w = t.w[a0][0] * t.w[b][1] * t.w[c][2];
+                s[0] += w * v.x;
+                s[1] += w * v.y;
+                s[2] += w * v.z;
+                s[3] += w * v.w;
             }
         }
     }
+    const int64_t p = idx[k];
     if (accumulate) {
         a[3 * p] += s[0];
         a[3 * p + 1] += s[1];
@@ -172,7 +226,9 @@ struct bhq_pm {
     int n = 0;
     double box = 0.0, rs = 0.0;
     std::string err;
-    bhq::DevArray rho, rk, phik, axk, ayk, azk, phim, axm, aym, azm;
+    bhq::DevArray rho, rk, phik, axk, ayk, azk, phim, axm, aym, azm, m4;
+    // per-particle sorting (grown to the largest n seen)
+    bhq::DevArray key, key2, idx, idx2, xs, sort_tmp, start, end;
     hipfftHandle fwd = 0, inv = 0;
     bool have_fwd = false, have_inv = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -199,7 +255,8 @@ void pm_free(bhq_pm *p)
     if (p->have_fwd) (void)hipfftDestroy(p->fwd);
     if (p->have_inv) (void)hipfftDestroy(p->inv);
     for (bhq::DevArray *a : {&p->rho, &p->rk, &p->phik, &p->axk, &p->ayk, &p->azk, &p->phim,
-                             &p->axm, &p->aym, &p->azm})
+                             &p->axm, &p->aym, &p->azm, &p->m4, &p->key, &p->key2, &p->idx,
+                             &p->idx2, &p->xs, &p->sort_tmp, &p->start, &p->end})
         a->release();
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
@@ -229,9 +286,9 @@ int bhq_pm_create(bhq_pm **out, int device, int nmesh, double box, double rs)
 {
     if (!out) return BHQ_E_ARG;
     *out = nullptr;
-    if (nmesh < 4 || nmesh > 2048 || (nmesh & 1) || !(box > 0.0) || !std::isfinite(box) ||
+    if (nmesh < 4 || nmesh > 1024 || (nmesh & 1) || !(box > 0.0) || !std::isfinite(box) ||
         !(rs > 0.0) || !std::isfinite(rs)) {
-        g_pm_create_error = "bhq_pm_create: need an even mesh size in [4, 2048], box > 0, rs > 0";
+        g_pm_create_error = "bhq_pm_create: need an even mesh size in [4, 1024], box > 0, rs > 0";
         return BHQ_E_ARG;
     }
     int count = 0;
@@ -259,6 +316,9 @@ int bhq_pm_create(bhq_pm **out, int device, int nmesh, double box, double rs)
         if (e == hipSuccess) e = a->reserve(n3 * sizeof(double));
     for (bhq::DevArray *a : {&p->rk, &p->phik, &p->axk, &p->ayk, &p->azk})
         if (e == hipSuccess) e = a->reserve(nc * sizeof(hipfftDoubleComplex));
+    if (e == hipSuccess) e = p->m4.reserve(n3 * sizeof(double4));
+    if (e == hipSuccess) e = p->start.reserve(n3 * sizeof(int32_t));
+    if (e == hipSuccess) e = p->end.reserve(n3 * sizeof(int32_t));
     if (e == hipSuccess) e = hipEventCreate(&p->ev0);
     if (e == hipSuccess) e = hipEventCreate(&p->ev1);
     if (e != hipSuccess) {
@@ -323,8 +383,38 @@ int bhq_pm_compute(bhq_pm *pm, int64_t np, const double *x, const double *m, dou
         return false;
     };
     if (!hipok(hipEventRecord(pm->ev0, s), "event")) return BHQ_E_HIP;
-    if (!hipok(hipMemsetAsync(pm->rho.p, 0, n3 * sizeof(double), s), "memset")) return BHQ_E_HIP;
-    hipLaunchKernelGGL(k_assign, dim3(nblocks(np)), dim3(kBlock), 0, s, np, x, m, ih, n,
+    // particles sorted by their nearest mesh point, cell ranges, density
+    for (bhq::DevArray *b : {&pm->key, &pm->key2})
+        if (!hipok(b->reserve((size_t)np * 4), "allocation")) return BHQ_E_NOMEM;
+    for (bhq::DevArray *b : {&pm->idx, &pm->idx2})
+        if (!hipok(b->reserve((size_t)np * 4), "allocation")) return BHQ_E_NOMEM;
+    if (!hipok(pm->xs.reserve((size_t)np * sizeof(double4)), "allocation")) return BHQ_E_NOMEM;
+    int bits = 1;
+    while (((uint64_t)1 << bits) < (uint64_t)n3) ++bits;
+    size_t tmp = 0;
+    if (!hipok(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, pm->key.as<uint32_t>(),
+                                                  pm->key2.as<uint32_t>(), pm->idx.as<int32_t>(),
+                                                  pm->idx2.as<int32_t>(), (int)np, 0, bits, s),
+               "sort size"))
+        return BHQ_E_HIP;
+    if (!hipok(pm->sort_tmp.reserve(tmp), "allocation")) return BHQ_E_NOMEM;
+    hipLaunchKernelGGL(k_cell_keys, dim3(nblocks(np)), dim3(kBlock), 0, s, np, x, ih, n,
+                       pm->key.as<uint32_t>(), pm->idx.as<int32_t>());
+    if (!hipok(hipGetLastError(), "cell keys")) return BHQ_E_HIP;
+    if (!hipok(hipcub::DeviceRadixSort::SortPairs(pm->sort_tmp.p, tmp, pm->key.as<uint32_t>(),
+                                                  pm->key2.as<uint32_t>(), pm->idx.as<int32_t>(),
+                                                  pm->idx2.as<int32_t>(), (int)np, 0, bits, s),
+               "sort"))
+        return BHQ_E_HIP;
+    if (!hipok(hipMemsetAsync(pm->start.p, 0, n3 * sizeof(int32_t), s), "memset") ||
+        !hipok(hipMemsetAsync(pm->end.p, 0, n3 * sizeof(int32_t), s), "memset"))
+        return BHQ_E_HIP;
+    hipLaunchKernelGGL(k_sorted, dim3(nblocks(np)), dim3(kBlock), 0, s, np,
+                       pm->key2.as<uint32_t>(), pm->idx2.as<int32_t>(), x, m,
+                       pm->xs.as<double4>(), pm->start.as<int32_t>(), pm->end.as<int32_t>());
+    if (!hipok(hipGetLastError(), "sorted records")) return BHQ_E_HIP;
+    hipLaunchKernelGGL(k_gather_rho, dim3(nblocks((int64_t)n3)), dim3(kBlock), 0, s, n, ih,
+                       pm->xs.as<double4>(), pm->start.as<int32_t>(), pm->end.as<int32_t>(),
                        pm->rho.as<double>());
     if (!hipok(hipGetLastError(), "assignment")) return BHQ_E_HIP;
     if (!fftok(hipfftSetStream(pm->fwd, s), "set stream") ||
@@ -346,9 +436,13 @@ int bhq_pm_compute(bhq_pm *pm, int64_t np, const double *x, const double *m, dou
                                  t.out->as<hipfftDoubleReal>()),
                    "inverse FFT"))
             return BHQ_E_HIP;
-    hipLaunchKernelGGL(k_interp, dim3(nblocks(np)), dim3(kBlock), 0, s, np, x, ih, n,
-                       pm->phim.as<double>(), pm->axm.as<double>(), pm->aym.as<double>(),
-                       pm->azm.as<double>(), a, pot, accumulate);
+    hipLaunchKernelGGL(k_interleave, dim3(nblocks((int64_t)n3)), dim3(kBlock), 0, s,
+                       (int64_t)n3, pm->axm.as<double>(), pm->aym.as<double>(),
+                       pm->azm.as<double>(), pm->phim.as<double>(), pm->m4.as<double4>());
+    if (!hipok(hipGetLastError(), "interleave")) return BHQ_E_HIP;
+    hipLaunchKernelGGL(k_interp, dim3(nblocks(np)), dim3(kBlock), 0, s, np,
+                       pm->xs.as<double4>(), pm->idx2.as<int32_t>(), ih, n,
+                       pm->m4.as<double4>(), a, pot, accumulate);
     if (!hipok(hipGetLastError(), "interpolation")) return BHQ_E_HIP;
     if (!hipok(hipEventRecord(pm->ev1, s), "event")) return BHQ_E_HIP;
     pm->launched = true;

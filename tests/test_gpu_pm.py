@@ -43,9 +43,12 @@ def test_pm_matches_reference(n, nmesh):
         log("case pm n=%d mesh=%d: force %.3g pot %.3g (rel. to rms), %.3f ms"
             % (n, nmesh, ea, ep, ms))
         assert ea < 1e-11 and ep < 1e-11
-        # accumulate adds the same values
+        # bitwise reproducible; accumulate adds the same values
+        a1, p1 = a.cpu().numpy(), p.cpu().numpy()
+        bhq.bhq_pm_compute(pm, xt, mt, a, p)
+        assert np.array_equal(a.cpu().numpy(), a1) and np.array_equal(p.cpu().numpy(), p1)
         bhq.bhq_pm_compute(pm, xt, mt, a, p, accumulate=True)
-        assert _rel(a.cpu().numpy(), 2 * a_ref) < 1e-11
+        assert np.array_equal(a.cpu().numpy(), a1 + a1)
     finally:
         bhq.bhq_pm_destroy(pm)
 
@@ -107,7 +110,8 @@ def test_treepm_total_matches_oracle():
 
 
 def test_pm_errors():
-    for args in ((3, 1.0, 0.1), (33, 1.0, 0.1), (32, 0.0, 0.1), (32, 1.0, -1.0)):
+    for args in ((3, 1.0, 0.1), (33, 1.0, 0.1), (32, 0.0, 0.1), (32, 1.0, -1.0),
+                 (2048, 1.0, 0.1)):
         with pytest.raises(bhq.BhqError) as ei:
             bhq.bhq_pm_create(*args)
         assert ei.value.code == bhq.E_ARG
