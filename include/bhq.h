@@ -349,6 +349,21 @@ int bhq_build_lists_device(bhq_ctx *ctx, int64_t n, const double *x,
                            const double *m, double theta, int ncrit,
                            int nleaf, double box, double rcut, void *stream);
 
+/* The same for nsys independent systems in one context, as
+ * bhq_build_lists_batch builds them: system s is particles sys_off[s] ..
+ * sys_off[s+1]-1 (host array, sys_off[0] == 0, strictly increasing, at
+ * most 2^20 systems and 2^31 - 1 particles), open boundaries, one root per
+ * system from its own bounding box; cells are numbered system by system.
+ * eps2 (device, may be NULL) gives each particle's squared softening in
+ * input order: the context then holds it in group order, as bhq_set_eps2_i
+ * would (values must be finite and > 0: BHQ_E_ARG otherwise).
+ * Errors as bhq_build_lists_device, BHQ_E_RANGE for bad offsets. */
+int bhq_build_lists_device_batch(bhq_ctx *ctx, int64_t nsys,
+                                 const int64_t *sys_off, const double *x,
+                                 const double *m, const double *eps2,
+                                 double theta, int ncrit, int nleaf,
+                                 void *stream);
+
 /* Sizes of the index lists a context holds: out[0..3] = groups, j-particle
  * entries, j-cell entries, cells in the cell pool.  BHQ_E_STATE without
  * index lists. */

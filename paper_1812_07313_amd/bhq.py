@@ -89,6 +89,9 @@ SIGNATURES = {
                                               ctypes.c_double, ctypes.c_int,
                                               ctypes.c_int, ctypes.c_double,
                                               ctypes.c_double, _P]),
+    "bhq_build_lists_device_batch": (ctypes.c_int, [_P, ctypes.c_int64, _I64, _P, _P, _P,
+                                                    ctypes.c_double, ctypes.c_int,
+                                                    ctypes.c_int, _P]),
     "bhq_get_lists_sizes": (ctypes.c_int, [_P, _I64]),
     "bhq_get_lists": (ctypes.c_int, [_P, _I64, _I64, _I64, _I64, _I64, _I32]),
     "bhq_get_cells": (ctypes.c_int, [_P, _D, _D, _D, _D]),
@@ -434,6 +437,19 @@ def bhq_build_lists_device(ctx, x, m, theta, ncrit, nleaf=8, box=0.0, rcut=0.0,
     _check(lib().bhq_build_lists_device(ctx, n, px, pm, float(theta), int(ncrit),
                                         int(nleaf), float(box), float(rcut),
                                         _stream_handle(stream)), ctx)
+
+
+def bhq_build_lists_device_batch(ctx, sys_off, x, m, theta, ncrit, nleaf=8, eps2=None,
+                                 stream=None):
+    """Independent systems (host sys_off[nsys+1]); x, m, eps2 (optional)
+    GPU tensors in input order."""
+    so = _i64(sys_off)
+    nsys = so.shape[0] - 1
+    n = int(m.shape[0])
+    _check(lib().bhq_build_lists_device_batch(
+        ctx, nsys, _ip(so), _device_ptr(x, (n, 3), "x"), _device_ptr(m, (n,), "m"),
+        None if eps2 is None else _device_ptr(eps2, (n,), "eps2"), float(theta),
+        int(ncrit), int(nleaf), _stream_handle(stream)), ctx)
 
 
 def bhq_get_lists_sizes(ctx):

@@ -1164,23 +1164,23 @@ static int check_device_range(bhq_ctx *ctx, const void *p, size_t bytes,
     return BHQ_OK;
 }
 
-int bhq_build_lists_device(bhq_ctx *ctx, int64_t n, const double *x,
-                           const double *m, double theta, int ncrit, int nleaf,
-                           double box, double rcut, void *stream)
+static int device_build(bhq_ctx *ctx, int64_t nsys, const int64_t *sys_off,
+                        const double *x, const double *m, const double *eps2, double theta,
+                        int ncrit, int nleaf, double box, double rcut, void *stream)
 {
-    CHECK_CTX(ctx);
-    if (n < 1 || n > 0x7fffffffLL || !x || !m || !(theta >= 0.0) ||
-        !std::isfinite(theta) || ncrit < 1 || nleaf < 1 || nleaf > ncrit ||
-        !(box >= 0.0) || !std::isfinite(box) || !(rcut >= 0.0) ||
-        !std::isfinite(rcut))
+    const int64_t n = sys_off[nsys];
+    if (n < 1 || n > 0x7fffffffLL || !x || !m || !(theta >= 0.0) || !std::isfinite(theta) ||
+        ncrit < 1 || nleaf < 1 || nleaf > ncrit || !(box >= 0.0) || !std::isfinite(box) ||
+        !(rcut >= 0.0) || !std::isfinite(rcut))
         return ctx->fail(BHQ_E_ARG, "build_lists_device: bad argument");
     TRY(ctx->select());
     TRY(check_device_range(ctx, x, (size_t)n * 3 * sizeof(double), "x"));
     TRY(check_device_range(ctx, m, (size_t)n * sizeof(double), "m"));
+    if (eps2) TRY(check_device_range(ctx, eps2, (size_t)n * sizeof(double), "eps2"));
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
 
-    bhq::TreeParams P{x, m, n, theta, ncrit, nleaf, box, rcut};
+    bhq::TreeParams P{x, m, eps2, n, nsys, sys_off, theta, ncrit, nleaf, box, rcut};
     bhq::TreeOut O;
     O.i_off = &ctx->arr[A_IOFF];
     O.jp_off = &ctx->arr[A_JPOFF];
@@ -1191,6 +1191,7 @@ int bhq_build_lists_device(bhq_ctx *ctx, int64_t n, const double *x,
     O.xi = &ctx->arr[A_XI];
     O.yi = &ctx->arr[A_YI];
     O.zi = &ctx->arr[A_ZI];
+    O.e2i = &ctx->arr[A_E2I];
     O.pool_p = &ctx->arr[A_POOLP];
     O.pool_c = &ctx->arr[A_POOLC];
     O.jp_idx = &ctx->arr[A_JPIDX];
@@ -1209,6 +1210,8 @@ int bhq_build_lists_device(bhq_ctx *ctx, int64_t n, const double *x,
         {A_AZ, (size_t)n * D}, {A_POT, (size_t)n * D},
     };
     for (auto &q : need) {
+        // A_E2I already holds the gathered softening when eps2 was given
+        if (q.a == A_E2I && eps2) continue;
         hipError_t e = ctx->arr[q.a].reserve(q.bytes);
         if (e != hipSuccess) return ctx->hip_fail(e, "hipMalloc");
     }
@@ -1226,7 +1229,10 @@ int bhq_build_lists_device(bhq_ctx *ctx, int64_t n, const double *x,
     ctx->npool_c = O.ncell;
     ctx->have_jp_idx = ctx->have_jc_idx = true;
     ctx->tree_order = true;
-    if (ctx->eps_mode == 2) ctx->eps_mode = 0;
+    if (eps2)
+        ctx->eps_mode = 2;
+    else if (ctx->eps_mode == 2)
+        ctx->eps_mode = 0;
     ctx->nslots = 0;
     const int orc = ctx->upload_order();
     if (orc != BHQ_OK) {
@@ -1235,6 +1241,32 @@ int bhq_build_lists_device(bhq_ctx *ctx, int64_t n, const double *x,
     }
     if (ctx->eps_mode == 1) TRY(ctx->fill_eps_uniform());
     return BHQ_OK;
+}
+
+int bhq_build_lists_device(bhq_ctx *ctx, int64_t n, const double *x,
+                           const double *m, double theta, int ncrit, int nleaf,
+                           double box, double rcut, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (n < 1 || n > 0x7fffffffLL) return ctx->fail(BHQ_E_ARG, "build_lists_device: bad n");
+    const int64_t off[2] = {0, n};
+    return device_build(ctx, 1, off, x, m, nullptr, theta, ncrit, nleaf, box, rcut, stream);
+}
+
+int bhq_build_lists_device_batch(bhq_ctx *ctx, int64_t nsys, const int64_t *sys_off,
+                                 const double *x, const double *m, const double *eps2,
+                                 double theta, int ncrit, int nleaf, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (nsys < 1 || nsys > (1 << 20) || !sys_off || sys_off[0] != 0)
+        return ctx->fail(BHQ_E_ARG, "build_lists_device_batch: bad systems");
+    for (int64_t q = 0; q < nsys; ++q)
+        if (sys_off[q + 1] <= sys_off[q])
+            return ctx->fail(BHQ_E_RANGE, "build_lists_device_batch: sys_off not strictly "
+                                          "increasing at %lld", (long long)q);
+    if (sys_off[nsys] > 0x7fffffffLL)
+        return ctx->fail(BHQ_E_ARG, "build_lists_device_batch: too many particles");
+    return device_build(ctx, nsys, sys_off, x, m, eps2, theta, ncrit, nleaf, 0.0, 0.0, stream);
 }
 
 int bhq_get_lists_sizes(const bhq_ctx *ctx, int64_t out[4])

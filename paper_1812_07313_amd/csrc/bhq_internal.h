@@ -139,7 +139,10 @@ hipError_t launch_energies(int64_t n, const double *m, const double *v,
 struct TreeParams {
     const double *x;
     const double *m;
+    const double *eps2;       // [n] per-particle softening squared, or NULL
     int64_t n;
+    int64_t nsys;             // independent systems (1: one system)
+    const int64_t *sys_off;   // host [nsys + 1]: system s is [sys_off[s], sys_off[s+1])
     double theta;
     int ncrit, nleaf;
     double box, rcut;
@@ -150,7 +153,8 @@ enum TreeBuf {
     T_KEY, T_KEY2, T_IDX0, T_SORT, T_BBOX, T_FLAG,
     T_CX, T_CY, T_CZ, T_SIDE, T_FIRST, T_COUNT, T_CHILD0, T_NCHILD, T_PARENT,
     T_DEPTH, T_CKEY, T_NCH, T_NOFF, T_GSTART, T_GROUPS, T_NSEL, T_WC, T_WL,
-    T_JPCNT, T_JCCNT, T_COUNT_
+    T_JPCNT, T_JCCNT, T_CSYS, T_SYSOFF, T_SYSOFF32, T_ROOTS, T_SYSROOT, T_LSC, T_PERM,
+    T_COUNT_
 };
 
 // Where the results go: arrays of the force context, filled in the layout
@@ -159,6 +163,7 @@ struct TreeOut {
     DevArray *i_off, *jp_off, *jc_off;        // int64 [ng+1]
     DevArray *gcx, *gcy, *gcz;                // FP64 [ng] group centres
     DevArray *xi, *yi, *zi;                   // FP64 [n] i-particles
+    DevArray *e2i;                            // FP64 [n] softening (when given)
     DevArray *pool_p;                         // PartRec [n], tree order
     DevArray *pool_c;                         // CellRec [ncell]
     DevArray *jp_idx, *jc_idx;                // int32 list entries

@@ -4,15 +4,18 @@
 // The construction is the host builder's (Kodama & Ishiyama, Sec. 1 for
 // the tree, Sec. 3.4 for the groups and their shared lists), step by step,
 // so that cells, moments, groups and lists come out identical:
-//   1. root cube from the bounding box (or [0, box)^3);
+//   1. root cube from the bounding box (or [0, box)^3); for a batch of
+//      independent systems one root per system from that system's box;
 //   2. a 63-bit key per particle by descending 21 levels (upper half along
 //      an axis iff the coordinate is >= the cell centre), then a stable
-//      radix sort by key (ties keep input order);
+//      radix sort by key (ties keep input order), segmented by system;
 //   3. cells breadth-first, one level per pass: a cell with more than nleaf
 //      particles above depth 21 gets one child per non-empty octant, found
 //      by binary search in the sorted keys; children are numbered in the
 //      order of their parents, then octants (the host's breadth-first ids);
-//      particles inside a leaf return to input order;
+//      particles inside a leaf return to input order; a batch's cells are
+//      then renumbered system by system (each system's cells breadth first,
+//      the host's concatenation of independently built systems);
 //   4. moments: leaves from their particles, parents from their children
 //      by the parallel-axis shift, deepest level first;
 //   5. groups: the largest cells with at most ncrit particles (or leaves),
@@ -60,7 +63,7 @@ struct alignas(16) WLink {
 
 struct Cells {
     double *cx, *cy, *cz, *side;
-    int32_t *first, *count, *child0, *nchild, *parent, *depth;
+    int32_t *first, *count, *child0, *nchild, *parent, *depth, *sys;
     uint64_t *key;
 };
 
@@ -124,28 +127,73 @@ __global__ __launch_bounds__(kBlock) void k_bbox_final(double *part, int nb)
     if (threadIdx.x < 6) part[threadIdx.x] = s[threadIdx.x][0];
 }
 
-// Non-finite positions or masses set *flag (a vector store of 1).
+// Non-finite positions or masses set flag[0]; a softening that is not
+// finite and positive sets flag[1] (vector stores of 1).
 __global__ __launch_bounds__(kBlock) void k_check_finite(const double *x, const double *m,
-                                                         int64_t n, int *flag)
+                                                         const double *eps2, int64_t n,
+                                                         int *flag)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     if (!isfinite(x[3 * p]) || !isfinite(x[3 * p + 1]) || !isfinite(x[3 * p + 2]) ||
         !isfinite(m[p]))
-        *flag = 1;
+        flag[0] = 1;
+    if (eps2 && !(isfinite(eps2[p]) && eps2[p] > 0.0)) flag[1] = 1;
+}
+
+// Bounding box of each system of a batch: one block per system.
+__global__ __launch_bounds__(kBlock) void k_bbox_sys(const double *x, const int64_t *sys_off,
+                                                     double *bb)
+{
+    __shared__ double sh[6][kBlock];
+    const int64_t a = sys_off[blockIdx.x], e = sys_off[blockIdx.x + 1];
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) lo[k] = hi[k] = x[3 * a + k];
+    for (int64_t p = a + threadIdx.x; p < e; p += kBlock)
+        for (int k = 0; k < 3; ++k) {
+            const double v = x[3 * p + k];
+            lo[k] = v < lo[k] ? v : lo[k];
+            hi[k] = v > hi[k] ? v : hi[k];
+        }
+    for (int k = 0; k < 3; ++k) {
+        sh[k][threadIdx.x] = lo[k];
+        sh[3 + k][threadIdx.x] = hi[k];
+    }
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 3; ++k) {
+                const double l = sh[k][threadIdx.x + h], u = sh[3 + k][threadIdx.x + h];
+                if (l < sh[k][threadIdx.x]) sh[k][threadIdx.x] = l;
+                if (u > sh[3 + k][threadIdx.x]) sh[3 + k][threadIdx.x] = u;
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) bb[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // ---- 2. keys ----------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_keys(const double *x, int64_t n, double r0,
-                                                 double r1, double r2, double rside,
-                                                 uint64_t *key, int32_t *idx)
+// roots[4 s .. 4 s + 3] = centre and side of system s's root cube.
+__global__ __launch_bounds__(kBlock) void k_keys(const double *x, int64_t n,
+                                                 const int64_t *sys_off, int nsys,
+                                                 const double *roots, uint64_t *key,
+                                                 int32_t *idx)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
+    int lo = 0, hi = nsys;  // system of p: sys_off[s] <= p < sys_off[s + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (sys_off[mid] <= p)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const double *rt = roots + 4 * lo;
     const double xp[3] = {x[3 * p], x[3 * p + 1], x[3 * p + 2]};
-    double c[3] = {r0, r1, r2};
-    double s = rside;
+    double c[3] = {rt[0], rt[1], rt[2]};
+    double s = rt[3];
     uint64_t k = 0;
     for (int lev = 0; lev < kMaxDepth; ++lev) {
         const double qd = s * 0.25;
@@ -236,6 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_level_write(Cells C, const uint64_t 
         C.child0[ch] = -1;
         C.nchild[ch] = 0;
         C.parent[ch] = c;
+        C.sys[ch] = C.sys[c];
     }
     C.child0[c] = child0;
     C.nchild[c] = j;
@@ -373,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_group_mark(Cells C, int32_t ncell, i
     const int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     if (c >= ncell) return;
     const bool cond = C.count[c] <= ncrit || C.child0[c] < 0;
-    const bool top = c == 0 || C.count[C.parent[c]] > ncrit;
+    const bool top = C.parent[c] < 0 || C.count[C.parent[c]] > ncrit;
     if (cond && top) gstart[C.first[c]] = c;
 }
 
@@ -423,6 +472,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_cells(Cells C, int32_t ncell,
 
 struct WalkArgs {
     const int32_t *groups;
+    const int32_t *cell_sys;           // system of each cell
+    const int32_t *sys_root;           // root cell of each system
     int64_t ng;
     const WCell *wc;
     const WLink *wl;
@@ -449,7 +500,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
     int64_t np = 0, nc = 0;
     const int64_t pb = FILL ? W.jp_off[gi] : 0, cb = FILL ? W.jc_off[gi] : 0;
     int sp = 0;
-    int32_t id = 0;  // the root first
+    int32_t id = W.sys_root[W.cell_sys[gid]];  // the group's own root first
     for (;;) {
         const WCell C = W.wc[id];
         const WLink L = W.wl[id];
@@ -525,12 +576,14 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
 
 __global__ __launch_bounds__(kBlock) void k_particles_out(const int32_t *idx, int64_t n,
                                                           const double *x, const double *m,
-                                                          PartRec *pool, double *xi,
-                                                          double *yi, double *zi)
+                                                          const double *eps2, PartRec *pool,
+                                                          double *xi, double *yi, double *zi,
+                                                          double *e2i)
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= n) return;
     const int64_t p = idx[k];
+    if (eps2) e2i[k] = eps2[p];
     PartRec r;
     r.x = x[3 * p];
     r.y = x[3 * p + 1];
@@ -559,21 +612,57 @@ __global__ __launch_bounds__(kBlock) void k_groups_out(Cells C, const int32_t *g
     gcz[g] = C.cz[c];
 }
 
-__global__ __launch_bounds__(kBlock) void k_set_cell(Cells C, double r0, double r1, double r2,
-                                                     double rside, int32_t n)
+__global__ __launch_bounds__(kBlock) void k_set_roots(Cells C, const double *roots,
+                                                      const int64_t *sys_off, int nsys)
 {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    C.cx[0] = r0;
-    C.cy[0] = r1;
-    C.cz[0] = r2;
-    C.side[0] = rside;
-    C.first[0] = 0;
-    C.count[0] = n;
-    C.key[0] = 0;
-    C.depth[0] = 0;
-    C.child0[0] = -1;
-    C.nchild[0] = 0;
-    C.parent[0] = -1;
+    const int sidx = blockIdx.x * kBlock + threadIdx.x;
+    if (sidx >= nsys) return;
+    C.cx[sidx] = roots[4 * sidx];
+    C.cy[sidx] = roots[4 * sidx + 1];
+    C.cz[sidx] = roots[4 * sidx + 2];
+    C.side[sidx] = roots[4 * sidx + 3];
+    C.first[sidx] = (int32_t)sys_off[sidx];
+    C.count[sidx] = (int32_t)(sys_off[sidx + 1] - sys_off[sidx]);
+    C.key[sidx] = 0;
+    C.depth[sidx] = 0;
+    C.child0[sidx] = -1;
+    C.nchild[sidx] = 0;
+    C.parent[sidx] = -1;
+    C.sys[sidx] = sidx;
+}
+
+// Cells per (depth, system), for the renumbering of a batch.
+__global__ __launch_bounds__(kBlock) void k_level_sys_count(Cells C, int32_t ncell, int nsys,
+                                                            int32_t *cnt)
+{
+    const int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (c >= ncell) return;
+    atomicAdd(cnt + C.depth[c] * nsys + C.sys[c], 1);
+}
+
+// New id of cell c: base[l][s] + (c - first[l][s]) for its depth l and
+// system s (device cells of one depth are ordered by system).
+__global__ __launch_bounds__(kBlock) void k_perm(Cells C, int32_t ncell, int nsys,
+                                                 const int32_t *base, const int32_t *first,
+                                                 int32_t *perm)
+{
+    const int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (c >= ncell) return;
+    const int t = C.depth[c] * nsys + C.sys[c];
+    perm[c] = base[t] + (c - first[t]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_permute(int32_t ncell, const int32_t *perm,
+                                                    const T *in, T *out, bool ids)
+{
+    const int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (c >= ncell) return;
+    T v = in[c];
+    if constexpr (sizeof(T) == 4) {
+        if (ids && v >= 0) v = perm[v];
+    }
+    out[perm[c]] = v;
 }
 
 }  // namespace
@@ -607,42 +696,79 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     } while (0)
 #define LAUNCHED(w) STEP(hipGetLastError(), w)
 
-    // input check and root cube
+    // input check, systems, root cubes
+    const int nsys = (int)P.nsys;
     STEP(B[T_FLAG].reserve(64), "allocation");
     STEP(hipMemsetAsync(B[T_FLAG].p, 0, 64, s), "memset");
     hipLaunchKernelGGL(k_check_finite, dim3(blocks(n, kBlock)), dim3(kBlock), 0, s, P.x, P.m,
-                       n, B[T_FLAG].as<int>());
+                       P.eps2, n, B[T_FLAG].as<int>());
     LAUNCHED("finite check");
-    int hflag = 0;
-    STEP(hipMemcpyAsync(&hflag, B[T_FLAG].p, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    int hflag2[2] = {0, 0};
+    STEP(hipMemcpyAsync(hflag2, B[T_FLAG].p, sizeof(hflag2), hipMemcpyDeviceToHost, s), "copy");
     STEP(hipStreamSynchronize(s), "sync");
-    if (hflag) {
+    if (hflag2[0]) {
         code = BHQ_E_NONFINITE;
         what = "non-finite position or mass";
         return fail();
     }
-    double rc[3], rside;
-    if (P.box > 0.0) {
-        rc[0] = rc[1] = rc[2] = 0.5 * P.box;
-        rside = P.box;
-    } else {
-        const int nb = (int)std::min<int64_t>(kBboxBlocks, blocks(n, kBlock));
-        STEP(B[T_BBOX].reserve((size_t)nb * 6 * sizeof(double)), "allocation");
-        hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kBlock), 0, s, P.x, n,
-                           B[T_BBOX].as<double>());
-        LAUNCHED("bounding box");
-        hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBlock), 0, s, B[T_BBOX].as<double>(),
-                           nb);
-        LAUNCHED("bounding box");
-        double bb[6];
-        STEP(hipMemcpyAsync(bb, B[T_BBOX].p, sizeof(bb), hipMemcpyDeviceToHost, s), "copy");
-        STEP(hipStreamSynchronize(s), "sync");
-        double ext = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            rc[k] = 0.5 * (bb[k] + bb[3 + k]);
-            ext = std::max(ext, bb[3 + k] - bb[k]);
+    if (hflag2[1]) {
+        code = BHQ_E_ARG;
+        what = "eps2 must be finite and > 0";
+        return fail();
+    }
+    int hflag = 0;
+    STEP(B[T_SYSOFF].reserve((size_t)(nsys + 1) * 8), "allocation");
+    STEP(B[T_SYSOFF32].reserve((size_t)(nsys + 1) * 4), "allocation");
+    STEP(hipMemcpyAsync(B[T_SYSOFF].p, P.sys_off, (size_t)(nsys + 1) * 8,
+                        hipMemcpyHostToDevice, s),
+         "copy");
+    std::vector<double> roots((size_t)nsys * 4);
+    {
+        std::vector<int32_t> so32((size_t)nsys + 1);
+        for (int k = 0; k <= nsys; ++k) so32[(size_t)k] = (int32_t)P.sys_off[k];
+        STEP(hipMemcpyAsync(B[T_SYSOFF32].p, so32.data(), (size_t)(nsys + 1) * 4,
+                            hipMemcpyHostToDevice, s),
+             "copy");
+        std::vector<double> bb((size_t)nsys * 6);
+        if (P.box > 0.0) {
+            for (int k = 0; k < 3; ++k) roots[(size_t)k] = 0.5 * P.box;
+            roots[3] = P.box;
+        } else {
+            if (nsys == 1) {
+                const int nb = (int)std::min<int64_t>(kBboxBlocks, blocks(n, kBlock));
+                STEP(B[T_BBOX].reserve((size_t)nb * 6 * sizeof(double)), "allocation");
+                hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kBlock), 0, s, P.x, n,
+                                   B[T_BBOX].as<double>());
+                LAUNCHED("bounding box");
+                hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBlock), 0, s,
+                                   B[T_BBOX].as<double>(), nb);
+                LAUNCHED("bounding box");
+            } else {
+                STEP(B[T_BBOX].reserve((size_t)nsys * 6 * sizeof(double)), "allocation");
+                hipLaunchKernelGGL(k_bbox_sys, dim3((unsigned)nsys), dim3(kBlock), 0, s, P.x,
+                                   B[T_SYSOFF].as<int64_t>(), B[T_BBOX].as<double>());
+                LAUNCHED("bounding boxes");
+            }
+            STEP(hipMemcpyAsync(bb.data(), B[T_BBOX].p, bb.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, s),
+                 "copy");
+            STEP(hipStreamSynchronize(s), "sync");
+            for (int q = 0; q < nsys; ++q) {
+                const double *b = &bb[(size_t)q * 6];
+                double *rt = &roots[(size_t)q * 4];
+                double ext = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    rt[k] = 0.5 * (b[k] + b[3 + k]);
+                    ext = std::max(ext, b[3 + k] - b[k]);
+                }
+                rt[3] = ext > 0.0 ? ext * (1.0 + std::ldexp(1.0, -20)) : 1.0;
+            }
         }
-        rside = ext > 0.0 ? ext * (1.0 + std::ldexp(1.0, -20)) : 1.0;
+        STEP(B[T_ROOTS].reserve(roots.size() * sizeof(double)), "allocation");
+        STEP(hipMemcpyAsync(B[T_ROOTS].p, roots.data(), roots.size() * sizeof(double),
+                            hipMemcpyHostToDevice, s),
+             "copy");
+        STEP(hipStreamSynchronize(s), "sync");
     }
 
     // keys, sort
@@ -650,26 +776,44 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     STEP(B[T_KEY2].reserve((size_t)n * 8), "allocation");
     STEP(B[T_IDX0].reserve((size_t)n * 4), "allocation");
     STEP(O.order->reserve((size_t)n * 4), "allocation");
-    hipLaunchKernelGGL(k_keys, dim3(blocks(n, kBlock)), dim3(kBlock), 0, s, P.x, n, rc[0],
-                       rc[1], rc[2], rside, B[T_KEY].as<uint64_t>(), B[T_IDX0].as<int32_t>());
+    hipLaunchKernelGGL(k_keys, dim3(blocks(n, kBlock)), dim3(kBlock), 0, s, P.x, n,
+                       B[T_SYSOFF].as<int64_t>(), nsys, B[T_ROOTS].as<double>(),
+                       B[T_KEY].as<uint64_t>(), B[T_IDX0].as<int32_t>());
     LAUNCHED("keys");
     size_t tmp = 0;
-    STEP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, B[T_KEY].as<uint64_t>(),
-                                            B[T_KEY2].as<uint64_t>(), B[T_IDX0].as<int32_t>(),
-                                            O.order->as<int32_t>(), (int)n, 0, 3 * kMaxDepth, s),
-         "sort size");
-    STEP(B[T_SORT].reserve(tmp), "allocation");
-    STEP(hipcub::DeviceRadixSort::SortPairs(B[T_SORT].p, tmp, B[T_KEY].as<uint64_t>(),
-                                            B[T_KEY2].as<uint64_t>(), B[T_IDX0].as<int32_t>(),
-                                            O.order->as<int32_t>(), (int)n, 0, 3 * kMaxDepth, s),
-         "sort");
+    if (nsys == 1) {
+        STEP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, B[T_KEY].as<uint64_t>(),
+                                                B[T_KEY2].as<uint64_t>(),
+                                                B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(),
+                                                (int)n, 0, 3 * kMaxDepth, s),
+             "sort size");
+        STEP(B[T_SORT].reserve(tmp), "allocation");
+        STEP(hipcub::DeviceRadixSort::SortPairs(B[T_SORT].p, tmp, B[T_KEY].as<uint64_t>(),
+                                                B[T_KEY2].as<uint64_t>(),
+                                                B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(),
+                                                (int)n, 0, 3 * kMaxDepth, s),
+             "sort");
+    } else {
+        const int32_t *so = B[T_SYSOFF32].as<int32_t>();
+        STEP(hipcub::DeviceSegmentedRadixSort::SortPairs(
+                 nullptr, tmp, B[T_KEY].as<uint64_t>(), B[T_KEY2].as<uint64_t>(),
+                 B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(), (int)n, nsys, so, so + 1, 0,
+                 3 * kMaxDepth, s),
+             "sort size");
+        STEP(B[T_SORT].reserve(tmp), "allocation");
+        STEP(hipcub::DeviceSegmentedRadixSort::SortPairs(
+                 B[T_SORT].p, tmp, B[T_KEY].as<uint64_t>(), B[T_KEY2].as<uint64_t>(),
+                 B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(), (int)n, nsys, so, so + 1, 0,
+                 3 * kMaxDepth, s),
+             "sort");
+    }
     const uint64_t *skey = B[T_KEY2].as<uint64_t>();
     int32_t *idx = O.order->as<int32_t>();
 
     // cells, level by level
     size_t cap = B[T_CX].p ? B[T_CX].cap / 8 : 0;
     const TreeBuf cbuf8[] = {T_CX, T_CY, T_CZ, T_SIDE, T_CKEY};
-    const TreeBuf cbuf4[] = {T_FIRST, T_COUNT, T_CHILD0, T_NCHILD, T_PARENT, T_DEPTH};
+    const TreeBuf cbuf4[] = {T_FIRST, T_COUNT, T_CHILD0, T_NCHILD, T_PARENT, T_DEPTH, T_CSYS};
     auto cells = [&]() {
         Cells C;
         C.cx = B[T_CX].as<double>();
@@ -683,6 +827,7 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
         C.nchild = B[T_NCHILD].as<int32_t>();
         C.parent = B[T_PARENT].as<int32_t>();
         C.depth = B[T_DEPTH].as<int32_t>();
+        C.sys = B[T_CSYS].as<int32_t>();
         return C;
     };
     auto ensure = [&](size_t need, size_t used) -> bool {
@@ -695,11 +840,12 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
         cap = nc;
         return true;
     };
-    if (!ensure((size_t)std::max<int64_t>(1024, n / 2), 0)) return fail();
-    hipLaunchKernelGGL(k_set_cell, dim3(1), dim3(64), 0, s, cells(), rc[0], rc[1], rc[2],
-                       rside, (int32_t)n);
-    LAUNCHED("root");
-    std::vector<int32_t> level{0, 1};  // level l is cells [level[l], level[l+1])
+    if (!ensure((size_t)std::max<int64_t>(std::max<int64_t>(1024, n / 2), 2 * nsys), 0))
+        return fail();
+    hipLaunchKernelGGL(k_set_roots, dim3(blocks(nsys, kBlock)), dim3(kBlock), 0, s, cells(),
+                       B[T_ROOTS].as<double>(), B[T_SYSOFF].as<int64_t>(), nsys);
+    LAUNCHED("roots");
+    std::vector<int32_t> level{0, nsys};  // level l is cells [level[l], level[l+1])
     STEP(B[T_NCH].reserve((size_t)std::max<int64_t>(n, 1) * 4 + 4), "allocation");
     STEP(B[T_NOFF].reserve((size_t)std::max<int64_t>(n, 1) * 4 + 4), "allocation");
     for (int lev = 0; lev < kMaxDepth; ++lev) {
@@ -756,6 +902,82 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
         LAUNCHED("cell moments");
     }
 
+    // a batch: renumber the cells system by system (each system breadth
+    // first), then the walk starts from each group's own root
+    std::vector<int32_t> sys_root((size_t)nsys, 0);
+    if (nsys > 1) {
+        const int nl = (int)level.size() - 1;
+        const size_t tab = (size_t)kFrames * nsys;
+        STEP(B[T_LSC].reserve(tab * 4 * 3), "allocation");
+        int32_t *cnt = B[T_LSC].as<int32_t>();
+        STEP(hipMemsetAsync(cnt, 0, tab * 4, s), "memset");
+        hipLaunchKernelGGL(k_level_sys_count, dim3(blocks(ncell, kBlock)), dim3(kBlock), 0, s,
+                           cells(), ncell, nsys, cnt);
+        LAUNCHED("level counts");
+        std::vector<int32_t> hc(tab), base(tab, 0), first(tab, 0);
+        STEP(hipMemcpyAsync(hc.data(), cnt, tab * 4, hipMemcpyDeviceToHost, s), "copy");
+        STEP(hipStreamSynchronize(s), "sync");
+        int64_t cb = 0;
+        for (int q = 0; q < nsys; ++q) {
+            sys_root[(size_t)q] = (int32_t)cb;
+            for (int l = 0; l < nl; ++l) {
+                base[(size_t)l * nsys + q] = (int32_t)cb;
+                cb += hc[(size_t)l * nsys + q];
+            }
+        }
+        for (int l = 0; l < nl; ++l) {
+            int64_t f = level[(size_t)l];
+            for (int q = 0; q < nsys; ++q) {
+                first[(size_t)l * nsys + q] = (int32_t)f;
+                f += hc[(size_t)l * nsys + q];
+            }
+        }
+        STEP(hipMemcpyAsync(cnt + tab, base.data(), tab * 4, hipMemcpyHostToDevice, s), "copy");
+        STEP(hipMemcpyAsync(cnt + 2 * tab, first.data(), tab * 4, hipMemcpyHostToDevice, s),
+             "copy");
+        STEP(B[T_PERM].reserve((size_t)ncell * 4), "allocation");
+        int32_t *perm = B[T_PERM].as<int32_t>();
+        hipLaunchKernelGGL(k_perm, dim3(blocks(ncell, kBlock)), dim3(kBlock), 0, s, cells(),
+                           ncell, nsys, cnt + tab, cnt + 2 * tab, perm);
+        LAUNCHED("renumbering");
+        // permute each cell array into a scratch buffer and copy it back (the
+        // arrays keep their allocations; everything is ordered on stream s)
+        const unsigned g = blocks(ncell, kBlock);
+        DevArray nb;
+        if (!hip(nb.reserve((size_t)ncell * sizeof(CellRec)), "allocation")) return fail();
+        auto apply = [&](DevArray &arr, size_t elem, int kind) -> bool {
+            if (kind == 0)
+                hipLaunchKernelGGL((k_permute<double>), dim3(g), dim3(kBlock), 0, s, ncell, perm,
+                                   arr.as<double>(), nb.as<double>(), false);
+            else if (kind == 1)
+                hipLaunchKernelGGL((k_permute<uint64_t>), dim3(g), dim3(kBlock), 0, s, ncell,
+                                   perm, arr.as<uint64_t>(), nb.as<uint64_t>(), false);
+            else if (kind == 2 || kind == 3)
+                hipLaunchKernelGGL((k_permute<int32_t>), dim3(g), dim3(kBlock), 0, s, ncell,
+                                   perm, arr.as<int32_t>(), nb.as<int32_t>(), kind == 3);
+            else
+                hipLaunchKernelGGL((k_permute<CellRec>), dim3(g), dim3(kBlock), 0, s, ncell,
+                                   perm, arr.as<CellRec>(), nb.as<CellRec>(), false);
+            if (!hip(hipGetLastError(), "renumbering")) return false;
+            return hip(hipMemcpyAsync(arr.p, nb.p, (size_t)ncell * elem,
+                                      hipMemcpyDeviceToDevice, s),
+                       "copy");
+        };
+        bool ok = true;
+        for (TreeBuf b : {T_CX, T_CY, T_CZ, T_SIDE}) ok = ok && apply(B[b], 8, 0);
+        ok = ok && apply(B[T_CKEY], 8, 1);
+        for (TreeBuf b : {T_FIRST, T_COUNT, T_NCHILD, T_DEPTH, T_CSYS}) ok = ok && apply(B[b], 4, 2);
+        for (TreeBuf b : {T_CHILD0, T_PARENT}) ok = ok && apply(B[b], 4, 3);
+        ok = ok && apply(*O.pool_c, sizeof(CellRec), 4);
+        (void)hipStreamSynchronize(s);
+        nb.release();
+        if (!ok) return fail();
+    }
+    STEP(B[T_SYSROOT].reserve((size_t)nsys * 4), "allocation");
+    STEP(hipMemcpyAsync(B[T_SYSROOT].p, sys_root.data(), (size_t)nsys * 4,
+                        hipMemcpyHostToDevice, s),
+         "copy");
+
     // groups in depth-first order
     STEP(B[T_GSTART].reserve((size_t)n * 4), "allocation");
     STEP(B[T_GROUPS].reserve((size_t)n * 4), "allocation");
@@ -798,6 +1020,8 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     STEP(hipMemsetAsync(B[T_JCCNT].as<int64_t>() + ng, 0, 8, s), "memset");
     WalkArgs W{};
     W.groups = groups;
+    W.cell_sys = B[T_CSYS].as<int32_t>();
+    W.sys_root = B[T_SYSROOT].as<int32_t>();
     W.ng = ng;
     W.wc = B[T_WC].as<WCell>();
     W.wl = B[T_WL].as<WLink>();
@@ -860,9 +1084,11 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     STEP(O.gcx->reserve((size_t)ng * 8), "allocation");
     STEP(O.gcy->reserve((size_t)ng * 8), "allocation");
     STEP(O.gcz->reserve((size_t)ng * 8), "allocation");
+    if (P.eps2) STEP(O.e2i->reserve((size_t)n * 8), "allocation");
     hipLaunchKernelGGL(k_particles_out, dim3(blocks(n, kBlock)), dim3(kBlock), 0, s, idx, n,
-                       P.x, P.m, O.pool_p->as<PartRec>(), O.xi->as<double>(),
-                       O.yi->as<double>(), O.zi->as<double>());
+                       P.x, P.m, P.eps2, O.pool_p->as<PartRec>(), O.xi->as<double>(),
+                       O.yi->as<double>(), O.zi->as<double>(),
+                       P.eps2 ? O.e2i->as<double>() : nullptr);
     LAUNCHED("particle pool");
     hipLaunchKernelGGL(k_groups_out, dim3(blocks(ng + 1, kBlock)), dim3(kBlock), 0, s, cells(),
                        groups, ng, n, O.i_off->as<int64_t>(), O.gcx->as<double>(),

@@ -139,7 +139,7 @@ def test_periodic_lattice_16m_sampled():
     _check("lattice", gpu, ref, mat["i_idx"])
 
 
-@pytest.mark.parametrize("which", ["cube", "clustered", "lattice"])
+@pytest.mark.parametrize("which", ["cube", "clustered", "lattice", "batched"])
 def test_device_lists_full_size(which):
     """Device-built lists at the benchmark sizes equal the host builder's
     entry for entry (particle order, offsets, every list entry in order)
@@ -151,13 +151,23 @@ def test_device_lists_full_size(which):
     elif which == "clustered":
         c = synth.config_clustered()
         box = rcut = 0.0
-    else:
+    elif which == "lattice":
         c = synth.config_lattice()
         box, rcut = 1.0, c["rcut"]
+    else:
+        systems = synth.batched_plummer(256)
+        sizes = np.array([len(q[1]) for q in systems])
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        c = dict(x=np.concatenate([q[0] for q in systems]),
+                 m=np.concatenate([q[1] for q in systems]), theta=0.6)
+        box = rcut = 0.0
     x, m = c["x"], c["m"]
-    ncrit = 64 if which == "lattice" else 256
+    ncrit = 64 if which in ("lattice", "batched") else 256
     log("case device lists full size %s (n=%d)" % (which, len(m)))
-    L = bhq.bhq_build_lists(x, m, c["theta"], ncrit, box=box, rcut=rcut)
+    if which == "batched":
+        L = bhq.bhq_build_lists_batch(off, x, m, c["theta"], ncrit)
+    else:
+        L = bhq.bhq_build_lists(x, m, c["theta"], ncrit, box=box, rcut=rcut)
     try:
         h = bhq.bhq_lists_export(L, len(m))
         hc = bhq.bhq_lists_cells(L)
@@ -168,7 +178,10 @@ def test_device_lists_full_size(which):
     try:
         xt = torch.from_numpy(x).cuda()
         mt = torch.from_numpy(m).cuda()
-        bhq.bhq_build_lists_device(ctx, xt, mt, c["theta"], ncrit, 8, box, rcut)
+        if which == "batched":
+            bhq.bhq_build_lists_device_batch(ctx, off, xt, mt, c["theta"], ncrit)
+        else:
+            bhq.bhq_build_lists_device(ctx, xt, mt, c["theta"], ncrit, 8, box, rcut)
         del xt, mt
         assert bhq.bhq_get_lists_sizes(ctx) == hs
         d = bhq.bhq_get_lists(ctx, len(m))

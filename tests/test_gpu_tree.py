@@ -224,3 +224,94 @@ def test_rebuild_reuses_context():
         assert_parity(errors(aa, pp, a_ref, p_ref), bhq.FP32_OFS64, "rebuild")
     finally:
         bhq.bhq_destroy(ctx)
+
+
+def _batch(systems):
+    sizes = np.array([len(s[1]) for s in systems])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    X = np.concatenate([s[0] for s in systems])
+    M = np.concatenate([s[1] for s in systems])
+    E2 = np.concatenate([np.full(len(s[1]), s[2] ** 2) for s in systems])
+    return off, X, M, E2
+
+
+def _host_batch(off, X, M, theta, ncrit, nleaf=8):
+    L = bhq.bhq_build_lists_batch(off, X, M, theta, ncrit, nleaf=nleaf)
+    try:
+        out = bhq.bhq_lists_export(L, len(M))
+        out["cells"] = bhq.bhq_lists_cells(L)
+        out["sizes"] = bhq.bhq_lists_sizes(L)
+    finally:
+        bhq.bhq_lists_free(L)
+    return out
+
+
+def test_device_batch_equals_host():
+    """Independent systems in one build, including one- and two-particle
+    systems: the device batch build equals bhq_build_lists_batch entry for
+    entry (cells numbered system by system)."""
+    systems = synth.batched_plummer(20, lo=8.0, hi=12.0)
+    systems.insert(3, (np.array([[0.1, 0.2, 0.3]]), np.array([1.0]), 0.1))
+    systems.insert(7, (np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5]]), np.array([0.5, 0.5]), 0.1))
+    off, X, M, E2 = _batch(systems)
+    log("case device batch: %d systems, %d particles" % (len(systems), len(M)))
+    h = _host_batch(off, X, M, 0.6, 64)
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        xt, mt = _dev(X, M)
+        bhq.bhq_build_lists_device_batch(ctx, off, xt, mt, 0.6, 64)
+        torch.cuda.synchronize()
+        d = bhq.bhq_get_lists(ctx, len(M))
+        d["cells"] = bhq.bhq_get_cells(ctx)
+        d["sizes"] = bhq.bhq_get_lists_sizes(ctx)
+    finally:
+        bhq.bhq_destroy(ctx)
+    _same(h, d, "batch")
+
+
+def test_device_batch_forces_with_softening():
+    """Per-system softening given to the device build: forces equal those
+    of host-built lists with bhq_set_eps2_i (bitwise) and match the oracle
+    system by system."""
+    systems = synth.batched_plummer(12, lo=9.0, hi=11.0)
+    off, X, M, E2 = _batch(systems)
+    ctx_d = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    ctx_h = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        xt, mt = _dev(X, M)
+        e2t = torch.from_numpy(E2).cuda()
+        bhq.bhq_build_lists_device_batch(ctx_d, off, xt, mt, 0.6, 64, eps2=e2t)
+        L = bhq.bhq_build_lists_batch(off, X, M, 0.6, 64)
+        bhq.bhq_set_lists_indexed(ctx_h, L, X, M)
+        idx = bhq.bhq_lists_export(L, len(M))["i_idx"]
+        bhq.bhq_lists_free(L)
+        bhq.bhq_set_eps2_i(ctx_h, E2[idx])
+        res = []
+        for c in (ctx_d, ctx_h):
+            bhq.bhq_compute(c)
+            res.append(bhq.bhq_get_result(c, len(M)))
+        assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+        a = np.zeros_like(res[0][0])
+        p = np.zeros_like(res[0][1])
+        a[idx] = res[0][0]
+        p[idx] = res[0][1]
+        for s, (x, m, eps) in enumerate(systems):
+            T = orc.Tree(x, m, 0.6, 64)
+            ar, pr = orc.eval_lists(orc.QUAD, orc.materialise(T, x, m), x, eps * eps)
+            sl = slice(off[s], off[s + 1])
+            assert_parity(errors(a[sl], p[sl], ar, pr), bhq.FP32_OFS64, "batch system %d" % s)
+        # a zero softening is refused, and the context then holds no lists
+        e2t[5] = 0.0
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_build_lists_device_batch(ctx_d, off, xt, mt, 0.6, 64, eps2=e2t)
+        assert ei.value.code == bhq.E_ARG
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_compute(ctx_d)
+        assert ei.value.code == bhq.E_STATE
+        for bad in ([0, 5, 5, len(M)], [1, len(M)]):
+            with pytest.raises(bhq.BhqError) as ei:
+                bhq.bhq_build_lists_device_batch(ctx_d, np.array(bad), xt, mt, 0.6, 64)
+            assert ei.value.code in (bhq.E_RANGE, bhq.E_ARG)
+    finally:
+        bhq.bhq_destroy(ctx_d)
+        bhq.bhq_destroy(ctx_h)
