@@ -407,6 +407,13 @@ int bhq_kick_drift(bhq_ctx *ctx, int64_t n, double *x, double *v,
                    const double *a, double dt_kick, double dt_drift,
                    void *stream);
 
+/* Periodic images: every coordinate x <- x - box floor(x / box), then
+ * x - box once more if rounding left it equal to box, so that x is in
+ * [0, box) (as the periodic tree builders need).  Asynchronous on
+ * `stream`.  Errors: BHQ_E_ARG (box <= 0), BHQ_E_RANGE, BHQ_E_HIP. */
+int bhq_wrap_periodic(bhq_ctx *ctx, int64_t n, double *x, double box,
+                      void *stream);
+
 /* Energies of n particles: out[0] = K = 1/2 sum m |v|^2 and, when pot is
  * given (the potentials of the softened kernels, which include each
  * particle's self pair -m/eps), out[1] = W = 1/2 sum m (pot + m / eps);

@@ -319,24 +319,44 @@ def relative_errors(a_test, a_ref):
             np.linalg.norm(a_ref, axis=1))
 
 
-def leapfrog(x, v, m, eps, dt, nsteps, theta, ncrit, kind=QUAD, nleaf=8):
+def leapfrog(x, v, m, eps, dt, nsteps, theta, ncrit, kind=QUAD, nleaf=8, box=0.0,
+             rs=0.0, rcut=0.0, pm_mesh=0):
     """Kick-drift-kick leapfrog (second order, time reversible; the
     integrator of the paper's cold-collapse runs), forces from the oracle's
     own tree and lists, rebuilt after every drift:
         v += dt/2 a(x);  x += dt v;  v += dt/2 a(x).
-    Returns (x, v, a, phi) after nsteps, FP64."""
+    Periodic TreePM (box > 0, split kinds): the split tree force (cutoff
+    decided in FP64 from group-relative offsets) plus, when pm_mesh > 0,
+    the particle-mesh long-range force of oracle.pm, with positions mapped
+    to [0, box) after each drift by x - box floor(x / box) (and one more box
+    off if that rounds to box).  Returns (x, v, a, phi) after nsteps, FP64."""
+    from . import pm as _pm
     x = np.array(x, np.float64).reshape(-1, 3)
     v = np.array(v, np.float64).reshape(-1, 3)
     m = np.asarray(m, np.float64)
+    split = kind in (SPLIT_QUAD, SPLIT_MONO)
 
     def force(xx):
-        T = Tree(xx, m, theta, ncrit, nleaf)
+        T = Tree(xx, m, theta, ncrit, nleaf, box=box, rcut=rcut)
+        if split:
+            a, phi = eval_lists(kind, materialise(T, xx, m), xx, 0.0, box=box, rs=rs,
+                                rcut=rcut, mask=MASK_F64_OFS)
+            if pm_mesh:
+                al, pl = _pm.pm(xx, m, box, pm_mesh, rs)
+                a, phi = a + al, phi + pl
+            return a, phi
         return eval_lists(kind, materialise(T, xx, m), xx, eps * eps)
+
+    def wrap(xx):
+        if box <= 0.0:
+            return xx
+        y = xx - box * np.floor(xx / box)
+        return np.where(y >= box, y - box, y)
 
     a, phi = force(x)
     for _ in range(nsteps):
         v = v + (0.5 * dt) * a
-        x = x + dt * v
+        x = wrap(x + dt * v)
         a, phi = force(x)
         v = v + (0.5 * dt) * a
     return x, v, a, phi

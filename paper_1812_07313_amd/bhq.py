@@ -100,6 +100,7 @@ SIGNATURES = {
                                       ctypes.c_double, ctypes.c_double, _P]),
     "bhq_energies": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P,
                                     ctypes.c_double, _D, _P]),
+    "bhq_wrap_periodic": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_double, _P]),
     "bhq_pm_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_double]),
     "bhq_pm_destroy": (ctypes.c_int, [_P]),
@@ -503,6 +504,12 @@ def bhq_kick_drift(ctx, x, v, a, dt_kick, dt_drift, stream=None):
                                 _dptr(v, (n, 3), "v"), _dptr(a, (n, 3), "a"),
                                 float(dt_kick), float(dt_drift),
                                 _stream_handle(stream)), ctx)
+
+
+def bhq_wrap_periodic(ctx, x, box, stream=None):
+    n = int(x.shape[0])
+    _check(lib().bhq_wrap_periodic(ctx, n, _dptr(x, (n, 3), "x"), float(box),
+                                   _stream_handle(stream)), ctx)
 
 
 def bhq_energies(ctx, m, v, pot=None, eps=0.0, stream=None):

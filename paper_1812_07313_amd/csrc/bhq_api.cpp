@@ -1405,6 +1405,18 @@ int bhq_kick_drift(bhq_ctx *ctx, int64_t n, double *x, double *v, const double *
     return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "kick_drift launch");
 }
 
+int bhq_wrap_periodic(bhq_ctx *ctx, int64_t n, double *x, double box, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (n < 0 || !x || !(box > 0.0) || !std::isfinite(box))
+        return ctx->fail(BHQ_E_ARG, "wrap_periodic: bad argument");
+    if (n == 0) return BHQ_OK;
+    TRY(ctx->select());
+    TRY(check_device_range(ctx, x, (size_t)n * 3 * sizeof(double), "x"));
+    hipError_t e = bhq::launch_wrap(n, x, box, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "wrap launch");
+}
+
 int bhq_energies(bhq_ctx *ctx, int64_t n, const double *m, const double *v,
                  const double *pot, double eps, double out[2], void *stream)
 {

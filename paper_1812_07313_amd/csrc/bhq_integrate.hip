@@ -43,6 +43,17 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(int64_t n, double *x, dou
     if (dtd != 0.0) x[i] = x[i] + dtd * vn;
 }
 
+// x <- x - box floor(x / box), then one more box off if rounding left it
+// at box: the periodic image in [0, box).
+__global__ __launch_bounds__(kBlock) void k_wrap(int64_t n3, double *x, double box)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n3) return;
+    double y = x[i] - box * floor(x[i] / box);
+    if (y >= box) y -= box;
+    x[i] = y;
+}
+
 // Per-block partial sums of K = 1/2 sum m |v|^2 and
 // W = 1/2 sum m (phi + m / eps) (the self pair's -m/eps removed), each
 // block over a fixed strided range, combined in a fixed order: the result
@@ -119,6 +130,13 @@ hipError_t launch_kick_drift(int64_t n, double *x, double *v, const double *a, d
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_kick_drift, dim3(blocks(3 * n)), dim3(kBlock), 0, s, n, x, v, a, dtk,
                        dtd);
+    return hipGetLastError();
+}
+
+hipError_t launch_wrap(int64_t n, double *x, double box, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_wrap, dim3(blocks(3 * n)), dim3(kBlock), 0, s, 3 * n, x, box);
     return hipGetLastError();
 }
 

@@ -129,6 +129,7 @@ hipError_t launch_scatter(const int32_t *order, int64_t n, const double *ax,
                           double *a_out, double *pot_out, hipStream_t s);
 hipError_t launch_kick_drift(int64_t n, double *x, double *v, const double *a,
                              double dtk, double dtd, hipStream_t s);
+hipError_t launch_wrap(int64_t n, double *x, double box, hipStream_t s);
 int energy_partials();  // partial-sum slots (pairs) used by launch_energies
 hipError_t launch_energies(int64_t n, const double *m, const double *v,
                            const double *pot, double eps, double *part,

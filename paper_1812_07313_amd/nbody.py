@@ -5,6 +5,11 @@ state resident in device memory (torch tensors, input order).
 
 Kick-drift-kick, as the paper's cold-collapse runs integrate (Sec. 5.2):
     v += dt/2 a;  x += dt v;  a = a(x);  v += dt/2 a.
+
+In a periodic box (box > 0) the force is TreePM: the short-range split
+kernel over the device-built lists (cells beyond rcut skipped) plus, with
+pm_mesh > 0, the particle-mesh long-range force; positions are mapped back
+to [0, box) after each drift.
 """
 from . import bhq
 
@@ -16,7 +21,8 @@ class NBody:
     bhq.FP64."""
 
     def __init__(self, x, v, m, eps, theta, ncrit=64, nleaf=8, kernel=bhq.QUAD,
-                 precision=bhq.FP32_OFS64, stream=None):
+                 precision=bhq.FP32_OFS64, stream=None, box=0.0, rs=0.0, rcut=0.0,
+                 pm_mesh=0):
         import torch
         self.torch = torch
         dev = torch.device("cuda")
@@ -35,12 +41,22 @@ class NBody:
         self.eps = float(eps)
         self.theta, self.ncrit, self.nleaf = float(theta), int(ncrit), int(nleaf)
         self.stream = stream
+        self.box, self.rs, self.rcut = float(box), float(rs), float(rcut)
         self.ctx = bhq.bhq_create(0, kernel, precision)
-        bhq.bhq_set_eps(self.ctx, self.eps)
+        self.pm = None
+        if self.box > 0.0:
+            bhq.bhq_set_split(self.ctx, self.rs, self.rcut, self.box)
+            if pm_mesh:
+                self.pm = bhq.bhq_pm_create(int(pm_mesh), self.box, self.rs)
+        else:
+            bhq.bhq_set_eps(self.ctx, self.eps)
         self.t = 0.0
         self.have_forces = False
 
     def close(self):
+        if self.pm is not None:
+            bhq.bhq_pm_destroy(self.pm)
+            self.pm = None
         if self.ctx is not None:
             bhq.bhq_destroy(self.ctx)
             self.ctx = None
@@ -54,9 +70,12 @@ class NBody:
     def forces(self):
         """Tree, lists and forces at the current positions."""
         bhq.bhq_build_lists_device(self.ctx, self.x, self.m, self.theta, self.ncrit,
-                                   self.nleaf, stream=self.stream)
+                                   self.nleaf, self.box, self.rcut, stream=self.stream)
         bhq.bhq_compute(self.ctx, self.stream)
         bhq.bhq_get_result_device(self.ctx, self.a, self.pot, self.stream)
+        if self.pm is not None:
+            bhq.bhq_pm_compute(self.pm, self.x, self.m, self.a, self.pot, accumulate=True,
+                               stream=self.stream)
         self.have_forces = True
 
     def step(self, dt, nsteps=1):
@@ -66,6 +85,8 @@ class NBody:
         for _ in range(nsteps):
             bhq.bhq_kick_drift(self.ctx, self.x, self.v, self.a, 0.5 * dt, dt,
                                self.stream)
+            if self.box > 0.0:
+                bhq.bhq_wrap_periodic(self.ctx, self.x, self.box, self.stream)
             self.forces()
             bhq.bhq_kick_drift(self.ctx, None, self.v, self.a, 0.5 * dt, 0.0,
                                self.stream)

@@ -142,3 +142,60 @@ def test_cold_collapse_small():
     p = r["profile"]
     core = [rho for rr, rho, c in zip(p["r"], p["rho"], p["count"]) if rr < 0.1 and c >= 50]
     assert core and max(core) > 20 * 3.0 / (4.0 * np.pi)
+
+
+def test_treepm_leapfrog_fp64_matches_oracle():
+    """Periodic TreePM, FP64: 4 steps on a perturbed 16^3 lattice with a
+    velocity field that carries particles across the box faces; positions
+    and velocities agree with the oracle's TreePM leapfrog (split tree on
+    its own lists + its PM + the same wrap) to the summation-order level."""
+    x, m = synth.perturbed_lattice(16, synth.rng(4))
+    v = synth.rng(6).normal(size=x.shape) * 0.2
+    nmesh = 16
+    rs = 1.25 / nmesh
+    rcut = 4.5 * rs
+    theta, ncrit, dt, steps = 0.5, 32, 2.0 ** -6, 4
+    log("case treepm leapfrog fp64 16^3")
+    xr, vr, ar, pr = orc.leapfrog(x, v, m, 0.0, dt, steps, theta, ncrit,
+                                  kind=orc.SPLIT_QUAD, box=1.0, rs=rs, rcut=rcut,
+                                  pm_mesh=nmesh)
+    with NBody(x, v, m, 0.0, theta, ncrit, kernel=bhq.SPLIT_QUAD, precision=bhq.FP64,
+               box=1.0, rs=rs, rcut=rcut, pm_mesh=nmesh) as sim:
+        sim.step(dt, steps)
+        xg, vg = sim.state()
+        ag = sim.a.cpu().numpy()
+        pg = sim.pot.cpu().numpy()
+    assert np.all((xg >= 0) & (xg < 1))
+    d = np.abs(xg - xr)
+    d = np.minimum(d, 1.0 - d)
+    dv = np.abs(vg - vr).max()
+    crossed = np.sum(np.any(np.abs(xr - (x + steps * dt * v)) > 0.5, axis=1))
+    log("  max |dx| %.3g  max |dv| %.3g  (%d particles wrapped)" % (d.max(), dv, crossed))
+    assert crossed > 0
+    assert d.max() < 1e-12 and dv < 1e-11
+    assert orc.relative_errors(ag, ar).max() < 1e-9
+    np.testing.assert_allclose(pg, pr, rtol=1e-9, atol=1e-12)
+
+
+def test_wrap_periodic_bitwise():
+    """bhq_wrap_periodic = x - box floor(x / box), one box off at box, in
+    plain FP64 (bitwise), for points inside, outside and on the faces."""
+    g = np.random.default_rng(8)
+    box = 0.75
+    x = np.concatenate([g.uniform(-3, 4, (997, 3)),
+                        np.array([[0.0, box, -box], [-1e-300, 2 * box, -0.0],
+                                  [box * (1 - 2 ** -53), -box * 2 ** -60, 3 * box]])])
+    ctx = bhq.bhq_create(0, bhq.SPLIT_QUAD, bhq.FP64)
+    try:
+        xt = torch.from_numpy(x.copy()).cuda()
+        bhq.bhq_wrap_periodic(ctx, xt, box)
+        xg = xt.cpu().numpy()
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_wrap_periodic(ctx, xt, 0.0)
+        assert ei.value.code == bhq.E_ARG
+    finally:
+        bhq.bhq_destroy(ctx)
+    y = x - box * np.floor(x / box)
+    y = np.where(y >= box, y - box, y)
+    assert np.array_equal(xg, y)
+    assert np.all((xg >= 0) & (xg < box))

@@ -53,3 +53,20 @@ def test_energy_bounded(orc):
     e0 = energy(xs, vs, phi0)
     x1, v1, _, phi1 = orc.leapfrog(x, v, m, eps, 0.005, 100, 0.5, 16)
     assert abs(energy(x1, v1, phi1) - e0) < 2e-3 * abs(e0)
+
+
+def test_periodic_wrap_and_split_reversible(orc):
+    """Periodic TreePM leapfrog (split tree + PM): reversible, and positions
+    stay in [0, box)."""
+    g = np.random.default_rng(43)
+    x = g.random((300, 3))
+    v = g.normal(size=(300, 3)) * 0.3
+    m = np.full(300, 1.0 / 300)
+    rs = 1.25 / 16
+    kw = dict(box=1.0, rs=rs, rcut=4.5 * rs, pm_mesh=16, kind=orc.SPLIT_QUAD)
+    x1, v1, _, _ = orc.leapfrog(x, v, m, 0.0, 0.01, 10, 0.5, 16, **kw)
+    assert np.all((x1 >= 0) & (x1 < 1))
+    x2, v2, _, _ = orc.leapfrog(x1, -v1, m, 0.0, 0.01, 10, 0.5, 16, **kw)
+    d = np.abs(x2 - x)
+    d = np.minimum(d, 1.0 - d)
+    assert d.max() < 1e-11 and np.abs(-v2 - v).max() < 1e-11
