@@ -396,6 +396,8 @@ def main():
                     choices=["cube", "sphere", "plummer16k", "clustered",
                              "batched", "lattice"])
     ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--ncrit", type=int, default=None,
+                    help="group size bound (default: the workload's)")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--ipt", type=int, default=2,
                     help="i-particles per thread (1 or 2)")
@@ -448,6 +450,8 @@ def main():
         del src, dst
 
     W = workload(args.workload, args.n)
+    if args.ncrit is not None:
+        W["ncrit"] = args.ncrit
     kernel = W["kernel"]
     n = len(W["m"])
     tuned = None

@@ -474,6 +474,8 @@ static double dist2_cube_cube(const double c1[3], double s1, const double c2[3],
 typedef struct {
     double theta2; /* theta^2 */
     double rcut;   /* > 0: prune nodes farther than rcut from the group */
+    double rdrop2; /* > 0: drop accepted nodes whose centre of mass lies at
+                      least sqrt(rdrop2) from the group cube */
     int64_t njp, njc;
     int64_t *jp;   /* NULL on the counting pass */
     int32_t *jc;
@@ -492,7 +494,13 @@ static void append_particles(const orc_tree *t, const onode *nd, walk_state *w)
  * of mass to the nearest point of the group cube and l the node side, the
  * node is accepted as a j-cell iff l^2 < theta^2 d^2 (Sec. 1; theta is
  * passed squared as in List 4).  An accepted one-particle node is entered
- * as a j-particle.  A rejected leaf contributes its particles. */
+ * as a j-particle.  A rejected leaf contributes its particles.
+ * With a cutoff, a node whose cube lies farther than rcut from the group
+ * cube is skipped with its subtree, and an accepted node whose centre of
+ * mass lies at least rcut (1 + 2^-16) from the group cube is dropped: every
+ * particle of the group lies in that cube, so each pair such an entry would
+ * form is beyond the cutoff, where the short-range terms vanish (the margin
+ * keeps the drop exact when r^2 is formed in single precision). */
 static void walk_node(const orc_tree *t, int32_t id, const onode *g,
                       walk_state *w)
 {
@@ -506,6 +514,7 @@ static void walk_node(const orc_tree *t, int32_t id, const onode *g,
             return;
         double d2 = dist2_point_cube(nd->com, g->center, g->side, t->box);
         if (nd->side * nd->side < w->theta2 * d2) {
+            if (w->rdrop2 > 0.0 && d2 >= w->rdrop2) return;
             if (nd->count == 1) {
                 append_particles(t, nd, w);
             } else {
@@ -630,9 +639,11 @@ int orc_build(int64_t n, const double *x, const double *m, double theta,
 
     /* counting pass, then filling pass */
     double theta2 = theta * theta;
+    double rdrop = rcut * (1.0 + 0x1p-16);
+    double rdrop2 = rcut > 0.0 ? rdrop * rdrop : 0.0;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t g = 0; g < ng; ++g) {
-        walk_state w = {theta2, rcut, 0, 0, NULL, NULL};
+        walk_state w = {theta2, rcut, rdrop2, 0, 0, NULL, NULL};
         if (g % walk_stride == 0)
             walk_node(t, root, &t->nodes[t->group_node[g]], &w);
         t->jp_off[g + 1] = w.njp;
@@ -650,7 +661,7 @@ int orc_build(int64_t n, const double *x, const double *m, double theta,
     }
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t g = 0; g < ng; ++g) {
-        walk_state w = {theta2, rcut, 0, 0, &t->jp_idx[t->jp_off[g]],
+        walk_state w = {theta2, rcut, rdrop2, 0, 0, &t->jp_idx[t->jp_off[g]],
                         &t->jc_node[t->jc_off[g]]};
         if (g % walk_stride == 0)
             walk_node(t, root, &t->nodes[t->group_node[g]], &w);

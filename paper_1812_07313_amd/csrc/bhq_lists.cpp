@@ -124,11 +124,23 @@ inline double dist2_cube_cube(const double *c1, double s1, const double *c2,
     return d2;
 }
 
+// With a cutoff rcut, an accepted cell whose centre of mass lies at least
+// rcut (1 + 2^-16) from the group cube is left out of the list: the group's
+// particles lie in that cube, so every pair it would form is beyond the
+// cutoff and the split kernels skip it (the margin covers r^2 formed in
+// FP32).  Returns the square of that distance, 0 without a cutoff.
+inline double drop_dist2(double rcut)
+{
+    const double r = rcut * (1.0 + 0x1p-16);
+    return rcut > 0.0 ? r * r : 0.0;
+}
+
 // Walk for one group; emits j-particles and j-cells through the callbacks.
 template <typename EmitP, typename EmitC>
 void walk_group(const bhq_lists &L, int32_t gid, double theta2, double rcut,
                 std::vector<int32_t> &stack, EmitP emit_p, EmitC emit_c)
 {
+    const double rdrop2 = drop_dist2(rcut);
     const Cell &g = L.cells[(size_t)gid];
     stack.clear();
     stack.push_back(0);
@@ -144,6 +156,7 @@ void walk_group(const bhq_lists &L, int32_t gid, double theta2, double rcut,
             const double d2 =
                 dist2_point_cube(&L.com[3 * (size_t)id], g.center, g.side, L.box);
             if (c.side * c.side < theta2 * d2) {
+                if (rdrop2 > 0.0 && d2 >= rdrop2) continue;
                 if (c.count == 1)
                     emit_p(L.order[(size_t)c.first]);
                 else

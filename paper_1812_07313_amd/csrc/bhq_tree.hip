@@ -24,7 +24,10 @@
 //      octant order), once to count and once to fill.  A cell that does not
 //      contain the group is accepted iff side^2 < theta^2 d^2 (d: its
 //      centre of mass to the group cube; minimum image in a periodic box,
-//      where cells farther than rcut from the group are skipped).
+//      where cells farther than rcut from the group are skipped, and
+//      accepted cells whose centre of mass lies at least rcut (1 + 2^-16)
+//      from the group cube are left out: beyond the cutoff for every
+//      particle of the group).
 // Every floating-point decision (key digits, acceptance) and every moment
 // is computed with the host builder's operations in the same order, with
 // no contraction into fused multiply-adds, so the results agree bit for
@@ -478,6 +481,9 @@ struct WalkArgs {
     const WCell *wc;
     const WLink *wl;
     double theta2, rcut, box;
+    double rdrop2;                     // accepted cells this far (squared) from the
+                                       // group cube are beyond the cutoff for all
+                                       // its particles and left out; 0: no cutoff
     int64_t *jp_cnt, *jc_cnt;          // count pass
     const int64_t *jp_off, *jc_off;    // fill pass
     int32_t *jp_idx, *jc_idx;
@@ -528,7 +534,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
                     if (v > 0.0) d2 += v * v;
                 }
                 if (C.side * C.side < W.theta2 * d2) {
-                    if (L.count == 1) {
+                    if (W.rdrop2 > 0.0 && d2 >= W.rdrop2) {
+                        // beyond the cutoff for every particle of the group
+                    } else if (L.count == 1) {
                         if (FILL) W.jp_idx[pb + np] = L.first;
                         ++np;
                     } else {
@@ -1027,6 +1035,10 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     W.wl = B[T_WL].as<WLink>();
     W.theta2 = P.theta * P.theta;
     W.rcut = P.rcut;
+    {
+        const double r = P.rcut * (1.0 + 0x1p-16);
+        W.rdrop2 = P.rcut > 0.0 ? r * r : 0.0;
+    }
     W.box = P.box;
     W.jp_cnt = B[T_JPCNT].as<int64_t>();
     W.jc_cnt = B[T_JCCNT].as<int64_t>();

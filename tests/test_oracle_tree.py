@@ -183,3 +183,45 @@ def test_split_tree_quad_beats_mono(orc):
     em = orc.relative_errors(orc.eval_lists(orc.SPLIT_MONO, mat, x, 0.0, box=1.0,
                                             rs=rs, rcut=rcut)[0], ad)
     assert np.sqrt(np.mean(eq ** 2)) < 0.5 * np.sqrt(np.mean(em ** 2))
+
+
+def test_split_tree_cutoff_pruning_is_exact(orc):
+    """The cutoff only removes entries whose every pair is beyond rcut:
+    lists built without it (the whole box walked, every accepted cell kept)
+    give the same short-range forces as the pruned lists, bit for bit, and
+    the pruned lists are much shorter.  This pins both the skip of cells
+    whose cube is beyond rcut and the drop of accepted cells whose centre
+    of mass is at least rcut from the group cube."""
+    x, m = synth.perturbed_lattice(16, synth.rng(4))
+    rs = 1.25 / 16
+    rcut = 4.5 * rs
+    kw = dict(box=1.0, rs=rs, rcut=rcut)
+    full = orc.Tree(x, m, 0.5, 32, box=1.0, rcut=0.0)
+    pruned = orc.Tree(x, m, 0.5, 32, box=1.0, rcut=rcut)
+    for kind in (orc.SPLIT_QUAD, orc.SPLIT_MONO):
+        a0, p0 = orc.eval_lists(kind, orc.materialise(full, x, m), x, 0.0, **kw)
+        a1, p1 = orc.eval_lists(kind, orc.materialise(pruned, x, m), x, 0.0, **kw)
+        assert np.array_equal(a0, a1) and np.array_equal(p0, p1)
+    assert pruned.n_jc < 0.5 * full.n_jc
+    # every kept cell has its centre of mass within rcut (1 + 2^-16) of the
+    # group cube, and the full lists hold cells that the cube test alone
+    # would keep but the centre-of-mass test drops
+    def dist(T, com, g):
+        d = np.abs(com - T.center[T.gnode[g]])
+        d = np.minimum(d, 1.0 - d) - 0.5 * T.side[T.gnode[g]]
+        return np.sqrt((np.maximum(d, 0) ** 2).sum(-1))
+
+    def cube_dist(T, nodes, g):
+        d = np.abs(T.center[nodes] - T.center[T.gnode[g]])
+        d = np.minimum(d, 1.0 - d) - 0.5 * (T.side[nodes][:, None] + T.side[T.gnode[g]])
+        return np.sqrt((np.maximum(d, 0) ** 2).sum(-1))
+
+    rdrop = rcut * (1 + 2.0 ** -16)
+    dropped = 0
+    for g in range(0, pruned.ngroups, 5):
+        kept = pruned.jc_node[pruned.jc_off[g]:pruned.jc_off[g + 1]]
+        assert np.all(dist(pruned, pruned.com[kept], g) < rdrop)
+        allc = full.jc_node[full.jc_off[g]:full.jc_off[g + 1]]
+        dropped += np.sum((cube_dist(full, allc, g) <= rcut)
+                          & (dist(full, full.com[allc], g) >= rdrop))
+    assert dropped > 0
