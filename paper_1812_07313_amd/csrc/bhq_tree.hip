@@ -20,8 +20,9 @@
 //      by the parallel-axis shift, deepest level first;
 //   5. groups: the largest cells with at most ncrit particles (or leaves),
 //      in depth-first order, which is the order of their first particle;
-//   6. lists: one thread per group walks the tree depth first (children in
-//      octant order), once to count and once to fill.  A cell that does not
+//   6. lists: eight lanes per group walk the tree depth first (children in
+//      octant order, all children of an opened cell classified at once),
+//      once to count and once to fill.  A cell that does not
 //      contain the group is accepted iff side^2 < theta^2 d^2 (d: its
 //      centre of mass to the group cube; minimum image in a periodic box,
 //      where cells farther than rcut from the group are skipped, and
@@ -49,7 +50,15 @@ namespace {
 
 constexpr int kMaxDepth = 21;
 constexpr int kFrames = kMaxDepth + 1;  // walk stack: root + one per depth
-constexpr int kWalkBlock = 64;
+constexpr int kWalkBlock = 128;             // walk: 16 groups of 8 lanes per block
+constexpr int kOct = 8;                     // lanes per group in the walk
+constexpr int kXcds = 8;                    // XCDs of the chip
+// walk grid: a multiple of kXcds blocks covering ng groups
+inline unsigned walk_blocks(int64_t ng)
+{
+    const int64_t b = (ng + kWalkBlock / kOct - 1) / (kWalkBlock / kOct);
+    return (unsigned)((b + kXcds - 1) / kXcds * kXcds);
+}
 constexpr int kBlock = 256;
 constexpr int kBboxBlocks = 1024;
 
@@ -435,9 +444,15 @@ struct NonNegative {
 
 // ---- 6. walk -----------------------------------------------------------------
 
-__device__ __forceinline__ double min_image(double v, double box)
+// |v - box rint(v / box)|, the distance to the nearest periodic image (|v|
+// without a box).  For |v| < box / 4 the quotient rounds to below 1/2, rint
+// gives 0 and the result is |v|: the division, a long instruction sequence
+// in FP64, is taken only for the far cells.
+__device__ __forceinline__ double abs_min_image(double v, double box)
 {
-    return box > 0.0 ? v - box * ::rint(v / box) : v;
+    const double a = ::fabs(v);
+    if (box > 0.0 && !(a < 0.25 * box)) return ::fabs(v - box * ::rint(v / box));
+    return a;
 }
 
 __device__ __forceinline__ bool contains(uint64_t ckey, int cdepth, uint64_t gkey,
@@ -490,91 +505,186 @@ struct WalkArgs {
     int *flag;                         // set if a stack would overflow
 };
 
+// A child of an opened cell, as the walk classifies it, in two ints:
+//   skipped (beyond the cutoff)         {-1, 0}
+//   j-cell id                           {id, 0}
+//   particles first .. first + count-1  {first, count}, count >= 1 (an
+//                                        accepted one-particle cell or an
+//                                        opened leaf)
+//   opened internal cell                {-2 - child0, nchild}
+__device__ __forceinline__ int2 classify(const WalkArgs &W, int32_t id, const WCell &G,
+                                         int gdepth)
+{
+    const WCell C = W.wc[id];
+    const WLink L = W.wl[id];
+    const int cdepth = L.nd >> 8;
+    const double box = W.box;
+    const double gc[3] = {G.cx, G.cy, G.cz};
+    if (!contains(C.key, cdepth, G.key, gdepth)) {
+        if (W.rcut > 0.0) {
+            const double cc[3] = {C.cx, C.cy, C.cz};
+            double d2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double v = abs_min_image(cc[k] - gc[k], box) -
+                                 0.5 * (C.side + G.side);
+                if (v > 0.0) d2 += v * v;
+            }
+            if (d2 > W.rcut * W.rcut) return make_int2(-1, 0);
+        }
+        const double cm[3] = {C.mx, C.my, C.mz};
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double v = abs_min_image(cm[k] - gc[k], box) - 0.5 * G.side;
+            if (v > 0.0) d2 += v * v;
+        }
+        if (C.side * C.side < W.theta2 * d2) {
+            // beyond the cutoff for every particle of the group
+            if (W.rdrop2 > 0.0 && d2 >= W.rdrop2) return make_int2(-1, 0);
+            return L.count == 1 ? make_int2(L.first, 1) : make_int2(id, 0);
+        }
+    }
+    if (L.child0 < 0) return L.count > 0 ? make_int2(L.first, L.count) : make_int2(-1, 0);
+    return make_int2(-2 - L.child0, L.nd & 0xff);
+}
+
+// Data movement inside an octet (8 aligned lanes) by DPP, on the VALU:
+// an inclusive prefix sum and a sum returned to every lane.  DPP works in
+// rows of 16 lanes, which hold two octets; every read below stays inside
+// the reading lane's octet (row_shr by d is used only by lanes k >= d).
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ int octet_scan(int v, int k)
+{
+    int u = dpp<0x111>(v);  // row_shr:1
+    v += k >= 1 ? u : 0;
+    u = dpp<0x112>(v);      // row_shr:2
+    v += k >= 2 ? u : 0;
+    u = dpp<0x114>(v);      // row_shr:4
+    v += k >= 4 ? u : 0;
+    return v;
+}
+
+__device__ __forceinline__ int octet_sum(int v)
+{
+    v += dpp<0x141>(v);  // row_half_mirror: lane 7 - k of the octet
+    v += dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]: lane k ^ 1
+    v += dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]: lane k ^ 2
+    return v;
+}
+
+// Octet walk: the 8 lanes of an octet walk one group.  Opening an internal
+// cell loads and classifies all of its children at once, one per lane, and
+// pushes them as a frame; a frame is emitted in octant order up to its next
+// opened internal child, whose subtree is walked before the rest of the
+// frame.  The lists therefore come out in the depth-first, octant order of
+// the host builder's walk, while the chain of dependent loads per group is
+// one per opened cell instead of one per visited cell.  The current frame
+// lives in registers; each lane keeps its child's entry of every frame in
+// LDS for the return from a subtree, and the frame's child count and cursor
+// are stored once per octet, written by all 8 lanes with the same value.
+// Control flow is uniform within an octet.  The fill pass writes only
+// inside the group's own segments of the lists.
 template <bool FILL>
 __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
 {
-    __shared__ int32_t s_cur[kFrames][kWalkBlock];
-    __shared__ int32_t s_end[kFrames][kWalkBlock];
-    const int lane = threadIdx.x;
-    const int64_t gi = (int64_t)blockIdx.x * kWalkBlock + lane;
-    if (gi >= W.ng) return;  // no block-wide synchronisation below
+    __shared__ int2 s_ent[kFrames][kWalkBlock];
+    __shared__ int32_t s_hdr[kFrames][kWalkBlock / kOct];  // nchild | cursor << 8
+    const int t = threadIdx.x;
+    const int k = t & (kOct - 1);
+    const int o = t / kOct;
+    // The hardware hands blocks to the XCDs round robin; XCD x walks the
+    // contiguous range of groups [x per, (x + 1) per) of blocks, so that
+    // neighbouring groups, whose walks read the same cells, share an L2.
+    const unsigned per = gridDim.x / kXcds;
+    const unsigned lb = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const int64_t gi = (int64_t)lb * (kWalkBlock / kOct) + o;
+    if (gi >= W.ng) return;  // whole octets leave; no block-wide synchronisation below
     const int32_t gid = W.groups[gi];
     const WCell G = W.wc[gid];
     const int gdepth = W.wl[gid].nd >> 8;
-    const double gc[3] = {G.cx, G.cy, G.cz};
-    const double box = W.box;
     int64_t np = 0, nc = 0;
     const int64_t pb = FILL ? W.jp_off[gi] : 0, cb = FILL ? W.jc_off[gi] : 0;
-    int sp = 0;
-    int32_t id = W.sys_root[W.cell_sys[gid]];  // the group's own root first
-    for (;;) {
-        const WCell C = W.wc[id];
-        const WLink L = W.wl[id];
-        const int cdepth = L.nd >> 8;
-        bool done = false;
-        if (!contains(C.key, cdepth, G.key, gdepth)) {
-            bool skip = false;
-            if (W.rcut > 0.0) {
-                const double cc[3] = {C.cx, C.cy, C.cz};
-                double d2 = 0.0;
-                for (int k = 0; k < 3; ++k) {
-                    const double v = ::fabs(min_image(cc[k] - gc[k], box)) -
-                                     0.5 * (C.side + G.side);
-                    if (v > 0.0) d2 += v * v;
-                }
-                skip = d2 > W.rcut * W.rcut;
-            }
-            if (skip) {
-                done = true;
-            } else {
-                const double cm[3] = {C.mx, C.my, C.mz};
-                double d2 = 0.0;
-                for (int k = 0; k < 3; ++k) {
-                    const double v = ::fabs(min_image(cm[k] - gc[k], box)) - 0.5 * G.side;
-                    if (v > 0.0) d2 += v * v;
-                }
-                if (C.side * C.side < W.theta2 * d2) {
-                    if (W.rdrop2 > 0.0 && d2 >= W.rdrop2) {
-                        // beyond the cutoff for every particle of the group
-                    } else if (L.count == 1) {
-                        if (FILL) W.jp_idx[pb + np] = L.first;
-                        ++np;
-                    } else {
-                        if (FILL) W.jc_idx[cb + nc] = id;
-                        ++nc;
-                    }
-                    done = true;
-                }
-            }
-        }
-        if (!done) {
-            if (L.child0 < 0) {
-                for (int32_t k = L.first; k < L.first + L.count; ++k) {
-                    if (FILL) W.jp_idx[pb + np] = k;
-                    ++np;
-                }
-            } else if (sp < kFrames) {
-                s_cur[sp][lane] = L.child0;
-                s_end[sp][lane] = L.child0 + (L.nd & 0xff);
-                ++sp;
-            } else {
-                *W.flag = 1;
-            }
-        }
-        // next cell: the next unvisited child of the deepest open frame
-        id = -1;
-        while (sp > 0) {
-            const int32_t cur = s_cur[sp - 1][lane];
-            if (cur < s_end[sp - 1][lane]) {
-                s_cur[sp - 1][lane] = cur + 1;
-                id = cur;
-                break;
-            }
-            --sp;
-        }
-        if (id < 0) break;
+    const int64_t pe = FILL ? W.jp_off[gi + 1] : 0, ce = FILL ? W.jc_off[gi + 1] : 0;
+    const int32_t root = W.sys_root[W.cell_sys[gid]];
+    const WLink R = W.wl[root];
+    int sp = 0, nch = 0, cur = 0;
+    int2 e = make_int2(-1, 0);
+    if (R.child0 < 0) {
+        // a one-leaf tree: the root contains the group and is opened
+        if (FILL)
+            for (int32_t j = k; j < R.count && pb + j < pe; j += kOct)
+                W.jp_idx[pb + j] = R.first + j;
+        np = R.count;
+    } else {
+        nch = R.nd & 0xff;
+        e = k < nch ? classify(W, R.child0 + k, G, gdepth) : make_int2(-1, 0);
+        s_ent[0][t] = e;
+        sp = 1;
     }
-    if (!FILL) {
+    // Each round: emit and return from frames (cheap) until the octet must
+    // open a child or is done, then open it (loads and classification).
+    // Octets of a wave reach their next opening at different steps; taking
+    // the openings in a round of their own lets the expensive part run for
+    // all octets of the wave together.
+    while (sp > 0) {
+        int32_t c0 = 0;
+        int n2 = -1;  // >= 0: open the cell whose children are c0 .. c0 + n2 - 1
+        for (;;) {
+            const bool mine = k >= cur && k < nch;
+            // the first opened internal child at or after the cursor
+            const uint64_t bal = __ballot(mine && e.x <= -2);
+            const uint32_t om = (uint32_t)(bal >> (t & 63 & ~(kOct - 1))) & 0xffu;
+            const int kstar = om ? __builtin_ctz(om) : nch;
+            // emit the children before it
+            const bool em = mine && k < kstar && e.x >= 0;
+            const int vp = em ? e.y : 0;            // particles
+            const int vc = em && e.y == 0 ? 1 : 0;  // cells
+            if (FILL) {
+                const int ip = octet_scan(vp, k), ic = octet_scan(vc, k);
+                if (em) {
+                    if (e.y == 0) {
+                        const int64_t q = cb + nc + ic - 1;
+                        if (q < ce) W.jc_idx[q] = e.x;
+                    } else {
+                        const int64_t q = pb + np + ip - e.y;
+                        for (int32_t j = 0; j < e.y && q + j < pe; ++j)
+                            W.jp_idx[q + j] = e.x + j;
+                    }
+                }
+            }
+            np += octet_sum(vp);
+            nc += octet_sum(vc);
+            if (kstar < nch) {
+                // descend into child kstar; this frame resumes after it
+                c0 = -2 - __shfl(e.x, kstar, kOct);
+                const int n = __shfl(e.y, kstar, kOct);
+                cur = kstar + 1;
+                if (sp < kFrames) {
+                    s_hdr[sp - 1][o] = nch | cur << 8;
+                    n2 = n;
+                    break;
+                }
+                if (k == 0) *W.flag = 1;  // the subtree is left out; the build fails
+                continue;
+            }
+            if (--sp == 0) break;
+            e = s_ent[sp - 1][t];
+            const int hdr = s_hdr[sp - 1][o];
+            nch = hdr & 0xff;
+            cur = hdr >> 8;
+        }
+        if (n2 < 0) break;
+        e = k < n2 ? classify(W, c0 + k, G, gdepth) : make_int2(-1, 0);
+        s_ent[sp][t] = e;
+        nch = n2;
+        cur = 0;
+        ++sp;
+    }
+    if (!FILL && k == 0) {
         W.jp_cnt[gi] = np;
         W.jc_cnt[gi] = nc;
     }
@@ -1043,7 +1153,7 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     W.jp_cnt = B[T_JPCNT].as<int64_t>();
     W.jc_cnt = B[T_JCCNT].as<int64_t>();
     W.flag = B[T_FLAG].as<int>();
-    hipLaunchKernelGGL(k_walk<false>, dim3(blocks(ng, kWalkBlock)), dim3(kWalkBlock), 0, s, W);
+    hipLaunchKernelGGL(k_walk<false>, dim3(walk_blocks(ng)), dim3(kWalkBlock), 0, s, W);
     LAUNCHED("walk (count)");
     for (int pass = 0; pass < 2; ++pass) {
         int64_t *cnt = pass ? B[T_JCCNT].as<int64_t>() : B[T_JPCNT].as<int64_t>();
@@ -1084,7 +1194,7 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     W.jc_off = O.jc_off->as<int64_t>();
     W.jp_idx = O.jp_idx->as<int32_t>();
     W.jc_idx = O.jc_idx->as<int32_t>();
-    hipLaunchKernelGGL(k_walk<true>, dim3(blocks(ng, kWalkBlock)), dim3(kWalkBlock), 0, s, W);
+    hipLaunchKernelGGL(k_walk<true>, dim3(walk_blocks(ng)), dim3(kWalkBlock), 0, s, W);
     LAUNCHED("walk (fill)");
 
     // particles and groups in the layout of the force context
