@@ -213,8 +213,11 @@ int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread,
 int bhq_get_tuning(const bhq_ctx *ctx, int out[5]);
 
 /* Order in which groups are handed to blocks.  Group g costs
- * c_g = ni_g (njp_g + 2.65 njc_g + 1) (a cell term costs about 53/20 of a
- * particle term; the 1 stands for loading and storing the i-particles).
+ * c_g = ni_g (100 njp_g + 265 njc_g + 100), in 64-bit integers (a cell term
+ * costs about 53/20 of a particle term; the last term stands for loading
+ * and storing the i-particles).  Group g of the XCD order goes to piece
+ * floor((2 B_g + c_g) / (2 T) xcds), with B_g the exact sum of the costs
+ * before g and T their total, evaluated in FP64.
  *   BHQ_ORDER_COST  every group sorted by c_g, largest first (longest
  *                   processing time first: the last blocks are short).
  *   BHQ_ORDER_XCD   the groups, in the order the lists give them (the host
@@ -242,6 +245,15 @@ int bhq_set_group_order(bhq_ctx *ctx, int mode, int window, int tail);
 
 /* Current group order: out[0..2] = mode, window, tail. */
 int bhq_get_group_order(const bhq_ctx *ctx, int out[3]);
+
+/* The launch slot table in use (the order above applied to the current
+ * groups): order[b] is the group of slot b or -1.  Lists built on the
+ * device get their table computed on the device (for windows and tails up
+ * to 1024), equal entry for entry to bhq_plan_order on their offsets.
+ * order may be NULL to query *nslots; otherwise it holds cap entries
+ * (host memory).  Errors: BHQ_E_ARG (null nslots), BHQ_E_STATE (no
+ * groups), BHQ_E_RANGE (cap too small), BHQ_E_HIP. */
+int bhq_get_order(bhq_ctx *ctx, int32_t *order, int64_t cap, int64_t *nslots);
 
 /* The slot table of a dispatch order, computed on the host for offsets
  * i_off, jp_off, jc_off of ng >= 1 groups (as bhq_set_groups takes them),

@@ -61,6 +61,7 @@ SIGNATURES = {
     "bhq_set_group_order": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int]),
     "bhq_get_group_order": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
+    "bhq_get_order": (ctypes.c_int, [_P, _I32, ctypes.c_int64, _I64]),
     "bhq_plan_order": (ctypes.c_int, [ctypes.c_int64, _I64, _I64, _I64,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, _I32, ctypes.c_int64,
@@ -323,6 +324,16 @@ def bhq_get_group_order(ctx):
     out = (ctypes.c_int * 3)()
     _check(lib().bhq_get_group_order(ctx, out), ctx)
     return dict(mode=out[0], window=out[1], tail=out[2])
+
+
+def bhq_get_order(ctx):
+    """The launch slot table in use (int32, -1 for empty slots)."""
+    n = ctypes.c_int64()
+    _check(lib().bhq_get_order(ctx, None, 0, ctypes.byref(n)), ctx)
+    out = np.zeros(n.value, np.int32)
+    _check(lib().bhq_get_order(ctx, out.ctypes.data_as(_I32), out.shape[0],
+                               ctypes.byref(n)), ctx)
+    return out
 
 
 def bhq_plan_order(i_off, jp_off, jc_off, mode=ORDER_XCD, window=ORDER_WINDOW,

@@ -33,7 +33,7 @@ enum Arr {
     A_AX, A_AY, A_AZ, A_POT,
     A_QUEUE,
     A_POOLP, A_POOLC, A_JPIDX, A_JCIDX,
-    A_TORDER, A_ENERGY,
+    A_TORDER, A_ENERGY, A_OSCRATCH,
     A_COUNT
 };
 
@@ -50,12 +50,10 @@ std::vector<int32_t> plan_order(int64_t ng, const int64_t *i_off,
                                 const int64_t *jp_off, const int64_t *jc_off,
                                 int mode, int window, int tail, int xcds)
 {
-    std::vector<double> cost((size_t)ng);
-    for (int64_t g = 0; g < ng; ++g) {
-        const double nig = (double)(i_off[g + 1] - i_off[g]);
-        cost[(size_t)g] = nig * ((double)(jp_off[g + 1] - jp_off[g]) +
-                                 2.65 * (double)(jc_off[g + 1] - jc_off[g]) + 1.0);
-    }
+    std::vector<uint64_t> cost((size_t)ng);
+    for (int64_t g = 0; g < ng; ++g)
+        cost[(size_t)g] = bhq::order_cost(i_off[g + 1] - i_off[g], jp_off[g + 1] - jp_off[g],
+                                          jc_off[g + 1] - jc_off[g]);
     auto costly_first = [&](int32_t a, int32_t b) {
         return cost[(size_t)a] > cost[(size_t)b];
     };
@@ -67,15 +65,13 @@ std::vector<int32_t> plan_order(int64_t ng, const int64_t *i_off,
     }
     // contiguous pieces of equal cost: group g goes to the piece holding the
     // midpoint of its cost interval (monotone in g)
-    double total = 0.0;
-    for (double c : cost) total += c;
+    uint64_t total = 0;
+    for (uint64_t c : cost) total += c;
     std::vector<std::vector<int32_t>> piece((size_t)xcds);
-    double before = 0.0;
+    uint64_t before = 0;
     for (int64_t g = 0; g < ng; ++g) {
-        const double mid = before + 0.5 * cost[(size_t)g];
+        const int x = bhq::order_piece(before, cost[(size_t)g], total, xcds, g, ng);
         before += cost[(size_t)g];
-        int x = total > 0.0 ? (int)(mid / total * xcds) : (int)(g * xcds / ng);
-        x = std::min(std::max(x, 0), xcds - 1);
         piece[(size_t)x].push_back((int32_t)g);
     }
     // windows of `window` groups from the start of a piece, and its last
@@ -274,15 +270,15 @@ struct bhq_ctx {
         ++args_version;
         return BHQ_OK;
     }
-    int fill_eps_uniform()
+    // Every i-particle's eps^2 = eps2_all, filled on the device (stream s,
+    // synchronised: the forces may be computed on another stream).
+    int fill_eps_uniform(hipStream_t s = nullptr)
     {
         if (ni == 0) return BHQ_OK;
-        try {
-            stage.assign((size_t)ni, eps2_all);
-        } catch (const std::bad_alloc &) {
-            return fail(BHQ_E_NOMEM, "host staging");
-        }
-        return put(A_E2I, 0, stage.data(), ni);
+        if (launched) (void)hipEventSynchronize(ev1);
+        hipError_t e = bhq::launch_fill_f64(arr[A_E2I].as<double>(), ni, eps2_all, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        return e == hipSuccess ? BHQ_OK : hip_fail(e, "eps fill");
     }
 };
 
@@ -776,6 +772,21 @@ int bhq_get_group_order(const bhq_ctx *ctx, int out[3])
     return BHQ_OK;
 }
 
+int bhq_get_order(bhq_ctx *ctx, int32_t *order, int64_t cap, int64_t *nslots)
+{
+    CHECK_CTX(ctx);
+    if (!nslots) return ctx->fail(BHQ_E_ARG, "get_order: null nslots");
+    if (ctx->ng < 0 || ctx->nslots <= 0) return ctx->fail(BHQ_E_STATE, "get_order: no groups");
+    *nslots = ctx->nslots;
+    if (!order) return BHQ_OK;
+    if (cap < ctx->nslots) return ctx->fail(BHQ_E_RANGE, "get_order: cap too small");
+    TRY(ctx->select());
+    if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
+    hipError_t e = hipMemcpy(order, ctx->arr[A_ORDER].p, (size_t)ctx->nslots * 4,
+                             hipMemcpyDeviceToHost);
+    return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "order copy");
+}
+
 int bhq_plan_order(int64_t ng, const int64_t *i_off, const int64_t *jp_off,
                    const int64_t *jc_off, int mode, int window, int tail,
                    int xcds, int32_t *order, int64_t cap, int64_t *nslots)
@@ -1234,12 +1245,30 @@ static int device_build(bhq_ctx *ctx, int64_t nsys, const int64_t *sys_off,
     else if (ctx->eps_mode == 2)
         ctx->eps_mode = 0;
     ctx->nslots = 0;
-    const int orc = ctx->upload_order();
+    int orc;
+    if (ctx->order_mode == BHQ_ORDER_XCD &&
+        bhq::plan_order_device_supported(ctx->order_window, ctx->order_tail)) {
+        // the offsets are on the device already: plan there
+        int64_t ns = 0;
+        orc = bhq::plan_order_device(O.ng, ctx->arr[A_IOFF].as<int64_t>(),
+                                     ctx->arr[A_JPOFF].as<int64_t>(),
+                                     ctx->arr[A_JCOFF].as<int64_t>(), ctx->order_window,
+                                     ctx->order_tail, BHQ_XCDS, ctx->arr[A_ORDER],
+                                     ctx->arr[A_OSCRATCH], &ns, s, &msg);
+        if (orc == BHQ_OK) {
+            ctx->nslots = ns;
+            ++ctx->args_version;
+        } else {
+            ctx->fail(orc, "%s", msg.c_str());
+        }
+    } else {
+        orc = ctx->upload_order();
+    }
     if (orc != BHQ_OK) {
         ctx->ng = -1;
         return orc;
     }
-    if (ctx->eps_mode == 1) TRY(ctx->fill_eps_uniform());
+    if (ctx->eps_mode == 1) TRY(ctx->fill_eps_uniform(s));
     return BHQ_OK;
 }
 

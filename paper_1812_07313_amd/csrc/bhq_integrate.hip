@@ -54,6 +54,12 @@ __global__ __launch_bounds__(kBlock) void k_wrap(int64_t n3, double *x, double b
     x[i] = y;
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_f64(double *v, int64_t n, double val)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) v[i] = val;
+}
+
 // Per-block partial sums of K = 1/2 sum m |v|^2 and
 // W = 1/2 sum m (phi + m / eps) (the self pair's -m/eps removed), each
 // block over a fixed strided range, combined in a fixed order: the result
@@ -137,6 +143,13 @@ hipError_t launch_wrap(int64_t n, double *x, double box, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_wrap, dim3(blocks(3 * n)), dim3(kBlock), 0, s, 3 * n, x, box);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *v, int64_t n, double val, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks(n)), dim3(kBlock), 0, s, v, n, val);
     return hipGetLastError();
 }
 

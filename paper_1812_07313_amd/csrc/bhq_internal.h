@@ -11,6 +11,29 @@
 
 namespace bhq {
 
+// Group dispatch order, shared by the host planner and the device planner
+// (constexpr functions compile for both sides, so the two give the same
+// table).  Cost of a group in units of 1/100 of a particle term:
+// ni (100 njp + 265 njc + 100): a cell term costs about 53/20 of a particle
+// term, and the last term stands for loading and storing the i-particles.
+constexpr uint64_t order_cost(int64_t ni, int64_t njp, int64_t njc)
+{
+    return (uint64_t)ni * (100u * (uint64_t)njp + 265u * (uint64_t)njc + 100u);
+}
+
+// XCD piece of group g: the piece holding the midpoint of the group's cost
+// interval [before, before + cost) within the total, as
+// floor((2 before + cost) / (2 total) * xcds) in FP64 (monotone in g);
+// by group count when every group is empty.
+constexpr int order_piece(uint64_t before, uint64_t cost, uint64_t total, int xcds, int64_t g,
+                          int64_t ng)
+{
+    const int x = total > 0
+                      ? (int)((double)(2 * before + cost) / (double)(2 * total) * (double)xcds)
+                      : (int)(g * xcds / ng);
+    return x < 0 ? 0 : (x > xcds - 1 ? xcds - 1 : x);
+}
+
 // One device array with reusable capacity (host-side handle).
 struct DevArray {
     void *p = nullptr;
@@ -130,6 +153,16 @@ hipError_t launch_scatter(const int32_t *order, int64_t n, const double *ax,
 hipError_t launch_kick_drift(int64_t n, double *x, double *v, const double *a,
                              double dtk, double dtd, hipStream_t s);
 hipError_t launch_wrap(int64_t n, double *x, double box, hipStream_t s);
+hipError_t launch_fill_f64(double *v, int64_t n, double val, hipStream_t s);
+
+// XCD dispatch order of ng groups whose offsets are in device memory,
+// computed on the GPU; equal to the host planner's table.  Supported for
+// window and tail up to 1024.  The table goes to `order`, its slot count
+// to *nslots; returns a BHQ_* code (message in *what).  Synchronises s.
+bool plan_order_device_supported(int window, int tail);
+int plan_order_device(int64_t ng, const int64_t *i_off, const int64_t *jp_off,
+                      const int64_t *jc_off, int window, int tail, int xcds, DevArray &order,
+                      DevArray &scratch, int64_t *nslots, hipStream_t s, std::string *what);
 int energy_partials();  // partial-sum slots (pairs) used by launch_energies
 hipError_t launch_energies(int64_t n, const double *m, const double *v,
                            const double *pot, double eps, double *part,

@@ -315,3 +315,26 @@ def test_device_batch_forces_with_softening():
     finally:
         bhq.bhq_destroy(ctx_d)
         bhq.bhq_destroy(ctx_h)
+
+
+@pytest.mark.parametrize("window,tail", [(256, 1024), (100, 333), (1, 0), (1024, 7),
+                                         (2000, 1024)])
+def test_device_order_equals_host_plan(window, tail):
+    """The slot table planned on the device for device-built lists equals
+    bhq_plan_order on the same offsets, entry for entry (the last case,
+    window 2000, is planned on the host)."""
+    x, m = synth.clustered(1 << 16, synth.rng(9))
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        bhq.bhq_set_group_order(ctx, bhq.ORDER_XCD, window, tail)
+        xt, mt = torch.from_numpy(x).cuda(), torch.from_numpy(m).cuda()
+        bhq.bhq_build_lists_device(ctx, xt, mt, 0.5, 32, 8)
+        dev = bhq.bhq_get_order(ctx)
+        L = bhq.bhq_get_lists(ctx)
+    finally:
+        bhq.bhq_destroy(ctx)
+    host = bhq.bhq_plan_order(L["i_off"], L["jp_off"], L["jc_off"], bhq.ORDER_XCD, window,
+                              tail)
+    log("case device order window %d tail %d: %d groups, %d slots"
+        % (window, tail, len(L["i_off"]) - 1, len(dev)))
+    assert np.array_equal(dev, host)

@@ -15,7 +15,7 @@ def _offsets(rng, ng, empty_frac=0.0):
     njp = rng.integers(0, 3000, ng)
     njc = rng.integers(0, 3000, ng)
     cat = lambda v: np.concatenate([[0], np.cumsum(v)]).astype(np.int64)
-    cost = ni * (njp + 2.65 * njc + 1.0)
+    cost = ni * (100 * njp + 265 * njc + 100)
     return cat(ni), cat(njp), cat(njc), cost
 
 
