@@ -109,18 +109,43 @@ __device__ __forceinline__ void pc_quad(const V4<R> &a, const V4<R> &b,
     az = fma(-rinv5, qz, az);
 }
 
-// Gaussian-split radial functions at r (with rinv = 1/r), u = r * i2rs:
-//   g = erfc(u) + (2u/sqrt(pi)) e^{-u^2}, h = (4u^3/sqrt(pi)) e^{-u^2}.
+// Constants of the Gaussian split, uniform over a launch: with
+// u = r / (2 r_s), i2rs = 1 / (2 r_s).
 template <typename R>
-struct SplitF {
-    R ec, g, h, k;  // k = (8 u^5 / sqrt(pi)) e^{-u^2}
+struct SplitK {
+    R i2rs, i2rs2;  // 1 / (2 r_s) and its square
+    R cs;           // i2rs * 2 / kErfcxDomain: s = r cs - 1 (FP32 fit variable)
+    R cg;           // i2rs * 2 / sqrt(pi): 2u/sqrt(pi) = r cg
+    R ch;           // i2rs * 4 / sqrt(pi): 4u^3/sqrt(pi) = r u^2 ch
 };
 
 template <typename R>
-__device__ __forceinline__ SplitF<R> split_f(R r, R i2rs)
+__device__ __forceinline__ SplitK<R> split_k(double rs)
+{
+    constexpr double k2rsqpi = 1.1283791670955126;  // 2 / sqrt(pi)
+    SplitK<R> K;
+    const double i2rs = 0.5 / rs;
+    K.i2rs = R(i2rs);
+    K.i2rs2 = R(i2rs * i2rs);
+    K.cs = R(i2rs * (2.0 / (double)kErfcxDomain));
+    K.cg = R(i2rs * k2rsqpi);
+    K.ch = R(i2rs * (2.0 * k2rsqpi));
+    return K;
+}
+
+// Gaussian-split radial functions at r (r2 = r^2), u = r / (2 r_s):
+//   ec = erfc(u), g = erfc(u) + (2u/sqrt(pi)) e^{-u^2},
+//   h = (4u^3/sqrt(pi)) e^{-u^2}, k = 2 u^2 h = (8 u^5 / sqrt(pi)) e^{-u^2}.
+template <typename R>
+struct SplitF {
+    R ec, g, h, k;
+};
+
+template <typename R>
+__device__ __forceinline__ SplitF<R> split_f(R r, R r2, const SplitK<R> &K)
 {
     const R rsqpi = R(0.56418958354775628694807945156);
-    const R u = r * i2rs;
+    const R u = r * K.i2rs;
     const R u2 = u * u;
     const R e = exp_r(-u2) * rsqpi;
     SplitF<R> f;
@@ -131,32 +156,46 @@ __device__ __forceinline__ SplitF<R> split_f(R r, R i2rs)
     return f;
 }
 
-// FP32: exp(-u^2) from the hardware base-2 exponential, with the rounding
-// error of the product u^2 * log2(e) fed back to first order, and
-// erfc(u) = exp(-u^2) erfcx(u) with erfcx from a fitted polynomial
+// FP32: E = exp(-u^2) from the hardware base-2 exponential, with the
+// rounding error of the product u^2 * log2(e) fed back to first order, and
+// erfcx(u) = exp(u^2) erfc(u) from a fitted polynomial X in s = r cs - 1
 // (erfcx_fit.h, valid for u <= kErfcxDomain; the host refuses FP32 split
-// kernels whose cutoff reaches beyond it).
-template <>
-__device__ __forceinline__ SplitF<float> split_f<float>(float r, float i2rs)
+// kernels whose cutoff reaches beyond it).  u^2 is formed from r^2, and
+// the factors 1 / (2 r_s) are folded into the constants, so u itself is
+// never needed.  t = X + 2u/sqrt(pi), so that erfc(u) = E X and g = E t.
+struct SplitEX {
+    float E, X, t, u2;
+};
+
+__device__ __forceinline__ SplitEX split_ex(float r, float r2, const SplitK<float> &K)
 {
     constexpr float kLog2e = 1.4426950408889634f;
     constexpr float kLn2 = 0.6931471805599453f;
-    constexpr float k2rsqpi = 1.1283791670955126f;  // 2 / sqrt(pi)
-    const float u = r * i2rs;
-    const float u2 = u * u;
-    const float a = u2 * -kLog2e;
-    const float da = fmaf(u2, -kLog2e, -a);
-    float E = __builtin_amdgcn_exp2f(a);
-    E = fmaf(E, da * kLn2, E);
-    const float s = fmaf(u, 2.0f / kErfcxDomain, -1.0f);
+    SplitEX v;
+    v.u2 = r2 * K.i2rs2;
+    const float a = v.u2 * -kLog2e;
+    const float da = fmaf(v.u2, -kLog2e, -a);
+    const float E = __builtin_amdgcn_exp2f(a);
+    v.E = fmaf(E, da * kLn2, E);
+    const float s = fmaf(r, K.cs, -1.0f);
     float X = kErfcxCoef[kErfcxDegree];
 #pragma unroll
     for (int k = kErfcxDegree - 1; k >= 0; --k) X = fmaf(X, s, kErfcxCoef[k]);
+    v.X = X;
+    v.t = fmaf(r, K.cg, X);
+    return v;
+}
+
+template <>
+__device__ __forceinline__ SplitF<float> split_f<float>(float r, float r2,
+                                                        const SplitK<float> &K)
+{
+    const SplitEX v = split_ex(r, r2, K);
     SplitF<float> f;
-    f.ec = E * X;
-    f.g = E * fmaf(u, k2rsqpi, X);
-    f.h = (2.0f * k2rsqpi) * u * u2 * E;
-    f.k = 2.0f * u2 * f.h;
+    f.ec = v.E * v.X;
+    f.g = v.E * v.t;
+    f.h = (r * v.u2) * K.ch * v.E;
+    f.k = 2.0f * v.u2 * f.h;
     return f;
 }
 
@@ -164,7 +203,7 @@ __device__ __forceinline__ SplitF<float> split_f<float>(float r, float i2rs)
 // r == 0 and r >= rcut.
 template <typename R>
 __device__ __forceinline__ void pp_split(const V4<R> &j, R xi, R yi, R zi,
-                                         R i2rs, R rcut2, R &ax, R &ay, R &az,
+                                         const SplitK<R> &K, R rcut2, R &ax, R &ay, R &az,
                                          R &pt)
 {
     const R dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
@@ -172,13 +211,35 @@ __device__ __forceinline__ void pp_split(const V4<R> &j, R xi, R yi, R zi,
     if (r2 > R(0) && r2 < rcut2) {
         const R rinv = rsq(r2);
         const R r = r2 * rinv;
-        const SplitF<R> f = split_f(r, i2rs);
+        const SplitF<R> f = split_f(r, r2, K);
         const R mr = j.w * rinv;
         const R c = mr * f.g * (rinv * rinv);
         pt = fma(mr, f.ec, pt);
         ax = fma(c, dx, ax);
         ay = fma(c, dy, ay);
         az = fma(c, dz, az);
+    }
+}
+
+// FP32: with w = m E / r, -phi += w X and a += w t / r^2 d.
+template <>
+__device__ __forceinline__ void pp_split<float>(const V4<float> &j, float xi, float yi,
+                                                float zi, const SplitK<float> &K,
+                                                float rcut2, float &ax, float &ay,
+                                                float &az, float &pt)
+{
+    const float dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    if (r2 > 0.0f && r2 < rcut2) {
+        const float rinv = rsq(r2);
+        const float r = r2 * rinv;
+        const SplitEX v = split_ex(r, r2, K);
+        const float w = j.w * rinv * v.E;
+        const float c = w * v.t * (rinv * rinv);
+        pt = fmaf(w, v.X, pt);
+        ax = fmaf(c, dx, ax);
+        ay = fmaf(c, dy, ay);
+        az = fmaf(c, dz, az);
     }
 }
 
@@ -190,7 +251,7 @@ __device__ __forceinline__ void pp_split(const V4<R> &j, R xi, R yi, R zi,
 template <typename R, bool QUAD>
 __device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b,
                                          const V4<R> &c, R xi, R yi, R zi,
-                                         R i2rs, R rcut2, R &ax, R &ay, R &az,
+                                         const SplitK<R> &K, R rcut2, R &ax, R &ay, R &az,
                                          R &pt)
 {
     const R dx = a.x - xi, dy = a.y - yi, dz = a.z - zi;
@@ -199,7 +260,7 @@ __device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b,
         const R rinv = rsq(r2);
         const R r = r2 * rinv;
         const R rinv2 = rinv * rinv;
-        const SplitF<R> f = split_f(r, i2rs);
+        const SplitF<R> f = split_f(r, r2, K);
         const R D1 = f.g * rinv2 * rinv;
         R phi = -a.w * f.ec * rinv;  // M Phi
         R coef = a.w * D1;
@@ -268,7 +329,7 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
     const int64_t c0 = A.jc_off[g], nc = A.jc_off[g + 1] - c0;
     const double box = A.box;
     const double ibox = PERIODIC ? 1.0 / box : 0.0;
-    const R i2rs = kSplit ? R(0.5 / A.rs) : R(0);
+    const SplitK<R> K = split_k<R>(kSplit ? A.rs : 1.0);
     const R rcut2 = kSplit ? R(A.rcut * A.rcut) : R(0);
     const bool indexed = A.jp_idx != nullptr;
     auto rel = [&](double v, double c) -> R {
@@ -347,7 +408,7 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
 #pragma unroll
                     for (int u = 0; u < IB; ++u) {
                         if (kSplit)
-                            pp_split(jv, xi[u], yi[u], zi[u], i2rs, rcut2, bx[u],
+                            pp_split(jv, xi[u], yi[u], zi[u], K, rcut2, bx[u],
                                      by[u], bz[u], bp[u]);
                         else
                             pp_plummer(jv, xi[u], yi[u], zi[u], e2[u], bx[u],
@@ -446,11 +507,11 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                                        by[u], bz[u], bp[u]);
                         else if (KIND == kSplitQuad)
                             pc_split<R, true>(ja, jb, jc, xi[u], yi[u], zi[u],
-                                              i2rs, rcut2, bx[u], by[u], bz[u],
+                                              K, rcut2, bx[u], by[u], bz[u],
                                               bp[u]);
                         else
                             pc_split<R, false>(ja, jb, jc, xi[u], yi[u], zi[u],
-                                               i2rs, rcut2, bx[u], by[u], bz[u],
+                                               K, rcut2, bx[u], by[u], bz[u],
                                                bp[u]);
                     }
                 }

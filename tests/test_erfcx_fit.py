@@ -1,7 +1,7 @@
 """The polynomial the FP32 split kernels use for erfcx(u) = exp(u^2)
 erfc(u): its coefficients, evaluated in FP32 by Horner's rule (fused
 multiply-add emulated exactly), match scipy's erfcx to 3e-7 relative on
-the whole domain 0 <= u <= 3, and the header matches its generator."""
+the whole domain 0 <= u <= 2.5, and the header matches its generator."""
 import os
 import re
 
@@ -23,7 +23,7 @@ def _header():
 
 def test_fit_accuracy_fp32():
     dom, c = _header()
-    assert dom == 3.0 and len(c) == 14
+    assert dom == 2.5 and len(c) == 13
     u = np.linspace(0.0, dom, 200001).astype(np.float32)
     # s = fma(u, fl32(2/dom), -1): the product of two FP32 values and the
     # subtraction are exact in FP64, so one rounding to FP32 emulates it
