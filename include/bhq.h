@@ -246,6 +246,16 @@ int bhq_set_group_order(bhq_ctx *ctx, int mode, int window, int tail);
 /* Current group order: out[0..2] = mode, window, tail. */
 int bhq_get_group_order(const bhq_ctx *ctx, int out[3]);
 
+/* What the last bhq_build_lists_device(_batch) on ctx did: out[0] = 1 if
+ * it walked the tree once (a rebuild: each group's entries went into a slot
+ * sized from the previous device build's longest lists, 1.25 times that
+ * plus 32, and were compacted), 0 if it counted first; out[1], out[2] =
+ * the longest particle and cell list of a group.  A rebuild whose groups
+ * outgrow their slots, or whose slots would take more than 4 times the
+ * previous lists' memory plus 256 MiB, counts first; the lists are the same
+ * either way.  All zero before the first device build. */
+int bhq_get_build_info(const bhq_ctx *ctx, int64_t out[3]);
+
 /* The launch slot table in use (the order above applied to the current
  * groups): order[b] is the group of slot b or -1.  Lists built on the
  * device get their table computed on the device (for windows and tails up

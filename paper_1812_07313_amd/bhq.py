@@ -62,6 +62,7 @@ SIGNATURES = {
                                            ctypes.c_int]),
     "bhq_get_group_order": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
     "bhq_get_order": (ctypes.c_int, [_P, _I32, ctypes.c_int64, _I64]),
+    "bhq_get_build_info": (ctypes.c_int, [_P, _I64]),
     "bhq_plan_order": (ctypes.c_int, [ctypes.c_int64, _I64, _I64, _I64,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, _I32, ctypes.c_int64,
@@ -324,6 +325,14 @@ def bhq_get_group_order(ctx):
     out = (ctypes.c_int * 3)()
     _check(lib().bhq_get_group_order(ctx, out), ctx)
     return dict(mode=out[0], window=out[1], tail=out[2])
+
+
+def bhq_get_build_info(ctx):
+    """(one_walk, longest particle list, longest cell list) of the last
+    device build."""
+    out = np.zeros(3, np.int64)
+    _check(lib().bhq_get_build_info(ctx, _ip(out)), ctx)
+    return bool(out[0]), int(out[1]), int(out[2])
 
 
 def bhq_get_order(ctx):

@@ -150,6 +150,10 @@ struct bhq_ctx {
     int order_mode = BHQ_ORDER_XCD, order_window = BHQ_ORDER_WINDOW,
         order_tail = BHQ_ORDER_TAIL;
     int64_t nslots = 0;
+    // device builds: slot sizes for the next one-walk build, and what the
+    // last build did (one walk or not, longest particle and cell lists)
+    int64_t walk_cap_p = 0, walk_cap_c = 0;
+    int64_t build_info[3] = {0, 0, 0};
     uint64_t args_version = 0;  // bumped when device pointers/params change
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -772,6 +776,14 @@ int bhq_get_group_order(const bhq_ctx *ctx, int out[3])
     return BHQ_OK;
 }
 
+int bhq_get_build_info(const bhq_ctx *ctx, int64_t out[3])
+{
+    CHECK_CTX(ctx);
+    if (!out) return BHQ_E_ARG;
+    for (int k = 0; k < 3; ++k) out[k] = ctx->build_info[k];
+    return BHQ_OK;
+}
+
 int bhq_get_order(bhq_ctx *ctx, int32_t *order, int64_t cap, int64_t *nslots)
 {
     CHECK_CTX(ctx);
@@ -1192,6 +1204,12 @@ static int device_build(bhq_ctx *ctx, int64_t nsys, const int64_t *sys_off,
     if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
 
     bhq::TreeParams P{x, m, eps2, n, nsys, sys_off, theta, ncrit, nleaf, box, rcut};
+    // A rebuild walks once into per-group slots sized from the previous
+    // device build's longest lists; the slots may take up to 4 times the
+    // previous lists' memory plus 256 MiB.
+    P.cap_p = ctx->walk_cap_p;
+    P.cap_c = ctx->walk_cap_c;
+    P.slot_bytes = ctx->ng >= 0 ? 16 * (ctx->njp + ctx->njc) + ((int64_t)256 << 20) : 0;
     bhq::TreeOut O;
     O.i_off = &ctx->arr[A_IOFF];
     O.jp_off = &ctx->arr[A_JPOFF];
@@ -1229,6 +1247,11 @@ static int device_build(bhq_ctx *ctx, int64_t nsys, const int64_t *sys_off,
     ctx->i_off.swap(O.h_i_off);
     ctx->jp_off.swap(O.h_jp_off);
     ctx->jc_off.swap(O.h_jc_off);
+    ctx->walk_cap_p = O.max_p + O.max_p / 4 + 32;
+    ctx->walk_cap_c = O.max_c + O.max_c / 4 + 32;
+    ctx->build_info[0] = O.one_walk ? 1 : 0;
+    ctx->build_info[1] = O.max_p;
+    ctx->build_info[2] = O.max_c;
     ctx->ng = O.ng;
     ctx->ni = n;
     ctx->njp = O.njp;

@@ -180,6 +180,13 @@ struct TreeParams {
     double theta;
     int ncrit, nleaf;
     double box, rcut;
+    // Per-group list capacities for a one-walk build (0: count, then fill).
+    // With capacities the walk writes each group's entries into a slot of
+    // that many entries and counts them; the lists are then compacted, or,
+    // if a group overflowed its slot, filled by a second walk with the exact
+    // offsets.
+    int64_t cap_p = 0, cap_c = 0;
+    int64_t slot_bytes = 0;  // upper bound on the slot memory of that mode
 };
 
 // Builder working memory, kept between builds of one context.
@@ -188,6 +195,7 @@ enum TreeBuf {
     T_CX, T_CY, T_CZ, T_SIDE, T_FIRST, T_COUNT, T_CHILD0, T_NCHILD, T_PARENT,
     T_DEPTH, T_CKEY, T_NCH, T_NOFF, T_GSTART, T_GROUPS, T_NSEL, T_WC, T_WL,
     T_JPCNT, T_JCCNT, T_CSYS, T_SYSOFF, T_SYSOFF32, T_ROOTS, T_SYSROOT, T_LSC, T_PERM,
+    T_JPSLOT, T_JCSLOT,
     T_COUNT_
 };
 
@@ -207,6 +215,9 @@ struct TreeOut {
     // sizes and host copies of the offsets, set on success
     int64_t ng = 0, njp = 0, njc = 0, ncell = 0;
     std::vector<int64_t> h_i_off, h_jp_off, h_jc_off;
+    // longest particle and cell list of a group; whether one walk sufficed
+    int64_t max_p = 0, max_c = 0;
+    bool one_walk = false;
 };
 
 // Returns a BHQ_* code; on failure *err names the step.

@@ -503,6 +503,7 @@ struct WalkArgs {
     const int64_t *jp_off, *jc_off;    // fill pass
     int32_t *jp_idx, *jc_idx;
     int *flag;                         // set if a stack would overflow
+    int64_t cap_p, cap_c;              // slot sizes of the one-walk mode
 };
 
 // A child of an opened cell, as the walk classifies it, in two ints:
@@ -588,7 +589,11 @@ __device__ __forceinline__ int octet_sum(int v)
 // are stored once per octet, written by all 8 lanes with the same value.
 // Control flow is uniform within an octet.  The fill pass writes only
 // inside the group's own segments of the lists.
-template <bool FILL>
+// Walk modes: count the entries; fill the lists at exact offsets; or fill
+// fixed slots of cap_p / cap_c entries per group and count (one walk).
+enum WalkMode { kWalkCount = 0, kWalkFill = 1, kWalkSlots = 2 };
+
+template <int MODE>
 __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
 {
     __shared__ int2 s_ent[kFrames][kWalkBlock];
@@ -607,8 +612,19 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
     const WCell G = W.wc[gid];
     const int gdepth = W.wl[gid].nd >> 8;
     int64_t np = 0, nc = 0;
-    const int64_t pb = FILL ? W.jp_off[gi] : 0, cb = FILL ? W.jc_off[gi] : 0;
-    const int64_t pe = FILL ? W.jp_off[gi + 1] : 0, ce = FILL ? W.jc_off[gi + 1] : 0;
+    constexpr bool FILL = MODE != kWalkCount;
+    int64_t pb = 0, cb = 0, pe = 0, ce = 0;  // where this group's entries go
+    if (MODE == kWalkFill) {
+        pb = W.jp_off[gi];
+        cb = W.jc_off[gi];
+        pe = W.jp_off[gi + 1];
+        ce = W.jc_off[gi + 1];
+    } else if (MODE == kWalkSlots) {
+        pb = gi * W.cap_p;
+        cb = gi * W.cap_c;
+        pe = pb + W.cap_p;
+        ce = cb + W.cap_c;
+    }
     const int32_t root = W.sys_root[W.cell_sys[gid]];
     const WLink R = W.wl[root];
     int sp = 0, nch = 0, cur = 0;
@@ -684,10 +700,24 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
         cur = 0;
         ++sp;
     }
-    if (!FILL && k == 0) {
+    if (MODE != kWalkFill && k == 0) {
         W.jp_cnt[gi] = np;
         W.jc_cnt[gi] = nc;
     }
+}
+
+// Lists of one-walk builds: group g's entries [0, off[g+1] - off[g]) of
+// its slot (cap entries from g cap) to out[off[g] ...]; one wave per group.
+__global__ __launch_bounds__(kBlock) void k_compact(int64_t ng, const int64_t *off,
+                                                    const int32_t *slot, int64_t cap,
+                                                    int32_t *out)
+{
+    const int64_t g = (int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+    if (g >= ng) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t o = off[g], n = off[g + 1] - o;
+    const int32_t *src = slot + g * cap;
+    for (int64_t j = lane; j < n; j += 64) out[o + j] = src[j];
 }
 
 // ---- outputs -----------------------------------------------------------------
@@ -1153,8 +1183,23 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     W.jp_cnt = B[T_JPCNT].as<int64_t>();
     W.jc_cnt = B[T_JCCNT].as<int64_t>();
     W.flag = B[T_FLAG].as<int>();
-    hipLaunchKernelGGL(k_walk<false>, dim3(walk_blocks(ng)), dim3(kWalkBlock), 0, s, W);
-    LAUNCHED("walk (count)");
+    // One walk into fixed slots when the caller gives capacities (from an
+    // earlier build) and the slots fit the memory bound; else count first.
+    const bool slots = P.cap_p > 0 && P.cap_c > 0 &&
+                       (double)ng * (double)(P.cap_p + P.cap_c) * 4.0 <= (double)P.slot_bytes;
+    if (slots) {
+        STEP(B[T_JPSLOT].reserve((size_t)ng * (size_t)P.cap_p * 4), "allocation");
+        STEP(B[T_JCSLOT].reserve((size_t)ng * (size_t)P.cap_c * 4), "allocation");
+        W.cap_p = P.cap_p;
+        W.cap_c = P.cap_c;
+        W.jp_idx = B[T_JPSLOT].as<int32_t>();
+        W.jc_idx = B[T_JCSLOT].as<int32_t>();
+        hipLaunchKernelGGL(k_walk<kWalkSlots>, dim3(walk_blocks(ng)), dim3(kWalkBlock), 0, s, W);
+        LAUNCHED("walk (slots)");
+    } else {
+        hipLaunchKernelGGL(k_walk<kWalkCount>, dim3(walk_blocks(ng)), dim3(kWalkBlock), 0, s, W);
+        LAUNCHED("walk (count)");
+    }
     for (int pass = 0; pass < 2; ++pass) {
         int64_t *cnt = pass ? B[T_JCCNT].as<int64_t>() : B[T_JPCNT].as<int64_t>();
         int64_t *off = pass ? O.jc_off->as<int64_t>() : O.jp_off->as<int64_t>();
@@ -1188,14 +1233,33 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
         return fail();
     }
     const int64_t njp = O.h_jp_off[(size_t)ng], njc = O.h_jc_off[(size_t)ng];
+    int64_t max_p = 0, max_c = 0;
+    for (int64_t g = 0; g < ng; ++g) {
+        max_p = std::max(max_p, O.h_jp_off[(size_t)g + 1] - O.h_jp_off[(size_t)g]);
+        max_c = std::max(max_c, O.h_jc_off[(size_t)g + 1] - O.h_jc_off[(size_t)g]);
+    }
     STEP(O.jp_idx->reserve((size_t)std::max<int64_t>(njp, 1) * 4), "allocation");
     STEP(O.jc_idx->reserve((size_t)std::max<int64_t>(njc, 1) * 4), "allocation");
-    W.jp_off = O.jp_off->as<int64_t>();
-    W.jc_off = O.jc_off->as<int64_t>();
-    W.jp_idx = O.jp_idx->as<int32_t>();
-    W.jc_idx = O.jc_idx->as<int32_t>();
-    hipLaunchKernelGGL(k_walk<true>, dim3(walk_blocks(ng)), dim3(kWalkBlock), 0, s, W);
-    LAUNCHED("walk (fill)");
+    O.one_walk = slots && max_p <= P.cap_p && max_c <= P.cap_c;
+    if (O.one_walk) {
+        // every group's entries are in its slots: compact them
+        const unsigned cb = blocks(ng, kBlock / 64);
+        hipLaunchKernelGGL(k_compact, dim3(cb), dim3(kBlock), 0, s, ng, O.jp_off->as<int64_t>(),
+                           B[T_JPSLOT].as<int32_t>(), P.cap_p, O.jp_idx->as<int32_t>());
+        LAUNCHED("compact");
+        hipLaunchKernelGGL(k_compact, dim3(cb), dim3(kBlock), 0, s, ng, O.jc_off->as<int64_t>(),
+                           B[T_JCSLOT].as<int32_t>(), P.cap_c, O.jc_idx->as<int32_t>());
+        LAUNCHED("compact");
+    } else {
+        W.jp_off = O.jp_off->as<int64_t>();
+        W.jc_off = O.jc_off->as<int64_t>();
+        W.jp_idx = O.jp_idx->as<int32_t>();
+        W.jc_idx = O.jc_idx->as<int32_t>();
+        hipLaunchKernelGGL(k_walk<kWalkFill>, dim3(walk_blocks(ng)), dim3(kWalkBlock), 0, s, W);
+        LAUNCHED("walk (fill)");
+    }
+    O.max_p = max_p;
+    O.max_c = max_c;
 
     // particles and groups in the layout of the force context
     STEP(O.pool_p->reserve((size_t)n * sizeof(PartRec)), "allocation");

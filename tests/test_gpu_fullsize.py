@@ -178,20 +178,24 @@ def test_device_lists_full_size(which):
     try:
         xt = torch.from_numpy(x).cuda()
         mt = torch.from_numpy(m).cuda()
-        if which == "batched":
-            bhq.bhq_build_lists_device_batch(ctx, off, xt, mt, c["theta"], ncrit)
-        else:
-            bhq.bhq_build_lists_device(ctx, xt, mt, c["theta"], ncrit, 8, box, rcut)
+        # the first build counts, then fills; the rebuild walks once into
+        # slots sized from the first (same lists either way)
+        for build in range(2):
+            if which == "batched":
+                bhq.bhq_build_lists_device_batch(ctx, off, xt, mt, c["theta"], ncrit)
+            else:
+                bhq.bhq_build_lists_device(ctx, xt, mt, c["theta"], ncrit, 8, box, rcut)
+            assert bhq.bhq_get_build_info(ctx)[0] == (build == 1)
+            assert bhq.bhq_get_lists_sizes(ctx) == hs
+            d = bhq.bhq_get_lists(ctx, len(m))
+            for k in ("i_idx", "i_off", "jp_off", "jc_off", "jc_cell", "jp_idx"):
+                assert np.array_equal(h[k], d[k]), (build, k)
+                del d[k]
+            dc = bhq.bhq_get_cells(ctx)
+            for k in ("com", "mass", "q", "trace"):
+                assert np.array_equal(hc[k].view(np.int64), dc[k].view(np.int64)), (build, k)
+            log("  build %d: %d groups, %d + %d entries, %d cells: identical" % ((build,) + hs))
         del xt, mt
-        assert bhq.bhq_get_lists_sizes(ctx) == hs
-        d = bhq.bhq_get_lists(ctx, len(m))
-        for k in ("i_idx", "i_off", "jp_off", "jc_off", "jc_cell", "jp_idx"):
-            assert np.array_equal(h[k], d[k]), k
-            del d[k]
-        dc = bhq.bhq_get_cells(ctx)
-        for k in ("com", "mass", "q", "trace"):
-            assert np.array_equal(hc[k].view(np.int64), dc[k].view(np.int64)), k
-        log("  %d groups, %d + %d entries, %d cells: identical" % hs)
     finally:
         bhq.bhq_destroy(ctx)
 

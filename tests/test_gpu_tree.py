@@ -226,6 +226,28 @@ def test_rebuild_reuses_context():
         bhq.bhq_destroy(ctx)
 
 
+def test_rebuild_one_walk_and_overflow():
+    """Rebuilds on one context: the second build of the same particles walks
+    once (slots sized from the first); a build with longer lists (smaller
+    theta) overflows its slots and counts first; the next one walks once
+    again.  Every build equals the host builder's lists."""
+    x, m = synth.plummer(30000, synth.rng(21))
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        expect = []
+        for theta, one_walk in ((0.7, False), (0.7, True), (0.4, False), (0.4, True)):
+            log("case device rebuild theta=%g" % theta)
+            h = _host(x, m, theta, 64)
+            d = _device(ctx, x, m, theta, 64)
+            _same(h, d, "rebuild theta %g" % theta)
+            info = bhq.bhq_get_build_info(ctx)
+            ni = np.diff(h["jp_off"]).max(), np.diff(h["jc_off"]).max()
+            assert info == (one_walk, int(ni[0]), int(ni[1])), (theta, info)
+            expect.append(info)
+    finally:
+        bhq.bhq_destroy(ctx)
+
+
 def _batch(systems):
     sizes = np.array([len(s[1]) for s in systems])
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
