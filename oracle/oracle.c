@@ -471,11 +471,26 @@ static double dist2_cube_cube(const double c1[3], double s1, const double c2[3],
     return d2;
 }
 
+/* Squared distance from point p to the box [lo, hi] (minimum image),
+ * formed about the box centre. */
+static double dist2_point_box(const double *p, const double *lo,
+                              const double *hi, double box)
+{
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double c = 0.5 * (lo[k] + hi[k]), h = 0.5 * (hi[k] - lo[k]);
+        double v = fabs(wrap(p[k] - c, box)) - h;
+        if (v > 0.0) d2 += v * v;
+    }
+    return d2;
+}
+
 typedef struct {
     double theta2; /* theta^2 */
     double rcut;   /* > 0: prune nodes farther than rcut from the group */
     double rdrop2; /* > 0: drop accepted nodes whose centre of mass lies at
-                      least sqrt(rdrop2) from the group cube */
+                      least sqrt(rdrop2) from the group's particles' box */
+    const double *gbox; /* that box: lo[3], hi[3] */
     int64_t njp, njc;
     int64_t *jp;   /* NULL on the counting pass */
     int32_t *jc;
@@ -497,10 +512,11 @@ static void append_particles(const orc_tree *t, const onode *nd, walk_state *w)
  * as a j-particle.  A rejected leaf contributes its particles.
  * With a cutoff, a node whose cube lies farther than rcut from the group
  * cube is skipped with its subtree, and an accepted node whose centre of
- * mass lies at least rcut (1 + 2^-16) from the group cube is dropped: every
- * particle of the group lies in that cube, so each pair such an entry would
- * form is beyond the cutoff, where the short-range terms vanish (the margin
- * keeps the drop exact when r^2 is formed in single precision). */
+ * mass lies at least rcut (1 + 2^-16) from the bounding box of the group's
+ * particles is dropped: every particle of the group lies in that box, so
+ * each pair such an entry would form is beyond the cutoff, where the
+ * short-range terms vanish (the margin keeps the drop exact when r^2 is
+ * formed in single precision). */
 static void walk_node(const orc_tree *t, int32_t id, const onode *g,
                       walk_state *w)
 {
@@ -514,7 +530,9 @@ static void walk_node(const orc_tree *t, int32_t id, const onode *g,
             return;
         double d2 = dist2_point_cube(nd->com, g->center, g->side, t->box);
         if (nd->side * nd->side < w->theta2 * d2) {
-            if (w->rdrop2 > 0.0 && d2 >= w->rdrop2) return;
+            if (w->rdrop2 > 0.0 &&
+                dist2_point_box(nd->com, w->gbox, w->gbox + 3, t->box) >= w->rdrop2)
+                return;
             if (nd->count == 1) {
                 append_particles(t, nd, w);
             } else {
@@ -641,9 +659,30 @@ int orc_build(int64_t n, const double *x, const double *m, double theta,
     double theta2 = theta * theta;
     double rdrop = rcut * (1.0 + 0x1p-16);
     double rdrop2 = rcut > 0.0 ? rdrop * rdrop : 0.0;
+    /* bounding box of each group's particles */
+    double *gbox = (double *)malloc((size_t)ng * 6 * sizeof(double));
+    if (!gbox) {
+        orc_free(t);
+        return ORC_E_NOMEM;
+    }
+    for (int64_t g = 0; g < ng; ++g) {
+        const onode *gn = &t->nodes[t->group_node[g]];
+        double *b = &gbox[6 * g];
+        for (int k = 0; k < 3; ++k) {
+            b[k] = INFINITY;
+            b[3 + k] = -INFINITY;
+        }
+        for (int64_t q = gn->first; q < gn->first + gn->count; ++q) {
+            const double *xp = &x[3 * t->perm[q]];
+            for (int k = 0; k < 3; ++k) {
+                if (xp[k] < b[k]) b[k] = xp[k];
+                if (xp[k] > b[3 + k]) b[3 + k] = xp[k];
+            }
+        }
+    }
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t g = 0; g < ng; ++g) {
-        walk_state w = {theta2, rcut, rdrop2, 0, 0, NULL, NULL};
+        walk_state w = {theta2, rcut, rdrop2, &gbox[6 * g], 0, 0, NULL, NULL};
         if (g % walk_stride == 0)
             walk_node(t, root, &t->nodes[t->group_node[g]], &w);
         t->jp_off[g + 1] = w.njp;
@@ -656,16 +695,18 @@ int orc_build(int64_t n, const double *x, const double *m, double theta,
     t->jp_idx = (int64_t *)malloc((size_t)(t->jp_off[ng] + 1) * sizeof(int64_t));
     t->jc_node = (int32_t *)malloc((size_t)(t->jc_off[ng] + 1) * sizeof(int32_t));
     if (!t->jp_idx || !t->jc_node) {
+        free(gbox);
         orc_free(t);
         return ORC_E_NOMEM;
     }
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t g = 0; g < ng; ++g) {
-        walk_state w = {theta2, rcut, rdrop2, 0, 0, &t->jp_idx[t->jp_off[g]],
-                        &t->jc_node[t->jc_off[g]]};
+        walk_state w = {theta2, rcut, rdrop2, &gbox[6 * g], 0, 0,
+                        &t->jp_idx[t->jp_off[g]], &t->jc_node[t->jc_off[g]]};
         if (g % walk_stride == 0)
             walk_node(t, root, &t->nodes[t->group_node[g]], &w);
     }
+    free(gbox);
     *out = t;
     return ORC_OK;
 }

@@ -195,7 +195,7 @@ enum TreeBuf {
     T_CX, T_CY, T_CZ, T_SIDE, T_FIRST, T_COUNT, T_CHILD0, T_NCHILD, T_PARENT,
     T_DEPTH, T_CKEY, T_NCH, T_NOFF, T_GSTART, T_GROUPS, T_NSEL, T_WC, T_WL,
     T_JPCNT, T_JCCNT, T_CSYS, T_SYSOFF, T_SYSOFF32, T_ROOTS, T_SYSROOT, T_LSC, T_PERM,
-    T_JPSLOT, T_JCSLOT,
+    T_JPSLOT, T_JCSLOT, T_GBOX,
     T_COUNT_
 };
 

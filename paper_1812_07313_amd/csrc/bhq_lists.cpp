@@ -21,6 +21,7 @@
 //      mass to the group cube (a one-particle cell becomes a j-particle);
 //      a rejected leaf contributes its particles.
 #include <algorithm>
+#include <limits>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -124,11 +125,25 @@ inline double dist2_cube_cube(const double *c1, double s1, const double *c2,
     return d2;
 }
 
+// Squared distance from point p to the box [lo, hi] (minimum image),
+// formed about the box centre.
+inline double dist2_point_box(const double *p, const double *lo, const double *hi,
+                              double box)
+{
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double c = 0.5 * (lo[k] + hi[k]), h = 0.5 * (hi[k] - lo[k]);
+        const double v = std::fabs(min_image(p[k] - c, box)) - h;
+        if (v > 0.0) d2 += v * v;
+    }
+    return d2;
+}
+
 // With a cutoff rcut, an accepted cell whose centre of mass lies at least
-// rcut (1 + 2^-16) from the group cube is left out of the list: the group's
-// particles lie in that cube, so every pair it would form is beyond the
-// cutoff and the split kernels skip it (the margin covers r^2 formed in
-// FP32).  Returns the square of that distance, 0 without a cutoff.
+// rcut (1 + 2^-16) from the bounding box of the group's particles is left
+// out of the list: every pair it would form is beyond the cutoff and the
+// split kernels skip it (the margin covers r^2 formed in FP32).  Returns
+// the square of that distance, 0 without a cutoff.
 inline double drop_dist2(double rcut)
 {
     const double r = rcut * (1.0 + 0x1p-16);
@@ -136,9 +151,10 @@ inline double drop_dist2(double rcut)
 }
 
 // Walk for one group; emits j-particles and j-cells through the callbacks.
+// gbox: lo[3], hi[3] of the group's particles (read only with a cutoff).
 template <typename EmitP, typename EmitC>
-void walk_group(const bhq_lists &L, int32_t gid, double theta2, double rcut,
-                std::vector<int32_t> &stack, EmitP emit_p, EmitC emit_c)
+void walk_group(const bhq_lists &L, int32_t gid, const double *gbox, double theta2,
+                double rcut, std::vector<int32_t> &stack, EmitP emit_p, EmitC emit_c)
 {
     const double rdrop2 = drop_dist2(rcut);
     const Cell &g = L.cells[(size_t)gid];
@@ -156,7 +172,9 @@ void walk_group(const bhq_lists &L, int32_t gid, double theta2, double rcut,
             const double d2 =
                 dist2_point_cube(&L.com[3 * (size_t)id], g.center, g.side, L.box);
             if (c.side * c.side < theta2 * d2) {
-                if (rdrop2 > 0.0 && d2 >= rdrop2) continue;
+                if (rdrop2 > 0.0 &&
+                    dist2_point_box(&L.com[3 * (size_t)id], gbox, gbox + 3, L.box) >= rdrop2)
+                    continue;
                 if (c.count == 1)
                     emit_p(L.order[(size_t)c.first]);
                 else
@@ -387,6 +405,28 @@ int build_one(int64_t n, const double (*x)[3], const double *m, double theta,
         }
         const int64_t ng = (int64_t)L->groups.size();
 
+        // bounding box of each group's particles (for the cutoff drop)
+        std::vector<double> gbox;
+        if (rcut > 0.0) {
+            gbox.resize((size_t)ng * 6);
+            for (int64_t gi = 0; gi < ng; ++gi) {
+                const Cell &g = L->cells[(size_t)L->groups[(size_t)gi]];
+                double *b = &gbox[(size_t)gi * 6];
+                for (int k = 0; k < 3; ++k) {
+                    b[k] = std::numeric_limits<double>::infinity();
+                    b[3 + k] = -std::numeric_limits<double>::infinity();
+                }
+                for (int64_t q = g.first; q < g.first + g.count; ++q) {
+                    const double *xp = x[L->order[(size_t)q]];
+                    for (int k = 0; k < 3; ++k) {
+                        b[k] = std::min(b[k], xp[k]);
+                        b[3 + k] = std::max(b[3 + k], xp[k]);
+                    }
+                }
+            }
+        }
+        auto gb = [&](int64_t gi) { return rcut > 0.0 ? &gbox[(size_t)gi * 6] : nullptr; };
+
         // 5. walk: count, prefix sums, fill
         const double theta2 = theta * theta;
         L->jp_off.assign((size_t)ng + 1, 0);
@@ -394,7 +434,7 @@ int build_one(int64_t n, const double (*x)[3], const double *m, double theta,
         parallel_for(ng, nthreads, [&](int64_t gi) {
             thread_local std::vector<int32_t> stack;
             int64_t np = 0, nc = 0;
-            walk_group(*L, L->groups[(size_t)gi], theta2, rcut, stack,
+            walk_group(*L, L->groups[(size_t)gi], gb(gi), theta2, rcut, stack,
                        [&](int64_t) { ++np; }, [&](int32_t) { ++nc; });
             L->jp_off[(size_t)gi + 1] = np;
             L->jc_off[(size_t)gi + 1] = nc;
@@ -409,7 +449,7 @@ int build_one(int64_t n, const double (*x)[3], const double *m, double theta,
             thread_local std::vector<int32_t> stack;
             int64_t *pp = L->jp_idx.data() + L->jp_off[(size_t)gi];
             int32_t *pc = L->jc_cell.data() + L->jc_off[(size_t)gi];
-            walk_group(*L, L->groups[(size_t)gi], theta2, rcut, stack,
+            walk_group(*L, L->groups[(size_t)gi], gb(gi), theta2, rcut, stack,
                        [&](int64_t p) { *pp++ = p; },
                        [&](int32_t c) { *pc++ = c; });
         });

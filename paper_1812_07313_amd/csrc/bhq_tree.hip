@@ -27,8 +27,8 @@
 //      centre of mass to the group cube; minimum image in a periodic box,
 //      where cells farther than rcut from the group are skipped, and
 //      accepted cells whose centre of mass lies at least rcut (1 + 2^-16)
-//      from the group cube are left out: beyond the cutoff for every
-//      particle of the group).
+//      from the bounding box of the group's particles are left out: beyond
+//      the cutoff for every particle of the group).
 // Every floating-point decision (key digits, acceptance) and every moment
 // is computed with the host builder's operations in the same order, with
 // no contraction into fused multiply-adds, so the results agree bit for
@@ -497,13 +497,16 @@ struct WalkArgs {
     const WLink *wl;
     double theta2, rcut, box;
     double rdrop2;                     // accepted cells this far (squared) from the
-                                       // group cube are beyond the cutoff for all
-                                       // its particles and left out; 0: no cutoff
+                                       // box of the group's particles are beyond the
+                                       // cutoff for all of them and left out; 0: no
+                                       // cutoff
     int64_t *jp_cnt, *jc_cnt;          // count pass
     const int64_t *jp_off, *jc_off;    // fill pass
     int32_t *jp_idx, *jc_idx;
     int *flag;                         // set if a stack would overflow
     int64_t cap_p, cap_c;              // slot sizes of the one-walk mode
+    const double *gbox;                // [6 ng] lo, hi of each group's particles
+                                       // (with a cutoff)
 };
 
 // A child of an opened cell, as the walk classifies it, in two ints:
@@ -514,7 +517,7 @@ struct WalkArgs {
 //                                        opened leaf)
 //   opened internal cell                {-2 - child0, nchild}
 __device__ __forceinline__ int2 classify(const WalkArgs &W, int32_t id, const WCell &G,
-                                         int gdepth)
+                                         int gdepth, const double *gb)
 {
     const WCell C = W.wc[id];
     const WLink L = W.wl[id];
@@ -540,7 +543,16 @@ __device__ __forceinline__ int2 classify(const WalkArgs &W, int32_t id, const WC
         }
         if (C.side * C.side < W.theta2 * d2) {
             // beyond the cutoff for every particle of the group
-            if (W.rdrop2 > 0.0 && d2 >= W.rdrop2) return make_int2(-1, 0);
+            if (W.rdrop2 > 0.0) {
+                // distance to the box [gb[0..2], gb[3..5]] of the group's particles
+                double b2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const double c = 0.5 * (gb[k] + gb[3 + k]), h = 0.5 * (gb[3 + k] - gb[k]);
+                    const double v = abs_min_image(cm[k] - c, box) - h;
+                    if (v > 0.0) b2 += v * v;
+                }
+                if (b2 >= W.rdrop2) return make_int2(-1, 0);
+            }
             return L.count == 1 ? make_int2(L.first, 1) : make_int2(id, 0);
         }
     }
@@ -611,6 +623,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
     const int32_t gid = W.groups[gi];
     const WCell G = W.wc[gid];
     const int gdepth = W.wl[gid].nd >> 8;
+    double gb[6] = {0, 0, 0, 0, 0, 0};
+    if (W.rdrop2 > 0.0)
+        for (int q = 0; q < 6; ++q) gb[q] = W.gbox[6 * gi + q];
     int64_t np = 0, nc = 0;
     constexpr bool FILL = MODE != kWalkCount;
     int64_t pb = 0, cb = 0, pe = 0, ce = 0;  // where this group's entries go
@@ -637,7 +652,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
         np = R.count;
     } else {
         nch = R.nd & 0xff;
-        e = k < nch ? classify(W, R.child0 + k, G, gdepth) : make_int2(-1, 0);
+        e = k < nch ? classify(W, R.child0 + k, G, gdepth, gb) : make_int2(-1, 0);
         s_ent[0][t] = e;
         sp = 1;
     }
@@ -694,7 +709,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
             cur = hdr >> 8;
         }
         if (n2 < 0) break;
-        e = k < n2 ? classify(W, c0 + k, G, gdepth) : make_int2(-1, 0);
+        e = k < n2 ? classify(W, c0 + k, G, gdepth, gb) : make_int2(-1, 0);
         s_ent[sp][t] = e;
         nch = n2;
         cur = 0;
@@ -704,6 +719,30 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
         W.jp_cnt[gi] = np;
         W.jc_cnt[gi] = nc;
     }
+}
+
+// Bounding box (lo[3], hi[3]) of each group's particles, for the cutoff
+// drop; one thread per group over its particles in tree order.
+__global__ __launch_bounds__(kBlock) void k_group_box(Cells C, const int32_t *groups,
+                                                      int64_t ng, const int32_t *idx,
+                                                      const double *x, double *gbox)
+{
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= ng) return;
+    const int32_t c = groups[g];
+    double b[6];
+    for (int k = 0; k < 3; ++k) {
+        b[k] = __builtin_inf();
+        b[3 + k] = -__builtin_inf();
+    }
+    for (int32_t q = C.first[c]; q < C.first[c] + C.count[c]; ++q) {
+        const double *xp = x + 3 * (int64_t)idx[q];
+        for (int k = 0; k < 3; ++k) {
+            b[k] = xp[k] < b[k] ? xp[k] : b[k];
+            b[3 + k] = xp[k] > b[3 + k] ? xp[k] : b[3 + k];
+        }
+    }
+    for (int k = 0; k < 6; ++k) gbox[6 * g + k] = b[k];
 }
 
 // Lists of one-walk builds: group g's entries [0, off[g+1] - off[g]) of
@@ -1183,6 +1222,14 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     W.jp_cnt = B[T_JPCNT].as<int64_t>();
     W.jc_cnt = B[T_JCCNT].as<int64_t>();
     W.flag = B[T_FLAG].as<int>();
+    W.gbox = nullptr;
+    if (W.rdrop2 > 0.0) {
+        STEP(B[T_GBOX].reserve((size_t)ng * 6 * 8), "allocation");
+        hipLaunchKernelGGL(k_group_box, dim3(blocks(ng, kBlock)), dim3(kBlock), 0, s, cells(),
+                           groups, ng, idx, P.x, B[T_GBOX].as<double>());
+        LAUNCHED("group boxes");
+        W.gbox = B[T_GBOX].as<double>();
+    }
     // One walk into fixed slots when the caller gives capacities (from an
     // earlier build) and the slots fit the memory bound; else count first.
     const bool slots = P.cap_p > 0 && P.cap_c > 0 &&
