@@ -187,9 +187,29 @@ def pm_long_range(torch, W, short_ms, repeats):
     finally:
         bhq.bhq_pm_destroy(pm)
     pm_ms = float(np.median(ms[1:]))
+    del xt, mt, a, p
     return {"nmesh": nmesh, "pm_ms": round(pm_ms, 3),
             "short_range_kernel_ms": round(short_ms, 3),
-            "treepm_force_ms": round(pm_ms + short_ms, 3)}
+            "treepm_force_ms": round(pm_ms + short_ms, 3),
+            "treepm_step_ms": round(treepm_step(torch, W, nmesh), 3)}
+
+
+def treepm_step(torch, W, nmesh, steps=3):
+    """Wall time of one periodic TreePM leapfrog step on the workload (kick,
+    drift, wrap, device list rebuild, split kernel, PM, kick), particles and
+    velocities in device memory, after one step that includes the first
+    (counting) list build."""
+    from paper_1812_07313_amd.nbody import NBody
+    v = np.zeros_like(W["x"])
+    with NBody(W["x"], v, W["m"], 0.0, W["theta"], W["ncrit"], min(8, W["ncrit"]),
+               kernel=W["kernel"], box=W["box"], rs=W["rs"], rcut=W["rcut"],
+               pm_mesh=nmesh) as sim:
+        sim.step(1e-3, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(1e-3, steps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
 
 
 def upload(ctx, W, L, indexed=False):
