@@ -248,8 +248,10 @@ int bhq_get_group_order(const bhq_ctx *ctx, int out[3]);
 
 /* What the last bhq_build_lists_device(_batch) on ctx did: out[0] = 1 if
  * it walked the tree once (a rebuild: each group's entries went into a slot
- * sized from the previous device build's longest lists, 1.25 times that
- * plus 32, and were compacted), 0 if it counted first; out[1], out[2] =
+ * of 1.25 times an earlier device build's longest list plus 32 entries, and
+ * were compacted; the slot size is kept from build to build while that
+ * formula gives between 3/4 of it and all of it), 0 if it counted first;
+ * out[1], out[2] =
  * the longest particle and cell list of a group.  A rebuild whose groups
  * outgrow their slots, or whose slots would take more than 4 times the
  * previous lists' memory plus 256 MiB, counts first; the lists are the same

@@ -1247,8 +1247,15 @@ static int device_build(bhq_ctx *ctx, int64_t nsys, const int64_t *sys_off,
     ctx->i_off.swap(O.h_i_off);
     ctx->jp_off.swap(O.h_jp_off);
     ctx->jc_off.swap(O.h_jc_off);
-    ctx->walk_cap_p = O.max_p + O.max_p / 4 + 32;
-    ctx->walk_cap_c = O.max_c + O.max_c / 4 + 32;
+    // slot sizes for the next rebuild: 1.25 times the longest lists plus 32;
+    // kept while that stays within [3/4, 1] of the current size, so that the
+    // slot memory keeps its size from step to step
+    auto next_cap = [](int64_t cur, int64_t longest) {
+        const int64_t want = longest + longest / 4 + 32;
+        return (want <= cur && 4 * want >= 3 * cur) ? cur : want;
+    };
+    ctx->walk_cap_p = next_cap(ctx->walk_cap_p, O.max_p);
+    ctx->walk_cap_c = next_cap(ctx->walk_cap_c, O.max_c);
     ctx->build_info[0] = O.one_walk ? 1 : 0;
     ctx->build_info[1] = O.max_p;
     ctx->build_info[2] = O.max_c;

@@ -38,7 +38,10 @@ constexpr int order_piece(uint64_t before, uint64_t cost, uint64_t total, int xc
 struct DevArray {
     void *p = nullptr;
     size_t cap = 0;
-    // At least `bytes` of capacity; old contents are not kept.
+    // At least `bytes` of capacity; old contents are not kept.  Growing an
+    // existing block leaves 25 % headroom, so that sizes that drift upwards
+    // from call to call (lists rebuilt every time step) do not free and
+    // allocate again each time.
     hipError_t reserve(size_t bytes)
     {
         if (bytes <= cap && p) return hipSuccess;
@@ -46,6 +49,7 @@ struct DevArray {
             (void)hipFree(p);
             p = nullptr;
             cap = 0;
+            bytes += bytes / 4;
         }
         if (bytes == 0) bytes = 256;
         hipError_t e = hipMalloc(&p, bytes);
