@@ -5,6 +5,8 @@ bit for bit: particle order, group offsets, every list entry in order, and
 the cell moments (the device computes them with the host's operations in
 the host's order).  Forces from device-built lists then equal, bit for bit,
 forces from the host-built lists, and match the FP64 oracle."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -360,3 +362,35 @@ def test_device_order_equals_host_plan(window, tail):
     log("case device order window %d tail %d: %d groups, %d slots"
         % (window, tail, len(L["i_off"]) - 1, len(dev)))
     assert np.array_equal(dev, host)
+
+
+def test_order_and_build_info_queries():
+    """bhq_get_order before any groups is a state error; bhq_get_build_info
+    is all zero before the first device build; a host-built upload keeps
+    the last device build's record."""
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_get_order(ctx)
+        assert ei.value.code == bhq.E_STATE
+        assert bhq.bhq_get_build_info(ctx) == (False, 0, 0)
+        assert bhq.lib().bhq_get_build_info(ctx, None) == bhq.E_ARG
+        x, m = synth.uniform_cube(5000, synth.rng(3))
+        d = _device(ctx, x, m, 0.6, 64)
+        info = bhq.bhq_get_build_info(ctx)
+        assert info == (False, int(np.diff(d["jp_off"]).max()), int(np.diff(d["jc_off"]).max()))
+        o = bhq.bhq_get_order(ctx)
+        assert sorted(o[o >= 0].tolist()) == list(range(len(d["i_off"]) - 1))
+        n = ctypes.c_int64()
+        small = np.zeros(1, np.int32)
+        rc = bhq.lib().bhq_get_order(ctx, small.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     1, ctypes.byref(n))
+        assert rc == bhq.E_RANGE and n.value == len(o)
+        L = bhq.bhq_build_lists(x, m, 0.6, 64)
+        try:
+            bhq.bhq_set_lists_indexed(ctx, L, x, m)
+        finally:
+            bhq.bhq_lists_free(L)
+        assert bhq.bhq_get_build_info(ctx) == info
+    finally:
+        bhq.bhq_destroy(ctx)
