@@ -505,6 +505,7 @@ struct WalkArgs {
     int32_t *jp_idx, *jc_idx;
     int *flag;                         // set if a stack would overflow
     int64_t cap_p, cap_c;              // slot sizes of the one-walk mode
+    int frames;                        // frame stack depth: levels of the tree
     const double *gbox;                // [6 ng] lo, hi of each group's particles
                                        // (with a cutoff)
 };
@@ -608,8 +609,13 @@ enum WalkMode { kWalkCount = 0, kWalkFill = 1, kWalkSlots = 2 };
 template <int MODE>
 __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
 {
-    __shared__ int2 s_ent[kFrames][kWalkBlock];
-    __shared__ int32_t s_hdr[kFrames][kWalkBlock / kOct];  // nchild | cursor << 8
+    // frame stack, W.frames deep (the tree's depth): a child entry per lane,
+    // then nchild | cursor << 8 per octet (dynamic LDS: a shallow tree
+    // leaves room for more resident waves)
+    extern __shared__ int2 s_walk[];
+    int2 (*s_ent)[kWalkBlock] = reinterpret_cast<int2 (*)[kWalkBlock]>(s_walk);
+    int32_t (*s_hdr)[kWalkBlock / kOct] = reinterpret_cast<int32_t (*)[kWalkBlock / kOct]>(
+        s_walk + (size_t)W.frames * kWalkBlock);
     const int t = threadIdx.x;
     const int k = t & (kOct - 1);
     const int o = t / kOct;
@@ -694,7 +700,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
                 c0 = -2 - __shfl(e.x, kstar, kOct);
                 const int n = __shfl(e.y, kstar, kOct);
                 cur = kstar + 1;
-                if (sp < kFrames) {
+                if (sp < W.frames) {
                     s_hdr[sp - 1][o] = nch | cur << 8;
                     n2 = n;
                     break;
@@ -1222,6 +1228,9 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     W.jp_cnt = B[T_JPCNT].as<int64_t>();
     W.jc_cnt = B[T_JCCNT].as<int64_t>();
     W.flag = B[T_FLAG].as<int>();
+    // one frame per level below the root: enough for the deepest opened cell
+    W.frames = std::max(1, std::min(kFrames, (int)level.size() - 1));
+    const size_t walk_lds = (size_t)W.frames * (kWalkBlock * sizeof(int2) + kWalkBlock / kOct * 4);
     W.gbox = nullptr;
     if (W.rdrop2 > 0.0) {
         STEP(B[T_GBOX].reserve((size_t)ng * 6 * 8), "allocation");
@@ -1241,10 +1250,10 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
         W.cap_c = P.cap_c;
         W.jp_idx = B[T_JPSLOT].as<int32_t>();
         W.jc_idx = B[T_JCSLOT].as<int32_t>();
-        hipLaunchKernelGGL(k_walk<kWalkSlots>, dim3(walk_blocks(ng)), dim3(kWalkBlock), 0, s, W);
+        hipLaunchKernelGGL(k_walk<kWalkSlots>, dim3(walk_blocks(ng)), dim3(kWalkBlock), walk_lds, s, W);
         LAUNCHED("walk (slots)");
     } else {
-        hipLaunchKernelGGL(k_walk<kWalkCount>, dim3(walk_blocks(ng)), dim3(kWalkBlock), 0, s, W);
+        hipLaunchKernelGGL(k_walk<kWalkCount>, dim3(walk_blocks(ng)), dim3(kWalkBlock), walk_lds, s, W);
         LAUNCHED("walk (count)");
     }
     for (int pass = 0; pass < 2; ++pass) {
@@ -1302,7 +1311,7 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
         W.jc_off = O.jc_off->as<int64_t>();
         W.jp_idx = O.jp_idx->as<int32_t>();
         W.jc_idx = O.jc_idx->as<int32_t>();
-        hipLaunchKernelGGL(k_walk<kWalkFill>, dim3(walk_blocks(ng)), dim3(kWalkBlock), 0, s, W);
+        hipLaunchKernelGGL(k_walk<kWalkFill>, dim3(walk_blocks(ng)), dim3(kWalkBlock), walk_lds, s, W);
         LAUNCHED("walk (fill)");
     }
     O.max_p = max_p;
