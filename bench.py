@@ -197,13 +197,13 @@ def pm_long_range(torch, W, short_ms, repeats):
 def treepm_step(torch, W, nmesh, steps=3):
     """Wall time of one periodic TreePM leapfrog step on the workload (kick,
     drift, wrap, device list rebuild, split kernel, PM, kick), particles and
-    velocities in device memory, after one step that includes the first
-    (counting) list build."""
+    velocities in device memory (put into tree order every 8 builds), after
+    one step that includes the first (counting) list build."""
     from paper_1812_07313_amd.nbody import NBody
     v = np.zeros_like(W["x"])
     with NBody(W["x"], v, W["m"], 0.0, W["theta"], W["ncrit"], min(8, W["ncrit"]),
                kernel=W["kernel"], box=W["box"], rs=W["rs"], rcut=W["rcut"],
-               pm_mesh=nmesh) as sim:
+               pm_mesh=nmesh, sort_every=8) as sim:
         sim.step(1e-3, 1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

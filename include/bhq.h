@@ -422,6 +422,23 @@ int bhq_get_cells(bhq_ctx *ctx, double (*com)[3], double *mass,
  * BHQ_E_HIP. */
 int bhq_get_result_device(bhq_ctx *ctx, double *a, double *pot, void *stream);
 
+/* Put the caller's particle arrays into the tree order of the current lists
+ * (built by bhq_build_lists_device(_batch) or set by bhq_set_lists_indexed):
+ * each of the nf <= 16 arrays fields[f] (device memory, n rows of
+ * row_bytes[f] bytes, a multiple of 8 from 8 to 64) is permuted in place so
+ * that row k holds the particle at tree position k.  n must be the
+ * particle count of the lists.  From then on the lists refer to the arrays
+ * in that order: bhq_get_result_device writes row k for tree position k,
+ * and bhq_get_lists reports the identity as i_idx.  For callers that keep
+ * their particles in tree order between rebuilds (time stepping), so that
+ * the next build reads them nearly in order.  Runs on `stream` after the
+ * last bhq_compute, and returns when done.  Errors: BHQ_E_STATE (no lists
+ * with a tree order), BHQ_E_ARG (n, nf, a field or its row size),
+ * BHQ_E_RANGE (an array that is not device memory of that size),
+ * BHQ_E_NOMEM / BHQ_E_HIP. */
+int bhq_sort_to_tree_order(bhq_ctx *ctx, int64_t n, int nf, void *const *fields,
+                           const int *row_bytes, void *stream);
+
 /* Leapfrog step pieces on n particles: v += dt_kick * a, then, unless
  * dt_drift == 0, x += dt_drift * v (x may be NULL then).  A kick-drift-kick
  * step is kick_drift(dt/2, dt), forces, kick_drift(dt/2, 0); consecutive

@@ -103,6 +103,9 @@ SIGNATURES = {
     "bhq_energies": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P,
                                     ctypes.c_double, _D, _P]),
     "bhq_wrap_periodic": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_double, _P]),
+    "bhq_sort_to_tree_order": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int,
+                                               ctypes.POINTER(_P),
+                                               ctypes.POINTER(ctypes.c_int), _P]),
     "bhq_pm_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_double]),
     "bhq_pm_destroy": (ctypes.c_int, [_P]),
@@ -530,6 +533,27 @@ def bhq_wrap_periodic(ctx, x, box, stream=None):
     n = int(x.shape[0])
     _check(lib().bhq_wrap_periodic(ctx, n, _dptr(x, (n, 3), "x"), float(box),
                                    _stream_handle(stream)), ctx)
+
+
+def bhq_sort_to_tree_order(ctx, fields, stream=None):
+    """Permute GPU tensors (each with n rows of 8 to 64 bytes, contiguous,
+    8-byte elements) in place into the tree order of the current lists."""
+    fields = list(fields)
+    if not fields:
+        raise ValueError("no fields")
+    n = int(fields[0].shape[0])
+    ptrs, rb = [], []
+    for k, t in enumerate(fields):
+        if not (hasattr(t, "is_cuda") and t.is_cuda) or not t.is_contiguous():
+            raise TypeError("field %d must be a contiguous GPU tensor" % k)
+        if int(t.shape[0]) != n or t.element_size() != 8:
+            raise ValueError("field %d must have %d rows of 8-byte elements" % (k, n))
+        ptrs.append(t.data_ptr())
+        rb.append(int(t.numel() // max(n, 1)) * 8)
+    arr = (_P * len(ptrs))(*ptrs)
+    rba = (ctypes.c_int * len(rb))(*rb)
+    _check(lib().bhq_sort_to_tree_order(ctx, n, len(ptrs), arr, rba,
+                                        _stream_handle(stream)), ctx)
 
 
 def bhq_energies(ctx, m, v, pot=None, eps=0.0, stream=None):

@@ -58,7 +58,7 @@ def density_profile(x, m, centre, rmin=0.01, rmax=10.0, nbins=30):
 
 
 def run(sim, n=4194304, t_end=10.0, dt=2.0 ** -8, eps=2.0 ** -8, ncrit=256, seed=0,
-        precision=bhq.FP32_OFS64, report=1.0):
+        precision=bhq.FP32_OFS64, report=1.0, sort_every=8):
     """One run; returns a dict with the timing, the energy history and the
     final density profile."""
     import torch
@@ -67,7 +67,8 @@ def run(sim, n=4194304, t_end=10.0, dt=2.0 ** -8, eps=2.0 ** -8, ncrit=256, seed
     nsteps = int(round(t_end / dt))
     every = max(1, int(round(report / dt)))
     hist = []
-    with NBody(x, v, m, eps, theta, ncrit, kernel=kernel, precision=precision) as nb:
+    with NBody(x, v, m, eps, theta, ncrit, kernel=kernel, precision=precision,
+               sort_every=sort_every) as nb:
         K, W = nb.energies()
         hist.append(dict(t=0.0, K=K, W=W))
         log("sim %s: n=%d kernel=%s theta=%g, %d steps; E0 = %.6f, 2K/|W| = %.4f"
@@ -119,11 +120,14 @@ def main():
     ap.add_argument("--dt", type=float, default=2.0 ** -8)
     ap.add_argument("--eps", type=float, default=2.0 ** -8)
     ap.add_argument("--ncrit", type=int, default=256)
+    ap.add_argument("--sort-every", type=int, default=8,
+                    help="put the particle state into tree order every k builds (0: never)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     results = {}
     for s in args.sims.split(","):
-        results[s] = run(s, args.n, args.t_end, args.dt, args.eps, args.ncrit)
+        results[s] = run(s, args.n, args.t_end, args.dt, args.eps, args.ncrit,
+                         sort_every=args.sort_every)
     out = dict(runs=results)
     if "A" in results:
         out["profile_vs_A"] = compare(results)

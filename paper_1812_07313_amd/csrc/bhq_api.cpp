@@ -33,7 +33,7 @@ enum Arr {
     A_AX, A_AY, A_AZ, A_POT,
     A_QUEUE,
     A_POOLP, A_POOLC, A_JPIDX, A_JCIDX,
-    A_TORDER, A_ENERGY, A_OSCRATCH,
+    A_TORDER, A_ENERGY, A_OSCRATCH, A_SORTSCRATCH,
     A_COUNT
 };
 
@@ -1443,6 +1443,46 @@ int bhq_get_result_device(bhq_ctx *ctx, double *a, double *pot, void *stream)
                             ctx->arr[A_AZ].as<double>(), ctx->arr[A_POT].as<double>(), a,
                             pot, s);
     return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "scatter launch");
+}
+
+int bhq_sort_to_tree_order(bhq_ctx *ctx, int64_t n, int nf, void *const *fields,
+                           const int *row_bytes, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (ctx->ng < 0 || !ctx->tree_order)
+        return ctx->fail(BHQ_E_STATE, "sort_to_tree_order: no lists with a tree order");
+    if (n != ctx->ni || nf < 0 || nf > 16 || (nf > 0 && (!fields || !row_bytes)))
+        return ctx->fail(BHQ_E_ARG, "sort_to_tree_order: bad argument");
+    for (int f = 0; f < nf; ++f)
+        if (!fields[f] || row_bytes[f] < 8 || row_bytes[f] > 64 || row_bytes[f] % 8 != 0)
+            return ctx->fail(BHQ_E_ARG, "sort_to_tree_order: field %d", f);
+    if (n == 0) return BHQ_OK;
+    TRY(ctx->select());
+    for (int f = 0; f < nf; ++f)
+        TRY(check_device_range(ctx, fields[f], (size_t)n * (size_t)row_bytes[f], "field"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // a pending force evaluation does not read these arrays; results it is
+    // still writing are scattered by the order replaced below, so wait
+    hipError_t e = hipStreamWaitEvent(s, ctx->ev1, 0);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipStreamWaitEvent");
+    int maxb = 8;
+    for (int f = 0; f < nf; ++f) maxb = std::max(maxb, row_bytes[f]);
+    e = ctx->arr[A_SORTSCRATCH].reserve((size_t)n * (size_t)maxb);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipMalloc");
+    const int32_t *order = ctx->arr[A_TORDER].as<int32_t>();
+    for (int f = 0; f < nf; ++f) {
+        const size_t bytes = (size_t)n * (size_t)row_bytes[f];
+        e = bhq::launch_gather_rows(n, row_bytes[f] / 8, fields[f], order,
+                                    ctx->arr[A_SORTSCRATCH].p, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(fields[f], ctx->arr[A_SORTSCRATCH].p, bytes,
+                               hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return ctx->hip_fail(e, "gather");
+    }
+    // the arrays are in tree order now: tree position k is row k
+    e = bhq::launch_iota(ctx->arr[A_TORDER].as<int32_t>(), n, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "tree order");
 }
 
 int bhq_kick_drift(bhq_ctx *ctx, int64_t n, double *x, double *v, const double *a,

@@ -54,6 +54,23 @@ __global__ __launch_bounds__(kBlock) void k_wrap(int64_t n3, double *x, double b
     x[i] = y;
 }
 
+// out row k = in row order[k], rows of w 8-byte words.
+__global__ __launch_bounds__(kBlock) void k_gather_rows(int64_t n, int w, const uint64_t *in,
+                                                        const int32_t *order, uint64_t *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n * w) return;
+    const int64_t k = i / w;
+    const int c = (int)(i - k * w);
+    out[i] = in[(int64_t)order[k] * w + c];
+}
+
+__global__ __launch_bounds__(kBlock) void k_iota(int32_t *v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) v[i] = (int32_t)i;
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_f64(double *v, int64_t n, double val)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -150,6 +167,22 @@ hipError_t launch_fill_f64(double *v, int64_t n, double val, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_f64, dim3(blocks(n)), dim3(kBlock), 0, s, v, n, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(int64_t n, int words, const void *in, const int32_t *order,
+                              void *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_rows, dim3(blocks(n * words)), dim3(kBlock), 0, s, n, words,
+                       static_cast<const uint64_t *>(in), order, static_cast<uint64_t *>(out));
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t *v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3(blocks(n)), dim3(kBlock), 0, s, v, n);
     return hipGetLastError();
 }
 

@@ -158,6 +158,10 @@ hipError_t launch_kick_drift(int64_t n, double *x, double *v, const double *a,
                              double dtk, double dtd, hipStream_t s);
 hipError_t launch_wrap(int64_t n, double *x, double box, hipStream_t s);
 hipError_t launch_fill_f64(double *v, int64_t n, double val, hipStream_t s);
+// out row k = in row order[k] (rows of `words` 8-byte words); v[k] = k.
+hipError_t launch_gather_rows(int64_t n, int words, const void *in, const int32_t *order,
+                              void *out, hipStream_t s);
+hipError_t launch_iota(int32_t *v, int64_t n, hipStream_t s);
 
 // XCD dispatch order of ng groups whose offsets are in device memory,
 // computed on the GPU; equal to the host planner's table.  Supported for

@@ -10,6 +10,11 @@ In a periodic box (box > 0) the force is TreePM: the short-range split
 kernel over the device-built lists (cells beyond rcut skipped) plus, with
 pm_mesh > 0, the particle-mesh long-range force; positions are mapped back
 to [0, box) after each drift.
+
+With sort_every = k > 0 the particle state is permuted into the tree order
+of every k-th build (bhq_sort_to_tree_order), so that later builds gather
+their particles nearly in order; state() and accelerations() still answer
+in the input order.
 """
 from . import bhq
 
@@ -22,7 +27,7 @@ class NBody:
 
     def __init__(self, x, v, m, eps, theta, ncrit=64, nleaf=8, kernel=bhq.QUAD,
                  precision=bhq.FP32_OFS64, stream=None, box=0.0, rs=0.0, rcut=0.0,
-                 pm_mesh=0):
+                 pm_mesh=0, sort_every=0):
         import torch
         self.torch = torch
         dev = torch.device("cuda")
@@ -38,6 +43,10 @@ class NBody:
         self.m = tens(m, (n,))
         self.a = torch.zeros((n, 3), dtype=torch.float64, device=dev)
         self.pot = torch.zeros(n, dtype=torch.float64, device=dev)
+        # ids[k]: input index of the particle in row k (rows move when sorted)
+        self.ids = torch.arange(n, dtype=torch.int64, device=dev)
+        self.sort_every = int(sort_every)
+        self.nforces = 0
         self.eps = float(eps)
         self.theta, self.ncrit, self.nleaf = float(theta), int(ncrit), int(nleaf)
         self.stream = stream
@@ -72,6 +81,10 @@ class NBody:
         bhq.bhq_build_lists_device(self.ctx, self.x, self.m, self.theta, self.ncrit,
                                    self.nleaf, self.box, self.rcut, stream=self.stream)
         bhq.bhq_compute(self.ctx, self.stream)
+        if self.sort_every > 0 and self.nforces % self.sort_every == 0:
+            bhq.bhq_sort_to_tree_order(self.ctx, [self.x, self.v, self.m, self.ids],
+                                       self.stream)
+        self.nforces += 1
         bhq.bhq_get_result_device(self.ctx, self.a, self.pot, self.stream)
         if self.pm is not None:
             bhq.bhq_pm_compute(self.pm, self.x, self.m, self.a, self.pot, accumulate=True,
@@ -100,7 +113,22 @@ class NBody:
         return bhq.bhq_energies(self.ctx, self.m, self.v, self.pot, self.eps,
                                 self.stream)
 
+    def _input_order(self, *arrays):
+        self.torch.cuda.synchronize()
+        ids = self.ids.cpu().numpy()
+        out = []
+        for t in arrays:
+            a = t.cpu().numpy()
+            b = a.copy()
+            b[ids] = a
+            out.append(b)
+        return out
+
     def state(self):
         """Host copies (x, v) in input order."""
-        self.torch.cuda.synchronize()
-        return self.x.cpu().numpy(), self.v.cpu().numpy()
+        return tuple(self._input_order(self.x, self.v))
+
+    def accelerations(self):
+        """Host copies (a, pot) of the last force evaluation, in input
+        order."""
+        return tuple(self._input_order(self.a, self.pot))

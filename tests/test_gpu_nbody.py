@@ -1,6 +1,8 @@
 """GPU: leapfrog time integration (device lists + forces + kick/drift every
 step) against the oracle's leapfrog over its own tree forces, and the
 time-step helpers of the C ABI against plain arithmetic on the host."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -199,3 +201,66 @@ def test_wrap_periodic_bitwise():
     y = np.where(y >= box, y - box, y)
     assert np.array_equal(xg, y)
     assert np.all((xg >= 0) & (xg < box))
+
+
+def test_sort_to_tree_order():
+    """bhq_sort_to_tree_order: the arrays come back permuted into tree order
+    (row k = input row order[k]), bhq_get_lists then reports the identity,
+    and the results of the same evaluation come back in the new order."""
+    x, v, m = _ic(5000, 7)
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        xt, vt, mt = (torch.from_numpy(a.copy()).cuda() for a in (x, v, m))
+        ids = torch.arange(len(m), dtype=torch.int64, device="cuda")
+        bhq.bhq_build_lists_device(ctx, xt, mt, 0.6, 64)
+        bhq.bhq_set_eps(ctx, 2.0 ** -6)
+        bhq.bhq_compute(ctx)
+        a0 = torch.zeros((len(m), 3), dtype=torch.float64, device="cuda")
+        bhq.bhq_get_result_device(ctx, a0)
+        order = bhq.bhq_get_lists(ctx, len(m))["i_idx"]
+        assert not np.array_equal(order, np.arange(len(m)))
+        bhq.bhq_sort_to_tree_order(ctx, [xt, vt, mt, ids])
+        assert np.array_equal(xt.cpu().numpy(), x[order])
+        assert np.array_equal(vt.cpu().numpy(), v[order])
+        assert np.array_equal(mt.cpu().numpy(), m[order])
+        assert np.array_equal(ids.cpu().numpy(), order)
+        assert np.array_equal(bhq.bhq_get_lists(ctx, len(m))["i_idx"], np.arange(len(m)))
+        a1 = torch.zeros_like(a0)
+        bhq.bhq_get_result_device(ctx, a1)
+        assert np.array_equal(a1.cpu().numpy(), a0.cpu().numpy()[order])
+        # errors: wrong count, row size not a multiple of 8
+        f = (ctypes.c_void_p * 1)(xt.data_ptr())
+        for n, rb in ((len(m) - 1, 24), (len(m), 12), (len(m), 72)):
+            r = (ctypes.c_int * 1)(rb)
+            assert bhq.lib().bhq_sort_to_tree_order(ctx, n, 1, f, r, None) == bhq.E_ARG
+    finally:
+        bhq.bhq_destroy(ctx)
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_sort_to_tree_order(ctx, [torch.zeros(10, dtype=torch.float64,
+                                                         device="cuda")])
+        assert ei.value.code == bhq.E_STATE
+    finally:
+        bhq.bhq_destroy(ctx)
+
+
+@pytest.mark.parametrize("kernel", [bhq.QUAD, bhq.MONO])
+def test_sorted_state_same_trajectory(kernel):
+    """NBody keeping its state in tree order (sorted at every build, or every
+    third) follows the same FP64 trajectory as the unsorted run: only the
+    order of the particles inside a leaf changes, and with it the summation
+    order."""
+    x, v, m = _ic(3000, 8)
+    eps, theta, ncrit, dt, steps = 2.0 ** -6, 0.5, 64, 2.0 ** -8, 8
+    out = []
+    for every in (0, 1, 3):
+        with NBody(x, v, m, eps, theta, ncrit, kernel=kernel, precision=bhq.FP64,
+                   sort_every=every) as sim:
+            sim.step(dt, steps)
+            out.append(sim.state() + sim.accelerations() + sim.energies())
+    for o in out[1:]:
+        for a, b in zip(out[0][:4], o[:4]):
+            np.testing.assert_allclose(a, b, rtol=0, atol=1e-11 * np.abs(a).max())
+        assert o[4] == pytest.approx(out[0][4], rel=1e-13)
+        assert o[5] == pytest.approx(out[0][5], rel=1e-13)
