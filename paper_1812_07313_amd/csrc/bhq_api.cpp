@@ -153,6 +153,9 @@ struct bhq_ctx {
     // device builds: slot sizes for the next one-walk build, and what the
     // last build did (one walk or not, longest particle and cell lists)
     int64_t walk_cap_p = 0, walk_cap_c = 0;
+    // depth and cell count of the last device-built tree
+    int tree_levels = 0;
+    int64_t tree_cells = 0;
     int64_t build_info[3] = {0, 0, 0};
     uint64_t args_version = 0;  // bumped when device pointers/params change
     hipStream_t cap_stream = nullptr;
@@ -1209,6 +1212,8 @@ static int device_build(bhq_ctx *ctx, int64_t nsys, const int64_t *sys_off,
     // previous lists' memory plus 256 MiB.
     P.cap_p = ctx->walk_cap_p;
     P.cap_c = ctx->walk_cap_c;
+    P.spec_levels = ctx->tree_levels;
+    P.spec_cells = ctx->tree_cells;
     P.slot_bytes = ctx->ng >= 0 ? 16 * (ctx->njp + ctx->njc) + ((int64_t)256 << 20) : 0;
     bhq::TreeOut O;
     O.i_off = &ctx->arr[A_IOFF];
@@ -1256,6 +1261,8 @@ static int device_build(bhq_ctx *ctx, int64_t nsys, const int64_t *sys_off,
     };
     ctx->walk_cap_p = next_cap(ctx->walk_cap_p, O.max_p);
     ctx->walk_cap_c = next_cap(ctx->walk_cap_c, O.max_c);
+    ctx->tree_levels = O.nlevels;
+    ctx->tree_cells = O.ncell;
     ctx->build_info[0] = O.one_walk ? 1 : 0;
     ctx->build_info[1] = O.max_p;
     ctx->build_info[2] = O.max_c;

@@ -195,6 +195,10 @@ struct TreeParams {
     // offsets.
     int64_t cap_p = 0, cap_c = 0;
     int64_t slot_bytes = 0;  // upper bound on the slot memory of that mode
+    // Depth (levels) and cell count of an earlier build of similar input:
+    // the levels are then built without host synchronisation (0: unknown).
+    int spec_levels = 0;
+    int64_t spec_cells = 0;
 };
 
 // Builder working memory, kept between builds of one context.
@@ -203,7 +207,7 @@ enum TreeBuf {
     T_CX, T_CY, T_CZ, T_SIDE, T_FIRST, T_COUNT, T_CHILD0, T_NCHILD, T_PARENT,
     T_DEPTH, T_CKEY, T_NCH, T_NOFF, T_GSTART, T_GROUPS, T_NSEL, T_WC, T_WL,
     T_JPCNT, T_JCCNT, T_CSYS, T_SYSOFF, T_SYSOFF32, T_ROOTS, T_SYSROOT, T_LSC, T_PERM,
-    T_JPSLOT, T_JCSLOT, T_GBOX,
+    T_JPSLOT, T_JCSLOT, T_GBOX, T_LV,
     T_COUNT_
 };
 
@@ -226,6 +230,7 @@ struct TreeOut {
     // longest particle and cell list of a group; whether one walk sufficed
     int64_t max_p = 0, max_c = 0;
     bool one_walk = false;
+    int nlevels = 0;  // levels of the tree (the root's included)
 };
 
 // Returns a BHQ_* code; on failure *err names the step.

@@ -251,34 +251,57 @@ __device__ __forceinline__ void octant_bounds(const uint64_t *skey, const Cells 
     b[8] = e;
 }
 
+// Level passes.  lv[l] is the first cell of level l (level l is cells
+// [lv[l], lv[l+1])), in device memory, so that a rebuild can run its levels
+// without the host reading their sizes.  A pass covers `bound` >= the
+// level's width threads (a host-side upper bound when the width is not
+// known there).
+
+// nch[t] = number of children of cell lv[L] + t (0 beyond the level).
+// After an overflow (*flag set) the level's cells may be incomplete: they
+// are not read, and the level gets no children.
 __global__ __launch_bounds__(kBlock) void k_level_count(Cells C, const uint64_t *skey,
-                                                        int32_t lo, int32_t hi, int nleaf,
-                                                        int32_t *nch)
+                                                        const int32_t *lv, int L, int32_t bound,
+                                                        int nleaf, const int *flag, int32_t *nch)
 {
-    const int32_t c = lo + (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (c >= hi) return;
+    const int32_t t = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (t >= bound) return;
+    const int32_t c = lv[L] + t;
     int32_t n = 0;
-    if (C.count[c] > nleaf && C.depth[c] < kMaxDepth) {
+    if (*flag == 0 && c < lv[L + 1] && C.count[c] > nleaf && C.depth[c] < kMaxDepth) {
         int32_t b[9];
         octant_bounds(skey, C, c, 3 * (kMaxDepth - 1 - C.depth[c]), b);
         for (int o = 0; o < 8; ++o) n += b[o + 1] > b[o];
     }
-    nch[c - lo] = n;
+    nch[t] = n;
 }
 
-__global__ __launch_bounds__(kBlock) void k_level_write(Cells C, const uint64_t *skey,
-                                                        int32_t lo, int32_t hi,
-                                                        const int32_t *nch,
-                                                        const int32_t *noff)
+// Children of level L from the exclusive sums noff of nch; thread 0 sets
+// lv[L + 2], the end of level L + 1.  Cells at or beyond `cap` are not
+// written: the end is clamped to cap and *flag is set.
+__global__ __launch_bounds__(kBlock) void k_level_write(Cells C, const uint64_t *skey, int32_t *lv,
+                                                        int L, int32_t bound, const int32_t *nch,
+                                                        const int32_t *noff, int32_t cap,
+                                                        int *flag)
 {
-    const int32_t c = lo + (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    const int32_t t = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    const int32_t lo = lv[L], hi = lv[L + 1];
+    if (t == 0) {
+        const int32_t w = hi - lo;
+        const int64_t end = w > 0 ? (int64_t)hi + noff[w - 1] + nch[w - 1] : (int64_t)hi;
+        lv[L + 2] = end > cap ? cap : (int32_t)end;
+        if (end > cap) *flag = 1;
+    }
+    if (t >= bound) return;
+    const int32_t c = lo + t;
     if (c >= hi) return;
-    if (nch[c - lo] == 0) return;
+    if (nch[t] == 0) return;
+    const int32_t child0 = hi + noff[t];
+    if ((int64_t)child0 + nch[t] > cap) return;
     const int d = C.depth[c];
     const int sh = 3 * (kMaxDepth - 1 - d);
     int32_t b[9];
     octant_bounds(skey, C, c, sh, b);
-    const int32_t child0 = hi + noff[c - lo];
     const double qd = C.side[c] * 0.25;
     const double pc[3] = {C.cx[c], C.cy[c], C.cz[c]};
     int32_t j = 0;
@@ -1041,21 +1064,80 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     std::vector<int32_t> level{0, nsys};  // level l is cells [level[l], level[l+1])
     STEP(B[T_NCH].reserve((size_t)std::max<int64_t>(n, 1) * 4 + 4), "allocation");
     STEP(B[T_NOFF].reserve((size_t)std::max<int64_t>(n, 1) * 4 + 4), "allocation");
-    for (int lev = 0; lev < kMaxDepth; ++lev) {
+    // level bounds on the device (kMaxDepth + 2 entries), then a flag
+    STEP(B[T_LV].reserve((size_t)(kMaxDepth + 3) * 4), "allocation");
+    int32_t *lv = B[T_LV].as<int32_t>();
+    int *lvflag = reinterpret_cast<int *>(lv + kMaxDepth + 2);
+    {
+        const int32_t init[3] = {0, nsys, 0};
+        STEP(hipMemcpyAsync(lv, init, 8, hipMemcpyHostToDevice, s), "copy");
+        STEP(hipMemcpyAsync(lvflag, init + 2, 4, hipMemcpyHostToDevice, s), "copy");
+    }
+    auto scan = [&](int32_t bound) -> bool {
+        size_t st = 0;
+        if (!hip(hipcub::DeviceScan::ExclusiveSum(nullptr, st, B[T_NCH].as<int32_t>(),
+                                                  B[T_NOFF].as<int32_t>(), bound, s),
+                 "scan size"))
+            return false;
+        if (!hip(B[T_SORT].reserve(std::max(st, B[T_SORT].cap)), "allocation")) return false;
+        return hip(hipcub::DeviceScan::ExclusiveSum(B[T_SORT].p, st, B[T_NCH].as<int32_t>(),
+                                                    B[T_NOFF].as<int32_t>(), bound, s),
+                   "scan");
+    };
+    auto level_pass = [&](int lev, int32_t bound) -> bool {
+        hipLaunchKernelGGL(k_level_count, dim3(blocks(bound, kBlock)), dim3(kBlock), 0, s,
+                           cells(), skey, (const int32_t *)lv, lev, bound, P.nleaf,
+                           (const int *)lvflag, B[T_NCH].as<int32_t>());
+        if (!hip(hipGetLastError(), "level count")) return false;
+        if (!scan(bound)) return false;
+        hipLaunchKernelGGL(k_level_write, dim3(blocks(bound, kBlock)), dim3(kBlock), 0, s,
+                           cells(), skey, lv, lev, bound, B[T_NCH].as<int32_t>(),
+                           B[T_NOFF].as<int32_t>(),
+                           (int32_t)std::min<size_t>(cap, 0x7fffffff), lvflag);
+        return hip(hipGetLastError(), "level write");
+    };
+    // A rebuild first runs as many levels as the previous build had with no
+    // host synchronisation: widths bounded by 8 times the level above and by
+    // n, cells by a capacity of 1.25 times the previous build's.  If the
+    // cells overflow, the levels are built again below, one at a time; if
+    // the tree goes deeper, the remaining levels are built that way.
+    bool done = false;
+    if (P.spec_levels > 0 && P.spec_cells > 0) {
+        const size_t want = (size_t)P.spec_cells + (size_t)P.spec_cells / 4 + 1024;
+        if (!ensure(std::min<size_t>(want, 0x7fffffff), (size_t)nsys)) return fail();
+        const int nl = std::min(P.spec_levels, kMaxDepth);
+        int64_t bound = nsys;
+        for (int lev = 0; lev < nl; ++lev) {
+            if (!level_pass(lev, (int32_t)bound)) return fail();
+            bound = std::min<int64_t>(8 * bound, n);
+        }
+        std::vector<int32_t> hl((size_t)kMaxDepth + 3);
+        STEP(hipMemcpyAsync(hl.data(), lv, hl.size() * 4, hipMemcpyDeviceToHost, s), "copy");
+        STEP(hipStreamSynchronize(s), "sync");
+        if (hl[(size_t)kMaxDepth + 2] == 0) {
+            for (int lev = 0; lev < nl; ++lev) {
+                const int32_t e = hl[(size_t)lev + 2];
+                if (e == level.back()) {  // level lev + 1 is empty: the tree ends
+                    done = true;
+                    break;
+                }
+                level.push_back(e);
+            }
+        } else {
+            const int32_t zero = 0;  // start again, level by level
+            STEP(hipMemcpyAsync(lvflag, &zero, 4, hipMemcpyHostToDevice, s), "copy");
+            STEP(hipStreamSynchronize(s), "sync");
+        }
+    }
+    for (int lev = (int)level.size() - 2; !done && lev < kMaxDepth; ++lev) {
         const int32_t lo = level[(size_t)lev], hi = level[(size_t)lev + 1];
         const int32_t w = hi - lo;
         if (w <= 0) break;
         hipLaunchKernelGGL(k_level_count, dim3(blocks(w, kBlock)), dim3(kBlock), 0, s, cells(),
-                           skey, lo, hi, P.nleaf, B[T_NCH].as<int32_t>());
+                           skey, (const int32_t *)lv, lev, w, P.nleaf, (const int *)lvflag,
+                           B[T_NCH].as<int32_t>());
         LAUNCHED("level count");
-        size_t st = 0;
-        STEP(hipcub::DeviceScan::ExclusiveSum(nullptr, st, B[T_NCH].as<int32_t>(),
-                                              B[T_NOFF].as<int32_t>(), w, s),
-             "scan size");
-        STEP(B[T_SORT].reserve(std::max(st, B[T_SORT].cap)), "allocation");
-        STEP(hipcub::DeviceScan::ExclusiveSum(B[T_SORT].p, st, B[T_NCH].as<int32_t>(),
-                                              B[T_NOFF].as<int32_t>(), w, s),
-             "scan");
+        if (!scan(w)) return fail();
         int32_t tail[2];
         STEP(hipMemcpyAsync(&tail[0], B[T_NOFF].as<int32_t>() + (w - 1), 4,
                             hipMemcpyDeviceToHost, s),
@@ -1073,7 +1155,8 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
         }
         if (!ensure((size_t)(hi + total), (size_t)hi)) return fail();
         hipLaunchKernelGGL(k_level_write, dim3(blocks(w, kBlock)), dim3(kBlock), 0, s, cells(),
-                           skey, lo, hi, B[T_NCH].as<int32_t>(), B[T_NOFF].as<int32_t>());
+                           skey, lv, lev, w, B[T_NCH].as<int32_t>(), B[T_NOFF].as<int32_t>(),
+                           (int32_t)std::min<size_t>(cap, 0x7fffffff), lvflag);
         LAUNCHED("level write");
         level.push_back((int32_t)(hi + total));
     }
@@ -1344,6 +1427,7 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     O.njp = njp;
     O.njc = njc;
     O.ncell = ncell;
+    O.nlevels = (int)level.size() - 1;
 #undef STEP
 #undef LAUNCHED
     return BHQ_OK;

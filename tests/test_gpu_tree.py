@@ -203,11 +203,14 @@ def test_device_build_errors():
 
 
 def test_rebuild_reuses_context():
-    """Two builds of different sizes in a row on one context, each equal
-    to the host builder's lists; the second evaluates correctly."""
+    """Builds of different sizes in a row on one context, each equal to the
+    host builder's lists: a smaller one (its levels built without host
+    synchronisation from the first build's depth), a larger one (whose
+    cells overflow that capacity, so its levels are built again one at a
+    time), and the same again; the last evaluates correctly."""
     ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
     try:
-        for n, seed in ((40000, 11), (7000, 12)):
+        for n, seed in ((40000, 11), (7000, 12), (60000, 13), (60000, 13)):
             x, m = synth.plummer(n, synth.rng(seed))
             log("case device rebuild n=%d" % n)
             h = _host(x, m, 0.6, 64)
