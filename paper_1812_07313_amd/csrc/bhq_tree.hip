@@ -996,33 +996,45 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
                        B[T_SYSOFF].as<int64_t>(), nsys, B[T_ROOTS].as<double>(),
                        B[T_KEY].as<uint64_t>(), B[T_IDX0].as<int32_t>());
     LAUNCHED("keys");
-    size_t tmp = 0;
-    if (nsys == 1) {
-        STEP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, B[T_KEY].as<uint64_t>(),
-                                                B[T_KEY2].as<uint64_t>(),
-                                                B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(),
-                                                (int)n, 0, 3 * kMaxDepth, s),
-             "sort size");
-        STEP(B[T_SORT].reserve(tmp), "allocation");
-        STEP(hipcub::DeviceRadixSort::SortPairs(B[T_SORT].p, tmp, B[T_KEY].as<uint64_t>(),
-                                                B[T_KEY2].as<uint64_t>(),
-                                                B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(),
-                                                (int)n, 0, 3 * kMaxDepth, s),
-             "sort");
-    } else {
+    // Stable sort of (key, input index) on key bits [lo_bit, 63).  Splitting
+    // a cell at depth d reads the key digit at bits 3 (kMaxDepth - 1 - d),
+    // so a tree of L levels needs the bits from 3 (kMaxDepth + 1 - L) up;
+    // the order inside a leaf does not matter (leaves are put back in input
+    // order).  A rebuild sorts the bits its previous depth needs; if the tree
+    // turns out deeper, the keys are sorted again on all bits.
+    auto sort_keys = [&](int lo_bit) -> bool {
+        size_t tmp = 0;
+        if (nsys == 1) {
+            if (!hip(hipcub::DeviceRadixSort::SortPairs(
+                         nullptr, tmp, B[T_KEY].as<uint64_t>(), B[T_KEY2].as<uint64_t>(),
+                         B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(), (int)n, lo_bit,
+                         3 * kMaxDepth, s),
+                     "sort size"))
+                return false;
+            if (!hip(B[T_SORT].reserve(std::max(tmp, B[T_SORT].cap)), "allocation")) return false;
+            return hip(hipcub::DeviceRadixSort::SortPairs(
+                           B[T_SORT].p, tmp, B[T_KEY].as<uint64_t>(), B[T_KEY2].as<uint64_t>(),
+                           B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(), (int)n, lo_bit,
+                           3 * kMaxDepth, s),
+                       "sort");
+        }
         const int32_t *so = B[T_SYSOFF32].as<int32_t>();
-        STEP(hipcub::DeviceSegmentedRadixSort::SortPairs(
-                 nullptr, tmp, B[T_KEY].as<uint64_t>(), B[T_KEY2].as<uint64_t>(),
-                 B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(), (int)n, nsys, so, so + 1, 0,
-                 3 * kMaxDepth, s),
-             "sort size");
-        STEP(B[T_SORT].reserve(tmp), "allocation");
-        STEP(hipcub::DeviceSegmentedRadixSort::SortPairs(
-                 B[T_SORT].p, tmp, B[T_KEY].as<uint64_t>(), B[T_KEY2].as<uint64_t>(),
-                 B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(), (int)n, nsys, so, so + 1, 0,
-                 3 * kMaxDepth, s),
-             "sort");
-    }
+        if (!hip(hipcub::DeviceSegmentedRadixSort::SortPairs(
+                     nullptr, tmp, B[T_KEY].as<uint64_t>(), B[T_KEY2].as<uint64_t>(),
+                     B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(), (int)n, nsys, so, so + 1,
+                     lo_bit, 3 * kMaxDepth, s),
+                 "sort size"))
+            return false;
+        if (!hip(B[T_SORT].reserve(std::max(tmp, B[T_SORT].cap)), "allocation")) return false;
+        return hip(hipcub::DeviceSegmentedRadixSort::SortPairs(
+                       B[T_SORT].p, tmp, B[T_KEY].as<uint64_t>(), B[T_KEY2].as<uint64_t>(),
+                       B[T_IDX0].as<int32_t>(), O.order->as<int32_t>(), (int)n, nsys, so,
+                       so + 1, lo_bit, 3 * kMaxDepth, s),
+                   "sort");
+    };
+    const bool spec = P.spec_levels > 0 && P.spec_cells > 0;
+    const int sort_lo = spec ? 3 * std::max(0, kMaxDepth + 1 - P.spec_levels) : 0;
+    if (!sort_keys(sort_lo)) return fail();
     const uint64_t *skey = B[T_KEY2].as<uint64_t>();
     int32_t *idx = O.order->as<int32_t>();
 
@@ -1102,7 +1114,7 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     // cells overflow, the levels are built again below, one at a time; if
     // the tree goes deeper, the remaining levels are built that way.
     bool done = false;
-    if (P.spec_levels > 0 && P.spec_cells > 0) {
+    if (spec) {
         const size_t want = (size_t)P.spec_cells + (size_t)P.spec_cells / 4 + 1024;
         if (!ensure(std::min<size_t>(want, 0x7fffffff), (size_t)nsys)) return fail();
         const int nl = std::min(P.spec_levels, kMaxDepth);
@@ -1123,8 +1135,13 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
                 }
                 level.push_back(e);
             }
-        } else {
-            const int32_t zero = 0;  // start again, level by level
+        }
+        if (!done) {
+            // the cells overflowed, or the tree is deeper than the sorted
+            // bits reach: sort on all bits and start again, level by level
+            level.assign({0, nsys});
+            if (sort_lo > 0 && !sort_keys(0)) return fail();
+            const int32_t zero = 0;
             STEP(hipMemcpyAsync(lvflag, &zero, 4, hipMemcpyHostToDevice, s), "copy");
             STEP(hipStreamSynchronize(s), "sync");
         }

@@ -146,7 +146,8 @@ def test_cold_collapse_small():
     assert core and max(core) > 20 * 3.0 / (4.0 * np.pi)
 
 
-def test_treepm_leapfrog_fp64_matches_oracle():
+@pytest.mark.parametrize("sort_every", [0, 2])
+def test_treepm_leapfrog_fp64_matches_oracle(sort_every):
     """Periodic TreePM, FP64: 4 steps on a perturbed 16^3 lattice with a
     velocity field that carries particles across the box faces; positions
     and velocities agree with the oracle's TreePM leapfrog (split tree on
@@ -162,11 +163,10 @@ def test_treepm_leapfrog_fp64_matches_oracle():
                                   kind=orc.SPLIT_QUAD, box=1.0, rs=rs, rcut=rcut,
                                   pm_mesh=nmesh)
     with NBody(x, v, m, 0.0, theta, ncrit, kernel=bhq.SPLIT_QUAD, precision=bhq.FP64,
-               box=1.0, rs=rs, rcut=rcut, pm_mesh=nmesh) as sim:
+               box=1.0, rs=rs, rcut=rcut, pm_mesh=nmesh, sort_every=sort_every) as sim:
         sim.step(dt, steps)
         xg, vg = sim.state()
-        ag = sim.a.cpu().numpy()
-        pg = sim.pot.cpu().numpy()
+        ag, pg = sim.accelerations()
     assert np.all((xg >= 0) & (xg < 1))
     d = np.abs(xg - xr)
     d = np.minimum(d, 1.0 - d)

@@ -397,3 +397,21 @@ def test_order_and_build_info_queries():
         assert bhq.bhq_get_build_info(ctx) == info
     finally:
         bhq.bhq_destroy(ctx)
+
+
+def test_rebuild_deeper_tree():
+    """A rebuild whose tree is much deeper than the previous one (the key
+    sort of the rebuild covers only the previous depth's bits): the build
+    sorts again on all bits and still equals the host builder's lists."""
+    g = np.random.default_rng(31)
+    x1 = g.random((2000, 3))
+    m1 = np.full(2000, 1.0 / 2000)
+    x2 = np.vstack([g.random((3000, 3)), np.full((40, 3), 0.3) + g.random((40, 3)) * 1e-9])
+    m2 = np.full(len(x2), 1.0 / len(x2))
+    ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+    try:
+        for x, m in ((x1, m1), (x1, m1), (x2, m2), (x2, m2), (x1, m1)):
+            log("case device rebuild deeper n=%d" % len(m))
+            _same(_host(x, m, 0.6, 32), _device(ctx, x, m, 0.6, 32), "deeper %d" % len(m))
+    finally:
+        bhq.bhq_destroy(ctx)
