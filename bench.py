@@ -452,7 +452,7 @@ def main():
                          "size, to calibrate HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build evaluates the force "
+        print("bench.py runs on one GPU only: the library evaluates the force "
               "path on a single MI355X (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)

@@ -76,3 +76,15 @@ def test_build_lists_argument_errors():
     with pytest.raises(bhq.BhqError) as ei:
         bhq.bhq_build_lists(xb, m, 0.5, 16)
     assert ei.value.code == bhq.E_NONFINITE
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py --gpus N with N > 1 exits with a message before touching a
+    GPU (one GPU only)."""
+    import subprocess
+    import sys
+    from conftest import ROOT
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
