@@ -332,7 +332,30 @@ def fixed_error_study(torch, ctx, W, ref, stream, steps):
     """Quadrupole versus monopole at equal rms force error: for monopole
     theta0 in {0.3, 0.5, 0.7} find the quadrupole theta with the same rms
     tree error (log-log interpolation over a theta grid), rebuild the
-    lists there and time both kernels, in FP32 and FP64."""
+    lists there and time both kernels, in FP32 and FP64, and the device
+    rebuild of the tree and lists at that theta: the total (build + FP32
+    force) is the GPU's counterpart of the paper's T_total."""
+    xt = torch.from_numpy(np.ascontiguousarray(W["x"])).cuda()
+    mt = torch.from_numpy(np.ascontiguousarray(W["m"])).cuda()
+    e2t = (torch.from_numpy(np.ascontiguousarray(W["eps2"])).cuda()
+           if W.get("eps2") is not None else None)
+    bctx = bhq.bhq_create(0, W["kernel"], bhq.FP32_OFS64)
+
+    def build_ms(theta):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if W.get("sys_off") is not None:
+                bhq.bhq_build_lists_device_batch(bctx, W["sys_off"], xt, mt, theta, W["ncrit"],
+                                                 min(8, W["ncrit"]), eps2=e2t)
+            else:
+                bhq.bhq_build_lists_device(bctx, xt, mt, theta, W["ncrit"],
+                                           min(8, W["ncrit"]), W.get("box", 0.0),
+                                           W.get("rcut", 0.0))
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts[1:])) * 1e3   # rebuilds
+
     def measure(kernel, theta, timing):
         L, _ = build_lists(W, theta, W["ncrit"])
         try:
@@ -350,8 +373,16 @@ def fixed_error_study(torch, ctx, W, ref, stream, steps):
                                         stream)
                 out["ms_" + bhq.PRECISION_NAMES[prec]] = round(km, 4)
             out["n_pp"], out["n_pc"] = pp, pc
+            out["build_ms"] = round(build_ms(theta), 4)
         return out
 
+    try:
+        return _fixed_error_rows(measure)
+    finally:
+        bhq.bhq_destroy(bctx)
+
+
+def _fixed_error_rows(measure):
     quad_grid = [measure(bhq.QUAD, th, False)
                  for th in (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0)]
     lt = np.log([q["theta"] for q in quad_grid])
@@ -371,7 +402,10 @@ def fixed_error_study(torch, ctx, W, ref, stream, steps):
                          quad_speedup_fp32=round(mono["ms_fp32_ofs64"] /
                                                  quad["ms_fp32_ofs64"], 3),
                          quad_speedup_fp64=round(mono["ms_fp64"] /
-                                                 quad["ms_fp64"], 3)))
+                                                 quad["ms_fp64"], 3),
+                         quad_speedup_total_fp32=round(
+                             (mono["build_ms"] + mono["ms_fp32_ofs64"]) /
+                             (quad["build_ms"] + quad["ms_fp32_ofs64"]), 3)))
         log("fixed error %.3g: mono theta %.2f %.3f ms | quad theta %.3f "
             "(err %.3g) %.3f ms" % (mono["err"]["rms"], th0,
                                     mono["ms_fp32_ofs64"], thq,
