@@ -129,6 +129,9 @@ struct bhq_ctx {
     bool have_i = false, have_jp = false, have_jc = false, have_t = false;
     // list mode after bhq_set_groups: 0 undecided, 1 materialised, 2 indexed
     int list_mode = 0;
+    // > 0: index lists in per-group slots of these sizes (a rebuilt
+    // device list); 0: compact lists at the offsets
+    int64_t list_slot_p = 0, list_slot_c = 0;
     int64_t npool_p = -1, npool_c = -1;
     // The particle pool is in tree order and A_TORDER[k] is the input index
     // of pool entry k (lists from bhq_set_lists_indexed or
@@ -276,6 +279,23 @@ struct bhq_ctx {
         nslots = (int64_t)order.size();
         ++args_version;
         return BHQ_OK;
+    }
+    // Copy a compact index list (cnt entries, group offsets in device array
+    // off) to the host; lists kept in per-group slots of `slot` entries are
+    // compacted on the device first.
+    int fetch_list(Arr a, Arr off, int64_t slot, int64_t cnt, int32_t *dst)
+    {
+        const void *src = arr[a].p;
+        hipError_t e = hipSuccess;
+        if (slot > 0) {
+            e = arr[A_SORTSCRATCH].reserve((size_t)cnt * 4);
+            if (e == hipSuccess)
+                e = bhq::launch_compact_lists(ng, arr[off].as<int64_t>(), arr[a].as<int32_t>(),
+                                              slot, arr[A_SORTSCRATCH].as<int32_t>(), nullptr);
+            src = arr[A_SORTSCRATCH].p;
+        }
+        if (e == hipSuccess) e = hipMemcpy(dst, src, (size_t)cnt * 4, hipMemcpyDeviceToHost);
+        return e == hipSuccess ? BHQ_OK : hip_fail(e, "list copy");
     }
     // Every i-particle's eps^2 = eps2_all, filled on the device (stream s,
     // synchronised: the forces may be computed on another stream).
@@ -503,6 +523,7 @@ int bhq_set_groups(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
     ctx->have_i = ctx->have_jp = ctx->have_jc = ctx->have_t = false;
     ctx->have_jp_idx = ctx->have_jc_idx = false;
     ctx->list_mode = 0;
+    ctx->list_slot_p = ctx->list_slot_c = 0;
     ctx->tree_order = false;
     if (ctx->eps_mode == 2) ctx->eps_mode = 0;
 
@@ -659,6 +680,8 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
         A.pool_c = ctx->arr[A_POOLC].as<bhq::CellRec>();
         A.jp_idx = ctx->arr[A_JPIDX].as<int32_t>();
         A.jc_idx = ctx->arr[A_JCIDX].as<int32_t>();
+        A.jp_slot = ctx->list_slot_p;
+        A.jc_slot = ctx->list_slot_c;
     }
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1273,6 +1296,8 @@ static int device_build(bhq_ctx *ctx, int64_t nsys, const int64_t *sys_off,
     ctx->have_i = true;
     ctx->have_jp = ctx->have_jc = ctx->have_t = false;
     ctx->list_mode = 2;
+    ctx->list_slot_p = O.slot_p;
+    ctx->list_slot_c = O.slot_c;
     ctx->npool_p = n;
     ctx->npool_c = O.ncell;
     ctx->have_jp_idx = ctx->have_jc_idx = true;
@@ -1375,20 +1400,15 @@ int bhq_get_lists(bhq_ctx *ctx, int64_t *i_idx, int64_t *i_off,
         }
         if (jp_idx && ctx->njp > 0) {
             std::vector<int32_t> v((size_t)ctx->njp);
-            hipError_t e = hipMemcpy(v.data(), ctx->arr[A_JPIDX].p,
-                                     (size_t)ctx->njp * 4, hipMemcpyDeviceToHost);
-            if (e != hipSuccess) return ctx->hip_fail(e, "hipMemcpy D2H");
+            TRY(ctx->fetch_list(A_JPIDX, A_JPOFF, ctx->list_slot_p, ctx->njp, v.data()));
             for (int64_t k = 0; k < ctx->njp; ++k)
                 jp_idx[k] = ctx->tree_order ? ord[(size_t)v[(size_t)k]] : v[(size_t)k];
         }
     } catch (const std::bad_alloc &) {
         return ctx->fail(BHQ_E_NOMEM, "host staging");
     }
-    if (jc_idx && ctx->njc > 0) {
-        hipError_t e = hipMemcpy(jc_idx, ctx->arr[A_JCIDX].p, (size_t)ctx->njc * 4,
-                                 hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return ctx->hip_fail(e, "hipMemcpy D2H");
-    }
+    if (jc_idx && ctx->njc > 0)
+        TRY(ctx->fetch_list(A_JCIDX, A_JCOFF, ctx->list_slot_c, ctx->njc, jc_idx));
     return BHQ_OK;
 }
 

@@ -128,6 +128,10 @@ struct ForceArgs {
     const CellRec *pool_c;
     const int32_t *jp_idx;
     const int32_t *jc_idx;
+    // > 0: index lists in per-group slots (rebuilt device lists): group g's
+    // entries start at g * jp_slot (jc_slot) instead of jp_off[g]; their
+    // counts are still jp_off[g + 1] - jp_off[g].
+    int64_t jp_slot, jc_slot;
 };
 
 constexpr int kQueueWords = 64;  // capacity of ForceArgs::queue
@@ -230,11 +234,18 @@ struct TreeOut {
     // longest particle and cell list of a group; whether one walk sufficed
     int64_t max_p = 0, max_c = 0;
     bool one_walk = false;
+    // one walk: jp_idx / jc_idx hold the per-group slots of these sizes
+    int64_t slot_p = 0, slot_c = 0;
     int nlevels = 0;  // levels of the tree (the root's included)
 };
 
 // Returns a BHQ_* code; on failure *err names the step.
 int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t stream,
                      std::string *err);
+
+// Lists in per-group slots (slot entries per group, counts from off) to
+// the compact layout out[off[g] ...].
+hipError_t launch_compact_lists(int64_t ng, const int64_t *off, const int32_t *slot,
+                                int64_t cap, int32_t *out, hipStream_t s);
 
 }  // namespace bhq

@@ -325,8 +325,9 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
     const int64_t i0 = A.i_off[g];
     const int64_t ni = A.i_off[g + 1] - i0;
     const double cx = A.gcx[g], cy = A.gcy[g], cz = A.gcz[g];
-    const int64_t p0 = A.jp_off[g], np = A.jp_off[g + 1] - p0;
-    const int64_t c0 = A.jc_off[g], nc = A.jc_off[g + 1] - c0;
+    const int64_t np = A.jp_off[g + 1] - A.jp_off[g], nc = A.jc_off[g + 1] - A.jc_off[g];
+    const int64_t p0 = A.jp_slot > 0 ? g * A.jp_slot : A.jp_off[g];
+    const int64_t c0 = A.jc_slot > 0 ? g * A.jc_slot : A.jc_off[g];
     const double box = A.box;
     const double ibox = PERIODIC ? 1.0 / box : 0.0;
     const SplitK<R> K = split_k<R>(kSplit ? A.rs : 1.0);

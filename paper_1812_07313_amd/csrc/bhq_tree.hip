@@ -788,6 +788,19 @@ __global__ __launch_bounds__(kBlock) void k_compact(int64_t ng, const int64_t *o
     for (int64_t j = lane; j < n; j += 64) out[o + j] = src[j];
 }
 
+}  // namespace
+
+hipError_t launch_compact_lists(int64_t ng, const int64_t *off, const int32_t *slot,
+                                int64_t cap, int32_t *out, hipStream_t s)
+{
+    if (ng <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact, dim3(blocks(ng, kBlock / 64)), dim3(kBlock), 0, s, ng, off,
+                       slot, cap, out);
+    return hipGetLastError();
+}
+
+namespace {
+
 // ---- outputs -----------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_particles_out(const int32_t *idx, int64_t n,
@@ -1394,19 +1407,19 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
         max_p = std::max(max_p, O.h_jp_off[(size_t)g + 1] - O.h_jp_off[(size_t)g]);
         max_c = std::max(max_c, O.h_jc_off[(size_t)g + 1] - O.h_jc_off[(size_t)g]);
     }
-    STEP(O.jp_idx->reserve((size_t)std::max<int64_t>(njp, 1) * 4), "allocation");
-    STEP(O.jc_idx->reserve((size_t)std::max<int64_t>(njc, 1) * 4), "allocation");
     O.one_walk = slots && max_p <= P.cap_p && max_c <= P.cap_c;
+    O.slot_p = O.slot_c = 0;
     if (O.one_walk) {
-        // every group's entries are in its slots: compact them
-        const unsigned cb = blocks(ng, kBlock / 64);
-        hipLaunchKernelGGL(k_compact, dim3(cb), dim3(kBlock), 0, s, ng, O.jp_off->as<int64_t>(),
-                           B[T_JPSLOT].as<int32_t>(), P.cap_p, O.jp_idx->as<int32_t>());
-        LAUNCHED("compact");
-        hipLaunchKernelGGL(k_compact, dim3(cb), dim3(kBlock), 0, s, ng, O.jc_off->as<int64_t>(),
-                           B[T_JCSLOT].as<int32_t>(), P.cap_c, O.jc_idx->as<int32_t>());
-        LAUNCHED("compact");
+        // every group's entries are in its slot: the slots become the lists
+        // (the force kernel reads group g from g * slot size), and the old
+        // list arrays the slots of the next rebuild
+        std::swap(*O.jp_idx, B[T_JPSLOT]);
+        std::swap(*O.jc_idx, B[T_JCSLOT]);
+        O.slot_p = P.cap_p;
+        O.slot_c = P.cap_c;
     } else {
+        STEP(O.jp_idx->reserve((size_t)std::max<int64_t>(njp, 1) * 4), "allocation");
+        STEP(O.jc_idx->reserve((size_t)std::max<int64_t>(njc, 1) * 4), "allocation");
         W.jp_off = O.jp_off->as<int64_t>();
         W.jc_off = O.jc_off->as<int64_t>();
         W.jp_idx = O.jp_idx->as<int32_t>();
