@@ -169,7 +169,10 @@ int bhq_set_pool_cells(bhq_ctx *ctx, int64_t n, const double (*x)[3],
 /* Index lists: entries adr .. adr+n-1 of the j-particle (resp. j-cell)
  * lists, each an index into the particle (resp. cell) pool.  The pool must
  * be set first; every index is checked on the host (0 <= idx < pool size,
- * else BHQ_E_RANGE), so the kernels never read outside the pools. */
+ * else BHQ_E_RANGE), so the kernels never read outside the pools.  adr is a
+ * position in the compact lists (group g's entries from jp_off[g]).  Lists
+ * that a device rebuild left in per-group slots are first made compact;
+ * that waits for all work on the device. */
 int bhq_set_jp_idx(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx);
 int bhq_set_jc_idx(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx);
 

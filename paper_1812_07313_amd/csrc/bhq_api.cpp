@@ -123,7 +123,10 @@ struct bhq_ctx {
     std::string err;
 
     int64_t ng = -1, ni = 0, njp = 0, njc = 0;
+    // Host copies of the group offsets.  After a device build they are
+    // copied from the device arrays on first use (off_stale).
     std::vector<int64_t> i_off, jp_off, jc_off;
+    bool off_stale = false;
     DevArray arr[A_COUNT];
 
     bool have_i = false, have_jp = false, have_jc = false, have_t = false;
@@ -259,10 +262,36 @@ struct bhq_ctx {
         ++args_version;
         return BHQ_OK;
     }
+    // Make the host copies of the offsets current (after a device build the
+    // device arrays are complete when the build returns).
+    int host_offsets()
+    {
+        if (!off_stale) return BHQ_OK;
+        const int rc = select();
+        if (rc != BHQ_OK) return rc;
+        try {
+            for (auto *v : {&i_off, &jp_off, &jc_off}) v->resize((size_t)ng + 1);
+        } catch (const std::bad_alloc &) {
+            return fail(BHQ_E_NOMEM, "host copy of offsets");
+        }
+        const struct {
+            Arr a;
+            std::vector<int64_t> *v;
+        } cp[3] = {{A_IOFF, &i_off}, {A_JPOFF, &jp_off}, {A_JCOFF, &jc_off}};
+        for (const auto &c : cp) {
+            hipError_t e = hipMemcpy(c.v->data(), arr[c.a].p, ((size_t)ng + 1) * 8,
+                                     hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "offsets D2H");
+        }
+        off_stale = false;
+        return BHQ_OK;
+    }
     // Compute the slot table for the current groups and order mode and
     // upload it.
     int upload_order()
     {
+        const int rc = host_offsets();
+        if (rc != BHQ_OK) return rc;
         std::vector<int32_t> order;
         try {
             order = plan_order(ng, i_off.data(), jp_off.data(), jc_off.data(),
@@ -278,6 +307,30 @@ struct bhq_ctx {
         if (e != hipSuccess) return hip_fail(e, "order upload");
         nslots = (int64_t)order.size();
         ++args_version;
+        return BHQ_OK;
+    }
+    // Turn lists kept in per-group slots into compact lists at the offsets
+    // (before entries are written at compact addresses).  Waits for all
+    // work on the device first: a launch in flight may still read them.
+    int unslot_lists()
+    {
+        const struct {
+            Arr a, off;
+            int64_t *slot, cnt;
+        } lists[2] = {{A_JPIDX, A_JPOFF, &list_slot_p, njp}, {A_JCIDX, A_JCOFF, &list_slot_c, njc}};
+        for (const auto &l : lists) {
+            if (*l.slot <= 0) continue;
+            hipError_t e = hipDeviceSynchronize();
+            if (e == hipSuccess) e = arr[A_SORTSCRATCH].reserve((size_t)std::max<int64_t>(l.cnt, 1) * 4);
+            if (e == hipSuccess)
+                e = bhq::launch_compact_lists(ng, arr[l.off].as<int64_t>(), arr[l.a].as<int32_t>(),
+                                              *l.slot, arr[A_SORTSCRATCH].as<int32_t>(), nullptr);
+            if (e == hipSuccess) e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "list compaction");
+            std::swap(arr[l.a], arr[A_SORTSCRATCH]);
+            *l.slot = 0;
+            ++args_version;
+        }
         return BHQ_OK;
     }
     // Copy a compact index list (cnt entries, group offsets in device array
@@ -511,6 +564,7 @@ int bhq_set_groups(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
         ctx->i_off.assign(i_off, i_off + ng + 1);
         ctx->jp_off.assign(jp_off, jp_off + ng + 1);
         ctx->jc_off.assign(jc_off, jc_off + ng + 1);
+        ctx->off_stale = false;
     } catch (const std::bad_alloc &) {
         ctx->ng = -1;
         return ctx->fail(BHQ_E_NOMEM, "host copy of offsets");
@@ -932,6 +986,7 @@ static int set_idx(bhq_ctx *ctx, Arr a, int64_t total, int64_t pool,
     TRY(ctx->select());
     TRY(ctx->use_indexed());
     if (n == 0) return BHQ_OK;
+    TRY(ctx->unslot_lists());
     hipError_t e = hipMemcpy(ctx->arr[a].as<int32_t>() + adr, idx,
                              (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice);
     return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "hipMemcpy H2D");
@@ -987,6 +1042,10 @@ int bhq_get_counts(const bhq_ctx *ctx, int64_t *n_pp, int64_t *n_pc)
 {
     if (!ctx || !n_pp || !n_pc) return BHQ_E_ARG;
     if (ctx->ng < 0) return BHQ_E_STATE;
+    // the host offsets are a cache of the device arrays: filling it leaves
+    // the context's state unchanged
+    const int rc = const_cast<bhq_ctx *>(ctx)->host_offsets();
+    if (rc != BHQ_OK) return rc;
     int64_t pp = 0, pc = 0;
     for (int64_t g = 0; g < ctx->ng; ++g) {
         const int64_t nig = ctx->i_off[(size_t)g + 1] - ctx->i_off[(size_t)g];
@@ -1237,7 +1296,7 @@ static int device_build(bhq_ctx *ctx, int64_t nsys, const int64_t *sys_off,
     P.cap_c = ctx->walk_cap_c;
     P.spec_levels = ctx->tree_levels;
     P.spec_cells = ctx->tree_cells;
-    P.slot_bytes = ctx->ng >= 0 ? 16 * (ctx->njp + ctx->njc) + ((int64_t)256 << 20) : 0;
+    P.slot_bytes = ctx->ng >= 0 ? bhq::slot_memory_bound(ctx->njp, ctx->njc) : 0;
     bhq::TreeOut O;
     O.i_off = &ctx->arr[A_IOFF];
     O.jp_off = &ctx->arr[A_JPOFF];
@@ -1272,18 +1331,9 @@ static int device_build(bhq_ctx *ctx, int64_t nsys, const int64_t *sys_off,
         hipError_t e = ctx->arr[q.a].reserve(q.bytes);
         if (e != hipSuccess) return ctx->hip_fail(e, "hipMalloc");
     }
-    ctx->i_off.swap(O.h_i_off);
-    ctx->jp_off.swap(O.h_jp_off);
-    ctx->jc_off.swap(O.h_jc_off);
-    // slot sizes for the next rebuild: 1.25 times the longest lists plus 32;
-    // kept while that stays within [3/4, 1] of the current size, so that the
-    // slot memory keeps its size from step to step
-    auto next_cap = [](int64_t cur, int64_t longest) {
-        const int64_t want = longest + longest / 4 + 32;
-        return (want <= cur && 4 * want >= 3 * cur) ? cur : want;
-    };
-    ctx->walk_cap_p = next_cap(ctx->walk_cap_p, O.max_p);
-    ctx->walk_cap_c = next_cap(ctx->walk_cap_c, O.max_c);
+    ctx->off_stale = true;
+    ctx->walk_cap_p = bhq::next_slot_cap(ctx->walk_cap_p, O.max_p);
+    ctx->walk_cap_c = bhq::next_slot_cap(ctx->walk_cap_c, O.max_c);
     ctx->tree_levels = O.nlevels;
     ctx->tree_cells = O.ncell;
     ctx->build_info[0] = O.one_walk ? 1 : 0;
@@ -1384,6 +1434,7 @@ int bhq_get_lists(bhq_ctx *ctx, int64_t *i_idx, int64_t *i_off,
                                       "known for lists set entry by entry");
     TRY(ctx->select());
     if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
+    TRY(ctx->host_offsets());
     const size_t ng1 = (size_t)ctx->ng + 1;
     if (i_off) std::memcpy(i_off, ctx->i_off.data(), ng1 * 8);
     if (jp_off) std::memcpy(jp_off, ctx->jp_off.data(), ng1 * 8);

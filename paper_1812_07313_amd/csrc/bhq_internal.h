@@ -205,13 +205,30 @@ struct TreeParams {
     int64_t spec_cells = 0;
 };
 
+// Slot sizing of one-walk rebuilds.  A group's slot holds 1.25 times the
+// longest list of the previous build plus 32 entries; the current size is
+// kept while that stays within [3/4, 1] of it, so that the slot memory
+// keeps its size from step to step.
+inline int64_t next_slot_cap(int64_t cur, int64_t longest)
+{
+    const int64_t want = longest + longest / 4 + 32;
+    return (want <= cur && 4 * want >= 3 * cur) ? cur : want;
+}
+
+// Memory the slots of a rebuild may take (bytes): 4 times that of the
+// previous build's lists plus 256 MiB.
+inline int64_t slot_memory_bound(int64_t njp, int64_t njc)
+{
+    return 16 * (njp + njc) + ((int64_t)256 << 20);
+}
+
 // Builder working memory, kept between builds of one context.
 enum TreeBuf {
     T_KEY, T_KEY2, T_IDX0, T_SORT, T_BBOX, T_FLAG,
     T_CX, T_CY, T_CZ, T_SIDE, T_FIRST, T_COUNT, T_CHILD0, T_NCHILD, T_PARENT,
     T_DEPTH, T_CKEY, T_NCH, T_NOFF, T_GSTART, T_GROUPS, T_NSEL, T_WC, T_WL,
     T_JPCNT, T_JCCNT, T_CSYS, T_SYSOFF, T_SYSOFF32, T_ROOTS, T_SYSROOT, T_LSC, T_PERM,
-    T_JPSLOT, T_JCSLOT, T_GBOX, T_LV,
+    T_JPSLOT, T_JCSLOT, T_GBOX, T_LV, T_STATS,
     T_COUNT_
 };
 
@@ -228,9 +245,8 @@ struct TreeOut {
     DevArray *order;                          // int32 [n]: input index of
                                               // tree position k
     DevArray *buf;                            // [T_COUNT_] working memory
-    // sizes and host copies of the offsets, set on success
+    // sizes, set on success (the offsets themselves stay on the device)
     int64_t ng = 0, njp = 0, njc = 0, ncell = 0;
-    std::vector<int64_t> h_i_off, h_jp_off, h_jc_off;
     // longest particle and cell list of a group; whether one walk sufficed
     int64_t max_p = 0, max_c = 0;
     bool one_walk = false;

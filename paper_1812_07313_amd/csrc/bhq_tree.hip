@@ -788,6 +788,16 @@ __global__ __launch_bounds__(kBlock) void k_compact(int64_t ng, const int64_t *o
     for (int64_t j = lane; j < n; j += 64) out[o + j] = src[j];
 }
 
+// stats[0], stats[1] = list totals (the scans' last entries), stats[4] =
+// the walk's overflow flag; stats[2], stats[3] hold the longest lists.
+__global__ void k_list_stats(int64_t ng, const int64_t *jp_off, const int64_t *jc_off,
+                             const int *flag, int64_t *stats)
+{
+    stats[0] = jp_off[ng];
+    stats[1] = jc_off[ng];
+    stats[4] = *flag;
+}
+
 }  // namespace
 
 hipError_t launch_compact_lists(int64_t ng, const int64_t *off, const int32_t *slot,
@@ -945,7 +955,6 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
         what = "eps2 must be finite and > 0";
         return fail();
     }
-    int hflag = 0;
     STEP(B[T_SYSOFF].reserve((size_t)(nsys + 1) * 8), "allocation");
     STEP(B[T_SYSOFF32].reserve((size_t)(nsys + 1) * 4), "allocation");
     STEP(hipMemcpyAsync(B[T_SYSOFF].p, P.sys_off, (size_t)(nsys + 1) * 8,
@@ -1379,34 +1388,32 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
         STEP(hipcub::DeviceScan::ExclusiveSum(B[T_SORT].p, st, cnt, off, (int)(ng + 1), s),
              "scan");
     }
-    try {
-        O.h_jp_off.resize((size_t)ng + 1);
-        O.h_jc_off.resize((size_t)ng + 1);
-        O.h_i_off.resize((size_t)ng + 1);
-    } catch (const std::bad_alloc &) {
-        code = BHQ_E_NOMEM;
-        what = "host offsets";
-        return fail();
+    // list totals, longest lists and the walk's overflow flag: the host
+    // needs only these five numbers (the offsets stay on the device)
+    STEP(B[T_STATS].reserve(8 * sizeof(int64_t)), "allocation");
+    int64_t *stats = B[T_STATS].as<int64_t>();
+    for (int pass = 0; pass < 2; ++pass) {
+        const int64_t *cnt = pass ? B[T_JCCNT].as<int64_t>() : B[T_JPCNT].as<int64_t>();
+        size_t st = 0;
+        STEP(hipcub::DeviceReduce::Max(nullptr, st, cnt, stats + 2 + pass, (int)ng, s),
+             "reduce size");
+        STEP(B[T_SORT].reserve(std::max(st, B[T_SORT].cap)), "allocation");
+        STEP(hipcub::DeviceReduce::Max(B[T_SORT].p, st, cnt, stats + 2 + pass, (int)ng, s),
+             "reduce");
     }
-    STEP(hipMemcpyAsync(O.h_jp_off.data(), O.jp_off->p, (size_t)(ng + 1) * 8,
-                        hipMemcpyDeviceToHost, s),
-         "copy");
-    STEP(hipMemcpyAsync(O.h_jc_off.data(), O.jc_off->p, (size_t)(ng + 1) * 8,
-                        hipMemcpyDeviceToHost, s),
-         "copy");
-    STEP(hipMemcpyAsync(&hflag, B[T_FLAG].p, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    hipLaunchKernelGGL(k_list_stats, dim3(1), dim3(1), 0, s, ng, O.jp_off->as<int64_t>(),
+                       O.jc_off->as<int64_t>(), B[T_FLAG].as<int>(), stats);
+    LAUNCHED("list totals");
+    int64_t hstats[5] = {0, 0, 0, 0, 0};
+    STEP(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s), "copy");
     STEP(hipStreamSynchronize(s), "sync");
-    if (hflag) {
+    if (hstats[4]) {
         code = BHQ_E_RANGE;
         what = "walk stack overflow";
         return fail();
     }
-    const int64_t njp = O.h_jp_off[(size_t)ng], njc = O.h_jc_off[(size_t)ng];
-    int64_t max_p = 0, max_c = 0;
-    for (int64_t g = 0; g < ng; ++g) {
-        max_p = std::max(max_p, O.h_jp_off[(size_t)g + 1] - O.h_jp_off[(size_t)g]);
-        max_c = std::max(max_c, O.h_jc_off[(size_t)g + 1] - O.h_jc_off[(size_t)g]);
-    }
+    const int64_t njp = hstats[0], njc = hstats[1];
+    const int64_t max_p = hstats[2], max_c = hstats[3];
     O.one_walk = slots && max_p <= P.cap_p && max_c <= P.cap_c;
     O.slot_p = O.slot_c = 0;
     if (O.one_walk) {
@@ -1418,8 +1425,17 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
         O.slot_p = P.cap_p;
         O.slot_c = P.cap_c;
     } else {
-        STEP(O.jp_idx->reserve((size_t)std::max<int64_t>(njp, 1) * 4), "allocation");
-        STEP(O.jc_idx->reserve((size_t)std::max<int64_t>(njc, 1) * 4), "allocation");
+        // The list arrays trade places with the slots on the next one-walk
+        // rebuild, so they are given the size of its slots where those will
+        // be used: then neither needs to grow again.
+        int64_t want_p = njp, want_c = njc;
+        const int64_t np2 = next_slot_cap(P.cap_p, max_p), nc2 = next_slot_cap(P.cap_c, max_c);
+        if ((double)ng * (double)(np2 + nc2) * 4.0 <= (double)slot_memory_bound(njp, njc)) {
+            want_p = std::max(want_p, ng * np2);
+            want_c = std::max(want_c, ng * nc2);
+        }
+        STEP(O.jp_idx->reserve((size_t)std::max<int64_t>(want_p, 1) * 4), "allocation");
+        STEP(O.jc_idx->reserve((size_t)std::max<int64_t>(want_c, 1) * 4), "allocation");
         W.jp_off = O.jp_off->as<int64_t>();
         W.jc_off = O.jc_off->as<int64_t>();
         W.jp_idx = O.jp_idx->as<int32_t>();
@@ -1449,9 +1465,6 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
                        groups, ng, n, O.i_off->as<int64_t>(), O.gcx->as<double>(),
                        O.gcy->as<double>(), O.gcz->as<double>());
     LAUNCHED("groups");
-    STEP(hipMemcpyAsync(O.h_i_off.data(), O.i_off->p, (size_t)(ng + 1) * 8,
-                        hipMemcpyDeviceToHost, s),
-         "copy");
     STEP(hipStreamSynchronize(s), "sync");
     O.ng = ng;
     O.njp = njp;

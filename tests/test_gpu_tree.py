@@ -253,6 +253,39 @@ def test_rebuild_one_walk_and_overflow():
         bhq.bhq_destroy(ctx)
 
 
+def test_partial_list_update_after_rebuild():
+    """bhq_set_jp_idx and bhq_set_jc_idx after a rebuild (whose lists stay in
+    per-group slots) write at compact list addresses, as after a first
+    build: the lists and the forces equal, bit for bit, those of a context
+    built once with the same entries overwritten."""
+    x, m = synth.plummer(20000, synth.rng(31))
+    xt, mt = _dev(x, m)
+    got = []
+    for builds in (1, 2):
+        log("case partial list update after %d device builds" % builds)
+        ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+        try:
+            for _ in range(builds):
+                bhq.bhq_build_lists_device(ctx, xt, mt, 0.6, 64, 8, 0.0, 0.0)
+            assert bhq.bhq_get_build_info(ctx)[0] == (builds == 2)
+            ng, njp, njc, _ = bhq.bhq_get_lists_sizes(ctx)
+            # pool indices 0..k-1 into the middle of the lists, across groups
+            bhq.bhq_set_jp_idx(ctx, njp // 3, np.arange(200, dtype=np.int32))
+            bhq.bhq_set_jc_idx(ctx, njc // 2, np.arange(150, dtype=np.int32)[::-1].copy())
+            bhq.bhq_set_eps(ctx, 0.01)
+            bhq.bhq_compute(ctx)
+            a, p = bhq.bhq_get_result(ctx, len(m))
+            got.append((bhq.bhq_get_lists(ctx, len(m)), a, p))
+        finally:
+            bhq.bhq_destroy(ctx)
+    (l1, a1, p1), (l2, a2, p2) = got
+    for k in ("i_idx", "i_off", "jp_off", "jp_idx", "jc_off", "jc_cell"):
+        assert np.array_equal(l1[k], l2[k]), k
+    assert np.array_equal(l2["jc_cell"][njc // 2:njc // 2 + 150], np.arange(150)[::-1])
+    assert np.array_equal(a1.view(np.int64), a2.view(np.int64))
+    assert np.array_equal(p1.view(np.int64), p2.view(np.int64))
+
+
 def _batch(systems):
     sizes = np.array([len(s[1]) for s in systems])
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
