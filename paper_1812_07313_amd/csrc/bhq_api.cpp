@@ -16,7 +16,7 @@
 
 #include "bhq.h"
 #include "bhq_internal.h"
-#include "erfcx_fit.h"
+#include "split_table.h"
 
 using bhq::DevArray;
 
@@ -699,10 +699,10 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
     if (split && !ctx->have_split)
         return ctx->fail(BHQ_E_STATE, "split kernel without bhq_set_split");
     if (split && ctx->precision == BHQ_FP32_OFS64 &&
-        ctx->rcut > 2.0 * (double)bhq::kErfcxDomain * ctx->rs)
+        ctx->rcut > 2.0 * (double)bhq::kSplitDomain * ctx->rs)
         return ctx->fail(BHQ_E_ARG, "FP32 split kernels need rcut <= %g rs "
                          "(the range of their erfc evaluation); use BHQ_FP64",
-                         2.0 * (double)bhq::kErfcxDomain);
+                         2.0 * (double)bhq::kSplitDomain);
     if (!split && ctx->eps_mode == 0)
         return ctx->fail(BHQ_E_STATE, "compute before set_eps / set_eps2_i");
     TRY(ctx->select());

@@ -36,7 +36,9 @@
 #include <hip/hip_runtime.h>
 
 #include "bhq_internal.h"
-#include "erfcx_fit.h"
+#include "split_table.h"
+
+#include <type_traits>
 
 namespace bhq {
 
@@ -109,137 +111,112 @@ __device__ __forceinline__ void pc_quad(const V4<R> &a, const V4<R> &b,
     az = fma(-rinv5, qz, az);
 }
 
-// Constants of the Gaussian split, uniform over a launch: with
-// u = r / (2 r_s), i2rs = 1 / (2 r_s).
+// Constants of the Gaussian split, uniform over a launch: u = r i2rs with
+// i2rs = 1 / (2 r_s); the FP32 table variable is t = r ct = u N / U.
 template <typename R>
 struct SplitK {
-    R i2rs, i2rs2;  // 1 / (2 r_s) and its square
-    R cs;           // i2rs * 2 / kErfcxDomain: s = r cs - 1 (FP32 fit variable)
-    R cg;           // i2rs * 2 / sqrt(pi): 2u/sqrt(pi) = r cg
-    R ch;           // i2rs * 4 / sqrt(pi): 4u^3/sqrt(pi) = r u^2 ch
+    R i2rs;
+    R ct;
 };
 
 template <typename R>
 __device__ __forceinline__ SplitK<R> split_k(double rs)
 {
-    constexpr double k2rsqpi = 1.1283791670955126;  // 2 / sqrt(pi)
     SplitK<R> K;
     const double i2rs = 0.5 / rs;
     K.i2rs = R(i2rs);
-    K.i2rs2 = R(i2rs * i2rs);
-    K.cs = R(i2rs * (2.0 / (double)kErfcxDomain));
-    K.cg = R(i2rs * k2rsqpi);
-    K.ch = R(i2rs * (2.0 * k2rsqpi));
+    K.ct = R(i2rs * ((double)kSplitIntervals / (double)kSplitDomain));
     return K;
 }
 
+// The FP32 table of the split radial functions (split_table.h) in device
+// memory, one V4 {c0, c1, c2, c3} per function and interval; each block of
+// a split kernel copies it to LDS, where lanes read their own intervals.
+struct SplitTab {
+    V4<float> v[kSplitFuncs * kSplitEntries];
+};
+
+constexpr SplitTab make_split_tab()
+{
+    SplitTab t{};
+    for (int f = 0; f < kSplitFuncs; ++f)
+        for (int q = 0; q < kSplitEntries; ++q)
+            t.v[f * kSplitEntries + q] = {kSplitTable[f][q][0], kSplitTable[f][q][1],
+                                          kSplitTable[f][q][2], kSplitTable[f][q][3]};
+    return t;
+}
+
+__device__ const SplitTab kSplitTabDev = make_split_tab();
+
 // Gaussian-split radial functions at r (r2 = r^2), u = r / (2 r_s):
 //   ec = erfc(u), g = erfc(u) + (2u/sqrt(pi)) e^{-u^2},
-//   h = (4u^3/sqrt(pi)) e^{-u^2}, k = 2 u^2 h = (8 u^5 / sqrt(pi)) e^{-u^2}.
+//   G2 = 3g + h, G3 = 15g + 5h + k, with h = (4u^3/sqrt(pi)) e^{-u^2} and
+//   k = 2 u^2 h (G2, G3 only for cells with the quadrupole).
+// FP64 evaluates them from the library's erfc and exp.  FP32 reads the
+// piecewise cubics of the table at t = r ct: interval q = floor(t), local
+// variable f = t - q, Horner's rule (valid for u up to kSplitDomain and one
+// interval beyond; the host refuses FP32 split kernels with a longer
+// cutoff).
 template <typename R>
-struct SplitF {
-    R ec, g, h, k;
+struct SplitG {
+    R ec, g, g2, g3;
 };
 
-template <typename R>
-__device__ __forceinline__ SplitF<R> split_f(R r, R r2, const SplitK<R> &K)
+__device__ __forceinline__ float horner(const V4<float> &c, float f)
 {
-    const R rsqpi = R(0.56418958354775628694807945156);
-    const R u = r * K.i2rs;
-    const R u2 = u * u;
-    const R e = exp_r(-u2) * rsqpi;
-    SplitF<R> f;
-    f.ec = erfc_r(u);
-    f.g = fma(R(2) * u, e, f.ec);
-    f.h = R(4) * u * u2 * e;
-    f.k = R(2) * u2 * f.h;
-    return f;
+    return fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
 }
 
-// FP32: E = exp(-u^2) from the hardware base-2 exponential, with the
-// rounding error of the product u^2 * log2(e) fed back to first order, and
-// erfcx(u) = exp(u^2) erfc(u) from a fitted polynomial X in s = r cs - 1
-// (erfcx_fit.h, valid for u <= kErfcxDomain; the host refuses FP32 split
-// kernels whose cutoff reaches beyond it).  u^2 is formed from r^2, and
-// the factors 1 / (2 r_s) are folded into the constants, so u itself is
-// never needed.  t = X + 2u/sqrt(pi), so that erfc(u) = E X and g = E t.
-struct SplitEX {
-    float E, X, t, u2;
-};
-
-__device__ __forceinline__ SplitEX split_ex(float r, float r2, const SplitK<float> &K)
+template <typename R, bool CELL>
+__device__ __forceinline__ SplitG<R> split_g(R r, const SplitK<R> &K, const V4<float> *tab)
 {
-    constexpr float kLog2e = 1.4426950408889634f;
-    constexpr float kLn2 = 0.6931471805599453f;
-    SplitEX v;
-    v.u2 = r2 * K.i2rs2;
-    const float a = v.u2 * -kLog2e;
-    const float da = fmaf(v.u2, -kLog2e, -a);
-    const float E = __builtin_amdgcn_exp2f(a);
-    v.E = fmaf(E, da * kLn2, E);
-    const float s = fmaf(r, K.cs, -1.0f);
-    float X = kErfcxCoef[kErfcxDegree];
-#pragma unroll
-    for (int k = kErfcxDegree - 1; k >= 0; --k) X = fmaf(X, s, kErfcxCoef[k]);
-    v.X = X;
-    v.t = fmaf(r, K.cg, X);
-    return v;
-}
-
-template <>
-__device__ __forceinline__ SplitF<float> split_f<float>(float r, float r2,
-                                                        const SplitK<float> &K)
-{
-    const SplitEX v = split_ex(r, r2, K);
-    SplitF<float> f;
-    f.ec = v.E * v.X;
-    f.g = v.E * v.t;
-    f.h = (r * v.u2) * K.ch * v.E;
-    f.k = 2.0f * v.u2 * f.h;
-    return f;
+    SplitG<R> s;
+    if constexpr (std::is_same<R, float>::value) {
+        const float t = r * K.ct;
+        const int q = (int)t;  // t >= 0
+        const float f = __builtin_amdgcn_fractf(t);
+        s.ec = horner(tab[q], f);
+        s.g = horner(tab[kSplitEntries + q], f);
+        if (CELL) {
+            s.g2 = horner(tab[2 * kSplitEntries + q], f);
+            s.g3 = horner(tab[3 * kSplitEntries + q], f);
+        }
+    } else {
+        const R rsqpi = R(0.56418958354775628694807945156);
+        const R u = r * K.i2rs;
+        const R u2 = u * u;
+        const R e = exp_r(-u2) * rsqpi;
+        s.ec = erfc_r(u);
+        s.g = fma(R(2) * u, e, s.ec);
+        if (CELL) {
+            const R h = R(4) * u * u2 * e;
+            const R k = R(2) * u2 * h;
+            s.g2 = fma(R(3), s.g, h);
+            s.g3 = fma(R(15), s.g, fma(R(5), h, k));
+        }
+    }
+    return s;
 }
 
 // Short-range particle: a += m g/r^3 d, -phi += m erfc(u)/r; masked at
 // r == 0 and r >= rcut.
 template <typename R>
 __device__ __forceinline__ void pp_split(const V4<R> &j, R xi, R yi, R zi,
-                                         const SplitK<R> &K, R rcut2, R &ax, R &ay, R &az,
-                                         R &pt)
+                                         const SplitK<R> &K, const V4<float> *tab, R rcut2,
+                                         R &ax, R &ay, R &az, R &pt)
 {
     const R dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
     const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     if (r2 > R(0) && r2 < rcut2) {
         const R rinv = rsq(r2);
         const R r = r2 * rinv;
-        const SplitF<R> f = split_f(r, r2, K);
+        const SplitG<R> f = split_g<R, false>(r, K, tab);
         const R mr = j.w * rinv;
         const R c = mr * f.g * (rinv * rinv);
         pt = fma(mr, f.ec, pt);
         ax = fma(c, dx, ax);
         ay = fma(c, dy, ay);
         az = fma(c, dz, az);
-    }
-}
-
-// FP32: with w = m E / r, -phi += w X and a += w t / r^2 d.
-template <>
-__device__ __forceinline__ void pp_split<float>(const V4<float> &j, float xi, float yi,
-                                                float zi, const SplitK<float> &K,
-                                                float rcut2, float &ax, float &ay,
-                                                float &az, float &pt)
-{
-    const float dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
-    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    if (r2 > 0.0f && r2 < rcut2) {
-        const float rinv = rsq(r2);
-        const float r = r2 * rinv;
-        const SplitEX v = split_ex(r, r2, K);
-        const float w = j.w * rinv * v.E;
-        const float c = w * v.t * (rinv * rinv);
-        pt = fmaf(w, v.X, pt);
-        ax = fmaf(c, dx, ax);
-        ay = fmaf(c, dy, ay);
-        az = fmaf(c, dz, az);
     }
 }
 
@@ -251,8 +228,8 @@ __device__ __forceinline__ void pp_split<float>(const V4<float> &j, float xi, fl
 template <typename R, bool QUAD>
 __device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b,
                                          const V4<R> &c, R xi, R yi, R zi,
-                                         const SplitK<R> &K, R rcut2, R &ax, R &ay, R &az,
-                                         R &pt)
+                                         const SplitK<R> &K, const V4<float> *tab, R rcut2,
+                                         R &ax, R &ay, R &az, R &pt)
 {
     const R dx = a.x - xi, dy = a.y - yi, dz = a.z - zi;
     const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
@@ -260,14 +237,14 @@ __device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b,
         const R rinv = rsq(r2);
         const R r = r2 * rinv;
         const R rinv2 = rinv * rinv;
-        const SplitF<R> f = split_f(r, r2, K);
+        const SplitG<R> f = split_g<R, QUAD>(r, K, tab);
         const R D1 = f.g * rinv2 * rinv;
         R phi = -a.w * f.ec * rinv;  // M Phi
         R coef = a.w * D1;
         if (QUAD) {
             const R rinv5 = rinv2 * rinv2 * rinv;
-            const R D2 = -fma(R(3), f.g, f.h) * rinv5;
-            const R D3 = fma(R(15), f.g, fma(R(5), f.h, f.k)) * rinv5 * rinv2;
+            const R D2 = -f.g2 * rinv5;
+            const R D3 = f.g3 * rinv5 * rinv2;
             const R qx = fma(b.z, dz, fma(b.y, dy, b.x * dx));
             const R qy = fma(c.x, dz, fma(b.w, dy, b.y * dx));
             const R qz = fma(c.y, dz, fma(c.x, dy, b.z * dx));
@@ -314,10 +291,11 @@ struct Smem {
 
 // Evaluate group g with a block of BS threads, each owning IB i-particles;
 // sa, sb, sc are LDS tiles of BS entries (sb, sc only for the quadrupole
-// kinds).
+// kinds); tab is the FP32 split table in LDS (FP32 split kinds only).
 template <typename R, int KIND, bool PERIODIC, int BS, int IB>
 __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
-                                              V4<R> *sa, V4<R> *sb, V4<R> *sc)
+                                              V4<R> *sa, V4<R> *sb, V4<R> *sc,
+                                              const V4<float> *tab)
 {
     constexpr bool kSplit = (KIND == kSplitQuad || KIND == kSplitMono);
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
@@ -409,7 +387,7 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
 #pragma unroll
                     for (int u = 0; u < IB; ++u) {
                         if (kSplit)
-                            pp_split(jv, xi[u], yi[u], zi[u], K, rcut2, bx[u],
+                            pp_split(jv, xi[u], yi[u], zi[u], K, tab, rcut2, bx[u],
                                      by[u], bz[u], bp[u]);
                         else
                             pp_plummer(jv, xi[u], yi[u], zi[u], e2[u], bx[u],
@@ -508,11 +486,11 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                                        by[u], bz[u], bp[u]);
                         else if (KIND == kSplitQuad)
                             pc_split<R, true>(ja, jb, jc, xi[u], yi[u], zi[u],
-                                              K, rcut2, bx[u], by[u], bz[u],
+                                              K, tab, rcut2, bx[u], by[u], bz[u],
                                               bp[u]);
                         else
                             pc_split<R, false>(ja, jb, jc, xi[u], yi[u], zi[u],
-                                               K, rcut2, bx[u], by[u], bz[u],
+                                               K, tab, rcut2, bx[u], by[u], bz[u],
                                                bp[u]);
                     }
                 }
@@ -559,6 +537,25 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
     }
 }
 
+// The FP32 split kinds keep the table of their radial functions in LDS.
+template <typename R, int KIND>
+constexpr int split_tab_size()
+{
+    return std::is_same<R, float>::value && (KIND == kSplitQuad || KIND == kSplitMono)
+               ? kSplitFuncs * kSplitEntries
+               : 1;
+}
+
+template <typename R, int KIND, int BS>
+__device__ __forceinline__ void load_split_tab(V4<float> *tab)
+{
+    if (split_tab_size<R, KIND>() > 1) {
+        for (int k = threadIdx.x; k < kSplitFuncs * kSplitEntries; k += BS)
+            tab[k] = kSplitTabDev.v[k];
+        __syncthreads();
+    }
+}
+
 template <typename R, int KIND, bool PERIODIC, int BS, int IB>
 __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel(const ForceArgs A)
 {
@@ -566,9 +563,11 @@ __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel(const ForceArgs
     __shared__ V4<R> sa[BS];
     __shared__ V4<R> sb[kCellQ ? BS : 1];
     __shared__ V4<R> sc[kCellQ ? BS : 1];
+    __shared__ V4<float> st[split_tab_size<R, KIND>()];
     const int64_t g = A.order ? A.order[blockIdx.x] : (int64_t)blockIdx.x;
     if (g < 0) return;  // empty slot (uniform over the block)
-    process_group<R, KIND, PERIODIC, BS, IB>(A, g, sa, sb, sc);
+    load_split_tab<R, KIND, BS>(st);
+    process_group<R, KIND, PERIODIC, BS, IB>(A, g, sa, sb, sc, st);
 }
 
 // Id of the XCD this wave runs on (hardware register XCC_ID, bits 3:0).
@@ -592,7 +591,9 @@ __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(cons
     __shared__ V4<R> sa[BS];
     __shared__ V4<R> sb[kCellQ ? BS : 1];
     __shared__ V4<R> sc[kCellQ ? BS : 1];
+    __shared__ V4<float> st[split_tab_size<R, KIND>()];
     __shared__ int64_t next;
+    load_split_tab<R, KIND, BS>(st);
     const int nq = A.xcds > 0 ? A.xcds : 1;
     const int64_t per_q = A.nslots / nq;  // nslots is a multiple of nq
     const int home = A.xcds > 0 ? xcd_id() % nq : 0;
@@ -606,7 +607,7 @@ __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(cons
             if (k >= per_q) break;
             const int64_t slot = k * nq + q;
             const int64_t g = A.order ? A.order[slot] : slot;
-            if (g >= 0) process_group<R, KIND, PERIODIC, BS, IB>(A, g, sa, sb, sc);
+            if (g >= 0) process_group<R, KIND, PERIODIC, BS, IB>(A, g, sa, sb, sc, st);
         }
     }
 }

@@ -1,0 +1,73 @@
+"""The table the FP32 split kernels use for the Gaussian-split radial
+functions (csrc/split_table.h): its piecewise cubics, evaluated in FP32 as
+the kernels do (interval q = floor(t), f = t - q, Horner's rule with fused
+multiply-adds emulated exactly), match the functions computed from scipy's
+erfc and numpy's exp to 3e-7 relative on 0 <= u <= 2.5, its first entries
+reproduce erfc(0) = 1, g(0) = 1, G2(0) = 3, G3(0) = 15, and the header
+matches its generator."""
+import importlib.util
+import os
+import re
+
+import numpy as np
+from scipy import special
+
+from conftest import ROOT
+
+CSRC = os.path.join(ROOT, "paper_1812_07313_amd", "csrc")
+
+
+def _header():
+    with open(os.path.join(CSRC, "split_table.h")) as f:
+        text = f.read()
+    dom = float(re.search(r"kSplitDomain = ([0-9.]+)f", text).group(1))
+    n = int(re.search(r"kSplitIntervals = (\d+);", text).group(1))
+    body = text[text.index("kSplitTable["):]
+    vals = [float(v) for v in re.findall(r"([-+0-9.]+e[-+0-9]+)f", body)]
+    return dom, n, np.array(vals, np.float32).reshape(4, n + 1, 4)
+
+
+def _reference(u):
+    """ec, g, G2, G3 written out from their definitions (FP64)."""
+    c = 2.0 / np.sqrt(np.pi)
+    E = np.exp(-u * u)
+    ec = special.erfc(u)
+    g = ec + c * u * E
+    h = 2.0 * c * u ** 3 * E
+    k = 2.0 * u * u * h
+    return ec, g, 3.0 * g + h, 15.0 * g + 5.0 * h + k
+
+
+def _fma32(a, b, c):
+    # a*b + c of FP32 values is exact in FP64 up to one rounding
+    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(np.float32)
+
+
+def test_table_accuracy_fp32():
+    dom, n, tab = _header()
+    assert dom == 2.5 and n == 128
+    t = np.linspace(0.0, n * (1.0 + 1e-6), 300001).astype(np.float32)
+    q = np.floor(t).astype(np.int64)
+    f = (t - q).astype(np.float32)  # exact in FP32
+    u = t.astype(np.float64) * (dom / n)
+    for j, ref in enumerate(_reference(u)):
+        c = tab[j][q]
+        acc = c[:, 3]
+        for k in (2, 1, 0):
+            acc = _fma32(acc, f, c[:, k])
+        assert np.max(np.abs(acc / ref - 1.0)) < 3e-7, j
+
+
+def test_table_at_zero():
+    _, _, tab = _header()
+    assert list(tab[:, 0, 0]) == [1.0, 1.0, 3.0, 15.0]
+
+
+def test_header_matches_generator():
+    spec = importlib.util.spec_from_file_location(
+        "gen", os.path.join(CSRC, "gen_split_table.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    _, _, tab = _header()
+    # the header holds the generator's FP64 coefficients rounded to FP32
+    np.testing.assert_allclose(tab, gen.table(), rtol=1.2e-7, atol=0)
