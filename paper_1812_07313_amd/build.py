@@ -22,9 +22,11 @@ ARCH = os.environ.get("BHQ_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["bhq_kernels.hip", "bhq_tree.hip", "bhq_integrate.hip", "bhq_pm.hip",
            "bhq_order.hip", "bhq_api.cpp", "bhq_lists.cpp"]
 # the tree builders take their floating-point decisions with the same
-# operations on host and device, and the leapfrog updates round like plain
-# FP64 arithmetic: no fused multiply-adds there
-NO_CONTRACT = {"bhq_tree.hip", "bhq_lists.cpp", "bhq_integrate.hip", "bhq_order.hip"}
+# operations on host and device, the leapfrog updates round like plain
+# FP64 arithmetic, and the particle-mesh kernels must find a particle's
+# mesh cell with the same bits in every kernel: no fused multiply-adds there
+NO_CONTRACT = {"bhq_tree.hip", "bhq_lists.cpp", "bhq_integrate.hip", "bhq_order.hip",
+               "bhq_pm.hip"}
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 

@@ -10,7 +10,10 @@
 //      at integer multiples of h): the particles are radix-sorted by their
 //      nearest mesh point, and one thread per mesh point sums, in a fixed
 //      order, the particles of the 27 cells around it (no atomics: the
-//      result is the same bits every run);
+//      result is the same bits every run).  A block takes a tile of
+//      2 x 8 x 16 mesh points and first copies the particles of the tile's
+//      cells and their neighbours (720 cells) to LDS, so that each particle
+//      is read from memory about twice instead of 27 times;
 //   2. forward real-to-complex FFT (hipFFT);
 //   3. one thread per complex mode: phi(k) = G(k) rho(k) with
 //      G = -4 pi exp(-k^2 r_s^2) / k^2 / W(k)^2, W = prod_a sinc(k_a h/2)^3
@@ -20,7 +23,9 @@
 //   5. the four meshes are interleaved into one (a_x, a_y, a_z, phi) record
 //      per mesh point, and one thread per particle, in the sorted order,
 //      interpolates them with the same TSC weights and writes its result
-//      at the particle's input position.
+//      at the particle's input position.  A block takes the particles of a
+//      tile of 2 x 8 x 16 cells, with the records of the tile's mesh points
+//      and their neighbours in LDS.
 // All FP64.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
@@ -35,6 +40,10 @@
 #include "bhq.h"
 #include "bhq_internal.h"
 
+// No contraction into fused multiply-adds: every kernel that locates a
+// particle's mesh cell must get the bits the sort keys were made with.
+#pragma clang fp contract(off)
+
 namespace {
 
 constexpr int kBlock = 256;
@@ -47,24 +56,79 @@ struct Tsc {
     double w[3][3];  // weights for offsets -1, 0, +1 per axis
 };
 
+// Offset of coordinate x from its nearest mesh point, in mesh spacings.
+__device__ __forceinline__ double tsc_d(double x, double ih, double &i0)
+{
+    const double u = x * ih;
+    i0 = floor(u + 0.5);
+    return u - i0;
+}
+
+// TSC weight of the mesh point at offset o (-1, 0, +1) for offset d.
+__device__ __forceinline__ double tsc_w(double d, int o)
+{
+    return o < 0 ? 0.5 * (0.5 - d) * (0.5 - d)
+                 : (o == 0 ? 0.75 - d * d : 0.5 * (0.5 + d) * (0.5 + d));
+}
+
 __device__ __forceinline__ Tsc tsc(const double *x, double ih, int n)
 {
     Tsc t;
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double u = x[a] * ih;
-        const double i0 = floor(u + 0.5);
-        const double d = u - i0;
+        double i0;
+        const double d = tsc_d(x[a], ih, i0);
         int64_t k = (int64_t)i0 % n;
         if (k < 0) k += n;
         t.i[a] = (int)k;
-        t.w[0][a] = 0.5 * (0.5 - d) * (0.5 - d);
-        t.w[1][a] = 0.75 - d * d;
-        t.w[2][a] = 0.5 * (0.5 + d) * (0.5 + d);
+        t.w[0][a] = tsc_w(d, -1);
+        t.w[1][a] = tsc_w(d, 0);
+        t.w[2][a] = tsc_w(d, 1);
     }
     return t;
 }
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// i mod n in [0, n) for any i (meshes smaller than a tile wrap several times)
+__device__ __forceinline__ int pmod(int i, int n)
+{
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Tiles of the mesh (points for the assignment, cells for the
+// interpolation): kTX x kTY x kTZ per block of kBlock threads, z fastest;
+// with their neighbours, kHX x kHY x kHZ.
+constexpr int kTX = 2, kTY = 8, kTZ = 16;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
+constexpr int kHalo = kHX * kHY * kHZ;
+constexpr int kGatherCap = 896;  // particles of a tile's neighbourhood held in LDS
+static_assert(kTX * kTY * kTZ == kBlock, "one tile point per thread");
+
+inline unsigned ntiles(int n)
+{
+    return (unsigned)(((n + kTX - 1) / kTX) * ((n + kTY - 1) / kTY) * ((n + kTZ - 1) / kTZ));
+}
+
+// Origin of block b's tile.
+__device__ __forceinline__ void tile_origin(int n, int &x0, int &y0, int &z0)
+{
+    const int nz = (n + kTZ - 1) / kTZ, ny = (n + kTY - 1) / kTY;
+    int b = (int)blockIdx.x;
+    z0 = (b % nz) * kTZ;
+    b /= nz;
+    y0 = (b % ny) * kTY;
+    x0 = (b / ny) * kTX;
+}
+
+// Mesh index of neighbourhood entry h of the tile at (x0, y0, z0).
+__device__ __forceinline__ int64_t halo_point(int h, int n, int x0, int y0, int z0)
+{
+    const int hz = h % kHZ, hy = (h / kHZ) % kHY, hx = h / (kHZ * kHY);
+    const int cx = pmod(x0 - 1 + hx, n), cy = pmod(y0 - 1 + hy, n), cz = pmod(z0 - 1 + hz, n);
+    return ((int64_t)cx * n + cy) * n + cz;
+}
 
 // Cell of the nearest mesh point of each particle, and the identity order.
 __global__ __launch_bounds__(kBlock) void k_cell_keys(int64_t np, const double *x, double ih,
@@ -92,35 +156,106 @@ __global__ __launch_bounds__(kBlock) void k_sorted(int64_t np, const uint32_t *k
     if (k == np - 1 || key[k + 1] != c) end[c] = (int32_t)(k + 1);
 }
 
-// rho at mesh point q: the particles whose nearest point is q - o,
-// o in {-1, 0, 1}^3, each with its TSC weight for offset o.
-__global__ __launch_bounds__(kBlock) void k_gather_rho(int n, double ih, const double4 *xs,
-                                                       const int32_t *start,
-                                                       const int32_t *end, double *rho)
+// Sum over the 27 neighbourhood cells of tile point (tx, ty, tz): cell h's
+// particles are src[first[h] ...] (first[h] + count[h]), in LDS as
+// (offsets from the nearest mesh point, m) or in memory as (x, y, z, m).
+template <bool LDS>
+__device__ __forceinline__ void gather_point(int tx, int ty, int tz, double ih,
+                                             const double4 *src, const int32_t *first,
+                                             const int32_t *count, double &sum)
 {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t n3 = (int64_t)n * n * n;
-    if (q >= n3) return;
-    const int qz = (int)(q % n), qy = (int)((q / n) % n), qx = (int)(q / ((int64_t)n * n));
-    double sum = 0.0;
+#pragma unroll
     for (int ox = -1; ox <= 1; ++ox) {
-        const int cx = wrap(qx - ox, n);
+#pragma unroll
         for (int oy = -1; oy <= 1; ++oy) {
-            const int cy = wrap(qy - oy, n);
+#pragma unroll
             for (int oz = -1; oz <= 1; ++oz) {
-                const int cz = wrap(qz - oz, n);
-                const int64_t c = ((int64_t)cx * n + cy) * n + cz;
-                const int32_t e = end[c];
-                for (int32_t k = start[c]; k < e; ++k) {
-                    const double4 r = xs[k];
-                    const double xp[3] = {r.x, r.y, r.z};
-                    const Tsc t = tsc(xp, ih, n);
-                    sum += r.w * t.w[ox + 1][0] * t.w[oy + 1][1] * t.w[oz + 1][2];
+                const int h = ((tx + 1 - ox) * kHY + (ty + 1 - oy)) * kHZ + (tz + 1 - oz);
+                const double4 *p = src + first[h];
+                const int32_t cnt = count[h];
+                for (int32_t k = 0; k < cnt; ++k) {
+                    const double4 r = p[k];
+                    double i0, dx = r.x, dy = r.y, dz = r.z;
+                    if (!LDS) {
+                        dx = tsc_d(r.x, ih, i0);
+                        dy = tsc_d(r.y, ih, i0);
+                        dz = tsc_d(r.z, ih, i0);
+                    }
+                    sum += r.w * tsc_w(dx, ox) * tsc_w(dy, oy) * tsc_w(dz, oz);
                 }
             }
         }
     }
-    rho[q] = sum;
+}
+
+// rho at mesh point q: the particles whose nearest point is q - o,
+// o in {-1, 0, 1}^3, each with its TSC weight for offset o, summed in the
+// order of o (x, then y, then z) and, within a cell, in the sorted order.
+// One thread per mesh point of the block's tile.  The particles of the
+// tile's neighbourhood go to LDS first (cell by cell, in neighbourhood
+// order, with their offsets from the nearest mesh point); a neighbourhood
+// with more than kGatherCap particles is read from memory instead, in the
+// same order.
+__global__ __launch_bounds__(kBlock) void k_gather_rho(int n, double ih, const double4 *xs,
+                                                       const int32_t *start,
+                                                       const int32_t *end, double *rho)
+{
+    typedef hipcub::BlockScan<int, kBlock> Scan;
+    __shared__ double4 sp[kGatherCap];
+    __shared__ int32_t sfirst[kHalo], scount[kHalo], sstart[kHalo];
+    __shared__ typename Scan::TempStorage scan_tmp;
+    __shared__ int stotal;
+    int x0, y0, z0;
+    tile_origin(n, x0, y0, z0);
+    const int t = threadIdx.x;
+    // counts of the neighbourhood's cells; thread t takes entries 3t .. 3t+2
+    constexpr int kPer = (kHalo + kBlock - 1) / kBlock;
+    int part = 0;
+    for (int u = 0; u < kPer; ++u) {
+        const int h = kPer * t + u;
+        if (h < kHalo) {
+            const int64_t c = halo_point(h, n, x0, y0, z0);
+            const int32_t s0 = start[c], c0 = end[c] - s0;
+            sstart[h] = s0;
+            scount[h] = c0;
+            part += c0;
+        }
+    }
+    int excl = 0, total = 0;
+    Scan(scan_tmp).ExclusiveSum(part, excl, total);
+    for (int u = 0; u < kPer; ++u) {
+        const int h = kPer * t + u;
+        if (h < kHalo) {
+            sfirst[h] = excl;
+            excl += scount[h];
+        }
+    }
+    if (t == 0) stotal = total;
+    __syncthreads();
+    const bool local = stotal <= kGatherCap;
+    if (local) {
+        for (int u = 0; u < kPer; ++u) {
+            const int h = kPer * t + u;
+            if (h < kHalo)
+                for (int k = 0; k < scount[h]; ++k) {
+                    const double4 r = xs[sstart[h] + k];
+                    double i0;
+                    const double dx = tsc_d(r.x, ih, i0), dy = tsc_d(r.y, ih, i0),
+                                 dz = tsc_d(r.z, ih, i0);
+                    sp[sfirst[h] + k] = make_double4(dx, dy, dz, r.w);
+                }
+        }
+    }
+    __syncthreads();
+    const int tz = t % kTZ, ty = (t / kTZ) % kTY, tx = t / (kTZ * kTY);
+    const int qx = x0 + tx, qy = y0 + ty, qz = z0 + tz;
+    if (qx >= n || qy >= n || qz >= n) return;
+    double sum = 0.0;
+    if (local)
+        gather_point<true>(tx, ty, tz, ih, sp, sfirst, scount, sum);
+    else
+        gather_point<false>(tx, ty, tz, ih, xs, sstart, scount, sum);
+    rho[((int64_t)qx * n + qy) * n + qz] = sum;
 }
 
 __device__ __forceinline__ double sinc_half(double kh)
@@ -177,45 +312,110 @@ __global__ __launch_bounds__(kBlock) void k_interleave(int64_t n3, const double 
     m4[q] = make_double4(axm[q], aym[q], azm[q], phim[q]);
 }
 
-// Particle k of the sorted order: 27-point TSC interpolation of the
-// interleaved mesh; the result goes to the particle's input index.
-__global__ __launch_bounds__(kBlock) void k_interp(int64_t np, const double4 *xs,
-                                                   const int32_t *idx, double ih, int n,
-                                                   const double4 *m4, double *a, double *pot,
-                                                   int accumulate)
+// One term of the 27-point interpolation, in the order of the points.
+__device__ __forceinline__ void interp_add(const Tsc &w, int a0, int b, int c, const double4 &v,
+                                           double *s4)
 {
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= np) return;
-    const double4 r = xs[k];
-    const double xp[3] = {r.x, r.y, r.z};
-    const Tsc t = tsc(xp, ih, n);
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int a0 = 0; a0 < 3; ++a0) {
-        const int ix = wrap(t.i[0] + a0 - 1, n);
-        for (int b = 0; b < 3; ++b) {
-            const int iy = wrap(t.i[1] + b - 1, n);
-            for (int c = 0; c < 3; ++c) {
-                const int iz = wrap(t.i[2] + c - 1, n);
-                const double4 v = m4[((int64_t)ix * n + iy) * n + iz];
-                const double w = t.w[a0][0] * t.w[b][1] * t.w[c][2];
-                s[0] += w * v.x;
-                s[1] += w * v.y;
-                s[2] += w * v.z;
-                s[3] += w * v.w;
+    const double wt = w.w[a0][0] * w.w[b][1] * w.w[c][2];
+    s4[0] += wt * v.x;
+    s4[1] += wt * v.y;
+    s4[2] += wt * v.z;
+    s4[3] += wt * v.w;
+}
+
+// The particles of the block's tile of cells (nearest mesh point in the
+// tile; a row of the tile along z is a contiguous range of the sorted
+// order): 27-point TSC interpolation of the interleaved mesh, whose records
+// around the tile are in LDS; each result goes to the particle's input
+// index.
+__global__ __launch_bounds__(kBlock) void k_interp(int n, const double4 *xs, const int32_t *idx,
+                                                   const int32_t *start, const int32_t *end,
+                                                   double ih, const double4 *m4, double *a,
+                                                   double *pot, int accumulate)
+{
+    constexpr int kRows = kTX * kTY;
+    __shared__ double4 sm[kHalo];
+    __shared__ int32_t rlo[kRows], rhi[kRows], rpre[kRows + 1];
+    int x0, y0, z0;
+    tile_origin(n, x0, y0, z0);
+    const int t = threadIdx.x;
+    for (int h = t; h < kHalo; h += kBlock) sm[h] = m4[halo_point(h, n, x0, y0, z0)];
+    if (t < kRows) {
+        rlo[t] = 0x7fffffff;
+        rhi[t] = 0;
+    }
+    __syncthreads();
+    {
+        // row r = (tx, ty): its particles are those of its non-empty cells
+        const int tz = t % kTZ, ty = (t / kTZ) % kTY, tx = t / (kTZ * kTY);
+        const int cx = x0 + tx, cy = y0 + ty, cz = z0 + tz;
+        if (cx < n && cy < n && cz < n) {
+            const int64_t c = ((int64_t)cx * n + cy) * n + cz;
+            const int32_t s0 = start[c], e0 = end[c];
+            if (e0 > s0) {
+                atomicMin(&rlo[tx * kTY + ty], s0);
+                atomicMax(&rhi[tx * kTY + ty], e0);
             }
         }
     }
-    const int64_t p = idx[k];
-    if (accumulate) {
-        a[3 * p] += s[0];
-        a[3 * p + 1] += s[1];
-        a[3 * p + 2] += s[2];
-        if (pot) pot[p] += s[3];
-    } else {
-        a[3 * p] = s[0];
-        a[3 * p + 1] = s[1];
-        a[3 * p + 2] = s[2];
-        if (pot) pot[p] = s[3];
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int r = 0; r < kRows; ++r) {
+            rpre[r] = acc;
+            acc += rhi[r] > rlo[r] ? rhi[r] - rlo[r] : 0;
+        }
+        rpre[kRows] = acc;
+    }
+    __syncthreads();
+    const int total = rpre[kRows];
+    for (int j = t; j < total; j += kBlock) {
+        int r = 0;
+        while (rpre[r + 1] <= j) ++r;
+        const int64_t k = rlo[r] + (j - rpre[r]);
+        const double4 rec = xs[k];
+        const double xp[3] = {rec.x, rec.y, rec.z};
+        const Tsc w = tsc(xp, ih, n);
+        // the particle's cell is in the tile (its sort key was computed by
+        // the same function): its neighbourhood entries are (w.i - origin) +
+        // (0 .. 2) per axis; a cell outside the tile would read the mesh
+        const int hx0 = w.i[0] - x0, hy0 = w.i[1] - y0, hz0 = w.i[2] - z0;
+        const bool in = hx0 >= 0 && hx0 < kTX && hy0 >= 0 && hy0 < kTY && hz0 >= 0 &&
+                        hz0 < kTZ;
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        if (in) {
+#pragma unroll
+            for (int a0 = 0; a0 < 3; ++a0)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        interp_add(w, a0, b, c,
+                                   sm[((hx0 + a0) * kHY + (hy0 + b)) * kHZ + (hz0 + c)], s4);
+        } else {
+#pragma unroll
+            for (int a0 = 0; a0 < 3; ++a0)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        interp_add(w, a0, b, c,
+                                   m4[((int64_t)wrap(w.i[0] + a0 - 1, n) * n +
+                                       wrap(w.i[1] + b - 1, n)) * n + wrap(w.i[2] + c - 1, n)],
+                                   s4);
+        }
+        const int64_t p = idx[k];
+        if (accumulate) {
+            a[3 * p] += s4[0];
+            a[3 * p + 1] += s4[1];
+            a[3 * p + 2] += s4[2];
+            if (pot) pot[p] += s4[3];
+        } else {
+            a[3 * p] = s4[0];
+            a[3 * p + 1] = s4[1];
+            a[3 * p + 2] = s4[2];
+            if (pot) pot[p] = s4[3];
+        }
     }
 }
 
@@ -413,7 +613,7 @@ int bhq_pm_compute(bhq_pm *pm, int64_t np, const double *x, const double *m, dou
                        pm->key2.as<uint32_t>(), pm->idx2.as<int32_t>(), x, m,
                        pm->xs.as<double4>(), pm->start.as<int32_t>(), pm->end.as<int32_t>());
     if (!hipok(hipGetLastError(), "sorted records")) return BHQ_E_HIP;
-    hipLaunchKernelGGL(k_gather_rho, dim3(nblocks((int64_t)n3)), dim3(kBlock), 0, s, n, ih,
+    hipLaunchKernelGGL(k_gather_rho, dim3(ntiles(n)), dim3(kBlock), 0, s, n, ih,
                        pm->xs.as<double4>(), pm->start.as<int32_t>(), pm->end.as<int32_t>(),
                        pm->rho.as<double>());
     if (!hipok(hipGetLastError(), "assignment")) return BHQ_E_HIP;
@@ -440,8 +640,8 @@ int bhq_pm_compute(bhq_pm *pm, int64_t np, const double *x, const double *m, dou
                        (int64_t)n3, pm->axm.as<double>(), pm->aym.as<double>(),
                        pm->azm.as<double>(), pm->phim.as<double>(), pm->m4.as<double4>());
     if (!hipok(hipGetLastError(), "interleave")) return BHQ_E_HIP;
-    hipLaunchKernelGGL(k_interp, dim3(nblocks(np)), dim3(kBlock), 0, s, np,
-                       pm->xs.as<double4>(), pm->idx2.as<int32_t>(), ih, n,
+    hipLaunchKernelGGL(k_interp, dim3(ntiles(n)), dim3(kBlock), 0, s, n, pm->xs.as<double4>(),
+                       pm->idx2.as<int32_t>(), pm->start.as<int32_t>(), pm->end.as<int32_t>(), ih,
                        pm->m4.as<double4>(), a, pot, accumulate);
     if (!hipok(hipGetLastError(), "interpolation")) return BHQ_E_HIP;
     if (!hipok(hipEventRecord(pm->ev1, s), "event")) return BHQ_E_HIP;

@@ -568,11 +568,11 @@ __device__ __forceinline__ int2 classify(const WalkArgs &W, int32_t id, const WC
         if (C.side * C.side < W.theta2 * d2) {
             // beyond the cutoff for every particle of the group
             if (W.rdrop2 > 0.0) {
-                // distance to the box [gb[0..2], gb[3..5]] of the group's particles
+                // distance to the box of the group's particles (centre
+                // gb[0..2], half widths gb[3..5])
                 double b2 = 0.0;
                 for (int k = 0; k < 3; ++k) {
-                    const double c = 0.5 * (gb[k] + gb[3 + k]), h = 0.5 * (gb[3 + k] - gb[k]);
-                    const double v = abs_min_image(cm[k] - c, box) - h;
+                    const double v = abs_min_image(cm[k] - gb[k], box) - gb[3 + k];
                     if (v > 0.0) b2 += v * v;
                 }
                 if (b2 >= W.rdrop2) return make_int2(-1, 0);
@@ -652,9 +652,15 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
     const int32_t gid = W.groups[gi];
     const WCell G = W.wc[gid];
     const int gdepth = W.wl[gid].nd >> 8;
+    // centre and half widths of the box (lo, hi) of the group's particles,
+    // with the host builder's operations
     double gb[6] = {0, 0, 0, 0, 0, 0};
     if (W.rdrop2 > 0.0)
-        for (int q = 0; q < 6; ++q) gb[q] = W.gbox[6 * gi + q];
+        for (int k = 0; k < 3; ++k) {
+            const double lo = W.gbox[6 * gi + k], hi = W.gbox[6 * gi + 3 + k];
+            gb[k] = 0.5 * (lo + hi);
+            gb[3 + k] = 0.5 * (hi - lo);
+        }
     int64_t np = 0, nc = 0;
     constexpr bool FILL = MODE != kWalkCount;
     int64_t pb = 0, cb = 0, pe = 0, ce = 0;  // where this group's entries go
