@@ -335,13 +335,15 @@ struct bhq_ctx {
     }
     // Copy a compact index list (cnt entries, group offsets in device array
     // off) to the host; lists kept in per-group slots of `slot` entries are
-    // compacted on the device first.
+    // compacted on the device first, into the scratch array (after all work
+    // on the device, which may still use that array, has finished).
     int fetch_list(Arr a, Arr off, int64_t slot, int64_t cnt, int32_t *dst)
     {
         const void *src = arr[a].p;
         hipError_t e = hipSuccess;
         if (slot > 0) {
-            e = arr[A_SORTSCRATCH].reserve((size_t)cnt * 4);
+            e = hipDeviceSynchronize();
+            if (e == hipSuccess) e = arr[A_SORTSCRATCH].reserve((size_t)cnt * 4);
             if (e == hipSuccess)
                 e = bhq::launch_compact_lists(ng, arr[off].as<int64_t>(), arr[a].as<int32_t>(),
                                               slot, arr[A_SORTSCRATCH].as<int32_t>(), nullptr);

@@ -232,18 +232,32 @@ __global__ __launch_bounds__(kBlock) void k_gather_rho(int n, double ih, const d
     }
     if (t == 0) stotal = total;
     __syncthreads();
-    const bool local = stotal <= kGatherCap;
+    const int ntot = stotal;
+    const bool local = ntot <= kGatherCap;
     if (local) {
-        for (int u = 0; u < kPer; ++u) {
-            const int h = kPer * t + u;
-            if (h < kHalo)
-                for (int k = 0; k < scount[h]; ++k) {
-                    const double4 r = xs[sstart[h] + k];
-                    double i0;
-                    const double dx = tsc_d(r.x, ih, i0), dy = tsc_d(r.y, ih, i0),
-                                 dz = tsc_d(r.z, ih, i0);
-                    sp[sfirst[h] + k] = make_double4(dx, dy, dz, r.w);
+        // entry j of the LDS copy belongs to the last cell h with
+        // sfirst[h] <= j (cells before it that are empty share its first
+        // entry; cells after it start beyond j); the threads' loads are
+        // independent, so they are all in flight at once
+        constexpr int kIter = (kGatherCap + kBlock - 1) / kBlock;
+#pragma unroll
+        for (int u = 0; u < kIter; ++u) {
+            const int j = t + u * kBlock;
+            if (j < ntot) {
+                int lo = 0, hi = kHalo;  // sfirst[lo] <= j; hi: past the answer
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (sfirst[mid] <= j)
+                        lo = mid;
+                    else
+                        hi = mid;
                 }
+                const double4 r = xs[sstart[lo] + (j - sfirst[lo])];
+                double i0;
+                const double dx = tsc_d(r.x, ih, i0), dy = tsc_d(r.y, ih, i0),
+                             dz = tsc_d(r.z, ih, i0);
+                sp[j] = make_double4(dx, dy, dz, r.w);
+            }
         }
     }
     __syncthreads();
@@ -339,7 +353,11 @@ __global__ __launch_bounds__(kBlock) void k_interp(int n, const double4 *xs, con
     int x0, y0, z0;
     tile_origin(n, x0, y0, z0);
     const int t = threadIdx.x;
-    for (int h = t; h < kHalo; h += kBlock) sm[h] = m4[halo_point(h, n, x0, y0, z0)];
+#pragma unroll
+    for (int u = 0; u < (kHalo + kBlock - 1) / kBlock; ++u) {
+        const int h = t + u * kBlock;
+        if (h < kHalo) sm[h] = m4[halo_point(h, n, x0, y0, z0)];
+    }
     if (t < kRows) {
         rlo[t] = 0x7fffffff;
         rhi[t] = 0;
