@@ -346,29 +346,35 @@ __global__ __launch_bounds__(kBlock) void k_leaf_order(Cells C, int32_t ncell, i
 
 // ---- 4. moments ---------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_moments_leaf(Cells C, int32_t ncell,
-                                                         const int32_t *idx, const double *x,
-                                                         const double *m, CellRec *pc)
+// Moments of a leaf from its particles, in input order (the host's sums, in
+// the host's order): mass and centre of mass, then the traceless
+// quadrupole and trace about the centre of mass.  P(k) gives particle k's
+// (m, x, y, z).  NMAX > 0: n <= NMAX, and the loops are unrolled to NMAX
+// (so that P may index registers); 0: plain loops.
+template <int NMAX, typename Part>
+__device__ __forceinline__ CellRec leaf_moments(int n, const double ctr[3], Part P)
 {
-    const int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (c >= ncell || C.child0[c] >= 0) return;
-    const int32_t f = C.first[c], e = f + C.count[c];
+    constexpr int kTrip = NMAX > 0 ? NMAX : 1;
+    const int trip = NMAX > 0 ? NMAX : n;
     double M = 0.0, s[3] = {0.0, 0.0, 0.0};
-    for (int32_t k = f; k < e; ++k) {
-        const int64_t p = idx[k];
-        const double mp = m[p];
-        M += mp;
-        for (int a = 0; a < 3; ++a) s[a] += mp * x[3 * p + a];
+#pragma unroll kTrip
+    for (int k = 0; k < trip; ++k) {
+        if (k >= n) break;
+        const double4 q = P(k);
+        M += q.x;
+        s[0] += q.x * q.y;
+        s[1] += q.x * q.z;
+        s[2] += q.x * q.w;
     }
-    const double ctr[3] = {C.cx[c], C.cy[c], C.cz[c]};
     double cm[3];
     for (int a = 0; a < 3; ++a) cm[a] = M > 0.0 ? s[a] / M : ctr[a];
     double q6[6] = {0, 0, 0, 0, 0, 0}, T = 0.0;
-    for (int32_t k = f; k < e; ++k) {
-        const int64_t p = idx[k];
-        const double mp = m[p];
-        const double d0 = x[3 * p] - cm[0], d1 = x[3 * p + 1] - cm[1],
-                     d2 = x[3 * p + 2] - cm[2];
+#pragma unroll kTrip
+    for (int k = 0; k < trip; ++k) {
+        if (k >= n) break;
+        const double4 q = P(k);
+        const double mp = q.x;
+        const double d0 = q.y - cm[0], d1 = q.z - cm[1], d2 = q.w - cm[2];
         const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
         q6[0] += mp * (3.0 * d0 * d0 - r2);
         q6[1] += mp * 3.0 * d0 * d1;
@@ -391,7 +397,36 @@ __global__ __launch_bounds__(kBlock) void k_moments_leaf(Cells C, int32_t ncell,
     r.q22 = q6[5];
     r.t = T;
     r.pad = 0.0;
-    pc[c] = r;
+    return r;
+}
+
+// One thread per leaf.  A leaf of up to kLeafCache particles loads all of
+// them into registers first (independent loads, all in flight at once)
+// and sums from there; a larger one (a leaf at the depth limit) reads them
+// from memory in each pass.
+constexpr int kLeafCache = 8;
+
+__global__ __launch_bounds__(kBlock) void k_moments_leaf(Cells C, int32_t ncell,
+                                                         const int32_t *idx, const double *x,
+                                                         const double *m, CellRec *pc)
+{
+    const int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (c >= ncell || C.child0[c] >= 0) return;
+    const int32_t f = C.first[c], n = C.count[c];
+    const double ctr[3] = {C.cx[c], C.cy[c], C.cz[c]};
+    auto mem = [&](int k) {
+        const int64_t p = idx[f + k];
+        return make_double4(m[p], x[3 * p], x[3 * p + 1], x[3 * p + 2]);
+    };
+    if (n <= kLeafCache) {
+        double4 q[kLeafCache];
+#pragma unroll
+        for (int k = 0; k < kLeafCache; ++k)
+            if (k < n) q[k] = mem(k);
+        pc[c] = leaf_moments<kLeafCache>(n, ctr, [&](int k) { return q[k]; });
+    } else {
+        pc[c] = leaf_moments<0>(n, ctr, mem);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_moments_level(Cells C, int32_t lo, int32_t hi,
