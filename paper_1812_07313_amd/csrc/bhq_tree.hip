@@ -805,12 +805,25 @@ __global__ __launch_bounds__(kBlock) void k_group_box(Cells C, const int32_t *gr
         b[k] = __builtin_inf();
         b[3 + k] = -__builtin_inf();
     }
-    for (int32_t q = C.first[c]; q < C.first[c] + C.count[c]; ++q) {
-        const double *xp = x + 3 * (int64_t)idx[q];
-        for (int k = 0; k < 3; ++k) {
-            b[k] = xp[k] < b[k] ? xp[k] : b[k];
-            b[3 + k] = xp[k] > b[3 + k] ? xp[k] : b[3 + k];
-        }
+    // chunks of 8 particles: their loads are independent and all in flight
+    // at once (minimum and maximum do not depend on the order)
+    constexpr int kChunk = 8;
+    const int32_t f = C.first[c], e = f + C.count[c];
+    for (int32_t q0 = f; q0 < e; q0 += kChunk) {
+        double v[kChunk][3];
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j)
+            if (q0 + j < e) {
+                const double *xp = x + 3 * (int64_t)idx[q0 + j];
+                for (int k = 0; k < 3; ++k) v[j][k] = xp[k];
+            }
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j)
+            if (q0 + j < e)
+                for (int k = 0; k < 3; ++k) {
+                    b[k] = v[j][k] < b[k] ? v[j][k] : b[k];
+                    b[3 + k] = v[j][k] > b[3 + k] ? v[j][k] : b[3 + k];
+                }
     }
     for (int k = 0; k < 6; ++k) gbox[6 * g + k] = b[k];
 }
