@@ -286,6 +286,38 @@ def test_partial_list_update_after_rebuild():
     assert np.array_equal(p1.view(np.int64), p2.view(np.int64))
 
 
+def test_host_views_after_rebuild():
+    """After a one-walk rebuild the group offsets stay on the device until
+    the host asks: bhq_get_counts gives the host builder's interaction
+    counts, and the host order planner (cost order), which reads the
+    offsets on the host, gives the forces of the device-planned XCD order
+    bit for bit (a group's forces do not depend on the launch order)."""
+    x, m = synth.plummer(25000, synth.rng(41))
+    xt, mt = _dev(x, m)
+    h = _host(x, m, 0.6, 64)
+    ni = np.diff(h["i_off"])
+    n_pp = int((ni * np.diff(h["jp_off"])).sum())
+    n_pc = int((ni * np.diff(h["jc_off"])).sum())
+    got = []
+    for mode in (bhq.ORDER_XCD, bhq.ORDER_COST):
+        log("case host views after rebuild, order mode %d" % mode)
+        ctx = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
+        try:
+            bhq.bhq_set_group_order(ctx, mode)
+            for _ in range(2):
+                bhq.bhq_build_lists_device(ctx, xt, mt, 0.6, 64, 8, 0.0, 0.0)
+            assert bhq.bhq_get_build_info(ctx)[0]
+            assert bhq.bhq_get_counts(ctx) == (n_pp, n_pc)
+            bhq.bhq_set_eps(ctx, 0.01)
+            bhq.bhq_compute(ctx)
+            got.append(bhq.bhq_get_result(ctx, len(m)))
+        finally:
+            bhq.bhq_destroy(ctx)
+    (a1, p1), (a2, p2) = got
+    assert np.array_equal(a1.view(np.int64), a2.view(np.int64))
+    assert np.array_equal(p1.view(np.int64), p2.view(np.int64))
+
+
 def _batch(systems):
     sizes = np.array([len(s[1]) for s in systems])
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
