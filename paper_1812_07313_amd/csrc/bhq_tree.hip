@@ -751,9 +751,12 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkArgs W)
                         const int64_t q = cb + nc + ic - 1;
                         if (q < ce) W.jc_idx[q] = e.x;
                     } else {
+                        // the entries that fit in the group's segment (none
+                        // past it: a slot overflow is detected from the counts)
                         const int64_t q = pb + np + ip - e.y;
-                        for (int32_t j = 0; j < e.y && q + j < pe; ++j)
-                            W.jp_idx[q + j] = e.x + j;
+                        const int32_t nw = (int32_t)(pe - q < (int64_t)e.y ? pe - q : e.y);
+                        int32_t *dst = W.jp_idx + q;
+                        for (int32_t j = 0; j < nw; ++j) dst[j] = e.x + j;
                     }
                 }
             }
