@@ -156,32 +156,58 @@ __global__ __launch_bounds__(kBlock) void k_sorted(int64_t np, const uint32_t *k
     if (k == np - 1 || key[k + 1] != c) end[c] = (int32_t)(k + 1);
 }
 
-// Sum over the 27 neighbourhood cells of tile point (tx, ty, tz): cell h's
-// particles are src[first[h] ...] (first[h] + count[h]), in LDS as
-// (offsets from the nearest mesh point, m) or in memory as (x, y, z, m).
-template <bool LDS>
-__device__ __forceinline__ void gather_point(int tx, int ty, int tz, double ih,
-                                             const double4 *src, const int32_t *first,
-                                             const int32_t *count, double &sum)
+// TSC weight for offset o (-1, 0, +1) with o known only at run time; the
+// same operations as tsc_w (negating d is exact).
+__device__ __forceinline__ double tsc_w_var(double d, int o)
+{
+    const double s = o < 0 ? -d : d;
+    return o == 0 ? 0.75 - d * d : 0.5 * (0.5 + s) * (0.5 + s);
+}
+
+// Sum over the neighbourhood of tile point (tx, ty, tz), row by row: for
+// each (ox, oy) the cells at z offsets +1, 0, -1 (neighbourhood z indices
+// tz .. tz + 2), each cell's particles in the sorted order.
+// LDS: the three cells' particles are contiguous in sp, as (offsets from
+// the nearest mesh point, m), with their neighbourhood z index in sz, so
+// that a row is one loop.  Memory: cell by cell from xs, the same order.
+__device__ __forceinline__ void gather_point_lds(int tx, int ty, int tz, const double4 *sp,
+                                                 const uint8_t *sz, const int32_t *first,
+                                                 const int32_t *count, double &sum)
+{
+#pragma unroll
+    for (int ox = -1; ox <= 1; ++ox) {
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int h0 = ((tx + 1 - ox) * kHY + (ty + 1 - oy)) * kHZ + tz;
+            const int32_t k0 = first[h0], k1 = first[h0 + 2] + count[h0 + 2];
+            for (int32_t k = k0; k < k1; ++k) {
+                const double4 r = sp[k];
+                const int oz = tz + 1 - sz[k];
+                sum += r.w * tsc_w(r.x, ox) * tsc_w(r.y, oy) * tsc_w_var(r.z, oz);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void gather_point_mem(int tx, int ty, int tz, double ih,
+                                                 const double4 *xs, const int32_t *start,
+                                                 const int32_t *count, double &sum)
 {
 #pragma unroll
     for (int ox = -1; ox <= 1; ++ox) {
 #pragma unroll
         for (int oy = -1; oy <= 1; ++oy) {
 #pragma unroll
-            for (int oz = -1; oz <= 1; ++oz) {
+            for (int oz = 1; oz >= -1; --oz) {
                 const int h = ((tx + 1 - ox) * kHY + (ty + 1 - oy)) * kHZ + (tz + 1 - oz);
-                const double4 *p = src + first[h];
+                const double4 *p = xs + start[h];
                 const int32_t cnt = count[h];
                 for (int32_t k = 0; k < cnt; ++k) {
                     const double4 r = p[k];
-                    double i0, dx = r.x, dy = r.y, dz = r.z;
-                    if (!LDS) {
-                        dx = tsc_d(r.x, ih, i0);
-                        dy = tsc_d(r.y, ih, i0);
-                        dz = tsc_d(r.z, ih, i0);
-                    }
-                    sum += r.w * tsc_w(dx, ox) * tsc_w(dy, oy) * tsc_w(dz, oz);
+                    double i0;
+                    const double dx = tsc_d(r.x, ih, i0), dy = tsc_d(r.y, ih, i0),
+                                 dz = tsc_d(r.z, ih, i0);
+                    sum += r.w * tsc_w(dx, ox) * tsc_w(dy, oy) * tsc_w_var(dz, oz);
                 }
             }
         }
@@ -189,8 +215,9 @@ __device__ __forceinline__ void gather_point(int tx, int ty, int tz, double ih,
 }
 
 // rho at mesh point q: the particles whose nearest point is q - o,
-// o in {-1, 0, 1}^3, each with its TSC weight for offset o, summed in the
-// order of o (x, then y, then z) and, within a cell, in the sorted order.
+// o in {-1, 0, 1}^3, each with its TSC weight for offset o, summed in a
+// fixed order: o_x, then o_y, then o_z = +1, 0, -1, and within a cell the
+// sorted order.
 // One thread per mesh point of the block's tile.  The particles of the
 // tile's neighbourhood go to LDS first (cell by cell, in neighbourhood
 // order, with their offsets from the nearest mesh point); a neighbourhood
@@ -202,6 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_rho(int n, double ih, const d
 {
     typedef hipcub::BlockScan<int, kBlock> Scan;
     __shared__ double4 sp[kGatherCap];
+    __shared__ uint8_t sz[kGatherCap];  // neighbourhood z index (< kHZ) of each particle
     __shared__ int32_t sfirst[kHalo], scount[kHalo], sstart[kHalo];
     __shared__ typename Scan::TempStorage scan_tmp;
     __shared__ int stotal;
@@ -257,6 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_rho(int n, double ih, const d
                 const double dx = tsc_d(r.x, ih, i0), dy = tsc_d(r.y, ih, i0),
                              dz = tsc_d(r.z, ih, i0);
                 sp[j] = make_double4(dx, dy, dz, r.w);
+                sz[j] = (uint8_t)(lo % kHZ);
             }
         }
     }
@@ -266,9 +295,9 @@ __global__ __launch_bounds__(kBlock) void k_gather_rho(int n, double ih, const d
     if (qx >= n || qy >= n || qz >= n) return;
     double sum = 0.0;
     if (local)
-        gather_point<true>(tx, ty, tz, ih, sp, sfirst, scount, sum);
+        gather_point_lds(tx, ty, tz, sp, sz, sfirst, scount, sum);
     else
-        gather_point<false>(tx, ty, tz, ih, xs, sstart, scount, sum);
+        gather_point_mem(tx, ty, tz, ih, xs, sstart, scount, sum);
     rho[((int64_t)qx * n + qy) * n + qz] = sum;
 }
 
