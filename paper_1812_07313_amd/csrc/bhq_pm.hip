@@ -78,8 +78,12 @@ __device__ __forceinline__ Tsc tsc(const double *x, double ih, int n)
     for (int a = 0; a < 3; ++a) {
         double i0;
         const double d = tsc_d(x[a], ih, i0);
-        int64_t k = (int64_t)i0 % n;
-        if (k < 0) k += n;
+        // i0 mod n; positions inside the box need no division
+        int64_t k = (int64_t)i0;
+        if (k < 0 || k >= n) {
+            k %= n;
+            if (k < 0) k += n;
+        }
         t.i[a] = (int)k;
         t.w[0][a] = tsc_w(d, -1);
         t.w[1][a] = tsc_w(d, 0);
