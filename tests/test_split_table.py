@@ -71,3 +71,17 @@ def test_header_matches_generator():
     _, _, tab = _header()
     # the header holds the generator's FP64 coefficients rounded to FP32
     np.testing.assert_allclose(tab, gen.table(), rtol=1.2e-7, atol=0)
+
+
+def test_pieces_join():
+    """Neighbouring cubics meet in value and slope (cubic Hermite pieces
+    share their end values and derivatives), up to FP32 rounding: a piece
+    evaluated at f = 1 equals the next at f = 0, and so do their slopes."""
+    dom, n, tab = _header()
+    c = tab.astype(np.float64)
+    end_val = c[:, :-1].sum(axis=2)                                   # f = 1
+    end_slope = c[:, :-1, 1] + 2 * c[:, :-1, 2] + 3 * c[:, :-1, 3]   # dF/df at 1
+    start_val, start_slope = c[:, 1:, 0], c[:, 1:, 1]
+    scale = np.abs(c[:, :, 0]).max(axis=1)[:, None]
+    assert np.max(np.abs(end_val - start_val) / scale) < 4e-7
+    assert np.max(np.abs(end_slope - start_slope) / scale) < 1e-7
