@@ -117,9 +117,10 @@ int bhq_set_eps2_i(bhq_ctx *ctx, int64_t ni, const double *eps2);
 
 /* Short-range split parameters for the SPLIT kernels: r_s > 0, cutoff
  * rcut > 0; box > 0 selects a periodic cube of that side (minimum-image
- * separations), box == 0 an open boundary.  The FP32 split kernels evaluate
- * erfc for r / (2 r_s) <= 2.5 only, so bhq_compute returns BHQ_E_ARG for
- * FP32 with rcut > 5 r_s (FP64 has no such limit).  In a periodic box every
+ * separations), box == 0 an open boundary.  The FP32 split kernels take
+ * erfc and the related radial functions from a table that covers
+ * r / (2 r_s) <= 2.5 only, so bhq_compute returns BHQ_E_ARG for FP32 with
+ * rcut > 5 r_s (FP64 calls erfc and exp and has no such limit).  In a periodic box every
  * group cell plus 2 rcut must stay below half the box. */
 int bhq_set_split(bhq_ctx *ctx, double rs, double rcut, double box);
 
