@@ -85,3 +85,20 @@ def test_pieces_join():
     scale = np.abs(c[:, :, 0]).max(axis=1)[:, None]
     assert np.max(np.abs(end_val - start_val) / scale) < 4e-7
     assert np.max(np.abs(end_slope - start_slope) / scale) < 1e-7
+
+
+def test_generator_derivatives():
+    """The exact derivatives the generator gives the Hermite pieces agree
+    with central differences of its function values."""
+    spec = importlib.util.spec_from_file_location(
+        "gen", os.path.join(CSRC, "gen_split_table.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    u = np.linspace(0.05, 2.6, 200)
+    h = 1e-5
+    vp, _ = gen.funcs(u + h)
+    vm, _ = gen.funcs(u - h)
+    _, ders = gen.funcs(u)
+    for j in range(4):
+        num = (vp[j] - vm[j]) / (2 * h)
+        assert np.max(np.abs(num - ders[j])) < 1e-8 * max(1.0, np.max(np.abs(ders[j]))), j
