@@ -53,6 +53,33 @@ def test_pm_matches_reference(n, nmesh):
         bhq.bhq_pm_destroy(pm)
 
 
+def test_pm_clustered_reads_memory():
+    """A clump: the neighbourhood of the tiles around it holds more particles
+    than the assignment keeps in LDS, so those tiles read the particles
+    from memory.  The result matches the reference as elsewhere, and is
+    the same bits every run."""
+    n, nmesh = 6000, 32
+    g = np.random.default_rng(17)
+    x = (0.5 + g.normal(size=(n, 3)) * 0.6 / nmesh) % 1.0
+    m = g.uniform(0.5, 1.5, n) / n
+    rs = 1.25 / nmesh
+    a_ref, p_ref = opm.pm(x, m, 1.0, nmesh, rs)
+    pm = bhq.bhq_pm_create(nmesh, 1.0, rs)
+    try:
+        xt, mt = _t(x), _t(m)
+        a = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+        p = torch.zeros(n, dtype=torch.float64, device="cuda")
+        bhq.bhq_pm_compute(pm, xt, mt, a, p)
+        ea, ep = _rel(a.cpu().numpy(), a_ref), _rel(p.cpu().numpy(), p_ref)
+        log("case pm clump n=%d mesh=%d: force %.3g pot %.3g" % (n, nmesh, ea, ep))
+        assert ea < 1e-11 and ep < 1e-11
+        a1 = a.cpu().numpy()
+        bhq.bhq_pm_compute(pm, xt, mt, a, p)
+        assert np.array_equal(a.cpu().numpy(), a1)
+    finally:
+        bhq.bhq_pm_destroy(pm)
+
+
 def test_pm_against_k_sum():
     """One unit mass: the GPU mesh force agrees with the mesh-free sum to
     the TSC accuracy at r_s = 1.25 mesh spacings."""
