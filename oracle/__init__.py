@@ -7,9 +7,8 @@ the smoke check and the CPU-baseline leg of the benchmark may import it.  It
 shares no code with the GPU library and is never called by it.
 """
 from .oracle import (  # noqa: F401
-    MONO, QUAD, SPLIT_QUAD, SPLIT_MONO, QUAD_SOFT, MASK_ABS, MASK_F32_OFS,
-    MASK_F64_OFS,
-    split_keep,
+    MONO, QUAD, SPLIT_QUAD, SPLIT_MONO, QUAD_SOFT, MASK_ABS, MASK_F64_OFS,
+    split_keep, mask_flips,
     build, lib, Tree, build_tree, eval_lists, direct, moments, pp_plummer,
     pc_quad, pc_quad_soft, pc_mono, pc_split, pp_split, split_derivs, num_threads,
     materialise, relative_errors, leapfrog,

@@ -162,16 +162,17 @@ void orc_split_derivs(double r, double rs, double *Phi, double *D1, double *D2,
 
 /* The cutoff of the split kernel is a discrete decision: a term is kept iff
  * its separation is non-zero and below rcut.  By definition that is decided
- * on d = r_j - r_i in FP64 (mode ORC_MASK_ABS).  Where a pair or cell sits
- * within rounding of rcut, an implementation that forms d differently may
- * decide the other way; to compare such an implementation term by term the
- * decision is taken as it takes it (the force values stay FP64):
- *   ORC_MASK_F32_OFS: positions relative to the group centre c rounded to
- *     FP32 (periodic: v - box * rint(v * (1/box)) first, in FP64), their
- *     FP32 difference, r^2 = fma(dz, dz, fma(dy, dy, dx * dx)) in FP32,
- *     kept iff 0 < r^2 < fl32(rcut * rcut);
- *   ORC_MASK_F64_OFS: the same in FP64 without the rounding to FP32. */
-enum { ORC_MASK_ABS = 0, ORC_MASK_F32_OFS = 1, ORC_MASK_F64_OFS = 2 };
+ * on d = r_j - r_i in FP64 (mode ORC_MASK_ABS).  An implementation that
+ * forms the separation from positions relative to a group centre c decides
+ * the same way except where |d| lies within rounding (~1e-16 relative) of
+ * rcut; mode ORC_MASK_F64_OFS takes the decision that way:
+ *   positions relative to c in FP64 (periodic: v - box * rint(v * (1/box))),
+ *   their difference, r^2 = fma(dz, dz, fma(dy, dy, dx * dx)),
+ *   kept iff 0 < r^2 < rcut * rcut.
+ * orc_mask_flips counts the terms of a set of lists on which the two modes
+ * disagree, so that a comparison made with ORC_MASK_F64_OFS can be shown to
+ * be one with the definition's decisions. */
+enum { ORC_MASK_ABS = 0, ORC_MASK_F64_OFS = 1 };
 
 static double wrap_ofs(double v, double box)
 {
@@ -181,16 +182,6 @@ static double wrap_ofs(double v, double box)
 int orc_split_keep(int mode, const double xj[3], const double xi[3],
                    const double c[3], double box, double rcut)
 {
-    if (mode == ORC_MASK_F32_OFS) {
-        float d[3];
-        for (int k = 0; k < 3; ++k) {
-            float pj = (float)wrap_ofs(xj[k] - c[k], box);
-            float pi = (float)wrap_ofs(xi[k] - c[k], box);
-            d[k] = pj - pi;
-        }
-        float r2 = fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
-        return r2 > 0.0f && r2 < (float)(rcut * rcut);
-    }
     if (mode == ORC_MASK_F64_OFS) {
         double d[3];
         for (int k = 0; k < 3; ++k)
@@ -205,6 +196,30 @@ int orc_split_keep(int mode, const double xj[3], const double xi[3],
     }
     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     return r2 > 0.0 && sqrt(r2) < rcut;
+}
+
+/* Number of (i, list entry) terms of the lists (arguments as orc_eval) on
+ * which ORC_MASK_ABS and ORC_MASK_F64_OFS decide differently. */
+int64_t orc_mask_flips(int64_t ng, const int64_t *i_idx, const int64_t *i_off,
+                       const double *x, const int64_t *jp_off, const double *jp_x,
+                       const int64_t *jc_off, const double *jc_x, double box, double rcut,
+                       const double *gcenter)
+{
+    int64_t flips = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : flips)
+    for (int64_t g = 0; g < ng; ++g) {
+        const double *c = &gcenter[3 * g];
+        for (int64_t k = i_off[g]; k < i_off[g + 1]; ++k) {
+            const double *xi = &x[3 * i_idx[k]];
+            for (int64_t j = jp_off[g]; j < jp_off[g + 1]; ++j)
+                flips += orc_split_keep(ORC_MASK_ABS, &jp_x[3 * j], xi, c, box, rcut) !=
+                         orc_split_keep(ORC_MASK_F64_OFS, &jp_x[3 * j], xi, c, box, rcut);
+            for (int64_t j = jc_off[g]; j < jc_off[g + 1]; ++j)
+                flips += orc_split_keep(ORC_MASK_ABS, &jc_x[3 * j], xi, c, box, rcut) !=
+                         orc_split_keep(ORC_MASK_F64_OFS, &jc_x[3 * j], xi, c, box, rcut);
+        }
+    }
+    return flips;
 }
 
 /* Short-range point mass without the cutoff test: a = m D1(r) d,

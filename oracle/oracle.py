@@ -12,7 +12,7 @@ import numpy as np
 
 MONO, QUAD, SPLIT_QUAD, SPLIT_MONO, QUAD_SOFT = 0, 1, 2, 3, 4
 # how the split kernel's cutoff decision is taken (see orc_split_keep)
-MASK_ABS, MASK_F32_OFS, MASK_F64_OFS = 0, 1, 2
+MASK_ABS, MASK_F64_OFS = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
@@ -55,6 +55,9 @@ def lib():
                                _D, _I64, _D, _D, _I64, _D, _D, _D, _D,
                                ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_int, _D, _D, _D]
+        L.orc_mask_flips.restype = ctypes.c_int64
+        L.orc_mask_flips.argtypes = [ctypes.c_int64, _I64, _I64, _D, _I64, _D, _I64,
+                                     _D, ctypes.c_double, ctypes.c_double, _D]
         L.orc_split_keep.restype = ctypes.c_int
         L.orc_split_keep.argtypes = [ctypes.c_int, _D, _D, _D, ctypes.c_double,
                                      ctypes.c_double]
@@ -228,6 +231,22 @@ def eval_lists(kind, mat, x, eps2, box=0.0, rs=0.0, rcut=0.0,
                    _dp(jc_m), _dp(jc_q), _dp(jc_t), float(box), float(rs),
                    float(rcut), int(mask), _dp(gc), _dp(a), _dp(phi))
     return a, phi
+
+
+def mask_flips(mat, x, box, rcut):
+    """Number of terms of the materialised lists on which the cutoff
+    decision from absolute FP64 separations (the definition, MASK_ABS) and
+    the one from FP64 offsets to the group centres (MASK_F64_OFS) differ."""
+    x = _cd(x).reshape(-1, 3)
+    i_idx = np.ascontiguousarray(mat["i_idx"], np.int64)
+    i_off = np.ascontiguousarray(mat["i_off"], np.int64)
+    jp_off = np.ascontiguousarray(mat["jp_off"], np.int64)
+    jc_off = np.ascontiguousarray(mat["jc_off"], np.int64)
+    ng = i_off.shape[0] - 1
+    return int(lib().orc_mask_flips(ng, _ip(i_idx), _ip(i_off), _dp(x), _ip(jp_off),
+                                    _dp(_cd(mat["jp_x"])), _ip(jc_off),
+                                    _dp(_cd(mat["jc_x"])), float(box), float(rcut),
+                                    _dp(_cd(mat["gcenter"]))))
 
 
 def direct(x, m, eps2=0.0, targets=None, split=False, box=0.0, rs=0.0,

@@ -7,6 +7,7 @@ Compiles the HIP kernels, the C-ABI layer and the host list builder into
 for all device code (``-packed-fp32-ops``); the compiler emits plain VALU
 FP32 operations.
 """
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -43,7 +44,7 @@ def build(verbose=False, extra=()):
     cc = hipcc()
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
         cmd = [cc, "-c", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -55,8 +56,13 @@ def build(verbose=False, extra=()):
         cmd += list(extra) + ["-o", obj, os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append(cmd)
         objs.append(obj)
+    # the sources compile independently: one compiler process each
+    workers = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with concurrent.futures.ThreadPoolExecutor(workers) as pool:
+        for f in [pool.submit(subprocess.run, c, check=True) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + [
         "-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib", "-lpthread"]

@@ -55,9 +55,12 @@ __device__ __forceinline__ double rsq(double v) { return ::rsqrt(v); }
 __device__ __forceinline__ double erfc_r(double v) { return ::erfc(v); }
 __device__ __forceinline__ double exp_r(double v) { return ::exp(v); }
 
+// Minimum image v - box rint(v / box), rounded as written (no contraction of
+// the product into the subtraction), so that every kernel forms the same
+// FP64 offsets.
 __device__ __forceinline__ double wrap(double v, double box, double ibox)
 {
-    return box > 0.0 ? v - box * ::rint(v * ibox) : v;
+    return box > 0.0 ? __dsub_rn(v, __dmul_rn(box, ::rint(__dmul_rn(v, ibox)))) : v;
 }
 
 constexpr int kMono = 0, kQuad = 1, kSplitQuad = 2, kSplitMono = 3, kQuadSoft = 4;
@@ -198,26 +201,66 @@ __device__ __forceinline__ SplitG<R> split_g(R r, const SplitK<R> &K, const V4<f
     return s;
 }
 
-// Short-range particle: a += m g/r^3 d, -phi += m erfc(u)/r; masked at
-// r == 0 and r >= rcut.
-template <typename R>
-__device__ __forceinline__ void pp_split(const V4<R> &j, R xi, R yi, R zi,
-                                         const SplitK<R> &K, const V4<float> *tab, R rcut2,
-                                         R &ax, R &ay, R &az, R &pt)
+// The cutoff is a decision on r^2, which the FP32 kernels form from FP32
+// offsets.  It is taken as the FP64 kernel takes it: FP64 offsets
+// X = wrap(v - c) from the group centre c, D = X_j - X_i, r^2 =
+// fma(Dz, Dz, fma(Dy, Dy, Dx Dx)), kept iff 0 < r^2 < rcut * rcut in FP64.
+// Outside a band around fl32(rcut^2) the FP32 r^2 decides the same way; a
+// term inside the band (rare) is decided again from the FP64 positions.
+//
+// Band: with u = 2^-24, FP32 offsets x = X (1 + e), |e| <= u, the FP32
+// difference and the three-term FMA chain give, to first order in u,
+// |r2_32 - |D|^2| <= 7 u |D|^2 + 4 u |X_i| |D|, and fl32(rcut^2) is within
+// u rcut^2 of rcut^2 (the FP64 side is exact to 2^-50).  Near the cutoff
+// |D| ~ rcut, so u (8 rcut^2 + 4 |X_i| rcut) bounds the difference;
+// band_i = u (16 rcut^2 + 8 |X_i| rcut) doubles it.  A term with
+// |r2_32 - fl32(rcut^2)| >= band_i is on the same side in both precisions.
+__device__ __forceinline__ float cut_band(float xi, float yi, float zi, float rcut)
 {
-    const R dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
-    const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    if (r2 > R(0) && r2 < rcut2) {
-        const R rinv = rsq(r2);
-        const R r = r2 * rinv;
-        const SplitG<R> f = split_g<R, false>(r, K, tab);
-        const R mr = j.w * rinv;
-        const R c = mr * f.g * (rinv * rinv);
-        pt = fma(mr, f.ec, pt);
-        ax = fma(c, dx, ax);
-        ay = fma(c, dy, ay);
-        az = fma(c, dz, az);
-    }
+    const float xn = __builtin_sqrtf(fmaf(zi, zi, fmaf(yi, yi, xi * xi)));
+    return 0x1p-21f * rcut * fmaf(2.0f, rcut, xn);  // u (16 rcut^2 + 8 |X_i| rcut)
+}
+
+// FP64 cutoff decision of the FP64 kernel for the FP64 offsets xj - xi
+// (each already wrapped relative to the group centre).
+__device__ __forceinline__ bool keep_f64(double djx, double djy, double djz, double rcut)
+{
+    const double r2 = fma(djz, djz, fma(djy, djy, djx * djx));
+    return r2 > 0.0 && r2 < rcut * rcut;
+}
+
+// Separation of a list entry from an i-particle and its squared length.
+template <typename R>
+struct Sep {
+    R dx, dy, dz, r2;
+};
+
+template <typename R>
+__device__ __forceinline__ Sep<R> separation(const V4<R> &j, R xi, R yi, R zi)
+{
+    Sep<R> s;
+    s.dx = j.x - xi;
+    s.dy = j.y - yi;
+    s.dz = j.z - zi;
+    s.r2 = fma(s.dz, s.dz, fma(s.dy, s.dy, s.dx * s.dx));
+    return s;
+}
+
+// Short-range particle at separation s, kept by the cutoff decision:
+// a += m g/r^3 d, -phi += m erfc(u)/r.
+template <typename R>
+__device__ __forceinline__ void pp_split(const V4<R> &j, const Sep<R> &s, const SplitK<R> &K,
+                                         const V4<float> *tab, R &ax, R &ay, R &az, R &pt)
+{
+    const R rinv = rsq(s.r2);
+    const R r = s.r2 * rinv;
+    const SplitG<R> f = split_g<R, false>(r, K, tab);
+    const R mr = j.w * rinv;
+    const R c = mr * f.g * (rinv * rinv);
+    pt = fma(mr, f.ec, pt);
+    ax = fma(c, s.dx, ax);
+    ay = fma(c, s.dy, ay);
+    az = fma(c, s.dz, az);
 }
 
 // Short-range cell expanded to second order about its centre of mass
@@ -226,44 +269,40 @@ __device__ __forceinline__ void pp_split(const V4<R> &j, R xi, R yi, R zi,
 //   a   = [M D1 + D3 dQd / 6 + T/6 (D3 r^2 + 5 D2)] d + D2/3 Qd
 // with D1 = g/r^3, D2 = -(3g + h)/r^5, D3 = (15g + 5h + k)/r^7.
 template <typename R, bool QUAD>
-__device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b,
-                                         const V4<R> &c, R xi, R yi, R zi,
-                                         const SplitK<R> &K, const V4<float> *tab, R rcut2,
-                                         R &ax, R &ay, R &az, R &pt)
+__device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b, const V4<R> &c,
+                                         const Sep<R> &s, const SplitK<R> &K,
+                                         const V4<float> *tab, R &ax, R &ay, R &az, R &pt)
 {
-    const R dx = a.x - xi, dy = a.y - yi, dz = a.z - zi;
-    const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    if (r2 > R(0) && r2 < rcut2) {
-        const R rinv = rsq(r2);
-        const R r = r2 * rinv;
-        const R rinv2 = rinv * rinv;
-        const SplitG<R> f = split_g<R, QUAD>(r, K, tab);
-        const R D1 = f.g * rinv2 * rinv;
-        R phi = -a.w * f.ec * rinv;  // M Phi
-        R coef = a.w * D1;
-        if (QUAD) {
-            const R rinv5 = rinv2 * rinv2 * rinv;
-            const R D2 = -f.g2 * rinv5;
-            const R D3 = f.g3 * rinv5 * rinv2;
-            const R qx = fma(b.z, dz, fma(b.y, dy, b.x * dx));
-            const R qy = fma(c.x, dz, fma(b.w, dy, b.y * dx));
-            const R qz = fma(c.y, dz, fma(c.x, dy, b.z * dx));
-            const R dqd = fma(dz, qz, fma(dy, qy, dx * qx));
-            const R t6 = c.z * R(1.0 / 6.0);
-            phi = fma(D2, dqd * R(1.0 / 6.0), phi);
-            phi = fma(t6, fma(D2, r2, R(3) * D1), phi);
-            coef = fma(D3, dqd * R(1.0 / 6.0), coef);
-            coef = fma(t6, fma(D3, r2, R(5) * D2), coef);
-            const R d23 = D2 * R(1.0 / 3.0);
-            ax = fma(d23, qx, ax);
-            ay = fma(d23, qy, ay);
-            az = fma(d23, qz, az);
-        }
-        pt -= phi;
-        ax = fma(coef, dx, ax);
-        ay = fma(coef, dy, ay);
-        az = fma(coef, dz, az);
+    const R dx = s.dx, dy = s.dy, dz = s.dz, r2 = s.r2;
+    const R rinv = rsq(r2);
+    const R r = r2 * rinv;
+    const R rinv2 = rinv * rinv;
+    const SplitG<R> f = split_g<R, QUAD>(r, K, tab);
+    const R D1 = f.g * rinv2 * rinv;
+    R phi = -a.w * f.ec * rinv;  // M Phi
+    R coef = a.w * D1;
+    if (QUAD) {
+        const R rinv5 = rinv2 * rinv2 * rinv;
+        const R D2 = -f.g2 * rinv5;
+        const R D3 = f.g3 * rinv5 * rinv2;
+        const R qx = fma(b.z, dz, fma(b.y, dy, b.x * dx));
+        const R qy = fma(c.x, dz, fma(b.w, dy, b.y * dx));
+        const R qz = fma(c.y, dz, fma(c.x, dy, b.z * dx));
+        const R dqd = fma(dz, qz, fma(dy, qy, dx * qx));
+        const R t6 = c.z * R(1.0 / 6.0);
+        phi = fma(D2, dqd * R(1.0 / 6.0), phi);
+        phi = fma(t6, fma(D2, r2, R(3) * D1), phi);
+        coef = fma(D3, dqd * R(1.0 / 6.0), coef);
+        coef = fma(t6, fma(D3, r2, R(5) * D2), coef);
+        const R d23 = D2 * R(1.0 / 3.0);
+        ax = fma(d23, qx, ax);
+        ay = fma(d23, qy, ay);
+        az = fma(d23, qz, az);
     }
+    pt -= phi;
+    ax = fma(coef, dx, ax);
+    ay = fma(coef, dy, ay);
+    az = fma(coef, dz, az);
 }
 
 // Compile-time tuning: unroll depth of the inner loops, and the occupancy
@@ -311,9 +350,10 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
     const SplitK<R> K = split_k<R>(kSplit ? A.rs : 1.0);
     const R rcut2 = kSplit ? R(A.rcut * A.rcut) : R(0);
     const bool indexed = A.jp_idx != nullptr;
-    auto rel = [&](double v, double c) -> R {
-        return PERIODIC ? R(wrap(v - c, box, ibox)) : R(v - c);
+    auto rel64 = [&](double v, double c) -> double {
+        return PERIODIC ? wrap(v - c, box, ibox) : v - c;
     };
+    auto rel = [&](double v, double c) -> R { return R(rel64(v, c)); };
 
     for (int64_t ib = 0; ib < ni; ib += (int64_t)BS * IB) {
         // nic i-particles in this pass, P threads per slice owning IB each
@@ -328,7 +368,11 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
         const int islot = t - slice * P;
         const bool active = slice < S;
 
-        R xi[IB], yi[IB], zi[IB], e2[IB];
+        // Cutoff limits per owned i-particle (split kernels): a term with
+        // r^2 < lim is kept, one with lim <= r^2 < hi lies in the FP32 band
+        // and is decided again in FP64 after the tile (FP32 only; FP64 keeps
+        // r^2 < rcut^2 directly).
+        R xi[IB], yi[IB], zi[IB], e2[IB], lim[IB], hi[IB];
 #pragma unroll
         for (int u = 0; u < IB; ++u) {
             // an i-slot past the end repeats a valid particle; its sums are
@@ -343,7 +387,53 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                 zi[u] = rel(A.zi[i], cz);
                 e2[u] = R(A.e2i[i]);
             }
+            lim[u] = hi[u] = rcut2;
+            if constexpr (kSplit && std::is_same<R, float>::value) {
+                const float band = cut_band(xi[u], yi[u], zi[u], float(A.rcut));
+                lim[u] = rcut2 - band;
+                hi[u] = rcut2 + band;
+            }
         }
+        // FP64 cutoff decision for i-slot u and entry e of the current tile
+        // (list position first + e).
+        auto exact = [&](int u, int64_t first, int e, bool cells) -> bool {
+            // the empty asm keeps the compiler from computing these
+            // addresses ahead of the tile loops (they would stay live there)
+            int lu = islot + u * P;
+            asm volatile("" : "+v"(lu), "+v"(e));
+            const int64_t i = i0 + ib + (lu < nic ? lu : islot);
+            const int64_t j = first + e;
+            double x, y, z;
+            if (cells) {
+                if (indexed) {
+                    const CellRec *C = A.pool_c + A.jc_idx[j];
+                    x = C->x, y = C->y, z = C->z;
+                } else {
+                    x = A.jcx[j], y = A.jcy[j], z = A.jcz[j];
+                }
+            } else {
+                if (indexed) {
+                    const PartRec *Q = A.pool_p + A.jp_idx[j];
+                    x = Q->x, y = Q->y, z = Q->z;
+                } else {
+                    x = A.jpx[j], y = A.jpy[j], z = A.jpz[j];
+                }
+            }
+            return keep_f64(rel64(x, cx) - rel64(A.xi[i], cx), rel64(y, cy) - rel64(A.yi[i], cy),
+                            rel64(z, cz) - rel64(A.zi[i], cz), A.rcut);
+        };
+        // Separations of entry jv from every owned i-particle and the
+        // cutoff decisions of the tile loops (split kernels); near collects
+        // whether a term fell in the FP32 band.
+        auto decide = [&](const V4<R> &jv, Sep<R> (&sp)[IB], bool (&keep)[IB], bool &near) {
+#pragma unroll
+            for (int u = 0; u < IB; ++u) {
+                sp[u] = separation(jv, xi[u], yi[u], zi[u]);
+                const bool lo = sp[u].r2 < lim[u];
+                keep[u] = sp[u].r2 > R(0) && lo;
+                if constexpr (std::is_same<R, float>::value) near |= !lo && sp[u].r2 < hi[u];
+            }
+        };
         R ax[IB], ay[IB], az[IB], pt[IB];
 #pragma unroll
         for (int u = 0; u < IB; ++u) ax[u] = ay[u] = az[u] = pt[u] = R(0);
@@ -381,17 +471,40 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
 #pragma unroll
                 for (int u = 0; u < IB; ++u) bx[u] = by[u] = bz[u] = bp[u] = R(0);
                 const V4<R> *pa = sa + slice * it;
+                bool near = false;
 #pragma unroll BHQ_UNROLL
                 for (int k = 0; k < it; ++k) {
                     const V4<R> jv = pa[k];
+                    if constexpr (kSplit) {
+                        Sep<R> sp[IB];
+                        bool keep[IB];
+                        decide(jv, sp, keep, near);
 #pragma unroll
-                    for (int u = 0; u < IB; ++u) {
-                        if (kSplit)
-                            pp_split(jv, xi[u], yi[u], zi[u], K, tab, rcut2, bx[u],
-                                     by[u], bz[u], bp[u]);
-                        else
-                            pp_plummer(jv, xi[u], yi[u], zi[u], e2[u], bx[u],
-                                       by[u], bz[u], bp[u]);
+                        for (int u = 0; u < IB; ++u)
+                            if (keep[u]) pp_split(jv, sp[u], K, tab, bx[u], by[u], bz[u], bp[u]);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < IB; ++u)
+                            pp_plummer(jv, xi[u], yi[u], zi[u], e2[u], bx[u], by[u], bz[u],
+                                       bp[u]);
+                    }
+                }
+                if constexpr (kSplit && std::is_same<R, float>::value) {
+                    // Band terms (rare): a lane that flagged one goes over
+                    // its entries again, decides each band term in FP64 and
+                    // adds the kept ones after the tile's other terms.
+                    if (__builtin_expect(near, 0)) {
+#pragma unroll 1
+                        for (int k = 0; k < it; ++k) {
+                            const V4<R> jv = pa[k];
+#pragma unroll
+                            for (int u = 0; u < IB; ++u) {
+                                const Sep<R> sp = separation(jv, xi[u], yi[u], zi[u]);
+                                if (sp.r2 >= lim[u] && sp.r2 < hi[u] &&
+                                    exact(u, p0 + base, slice * it + k, false))
+                                    pp_split(jv, sp, K, tab, bx[u], by[u], bz[u], bp[u]);
+                            }
+                        }
                     }
                 }
 #pragma unroll
@@ -466,6 +579,7 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
 #pragma unroll
                 for (int u = 0; u < IB; ++u) bx[u] = by[u] = bz[u] = bp[u] = R(0);
                 const int e0 = slice * it;
+                bool near = false;
 #pragma unroll BHQ_UNROLL
                 for (int k = 0; k < it; ++k) {
                     const int e = e0 + k;
@@ -475,23 +589,48 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                         jb = sb[e];
                         jc = sc[e];
                     }
+                    if constexpr (kSplit) {
+                        Sep<R> sp[IB];
+                        bool keep[IB];
+                        decide(ja, sp, keep, near);
 #pragma unroll
-                    for (int u = 0; u < IB; ++u) {
-                        if (KIND == kQuad || KIND == kQuadSoft)
-                            pc_quad<R, KIND == kQuadSoft>(ja, jb, jc, xi[u], yi[u],
-                                                          zi[u], e2[u], bx[u], by[u],
-                                                          bz[u], bp[u]);
-                        else if (KIND == kMono)
-                            pp_plummer(ja, xi[u], yi[u], zi[u], e2[u], bx[u],
-                                       by[u], bz[u], bp[u]);
-                        else if (KIND == kSplitQuad)
-                            pc_split<R, true>(ja, jb, jc, xi[u], yi[u], zi[u],
-                                              K, tab, rcut2, bx[u], by[u], bz[u],
-                                              bp[u]);
-                        else
-                            pc_split<R, false>(ja, jb, jc, xi[u], yi[u], zi[u],
-                                               K, tab, rcut2, bx[u], by[u], bz[u],
-                                               bp[u]);
+                        for (int u = 0; u < IB; ++u)
+                            if (keep[u])
+                                pc_split<R, KIND == kSplitQuad>(ja, jb, jc, sp[u], K, tab, bx[u],
+                                                                by[u], bz[u], bp[u]);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < IB; ++u) {
+                            if (KIND == kQuad || KIND == kQuadSoft)
+                                pc_quad<R, KIND == kQuadSoft>(ja, jb, jc, xi[u], yi[u], zi[u],
+                                                              e2[u], bx[u], by[u], bz[u], bp[u]);
+                            else
+                                pp_plummer(ja, xi[u], yi[u], zi[u], e2[u], bx[u], by[u], bz[u],
+                                           bp[u]);
+                        }
+                    }
+                }
+                if constexpr (kSplit && std::is_same<R, float>::value) {
+                    // band terms, as for the particles
+                    if (__builtin_expect(near, 0)) {
+#pragma unroll 1
+                        for (int k = 0; k < it; ++k) {
+                            const int e = e0 + k;
+                            const V4<R> ja = sa[e];
+                            V4<R> jb, jc;
+                            if (kCellQ) {
+                                jb = sb[e];
+                                jc = sc[e];
+                            }
+#pragma unroll
+                            for (int u = 0; u < IB; ++u) {
+                                const Sep<R> sp = separation(ja, xi[u], yi[u], zi[u]);
+                                if (sp.r2 >= lim[u] && sp.r2 < hi[u] &&
+                                    exact(u, c0 + base, e, true))
+                                    pc_split<R, KIND == kSplitQuad>(ja, jb, jc, sp, K, tab,
+                                                                    bx[u], by[u], bz[u], bp[u]);
+                            }
+                        }
                     }
                 }
 #pragma unroll

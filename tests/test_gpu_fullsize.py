@@ -8,8 +8,9 @@ check on smaller inputs).
 
 Bars: FP32 with FP64 offsets <= 2e-6 rms and <= 1e-4 max relative
 acceleration error per particle; FP64 <= 1e-12 rms and <= 1e-10 max.  For
-the short-range split kernel the cutoff is decided the way each kernel
-precision decides it.
+the short-range split kernel the oracle decides the cutoff from FP64
+offsets to the group centres, which on the compared lists is shown to agree
+with the definition's absolute FP64 separations term by term.
 """
 import numpy as np
 import pytest
@@ -19,8 +20,6 @@ from _parity import assert_parity, errors, log
 from paper_1812_07313_amd import bhq, synth
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
-
-SPLIT_MASK = {bhq.FP32_OFS64: orc.MASK_F32_OFS, bhq.FP64: orc.MASK_F64_OFS}
 
 
 def _gpu_product(x, m, theta, ncrit, kernel, eps=None, eps2=None, box=0.0,
@@ -131,12 +130,12 @@ def test_periodic_lattice_16m_sampled():
     T = orc.Tree(x, m, 0.5, 64, box=1.0, rcut=rcut, walk_stride=2000)
     groups = np.arange(0, T.ngroups, 2000)
     mat = T.sample_mat(x, m, groups)
-
-    def ref(prec):
-        return orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=1.0, rs=rs,
-                              rcut=rcut, mask=SPLIT_MASK[prec])
-
-    _check("lattice", gpu, ref, mat["i_idx"])
+    flips = orc.mask_flips(mat, x, 1.0, rcut)
+    log("  cutoff decisions differing from the definition's: %d" % flips)
+    assert flips == 0
+    ref = orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=1.0, rs=rs, rcut=rcut,
+                         mask=orc.MASK_F64_OFS)
+    _check("lattice", gpu, lambda prec: ref, mat["i_idx"])
 
 
 @pytest.mark.parametrize("which", ["cube", "clustered", "lattice", "batched"])

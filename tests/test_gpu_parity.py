@@ -17,7 +17,6 @@ pytestmark = pytest.mark.gpu
 KINDS = [(bhq.QUAD, orc.QUAD), (bhq.MONO, orc.MONO),
          (bhq.QUAD_SOFT, orc.QUAD_SOFT)]
 PRECS = [bhq.FP32_OFS64, bhq.FP64]
-SPLIT_MASK = {bhq.FP32_OFS64: orc.MASK_F32_OFS, bhq.FP64: orc.MASK_F64_OFS}
 
 
 @pytest.fixture(scope="module")
@@ -253,14 +252,15 @@ def test_split_kernel_periodic(ctx, nside):
     log("case split lattice %d^3 rs=%g rcut=%g" % (nside, rs, rcut))
     T = orc.Tree(x, m, 0.5, 64, box=1.0, rcut=rcut)
     mat = orc.materialise(T, x, m)
+    # the cutoff decisions from FP64 offsets to the group centres are the
+    # definition's (absolute FP64 separations) on every term of these lists
+    assert orc.mask_flips(mat, x, 1.0, rcut) == 0
     upload(ctx, mat, x, split=(rs, rcut, 1.0))
     for bk, ok in ((bhq.SPLIT_QUAD, orc.SPLIT_QUAD),
                    (bhq.SPLIT_MONO, orc.SPLIT_MONO)):
         for prec in PRECS:
-            # the cutoff is decided as the kernel decides it (a discrete
-            # choice made in floating point); the terms stay FP64
             a_ref, p_ref = orc.eval_lists(ok, mat, x, 0.0, box=1.0, rs=rs,
-                                          rcut=rcut, mask=SPLIT_MASK[prec])
+                                          rcut=rcut, mask=orc.MASK_F64_OFS)
             log("  kernel=%s precision=%s" % (bhq.KERNEL_NAMES[bk],
                                                bhq.PRECISION_NAMES[prec]))
             a, p = run(ctx, mat, len(m), bk, prec)
@@ -309,20 +309,96 @@ def test_index_lists_equal_materialised(ctx):
 
 
 def test_split_fp32_cutoff_range(ctx):
-    """FP32 split kernels evaluate erfc for r / 2r_s <= 3 only: a cutoff
-    beyond 6 r_s is refused for FP32 and accepted for FP64."""
+    """FP32 split kernels take erfc and the related functions from a table
+    of r / 2r_s in [0, 2.5] (plus one interval for the rounding of r at the
+    cutoff): a cutoff of 5 r_s is accepted and evaluated to the FP32 bar,
+    5.2 r_s and 7.5 r_s are refused for FP32 and accepted for FP64."""
     x, m = synth.perturbed_lattice(8, synth.rng(4))
-    T = orc.Tree(x, m, 0.5, 64, box=1.0, rcut=0.3)
+    rs = 0.04
+    for rcut in (0.3, 5.2 * rs):
+        T = orc.Tree(x, m, 0.5, 64, box=1.0, rcut=rcut)
+        mat = orc.materialise(T, x, m)
+        upload(ctx, mat, x, split=(rs, rcut, 1.0))
+        bhq.bhq_set_kernel(ctx, bhq.SPLIT_QUAD, bhq.FP32_OFS64)
+        with pytest.raises(bhq.BhqError) as ei:
+            bhq.bhq_compute(ctx)
+        assert ei.value.code == bhq.E_ARG
+        a_ref, p_ref = orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=1.0, rs=rs,
+                                      rcut=rcut, mask=orc.MASK_F64_OFS)
+        a, p = run(ctx, mat, len(m), bhq.SPLIT_QUAD, bhq.FP64)
+        assert_parity(errors(a, p, a_ref, p_ref), bhq.FP64, "split fp64 rcut %g" % rcut)
+    # the accepted edge: terms out to u = 2.5, the last table interval
+    # (group cells of 1/8 plus 2 rcut stay below half the box)
+    x, m = synth.perturbed_lattice(24, synth.rng(5))
+    rs = 1.25 / 64
+    rcut = 5.0 * rs
+    T = orc.Tree(x, m, 0.5, 64, box=1.0, rcut=rcut)
     mat = orc.materialise(T, x, m)
-    upload(ctx, mat, x, split=(0.04, 0.3, 1.0))   # rcut = 7.5 rs
-    bhq.bhq_set_kernel(ctx, bhq.SPLIT_QUAD, bhq.FP32_OFS64)
-    with pytest.raises(bhq.BhqError) as ei:
-        bhq.bhq_compute(ctx)
-    assert ei.value.code == bhq.E_ARG
-    a_ref, p_ref = orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=1.0, rs=0.04,
-                                  rcut=0.3, mask=orc.MASK_F64_OFS)
-    a, p = run(ctx, mat, len(m), bhq.SPLIT_QUAD, bhq.FP64)
-    assert_parity(errors(a, p, a_ref, p_ref), bhq.FP64, "split fp64 wide cutoff")
+    assert orc.mask_flips(mat, x, 1.0, rcut) == 0
+    upload(ctx, mat, x, split=(rs, rcut, 1.0))
+    for bk, ok in ((bhq.SPLIT_QUAD, orc.SPLIT_QUAD), (bhq.SPLIT_MONO, orc.SPLIT_MONO)):
+        a_ref, p_ref = orc.eval_lists(ok, mat, x, 0.0, box=1.0, rs=rs, rcut=rcut,
+                                      mask=orc.MASK_F64_OFS)
+        for prec in PRECS:
+            a, p = run(ctx, mat, len(m), bk, prec)
+            err = errors(a, p, a_ref, p_ref)
+            log("  rcut = 5 rs kernel=%s precision=%s %s"
+                % (bhq.KERNEL_NAMES[bk], bhq.PRECISION_NAMES[prec], err))
+            assert_parity(err, prec, "split rcut = 5 rs")
+
+
+def _band_pairs(rcut, deltas, seed):
+    """Isolated pairs in the periodic unit box, pair k at separation
+    rcut (1 + deltas[k]) along a random direction, pairs 0.2 apart."""
+    g = np.random.default_rng(seed)
+    n = len(deltas)
+    side = int(np.ceil(n ** (1.0 / 3.0)))
+    x = np.zeros((2 * n, 3))
+    for k, dlt in enumerate(deltas):
+        c = (np.array([k % side, (k // side) % side, k // side ** 2]) + 0.5) / side
+        c = c + g.uniform(-0.02, 0.02, 3)
+        u = g.normal(size=3)
+        u /= np.linalg.norm(u)
+        x[2 * k] = c
+        x[2 * k + 1] = c + rcut * (1.0 + dlt) * u
+    return np.mod(x, 1.0), np.full(2 * n, 1.0 / (2 * n))
+
+
+@pytest.mark.parametrize("ncrit,nleaf", [(2, 2), (16, 8)])
+def test_split_cutoff_band_pairs(ctx, ncrit, nleaf):
+    """Pairs whose separation lies within FP32 rounding of the cutoff (the
+    band where FP32 r^2 cannot tell the sides apart): the FP32 split kernels
+    take every such decision as the FP64 definition does, so each pair's
+    force is the oracle's (within the FP32 bar) or exactly zero with it.
+    Groups of one pair, and of eight pairs (i-particles up to ~0.2 from the
+    group centre, which widens the band)."""
+    rs = 1.25 / 256
+    rcut = 4.5 * rs
+    mags = np.geomspace(1e-9, 1e-6, 32)
+    deltas = np.concatenate([mags, -mags])
+    x, m = _band_pairs(rcut, deltas, 11)
+    log("case band pairs ncrit=%d nleaf=%d" % (ncrit, nleaf))
+    T = orc.Tree(x, m, 0.0, ncrit, nleaf=nleaf, box=1.0, rcut=rcut)
+    mat = orc.materialise(T, x, m)
+    assert orc.mask_flips(mat, x, 1.0, rcut) == 0
+    upload(ctx, mat, x, split=(rs, rcut, 1.0))
+    a_ref, p_ref = orc.eval_lists(orc.SPLIT_MONO, mat, x, 0.0, box=1.0, rs=rs, rcut=rcut,
+                                  mask=orc.MASK_F64_OFS)
+    kept = np.any(a_ref != 0.0, axis=1)
+    # both decisions occur, and they follow the sign of the offset from rcut
+    assert np.array_equal(kept[0::2], deltas < 0) and np.array_equal(kept[1::2], deltas < 0)
+    for bk in (bhq.SPLIT_MONO, bhq.SPLIT_QUAD):
+        for prec in PRECS:
+            a, p = run(ctx, mat, len(m), bk, prec)
+            log("  band pairs kernel=%s precision=%s: %d of %d particles kept"
+                % (bhq.KERNEL_NAMES[bk], bhq.PRECISION_NAMES[prec],
+                   int(np.any(a != 0.0, axis=1).sum()), len(m)))
+            assert np.array_equal(np.any(a != 0.0, axis=1), kept), (bk, prec)
+            assert np.array_equal(p != 0.0, kept), (bk, prec)
+            ea = orc.relative_errors(a[kept], a_ref[kept])
+            ep = np.abs(p[kept] - p_ref[kept]) / np.abs(p_ref[kept])
+            tol = 1e-5 if prec == bhq.FP32_OFS64 else 1e-12
+            assert ea.max() <= tol and ep.max() <= tol, (bk, prec, ea.max(), ep.max())
 
 
 def test_index_lists_split_periodic(ctx):
@@ -335,7 +411,7 @@ def test_index_lists_split_periodic(ctx):
     _upload_indexed(ctx, T, mat, x, m, split=(rs, rcut, box))
     for prec in PRECS:
         a_ref, p_ref = orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=box,
-                                      rs=rs, rcut=rcut, mask=SPLIT_MASK[prec])
+                                      rs=rs, rcut=rcut, mask=orc.MASK_F64_OFS)
         a, p = run(ctx, mat, len(m), bhq.SPLIT_QUAD, prec)
         err = errors(a, p, a_ref, p_ref)
         log("  precision=%s %s" % (bhq.PRECISION_NAMES[prec], err))

@@ -210,7 +210,7 @@ def test_split_pair_gradient(orc):
 
 
 def test_split_cutoff_decision_modes(orc):
-    """The cutoff decision taken as the FP32 / FP64 kernels take it agrees
+    """The cutoff decision taken from FP64 offsets to a group centre agrees
     with the definition (FP64, absolute separations) everywhere except
     within rounding of r = rcut; the self pair is always excluded."""
     g = np.random.default_rng(21)
@@ -225,25 +225,55 @@ def test_split_cutoff_decision_modes(orc):
         d -= np.rint(d)
         r = np.linalg.norm(d)
         modes = [orc.split_keep(mm, xj, xi, c, box, rcut)
-                 for mm in (orc.MASK_ABS, orc.MASK_F32_OFS, orc.MASK_F64_OFS)]
+                 for mm in (orc.MASK_ABS, orc.MASK_F64_OFS)]
         assert modes[0] == (r < rcut)
-        if abs(r - rcut) > 1e-5 * rcut:
-            assert modes[0] == modes[1] == modes[2]
+        if abs(r - rcut) > 1e-12 * rcut:
+            assert modes[0] == modes[1]
             agree += 1
-    assert agree > 3900
-    for mm in (orc.MASK_ABS, orc.MASK_F32_OFS, orc.MASK_F64_OFS):
+    assert agree > 3990
+    for mm in (orc.MASK_ABS, orc.MASK_F64_OFS):
         assert not orc.split_keep(mm, c, c, c, box, rcut)
     # just inside / outside the cutoff along an axis, far from rounding
     xi = c.copy()
     for frac, keep in ((0.999, True), (1.001, False)):
         xj = xi + np.array([rcut * frac, 0, 0])
-        for mm in (orc.MASK_ABS, orc.MASK_F32_OFS, orc.MASK_F64_OFS):
+        for mm in (orc.MASK_ABS, orc.MASK_F64_OFS):
             assert orc.split_keep(mm, xj, xi, c, box, rcut) == keep
     # minimum image across the periodic boundary
     xi = np.array([0.999, 0.5, 0.5])
     xj = np.array([0.004, 0.5, 0.5])
-    for mm in (orc.MASK_ABS, orc.MASK_F32_OFS, orc.MASK_F64_OFS):
+    for mm in (orc.MASK_ABS, orc.MASK_F64_OFS):
         assert orc.split_keep(mm, xj, xi, np.array([0.995, 0.5, 0.5]), box, rcut)
+
+
+def test_mask_flips_counts_disagreements(orc):
+    """mask_flips counts exactly the terms on which the two decisions
+    differ: a pair placed within an ulp of the cutoff, where they can
+    disagree, is found by search and counted once (in both directions of
+    the pair list); lists far from the cutoff give zero."""
+    g = np.random.default_rng(5)
+    rcut, box = 0.0215, 1.0
+    found = None
+    for _ in range(20000):
+        xi = g.uniform(0.3, 0.7, 3)
+        u = g.normal(size=3)
+        u /= np.linalg.norm(u)
+        xj = xi + rcut * u * (1.0 + g.uniform(-4e-16, 4e-16))
+        c = xi + g.uniform(-0.01, 0.01, 3)
+        if orc.split_keep(orc.MASK_ABS, xj, xi, c, box, rcut) != \
+                orc.split_keep(orc.MASK_F64_OFS, xj, xi, c, box, rcut):
+            found = (xi, xj, c)
+            break
+    assert found is not None
+    xi, xj, c = found
+    x = np.array([xi, xj])
+    mat = dict(i_idx=np.array([0], np.int64), i_off=np.array([0, 1], np.int64),
+               jp_off=np.array([0, 2], np.int64), jp_x=x.copy(),
+               jc_off=np.array([0, 0], np.int64), jc_x=np.zeros((0, 3)),
+               gcenter=c.reshape(1, 3))
+    assert orc.mask_flips(mat, x, box, rcut) == 1
+    mat["jp_x"] = np.array([xi, xi + np.array([0.5 * rcut, 0, 0])])
+    assert orc.mask_flips(mat, x, box, rcut) == 0
 
 
 # --- the complete softened quadrupole (with the trace term) ---------------------
