@@ -460,6 +460,8 @@ def main():
                     help="i-particles per thread (1 or 2)")
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--jsplit", type=int, default=1,
+                    help="parts each group's lists are cut into (1, 2, 4, 8)")
     ap.add_argument("--order", default="xcd", choices=["xcd", "cost"],
                     help="group dispatch order: contiguous pieces of equal "
                          "cost per XCD (windows sorted longest first), or "
@@ -531,6 +533,7 @@ def main():
         W["ncrit"] = tuned["ncrit"]
         args.block, args.persistent = tuned["block"], tuned["persistent"]
         args.ipt = tuned["i_per_thread"]
+        args.graph, args.jsplit = tuned["use_graph"], tuned["jsplit"]
         args.order = {v: k for k, v in ORDERS.items()}[tuned["order"]]
         log("autotuned: %s" % tuned)
     L, t_build = build_lists(W, W["theta"], W["ncrit"])
@@ -546,7 +549,7 @@ def main():
         bhq.bhq_lists_free(L)
         bhq.bhq_set_tuning(ctx, args.block, args.ipt,
                            tuned["blocks_per_cu"] if tuned else 0,
-                           args.persistent, args.graph)
+                           args.persistent, args.graph, args.jsplit)
         bhq.bhq_set_group_order(ctx, ORDERS[args.order], args.order_window,
                                 args.order_tail)
         n_pp, n_pc = bhq.bhq_get_counts(ctx)
@@ -647,7 +650,8 @@ def main():
                    "lists": args.lists, "autotuned": tuned,
                    "launch": {"block": args.block, "i_per_thread": args.ipt,
                               "persistent": args.persistent,
-                              "graph": args.graph, "order": args.order,
+                              "graph": args.graph, "jsplit": args.jsplit,
+                              "order": args.order,
                               "order_window": args.order_window,
                               "order_tail": args.order_tail}},
         "s_per_force_eval": round(ms_step * 1e-3, 6),

@@ -194,27 +194,39 @@ int bhq_get_counts(const bhq_ctx *ctx, int64_t *n_pp, int64_t *n_pc);
  * measured with HIP events on the compute stream.  Waits for it. */
 int bhq_get_kernel_ms(bhq_ctx *ctx, double *ms);
 
-/* Launch shape (an autotuner's knobs).
- *   block          threads per block and LDS tile depth: 128 or 256 (0: 256)
- *   i_per_thread   i-particles owned by each thread: 1 or 2 (0: 2)
- *   blocks_per_cu  persistent grid size per compute unit (0: as many blocks
- *                  as fit), ignored when persistent == 0
+/* Launch shape: the autotuner's knobs (ncrit, the other knob, shapes the
+ * lists; the group size n_crit is the paper's tuning parameter, Sec. 3.4).
+ *   block          threads per block, which is also the depth of one LDS
+ *                  tile of list entries: 128 or 256 (0: 256)
+ *   i_per_thread   i-particles owned by each thread, so that one LDS read of
+ *                  a list entry feeds that many interactions (the paper packs
+ *                  i-particles into SIMD registers for the same reuse,
+ *                  Sec. 3.3): 1 or 2 (0: 2)
+ *   blocks_per_cu  persistent grid size per compute unit, i.e. resident
+ *                  blocks (waves) per CU (0: as many blocks as fit), ignored
+ *                  when persistent == 0
  *   persistent     0: one block per launch slot of the group order
  *                  (bhq_set_group_order); 1: a machine-sized grid pulls
  *                  groups in that order from device counters
  *   use_graph      1: bhq_compute records its launches into a HIP graph once
  *                  and replays it while kernel, precision, shape and data
  *                  layout are unchanged (re-recorded otherwise)
+ *   jsplit         1, 2, 4 or 8 (0: 1): each group's particle and cell lists
+ *                  are cut into jsplit parts of nearly equal length, taken by
+ *                  different blocks, whose partial sums a second kernel adds
+ *                  in part order (for inputs with too few groups to fill the
+ *                  GPU, the small-N regime of Sec. 5.2); the context keeps a
+ *                  buffer of 32 jsplit ni bytes for the parts
  * The persistent queue and graph replay do not change results (bitwise).
- * block and i_per_thread change how a group's list is split across
- * threads and so the order of the FP32/FP64 sums (results agree to
- * rounding).  Errors: BHQ_E_ARG for values outside these sets. */
+ * block, i_per_thread and jsplit change how a group's lists are split
+ * across threads and blocks and so the order of the FP32/FP64 sums (results
+ * agree to rounding).  Errors: BHQ_E_ARG for values outside these sets. */
 int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread,
-                   int blocks_per_cu, int persistent, int use_graph);
+                   int blocks_per_cu, int persistent, int use_graph, int jsplit);
 
-/* Current launch shape: out[0..4] = block, i_per_thread, blocks_per_cu,
- * persistent, use_graph. */
-int bhq_get_tuning(const bhq_ctx *ctx, int out[5]);
+/* Current launch shape: out[0..5] = block, i_per_thread, blocks_per_cu,
+ * persistent, use_graph, jsplit. */
+int bhq_get_tuning(const bhq_ctx *ctx, int out[6]);
 
 /* Order in which groups are handed to blocks.  Group g costs
  * c_g = ni_g (100 njp_g + 265 njc_g + 100), in 64-bit integers (a cell term

@@ -33,7 +33,7 @@ enum Arr {
     A_AX, A_AY, A_AZ, A_POT,
     A_QUEUE,
     A_POOLP, A_POOLC, A_JPIDX, A_JCIDX,
-    A_TORDER, A_ENERGY, A_OSCRATCH, A_SORTSCRATCH,
+    A_TORDER, A_ENERGY, A_OSCRATCH, A_SORTSCRATCH, A_PART,
     A_COUNT
 };
 
@@ -168,7 +168,7 @@ struct bhq_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     struct {
-        int kernel, precision, block, i_per_thread, persistent, blocks_per_cu;
+        int kernel, precision, block, i_per_thread, persistent, blocks_per_cu, jsplit;
         uint64_t version;
     } graph_key{};
 
@@ -203,10 +203,18 @@ struct bhq_ctx {
         hipError_t e = hipSetDevice(device);
         return e == hipSuccess ? BHQ_OK : hip_fail(e, "hipSetDevice");
     }
+    // Wait until the last compute has finished with the inputs (it may run
+    // on a stream that does not synchronise with the null stream, which the
+    // host uploads use).
+    void quiesce()
+    {
+        if (launched) (void)hipEventSynchronize(ev1);
+    }
     // Upload n doubles to array a at element offset off.
     int put(Arr a, int64_t off, const double *src, int64_t n)
     {
         if (n == 0) return BHQ_OK;
+        quiesce();
         hipError_t e = hipMemcpy(arr[a].as<double>() + off, src,
                                  (size_t)n * sizeof(double),
                                  hipMemcpyHostToDevice);
@@ -233,6 +241,7 @@ struct bhq_ctx {
             return fail(BHQ_E_STATE, "lists already given as indices since "
                                      "the last set_groups");
         if (list_mode == 1) return BHQ_OK;
+        quiesce();
         const size_t D = sizeof(double);
         const Arr jp[] = {A_JPX, A_JPY, A_JPZ, A_JPM};
         const Arr jc[] = {A_JCX, A_JCY, A_JCZ, A_JCM, A_Q00, A_Q01, A_Q02,
@@ -255,6 +264,7 @@ struct bhq_ctx {
             return fail(BHQ_E_STATE, "lists already materialised since the "
                                      "last set_groups");
         if (list_mode == 2) return BHQ_OK;
+        quiesce();
         hipError_t e = arr[A_JPIDX].reserve((size_t)njp * 4);
         if (e == hipSuccess) e = arr[A_JCIDX].reserve((size_t)njc * 4);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc");
@@ -677,9 +687,10 @@ int bhq_set_jc(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
     return BHQ_OK;
 }
 
-int bhq_compute(bhq_ctx *ctx, void *stream)
+// Checks that a compute can run and fills the kernel arguments from the
+// context (results into the context's arrays).
+static int prepare_compute(bhq_ctx *ctx, bhq::ForceArgs &A)
 {
-    CHECK_CTX(ctx);
     if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "compute before set_groups");
     if (!ctx->have_i && ctx->ni > 0)
         return ctx->fail(BHQ_E_STATE, "compute before set_i");
@@ -709,7 +720,7 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
         return ctx->fail(BHQ_E_STATE, "compute before set_eps / set_eps2_i");
     TRY(ctx->select());
 
-    bhq::ForceArgs A{};
+    A = bhq::ForceArgs{};
     auto D = [&](Arr a) { return ctx->arr[a].as<double>(); };
     A.ng = ctx->ng;
     A.nslots = ctx->nslots;
@@ -726,6 +737,8 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
     A.q11 = D(A_Q11); A.q12 = D(A_Q12); A.q22 = D(A_Q22);
     A.jct = D(A_JCT);
     A.ax = D(A_AX); A.ay = D(A_AY); A.az = D(A_AZ); A.pot = D(A_POT);
+    A.out_stride = 1;
+    A.ni = ctx->ni;
     A.box = split ? ctx->box : 0.0;
     A.rs = ctx->rs;
     A.rcut = ctx->rcut;
@@ -740,6 +753,27 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
         A.jc_slot = ctx->list_slot_c;
     }
 
+    return BHQ_OK;
+}
+
+int bhq_compute(bhq_ctx *ctx, void *stream)
+{
+    CHECK_CTX(ctx);
+    bhq::ForceArgs A;
+    TRY(prepare_compute(ctx, A));
+
+    if (ctx->cfg.jsplit > 1) {
+        // parts of every i-particle's sums (32 B per entry covers FP64)
+        const size_t bytes = (size_t)ctx->cfg.jsplit * (size_t)ctx->ni * 32;
+        if (bytes > ctx->arr[A_PART].cap) {
+            ctx->quiesce();
+            hipError_t e = ctx->arr[A_PART].reserve(bytes);
+            if (e != hipSuccess) return ctx->hip_fail(e, "hipMalloc (j-split parts)");
+            ++ctx->args_version;
+        }
+        A.part = ctx->arr[A_PART].p;
+    }
+
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
     if (ctx->use_graph) {
@@ -750,6 +784,7 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
             ctx->graph_key.i_per_thread == ctx->cfg.i_per_thread &&
             ctx->graph_key.persistent == ctx->cfg.persistent &&
             ctx->graph_key.blocks_per_cu == ctx->cfg.blocks_per_cu &&
+            ctx->graph_key.jsplit == ctx->cfg.jsplit &&
             ctx->graph_key.version == ctx->args_version;
         if (!same) {
             if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
@@ -780,6 +815,7 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
             ctx->graph_key.i_per_thread = ctx->cfg.i_per_thread;
             ctx->graph_key.persistent = ctx->cfg.persistent;
             ctx->graph_key.blocks_per_cu = ctx->cfg.blocks_per_cu;
+            ctx->graph_key.jsplit = ctx->cfg.jsplit;
             ctx->graph_key.version = ctx->args_version;
         }
         e = hipEventRecord(ctx->ev0, s);
@@ -800,11 +836,14 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
 }
 
 int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread,
-                   int blocks_per_cu, int persistent, int use_graph)
+                   int blocks_per_cu, int persistent, int use_graph, int jsplit)
 {
     CHECK_CTX(ctx);
     if (block == 0) block = 256;
     if (i_per_thread == 0) i_per_thread = 2;
+    if (jsplit == 0) jsplit = 1;
+    if (jsplit != 1 && jsplit != 2 && jsplit != 4 && jsplit != 8)
+        return ctx->fail(BHQ_E_ARG, "jsplit must be 1, 2, 4 or 8 (or 0)");
     if (block != 128 && block != 256)
         return ctx->fail(BHQ_E_ARG, "block must be 128 or 256 (or 0)");
     if (i_per_thread != 1 && i_per_thread != 2)
@@ -817,11 +856,12 @@ int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread,
     ctx->cfg.i_per_thread = i_per_thread;
     ctx->cfg.blocks_per_cu = blocks_per_cu;
     ctx->cfg.persistent = persistent;
+    ctx->cfg.jsplit = jsplit;
     ctx->use_graph = use_graph;
     return BHQ_OK;
 }
 
-int bhq_get_tuning(const bhq_ctx *ctx, int out[5])
+int bhq_get_tuning(const bhq_ctx *ctx, int out[6])
 {
     if (!ctx || !out) return BHQ_E_ARG;
     out[0] = ctx->cfg.block;
@@ -829,6 +869,7 @@ int bhq_get_tuning(const bhq_ctx *ctx, int out[5])
     out[2] = ctx->cfg.blocks_per_cu;
     out[3] = ctx->cfg.persistent;
     out[4] = ctx->use_graph;
+    out[5] = ctx->cfg.jsplit;
     return BHQ_OK;
 }
 
@@ -924,6 +965,7 @@ int bhq_set_pool_particles(bhq_ctx *ctx, int64_t n, const double (*x)[3],
     }
     for (int64_t k = 0; k < n; ++k)
         rec[(size_t)k] = bhq::PartRec{x[k][0], x[k][1], x[k][2], m[k]};
+    ctx->quiesce();
     hipError_t e = ctx->arr[A_POOLP].reserve((size_t)n * sizeof(bhq::PartRec));
     if (e == hipSuccess && n > 0)
         e = hipMemcpy(ctx->arr[A_POOLP].p, rec.data(),
@@ -958,6 +1000,7 @@ int bhq_set_pool_cells(bhq_ctx *ctx, int64_t n, const double (*x)[3],
                                       q[k][0], q[k][1], q[k][2], q[k][3],
                                       q[k][4], q[k][5], trace ? trace[k] : 0.0,
                                       0.0};
+    ctx->quiesce();
     hipError_t e = ctx->arr[A_POOLC].reserve((size_t)n * sizeof(bhq::CellRec));
     if (e == hipSuccess && n > 0)
         e = hipMemcpy(ctx->arr[A_POOLC].p, rec.data(),
@@ -989,6 +1032,7 @@ static int set_idx(bhq_ctx *ctx, Arr a, int64_t total, int64_t pool,
     TRY(ctx->use_indexed());
     if (n == 0) return BHQ_OK;
     TRY(ctx->unslot_lists());
+    ctx->quiesce();
     hipError_t e = hipMemcpy(ctx->arr[a].as<int32_t>() + adr, idx,
                              (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice);
     return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, "hipMemcpy H2D");

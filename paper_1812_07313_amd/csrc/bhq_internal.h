@@ -116,7 +116,10 @@ struct ForceArgs {
     const double *jcx, *jcy, *jcz, *jcm;           // [njc] j-cell com, mass
     const double *q00, *q01, *q02, *q11, *q12, *q22;  // [njc] quadrupole
     const double *jct;              // [njc] trace (split kernel)
-    double *ax, *ay, *az, *pot;     // [ni] results (FP64)
+    double *ax, *ay, *az, *pot;     // [ni] results (FP64): element i at
+                                    // ax[i * out_stride] (pot may be NULL)
+    int64_t out_stride;             // 1: SoA arrays; 3: ax = a[.][0] of an
+                                    // AoS a[ni][3] (ay, az the next ones)
     double box;                     // > 0: periodic minimum image
     double rs, rcut;                // split-kernel parameters
     unsigned int *queue;            // slot counters of the persistent kernel
@@ -132,6 +135,14 @@ struct ForceArgs {
     // entries start at g * jp_slot (jc_slot) instead of jp_off[g]; their
     // counts are still jp_off[g + 1] - jp_off[g].
     int64_t jp_slot, jc_slot;
+    // Cross-block j-split (LaunchCfg::jsplit = J > 1): the block for part
+    // s of a group takes entries [n s / J, n (s + 1) / J) of each of its
+    // lists and writes its sums for i-particle i to part[s * ni + i]
+    // (x, y, z, -phi in the working precision: 16 B per entry in FP32,
+    // 32 B in FP64); a reduction then adds the J parts of each particle in
+    // the order s = 0, 1, ... and writes the results.
+    void *part;
+    int64_t ni;                     // i-particles (i_off[ng])
 };
 
 constexpr int kQueueWords = 64;  // capacity of ForceArgs::queue
@@ -147,7 +158,11 @@ struct LaunchCfg {
     int persistent = 0;
     int blocks_per_cu = 0;
     int num_cu = 0;
+    int jsplit = 1;        // parts of each group's lists (1, 2, 4 or 8)
 };
+
+constexpr int kMaxJsplit = 8;
+
 
 // Launch the force kernel for (kernel, precision) on `stream`.  Returns
 // the launch status.

@@ -331,8 +331,10 @@ struct Smem {
 // Evaluate group g with a block of BS threads, each owning IB i-particles;
 // sa, sb, sc are LDS tiles of BS entries (sb, sc only for the quadrupole
 // kinds); tab is the FP32 split table in LDS (FP32 split kinds only).
+// Part js of nj of each list (cross-block j-split; nj == 1: the whole
+// lists): the results go to the part buffer instead of the outputs.
 template <typename R, int KIND, bool PERIODIC, int BS, int IB>
-__device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
+__device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g, int js, int nj,
                                               V4<R> *sa, V4<R> *sb, V4<R> *sc,
                                               const V4<float> *tab)
 {
@@ -342,9 +344,11 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
     const int64_t i0 = A.i_off[g];
     const int64_t ni = A.i_off[g + 1] - i0;
     const double cx = A.gcx[g], cy = A.gcy[g], cz = A.gcz[g];
-    const int64_t np = A.jp_off[g + 1] - A.jp_off[g], nc = A.jc_off[g + 1] - A.jc_off[g];
-    const int64_t p0 = A.jp_slot > 0 ? g * A.jp_slot : A.jp_off[g];
-    const int64_t c0 = A.jc_slot > 0 ? g * A.jc_slot : A.jc_off[g];
+    const int64_t npg = A.jp_off[g + 1] - A.jp_off[g], ncg = A.jc_off[g + 1] - A.jc_off[g];
+    const int64_t pb = npg * js / nj, cb = ncg * js / nj;
+    const int64_t np = npg * (js + 1) / nj - pb, nc = ncg * (js + 1) / nj - cb;
+    const int64_t p0 = (A.jp_slot > 0 ? g * A.jp_slot : A.jp_off[g]) + pb;
+    const int64_t c0 = (A.jc_slot > 0 ? g * A.jc_slot : A.jc_off[g]) + cb;
     const double box = A.box;
     const double ibox = PERIODIC ? 1.0 / box : 0.0;
     const SplitK<R> K = split_k<R>(kSplit ? A.rs : 1.0);
@@ -667,10 +671,20 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g,
                     sp += v.w;
                 }
                 const int64_t i = i0 + ib + li;
-                A.ax[i] = (double)sx;
-                A.ay[i] = (double)sy;
-                A.az[i] = (double)sz;
-                A.pot[i] = -(double)sp;
+                if (nj > 1) {
+                    V4<R> v;
+                    v.x = sx;
+                    v.y = sy;
+                    v.z = sz;
+                    v.w = sp;
+                    static_cast<V4<R> *>(A.part)[js * A.ni + i] = v;
+                } else {
+                    const int64_t o = i * A.out_stride;
+                    A.ax[o] = (double)sx;
+                    A.ay[o] = (double)sy;
+                    A.az[o] = (double)sz;
+                    if (A.pot) A.pot[i] = -(double)sp;
+                }
             }
         }
     }
@@ -703,10 +717,15 @@ __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel(const ForceArgs
     __shared__ V4<R> sb[kCellQ ? BS : 1];
     __shared__ V4<R> sc[kCellQ ? BS : 1];
     __shared__ V4<float> st[split_tab_size<R, KIND>()];
-    const int64_t g = A.order ? A.order[blockIdx.x] : (int64_t)blockIdx.x;
+    // block b: slot b % nslots, part b / nslots of its group's lists (the
+    // slot of a block keeps its XCD, b % 8, when nslots is a multiple of 8)
+    const int nj = (int)(gridDim.x / A.nslots);
+    const int js = (int)(blockIdx.x / A.nslots);
+    const int64_t slot = blockIdx.x - (int64_t)js * A.nslots;
+    const int64_t g = A.order ? A.order[slot] : slot;
     if (g < 0) return;  // empty slot (uniform over the block)
     load_split_tab<R, KIND, BS>(st);
-    process_group<R, KIND, PERIODIC, BS, IB>(A, g, sa, sb, sc, st);
+    process_group<R, KIND, PERIODIC, BS, IB>(A, g, js, nj, sa, sb, sc, st);
 }
 
 // Id of the XCD this wave runs on (hardware register XCC_ID, bits 3:0).
@@ -724,7 +743,8 @@ __device__ __forceinline__ int xcd_id()
 // counter once it has passed that counter's slot count, so every block
 // exits.
 template <typename R, int KIND, bool PERIODIC, int BS, int IB>
-__global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(const ForceArgs A)
+__global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(const ForceArgs A,
+                                                                           int nj)
 {
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
     __shared__ V4<R> sa[BS];
@@ -736,6 +756,8 @@ __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(cons
     const int nq = A.xcds > 0 ? A.xcds : 1;
     const int64_t per_q = A.nslots / nq;  // nslots is a multiple of nq
     const int home = A.xcds > 0 ? xcd_id() % nq : 0;
+    // counter q hands out per_q * nj items: item k is local slot k % per_q
+    // of queue q (launch slot (k % per_q) * nq + q), list part k / per_q
     for (int r = 0; r < nq; ++r) {
         const int q = (home + r) % nq;
         for (;;) {
@@ -743,12 +765,36 @@ __global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(cons
             __syncthreads();
             const int64_t k = next;
             __syncthreads();
-            if (k >= per_q) break;
-            const int64_t slot = k * nq + q;
+            if (k >= per_q * nj) break;
+            const int js = (int)(k / per_q);
+            const int64_t slot = (k - js * per_q) * nq + q;
             const int64_t g = A.order ? A.order[slot] : slot;
-            if (g >= 0) process_group<R, KIND, PERIODIC, BS, IB>(A, g, sa, sb, sc, st);
+            if (g >= 0) process_group<R, KIND, PERIODIC, BS, IB>(A, g, js, nj, sa, sb, sc, st);
         }
     }
+}
+
+// Sum of the nj parts of every i-particle in the order s = 0, 1, ... (in
+// the working precision), written to the outputs.
+template <typename R>
+__global__ __launch_bounds__(256) void reduce_parts(const ForceArgs A, int nj)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.ni) return;
+    const V4<R> *part = static_cast<const V4<R> *>(A.part);
+    V4<R> s = part[i];
+    for (int k = 1; k < nj; ++k) {
+        const V4<R> v = part[k * A.ni + i];
+        s.x += v.x;
+        s.y += v.y;
+        s.z += v.z;
+        s.w += v.w;
+    }
+    const int64_t o = i * A.out_stride;
+    A.ax[o] = (double)s.x;
+    A.ay[o] = (double)s.y;
+    A.az[o] = (double)s.z;
+    if (A.pot) A.pot[i] = -(double)s.w;
 }
 
 __global__ void reset_queue(unsigned int *q)
@@ -759,6 +805,8 @@ __global__ void reset_queue(unsigned int *q)
 template <typename R, int KIND, bool P, int BS, int IB>
 hipError_t launch_one(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
 {
+    const int nj = cfg.jsplit;
+    const int64_t items = A.nslots * nj;
     if (cfg.persistent) {
         hipLaunchKernelGGL(reset_queue, dim3(1), dim3(kQueueWords), 0, s, A.queue);
         hipError_t e = hipGetLastError();
@@ -771,13 +819,17 @@ hipError_t launch_one(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
             if (per_cu < 1) per_cu = 1;
         }
         const int64_t want = (int64_t)per_cu * cfg.num_cu;
-        const unsigned grid = (unsigned)(want < A.nslots ? want : A.nslots);
+        const unsigned grid = (unsigned)(want < items ? want : items);
         hipLaunchKernelGGL((force_kernel_persistent<R, KIND, P, BS, IB>),
-                           dim3(grid), dim3(BS), 0, s, A);
+                           dim3(grid), dim3(BS), 0, s, A, nj);
     } else {
         hipLaunchKernelGGL((force_kernel<R, KIND, P, BS, IB>),
-                           dim3((unsigned)A.nslots), dim3(BS), 0, s, A);
+                           dim3((unsigned)items), dim3(BS), 0, s, A);
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nj == 1 || A.ni == 0) return e;
+    hipLaunchKernelGGL(reduce_parts<R>, dim3((unsigned)((A.ni + 255) / 256)), dim3(256), 0, s,
+                       A, nj);
     return hipGetLastError();
 }
 
@@ -828,6 +880,10 @@ hipError_t launch_force(int kernel, int precision, const ForceArgs &A,
     if (cfg.i_per_thread != 1 && cfg.i_per_thread != 2) return hipErrorInvalidValue;
     if (cfg.persistent && (!A.queue || cfg.num_cu <= 0))
         return hipErrorInvalidValue;
+    if (cfg.jsplit < 1 || cfg.jsplit > kMaxJsplit || (cfg.jsplit > 1 && !A.part))
+        return hipErrorInvalidValue;
+    if (A.nslots * cfg.jsplit > 0x7fffffff) return hipErrorInvalidValue;
+    if (A.out_stride != 1 && A.out_stride != 3) return hipErrorInvalidValue;
     return precision == 1 ? launch_prec<double>(kernel, A, cfg, stream)
                           : launch_prec<float>(kernel, A, cfg, stream);
 }

@@ -1,8 +1,11 @@
 """Autotuner for the force evaluation: chooses the group size bound ncrit
-(which changes the interaction lists), the launch shape (block size,
-i-particles per thread, persistent queue, persistent grid size) and the
-group dispatch order that minimise the time of one force evaluation.  Interactions per second alone would reward larger ncrit (more,
-cheaper interactions), so the objective is seconds per evaluation.
+(which changes the interaction lists; the paper's n_crit, Sec. 3.4), the
+launch shape (block size = LDS tile depth, i-particles per thread, persistent
+queue and its grid size = resident blocks per CU, HIP graph replay, and the
+cross-block j-split for inputs with too few groups to fill the GPU) and the
+group dispatch order that minimise the time of one force evaluation.
+Interactions per second alone would reward larger ncrit (more, cheaper
+interactions), so the objective is seconds per evaluation.
 
 Results are cached in a JSON file keyed by device architecture, a caller
 supplied workload key, kernel, precision and theta, so that a repeated
@@ -20,10 +23,14 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bhq",
                              "tune.json")
 
 NCRITS = (64, 128, 256)
-# (block, i_per_thread, blocks_per_cu, persistent)
-SHAPES = ((256, 1, 0, 0), (256, 2, 0, 0), (128, 1, 0, 0), (128, 2, 0, 0),
-          (256, 1, 0, 1), (256, 2, 0, 1), (128, 2, 4, 1))
+# launch shapes: (block, i_per_thread, blocks_per_cu, persistent, use_graph)
+SHAPES = ((256, 1, 0, 0, 0), (256, 2, 0, 0, 0), (128, 1, 0, 0, 0), (128, 2, 0, 0, 0),
+          (256, 1, 0, 1, 0), (256, 2, 0, 1, 0), (128, 2, 4, 1, 0),
+          (256, 1, 0, 1, 1), (256, 2, 0, 1, 1), (256, 2, 0, 0, 1))
+JSPLITS = (1,)
+SMALL_JSPLITS = (1, 2, 4, 8)   # for inputs of a few hundred groups
 ORDERS = (bhq.ORDER_XCD, bhq.ORDER_COST)
+KNOBS = ("block", "i_per_thread", "blocks_per_cu", "persistent", "use_graph")
 
 
 def _load(path):
@@ -48,20 +55,27 @@ def cache_key(arch, workload, kernel, precision, theta):
                                         bhq.PRECISION_NAMES[precision], theta)
 
 
-def search(measure, ncrits=NCRITS, shapes=SHAPES, orders=ORDERS):
-    """Exhaustive search.  measure(ncrit, block, i_per_thread,
-    blocks_per_cu, persistent, order) returns seconds per evaluation.
-    Returns (best, table)."""
+def search(measure, ncrits=NCRITS, shapes=SHAPES, orders=ORDERS, jsplits=JSPLITS):
+    """Exhaustive search.  measure(ncrit, cfg) with cfg a dict of the launch
+    knobs (block, i_per_thread, blocks_per_cu, persistent, use_graph, jsplit,
+    order) returns seconds per evaluation.  Returns (best, table)."""
     table = []
     for nc in ncrits:
-        for block, ipt, bpc, pers in shapes:
-            for order in orders:
-                t = measure(nc, block, ipt, bpc, pers, order)
-                table.append(dict(ncrit=nc, block=block, i_per_thread=ipt,
-                                  blocks_per_cu=bpc, persistent=pers,
-                                  order=order, seconds=t))
+        for shape in shapes:
+            for js in jsplits:
+                for order in orders:
+                    cfg = dict(zip(KNOBS, shape), jsplit=js, order=order)
+                    t = measure(nc, cfg)
+                    table.append(dict(cfg, ncrit=nc, seconds=t))
     best = min(table, key=lambda r: r["seconds"])
     return dict(best), table
+
+
+def apply(ctx, cfg):
+    """Set a configuration's launch knobs and order on ctx."""
+    bhq.bhq_set_tuning(ctx, cfg["block"], cfg["i_per_thread"], cfg["blocks_per_cu"],
+                       cfg["persistent"], cfg.get("use_graph", 0), cfg.get("jsplit", 1))
+    bhq.bhq_set_group_order(ctx, cfg["order"])
 
 
 def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
@@ -72,7 +86,7 @@ def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
     (median of `repeats` launches after one warm-up)."""
     state = {"ncrit": None}
 
-    def measure(ncrit, block, ipt, bpc, pers, order=bhq.ORDER_XCD):
+    def measure(ncrit, cfg):
         if state["ncrit"] != ncrit:
             if sys_off is not None:
                 L = bhq.bhq_build_lists_batch(sys_off, x, m, theta, ncrit,
@@ -96,8 +110,7 @@ def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
                 bhq.bhq_set_split(ctx, rs, rcut, box)
             state["ncrit"] = ncrit
         bhq.bhq_set_kernel(ctx, kernel, precision)
-        bhq.bhq_set_tuning(ctx, block, ipt, bpc, pers, 0)
-        bhq.bhq_set_group_order(ctx, order)
+        apply(ctx, cfg)
         bhq.bhq_compute(ctx, stream)
         bhq.bhq_get_kernel_ms(ctx)
         ts = []
@@ -111,23 +124,21 @@ def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
 
 def autotune(ctx, x, m, theta, workload, arch="gfx950", kernel=bhq.QUAD,
              precision=bhq.FP32_OFS64, cache=DEFAULT_CACHE, ncrits=NCRITS,
-             shapes=SHAPES, orders=ORDERS, force=False, **kw):
+             shapes=SHAPES, orders=ORDERS, jsplits=JSPLITS, force=False, **kw):
     """Tune (or read from the cache) and leave ctx holding the best lists
     and launch shape.  Returns dict(best=..., table=..., cached=bool)."""
     key = cache_key(arch, workload, kernel, precision, theta)
     db = _load(cache)
     measure = gpu_measure(ctx, x, m, theta, kernel=kernel, precision=precision,
                           **kw)
-    if not force and key in db and "order" in db[key]["best"]:
+    if not force and key in db and "jsplit" in db[key]["best"]:
         best = db[key]["best"]
-        measure(best["ncrit"], best["block"], best["i_per_thread"],
-                best["blocks_per_cu"], best["persistent"], best["order"])
+        measure(best["ncrit"], best)
         return dict(best=best, table=db[key]["table"], cached=True)
     t0 = time.perf_counter()
-    best, table = search(measure, ncrits, shapes, orders)
+    best, table = search(measure, ncrits, shapes, orders, jsplits)
     db = _load(cache)
     db[key] = dict(best=best, table=table, seconds_spent=time.perf_counter() - t0)
     _store(cache, db)
-    measure(best["ncrit"], best["block"], best["i_per_thread"],
-            best["blocks_per_cu"], best["persistent"], best["order"])
+    measure(best["ncrit"], best)
     return dict(best=best, table=table, cached=False)

@@ -47,8 +47,20 @@ def test_launch_shapes(ctx, cube_case):
                     bhq.bhq_set_tuning(ctx, block, ipt, bpc, 1)
                     a1, p1 = run(ctx, mat, len(m), bhq.QUAD, prec)
                     assert np.array_equal(a0, a1) and np.array_equal(p0, p1)
+                for js in (2, 4, 8):
+                    # cross-block j-split: parts of the lists in different
+                    # blocks, added in part order; the persistent queue
+                    # hands out the same parts
+                    log("  jsplit=%d" % js)
+                    bhq.bhq_set_tuning(ctx, block, ipt, 0, 0, 0, js)
+                    a2, p2 = run(ctx, mat, len(m), bhq.QUAD, prec)
+                    assert_parity(errors(a2, p2, a_ref, p_ref), prec,
+                                  "block %d ipt %d jsplit %d" % (block, ipt, js))
+                    bhq.bhq_set_tuning(ctx, block, ipt, 2, 1, 0, js)
+                    a3, p3 = run(ctx, mat, len(m), bhq.QUAD, prec)
+                    assert np.array_equal(a2, a3) and np.array_equal(p2, p3)
         t = bhq.bhq_get_tuning(ctx)
-        assert t["persistent"] == 1 and t["i_per_thread"] == 2
+        assert t["persistent"] == 1 and t["i_per_thread"] == 2 and t["jsplit"] == 8
     bhq.bhq_set_tuning(ctx)
 
 
@@ -85,7 +97,8 @@ def test_group_orders_bitwise(ctx, cube_case):
 
 def test_tuning_argument_errors(ctx):
     for args in ((64, 1, 0, 0, 0), (256, 3, 0, 0, 0), (256, 1, -1, 0, 0),
-                 (256, 1, 0, 2, 0), (256, 1, 0, 0, 3)):
+                 (256, 1, 0, 2, 0), (256, 1, 0, 0, 3), (256, 1, 0, 0, 0, 3),
+                 (256, 1, 0, 0, 0, 16), (256, 1, 0, 0, 0, -1)):
         with pytest.raises(bhq.BhqError) as ei:
             bhq.bhq_set_tuning(ctx, *args)
         assert ei.value.code == bhq.E_ARG

@@ -23,9 +23,12 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 
 def _gpu_product(x, m, theta, ncrit, kernel, eps=None, eps2=None, box=0.0,
-                 rcut=0.0, rs=0.0, sys_off=None):
-    """Bench configuration: host builder lists, index upload, default launch;
-    returns {precision: (a, phi)} in original particle order."""
+                 rcut=0.0, rs=0.0, sys_off=None, tuning=None, replays=1):
+    """Bench configuration: host builder lists, index upload, the default
+    launch or the given bhq_set_tuning arguments; returns {precision:
+    (a, phi)} in original particle order.  With replays > 1 every further
+    compute (a graph replay when the tuning asks for one) must give the
+    first one's result bit for bit."""
     if sys_off is not None:
         L = bhq.bhq_build_lists_batch(sys_off, x, m, theta, ncrit)
     else:
@@ -43,10 +46,16 @@ def _gpu_product(x, m, theta, ncrit, kernel, eps=None, eps2=None, box=0.0,
             bhq.bhq_set_eps(ctx, eps)
         if rs:
             bhq.bhq_set_split(ctx, rs, rcut, box)
+        if tuning is not None:
+            bhq.bhq_set_tuning(ctx, *tuning)
         for prec in (bhq.FP32_OFS64, bhq.FP64):
             bhq.bhq_set_kernel(ctx, kernel, prec)
             bhq.bhq_compute(ctx)
             a_g, p_g = bhq.bhq_get_result(ctx, len(m))
+            for _ in range(replays - 1):
+                bhq.bhq_compute(ctx)
+                a_r, p_r = bhq.bhq_get_result(ctx, len(m))
+                assert np.array_equal(a_g, a_r) and np.array_equal(p_g, p_r)
             a = np.empty_like(a_g)
             p = np.empty_like(p_g)
             a[idx] = a_g
@@ -99,7 +108,9 @@ def test_clustered_4m_sampled():
 
 def test_batched_256_systems():
     """256 Plummer systems, N log-uniform in [2^10, 2^16], own eps each,
-    theta = 0.6, ncrit = 64, one launch: every particle."""
+    theta = 0.6, ncrit = 64: every particle, from one eager launch and from
+    one persistent launch replayed from a HIP graph (three replays, each
+    bitwise equal to the eager launch's result)."""
     systems = synth.batched_plummer(256)
     sizes = np.array([len(s[1]) for s in systems])
     off = np.concatenate([[0], np.cumsum(sizes)])
@@ -108,6 +119,12 @@ def test_batched_256_systems():
     E2 = np.concatenate([np.full(len(s[1]), s[2] ** 2) for s in systems])
     log("case batched 256 systems, %d particles" % len(M))
     gpu = _gpu_product(X, M, 0.6, 64, bhq.QUAD, eps2=E2, sys_off=off)
+    log("  persistent launch replayed from a HIP graph")
+    gpu_graph = _gpu_product(X, M, 0.6, 64, bhq.QUAD, eps2=E2, sys_off=off,
+                             tuning=(256, 2, 0, 1, 1, 1), replays=3)
+    for prec in gpu:
+        assert np.array_equal(gpu[prec][0], gpu_graph[prec][0])
+        assert np.array_equal(gpu[prec][1], gpu_graph[prec][1])
     a_ref = np.zeros((len(M), 3))
     p_ref = np.zeros(len(M))
     for s, (x, m, eps) in enumerate(systems):

@@ -196,6 +196,30 @@ def test_stream_and_timing(ctx):
     assert (n_pp, n_pc) == T.interaction_counts()
 
 
+def test_upload_waits_for_compute_on_stream(ctx):
+    """Host uploads after a compute on a non-blocking stream wait for it:
+    the result is that of the data the compute was launched with."""
+    torch = pytest.importorskip("torch")
+    x, m = synth.plummer(65536, synth.rng(12))
+    T = orc.Tree(x, m, 0.3, 64)
+    mat = orc.materialise(T, x, m)
+    upload(ctx, mat, x, eps2=1e-4)
+    a0, p0 = run(ctx, mat, len(m), bhq.QUAD, bhq.FP32_OFS64)
+    s = torch.cuda.Stream()
+    for _ in range(3):
+        bhq.bhq_compute(ctx, s)
+        # new positions and a new particle list while the kernel may run
+        bhq.bhq_set_i(ctx, x[mat["i_idx"]] + 0.25)
+        bhq.bhq_set_jp(ctx, 0, mat["jp_x"] + 0.5, mat["jp_m"])
+        a_g, p_g = bhq.bhq_get_result(ctx, len(m))
+        a1 = np.zeros_like(a0)
+        p1 = np.zeros_like(p0)
+        a1[mat["i_idx"]] = a_g
+        p1[mat["i_idx"]] = p_g
+        assert np.array_equal(a0, a1) and np.array_equal(p0, p1)
+        upload(ctx, mat, x, eps2=1e-4)
+
+
 def test_state_errors(ctx):
     c2 = bhq.bhq_create(0, bhq.QUAD, bhq.FP32_OFS64)
     try:

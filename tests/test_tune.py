@@ -12,14 +12,17 @@ from paper_1812_07313_amd import bhq, synth, tune
 def test_search_picks_minimum_and_cache_roundtrip(tmp_path):
     cost = {64: 3.0, 128: 2.0, 256: 2.5}
 
-    def measure(nc, block, ipt, bpc, pers, order):
-        return (cost[nc] + (0.1 if block == 128 else 0.0) - 0.05 * pers
-                - 0.01 * ipt - 0.001 * (order == bhq.ORDER_COST))
+    def measure(nc, c):
+        return (cost[nc] + (0.1 if c["block"] == 128 else 0.0) - 0.05 * c["persistent"]
+                - 0.01 * c["i_per_thread"] - 0.001 * (c["order"] == bhq.ORDER_COST)
+                - 0.002 * c["use_graph"] + 0.0001 * c["jsplit"])
 
-    best, table = tune.search(measure)
-    assert len(table) == len(tune.NCRITS) * len(tune.SHAPES) * len(tune.ORDERS)
+    best, table = tune.search(measure, jsplits=tune.SMALL_JSPLITS)
+    assert len(table) == (len(tune.NCRITS) * len(tune.SHAPES) * len(tune.ORDERS)
+                          * len(tune.SMALL_JSPLITS))
     assert best["ncrit"] == 128 and best["block"] == 256 and best["persistent"] == 1
     assert best["i_per_thread"] == 2 and best["order"] == bhq.ORDER_COST
+    assert best["use_graph"] == 1 and best["jsplit"] == 1
     assert best["seconds"] == min(r["seconds"] for r in table)
     path = str(tmp_path / "tune.json")
     key = tune.cache_key("gfx950", "w", bhq.QUAD, bhq.FP32_OFS64, 0.6)
@@ -42,7 +45,7 @@ def test_autotune_batched_systems_parity(tmp_path):
         log("case autotune batched %d particles" % len(M))
         r = tune.autotune(ctx, X, M, 0.6, "test-batched", cache=path,
                           ncrits=(64, 128), eps2_per_particle=E2, sys_off=off,
-                          repeats=2)
+                          jsplits=(1, 2), repeats=2)
         assert not r["cached"]
         best = r["best"]
         log("  best %s" % best)
@@ -66,7 +69,8 @@ def test_autotune_batched_systems_parity(tmp_path):
         p[idx] = p_g
         assert_parity(errors(a, p, a_ref, p_ref), bhq.FP32_OFS64, "autotuned")
         r2 = tune.autotune(ctx, X, M, 0.6, "test-batched", cache=path,
-                           ncrits=(64, 128), eps2_per_particle=E2, sys_off=off)
+                           ncrits=(64, 128), eps2_per_particle=E2, sys_off=off,
+                           jsplits=(1, 2))
         assert r2["cached"] and r2["best"] == best
     finally:
         bhq.bhq_destroy(ctx)
