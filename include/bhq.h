@@ -182,6 +182,22 @@ int bhq_set_jc_idx(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx);
  * softening are missing; BHQ_E_HIP on a launch failure. */
 int bhq_compute(bhq_ctx *ctx, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the force
+ * evaluation of bhq_compute with the context's inputs and launch shape,
+ * allocating nothing.  Results go straight to the caller's device arrays
+ * a[ni][3] and pot[ni] (FP64, group order; pot may be NULL), which must lie
+ * in device memory of the context's device.  The persistent queue counters
+ * and the j-split parts live in a static array of the library (256 B plus
+ * 16 MiB per device, held until the process ends), so jsplit * ni * 16 B
+ * (FP32) or 32 B (FP64) must fit 16 MiB: BHQ_E_RANGE otherwise.  Every call
+ * on one device shares that array: calls that overlap in time on one
+ * device (two streams, or two host threads) race and give wrong results.
+ * No graph is recorded (use_graph is ignored).  Asynchronous on `stream`;
+ * bhq_get_kernel_ms times it.  Errors as bhq_compute, plus BHQ_E_ARG / 
+ * BHQ_E_RANGE for the output arrays. */
+int bhq_compute_noalloc(bhq_ctx *ctx, double *a, double *pot, void *stream);
+
 /* Wait for the last compute and copy out a[ni][3] and pot[ni] (FP64, group
  * order).  Either pointer may be NULL. */
 int bhq_get_result(bhq_ctx *ctx, double (*a)[3], double *pot);

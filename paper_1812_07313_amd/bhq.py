@@ -51,6 +51,7 @@ SIGNATURES = {
     "bhq_set_jc": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _D, _D,
                                   _D, _D]),
     "bhq_compute": (ctypes.c_int, [_P, _P]),
+    "bhq_compute_noalloc": (ctypes.c_int, [_P, _P, _P, _P]),
     "bhq_get_result": (ctypes.c_int, [_P, _D, _D]),
     "bhq_get_counts": (ctypes.c_int, [_P, _I64, _I64]),
     "bhq_get_kernel_ms": (ctypes.c_int, [_P, _D]),
@@ -284,6 +285,15 @@ def bhq_set_jc_idx(ctx, adr, idx):
 
 def bhq_compute(ctx, stream=None):
     _check(lib().bhq_compute(ctx, _stream_handle(stream)), ctx)
+
+
+def bhq_compute_noalloc(ctx, a, pot=None, stream=None):
+    """Force evaluation into caller GPU tensors a (ni, 3) and pot (ni,) or
+    None, float64, group order; allocates nothing."""
+    n = int(a.shape[0])
+    pa = _device_ptr(a, (n, 3), "a")
+    pp = None if pot is None else _device_ptr(pot, (n,), "pot")
+    _check(lib().bhq_compute_noalloc(ctx, pa, pp, _stream_handle(stream)), ctx)
 
 
 def bhq_get_result(ctx, ni):

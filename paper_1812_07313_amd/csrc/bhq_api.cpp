@@ -434,6 +434,14 @@ int bhq_create(bhq_ctx **out, int device, int kernel, int precision)
         delete c;
         return BHQ_E_HIP;
     }
+    // the static working memory of bhq_compute_noalloc: find its address
+    // on this device once (device current)
+    if (bhq::scratch_init(device) != hipSuccess) {
+        g_create_error = "bhq_create: static working memory not found on the device";
+        c->arr[A_QUEUE].release();
+        delete c;
+        return BHQ_E_HIP;
+    }
     if (hipEventCreate(&c->ev0) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess) {
         g_create_error = "bhq_create: hipEventCreate failed";
@@ -828,6 +836,46 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
         e = bhq::launch_force(ctx->kernel, ctx->precision, A, ctx->cfg, s);
         if (e != hipSuccess) return ctx->hip_fail(e, "force kernel launch");
     }
+    e = hipEventRecord(ctx->ev1, s);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipEventRecord");
+    ctx->launched = true;
+    ctx->last_stream = s;
+    return BHQ_OK;
+}
+
+static int check_device_range(bhq_ctx *ctx, const void *p, size_t bytes, const char *name);
+
+int bhq_compute_noalloc(bhq_ctx *ctx, double *a, double *pot, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (!a) return ctx->fail(BHQ_E_ARG, "compute_noalloc: a is NULL");
+    bhq::ForceArgs A;
+    TRY(prepare_compute(ctx, A));
+    const size_t entry = ctx->precision == BHQ_FP64 ? 32 : 16;
+    if (ctx->cfg.jsplit > 1 &&
+        (size_t)ctx->cfg.jsplit * (size_t)ctx->ni * entry > bhq::kScratchPartBytes)
+        return ctx->fail(BHQ_E_RANGE,
+                         "compute_noalloc: jsplit %d x %lld i-particles x %zu B of parts "
+                         "exceed the static %zu B (use a smaller jsplit, or bhq_compute)",
+                         ctx->cfg.jsplit, (long long)ctx->ni, entry, bhq::kScratchPartBytes);
+    if (ctx->ni > 0) {
+        TRY(check_device_range(ctx, a, (size_t)ctx->ni * 3 * sizeof(double), "a"));
+        if (pot) TRY(check_device_range(ctx, pot, (size_t)ctx->ni * sizeof(double), "pot"));
+    }
+    char *sp = static_cast<char *>(bhq::scratch_ptr(ctx->device));
+    if (!sp) return ctx->fail(BHQ_E_STATE, "compute_noalloc: static working memory not found");
+    A.ax = a;
+    A.ay = a + 1;
+    A.az = a + 2;
+    A.pot = pot;
+    A.out_stride = 3;
+    A.queue = reinterpret_cast<unsigned int *>(sp);
+    A.part = sp + bhq::kScratchQueueBytes;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipEventRecord(ctx->ev0, s);
+    if (e != hipSuccess) return ctx->hip_fail(e, "hipEventRecord");
+    e = bhq::launch_force(ctx->kernel, ctx->precision, A, ctx->cfg, s);
+    if (e != hipSuccess) return ctx->hip_fail(e, "force kernel launch");
     e = hipEventRecord(ctx->ev1, s);
     if (e != hipSuccess) return ctx->hip_fail(e, "hipEventRecord");
     ctx->launched = true;

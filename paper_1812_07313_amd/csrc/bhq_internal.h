@@ -163,6 +163,17 @@ struct LaunchCfg {
 
 constexpr int kMaxJsplit = 8;
 
+// Static working memory for callers that cannot allocate (bhq_compute_noalloc):
+// a file-scope device array in bhq_kernels.hip holding the persistent
+// queue counters (the first kScratchQueueBytes) and the j-split parts (the
+// next kScratchPartBytes).  Each device has its own copy.
+constexpr size_t kScratchQueueBytes = 256;
+constexpr size_t kScratchPartBytes = (size_t)16 << 20;
+// Look up the array's device address on `device` (made current by the
+// caller) once and keep it; returns the lookup's status.
+hipError_t scratch_init(int device);
+// The address found by scratch_init on `device`, or NULL.
+void *scratch_ptr(int device);
 
 // Launch the force kernel for (kernel, precision) on `stream`.  Returns
 // the launch status.

@@ -38,6 +38,7 @@
 #include "bhq_internal.h"
 #include "split_table.h"
 
+#include <mutex>
 #include <type_traits>
 
 namespace bhq {
@@ -867,7 +868,35 @@ hipError_t launch_prec(int kernel, const ForceArgs &A, const LaunchCfg &cfg,
     }
 }
 
+// Working memory of bhq_compute_noalloc: queue counters, then j-split
+// parts.  In host code this name is a stand-in, not a device address; the
+// address comes from hipGetSymbolAddress (scratch_init).
+static __device__ __align__(256) unsigned char scratch[kScratchQueueBytes + kScratchPartBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+hipError_t scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void *scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch_ptr[device];
+}
 
 hipError_t launch_force(int kernel, int precision, const ForceArgs &A,
                         const LaunchCfg &cfg, hipStream_t stream)
