@@ -177,6 +177,65 @@ int bhq_set_pool_cells(bhq_ctx *ctx, int64_t n, const double (*x)[3],
 int bhq_set_jp_idx(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx);
 int bhq_set_jc_idx(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx);
 
+/* ------------------------------------------------------------------------
+ * Device-pointer twins of the set calls above: the same arguments, with
+ * every array in device memory of the context's device (torch tensors or
+ * hipMalloc'd arrays, each range inside one allocation; BHQ_E_ARG for host
+ * memory, BHQ_E_RANGE for a range past the end of its allocation).  The
+ * paper's set calls copy host data into the kernel's own structures
+ * (Sec. 3.4, List 3); these copy device data the same way, without a host
+ * round trip.  Each call waits for the context's last compute, checks the
+ * caller's arrays on the device (the same checks as the host twin: finite
+ * values, eps2 > 0, offsets from 0 and monotone, indices inside the pool),
+ * and only then copies them into the context with kernels on `stream`
+ * (NULL: the null stream).  It returns when the copy is complete: the
+ * caller's memory is borrowed for the duration of the call, and may be
+ * changed or freed once the call returns.  On a failed check the context
+ * is left as it was.
+ * ------------------------------------------------------------------------ */
+
+/* bhq_set_groups with i_off, center, jp_off, jc_off in device memory.  The
+ * group dispatch order is planned on the device (as for device-built
+ * lists).  Also BHQ_E_RANGE for offsets that do not start at 0 or are not
+ * monotone, BHQ_E_NONFINITE for centres. */
+int bhq_set_groups_dev(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
+                       const double (*center)[3], const int64_t *jp_off,
+                       const int64_t *jc_off, void *stream);
+
+/* bhq_set_i with x[ni][3] in device memory (group order). */
+int bhq_set_i_dev(bhq_ctx *ctx, int64_t ni, const double (*x)[3], void *stream);
+
+/* bhq_set_eps2_i with eps2[ni] in device memory (the per-particle eps^2 of
+ * the i-particle structure, List 2). */
+int bhq_set_eps2_i_dev(bhq_ctx *ctx, int64_t ni, const double *eps2, void *stream);
+
+/* bhq_set_jp with x[n][3], m[n] in device memory: j-particle entries
+ * adr .. adr+n-1 of the materialised lists (the paper's j-particle set
+ * call, Sec. 3.4). */
+int bhq_set_jp_dev(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
+                   const double *m, void *stream);
+
+/* bhq_set_jc with x[n][3], m[n], q[n][6] (List 1 order), trace[n] (may be
+ * NULL) in device memory: j-cell entries adr .. adr+n-1 (the paper's j-cell
+ * set call, List 3). */
+int bhq_set_jc_dev(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
+                   const double *m, const double (*q)[6], const double *trace,
+                   void *stream);
+
+/* bhq_set_pool_particles / bhq_set_pool_cells with device arrays. */
+int bhq_set_pool_particles_dev(bhq_ctx *ctx, int64_t n, const double (*x)[3],
+                               const double *m, void *stream);
+int bhq_set_pool_cells_dev(bhq_ctx *ctx, int64_t n, const double (*x)[3],
+                           const double *m, const double (*q)[6],
+                           const double *trace, void *stream);
+
+/* bhq_set_jp_idx / bhq_set_jc_idx with idx[n] in device memory; every index
+ * is checked against its pool on the device (BHQ_E_RANGE). */
+int bhq_set_jp_idx_dev(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx,
+                       void *stream);
+int bhq_set_jc_idx_dev(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx,
+                       void *stream);
+
 /* Launch the force evaluation on HIP stream `stream` (NULL: the null
  * stream).  Asynchronous.  Errors: BHQ_E_STATE if groups, i-particles or
  * softening are missing; BHQ_E_HIP on a launch failure. */

@@ -50,6 +50,16 @@ SIGNATURES = {
                                   _D]),
     "bhq_set_jc": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _D, _D,
                                   _D, _D]),
+    "bhq_set_groups_dev": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, _P, _P]),
+    "bhq_set_i_dev": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
+    "bhq_set_eps2_i_dev": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
+    "bhq_set_jp_dev": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P, _P]),
+    "bhq_set_jc_dev": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P, _P, _P,
+                                      _P]),
+    "bhq_set_pool_particles_dev": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P]),
+    "bhq_set_pool_cells_dev": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, _P, _P]),
+    "bhq_set_jp_idx_dev": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
+    "bhq_set_jc_idx_dev": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "bhq_compute": (ctypes.c_int, [_P, _P]),
     "bhq_compute_noalloc": (ctypes.c_int, [_P, _P, _P, _P]),
     "bhq_get_result": (ctypes.c_int, [_P, _D, _D]),
@@ -461,6 +471,86 @@ def _device_ptr(t, shape, name):
     if tuple(t.shape) != shape:
         raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), shape))
     return t.data_ptr()
+
+
+def _dev_arg(t, shape, dtype, name):
+    """Address of a contiguous GPU tensor of the given dtype ("float64",
+    "int64", "int32") and shape, or None for t None."""
+    if t is None:
+        return None
+    if not (hasattr(t, "is_cuda") and t.is_cuda):
+        raise TypeError("%s must be a GPU tensor" % name)
+    if str(t.dtype) != "torch." + dtype or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor" % (name, dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return t.data_ptr()
+
+
+def bhq_set_groups_dev(ctx, i_off, center, jp_off, jc_off, stream=None):
+    """Offsets (ng+1,) int64 and centres (ng, 3) float64 GPU tensors."""
+    ng = int(center.shape[0])
+    _check(lib().bhq_set_groups_dev(
+        ctx, ng, _dev_arg(i_off, (ng + 1,), "int64", "i_off"),
+        _dev_arg(center, (ng, 3), "float64", "center"),
+        _dev_arg(jp_off, (ng + 1,), "int64", "jp_off"),
+        _dev_arg(jc_off, (ng + 1,), "int64", "jc_off"), _stream_handle(stream)), ctx)
+
+
+def bhq_set_i_dev(ctx, x, stream=None):
+    n = int(x.shape[0])
+    _check(lib().bhq_set_i_dev(ctx, n, _dev_arg(x, (n, 3), "float64", "x"),
+                               _stream_handle(stream)), ctx)
+
+
+def bhq_set_eps2_i_dev(ctx, eps2, stream=None):
+    n = int(eps2.shape[0])
+    _check(lib().bhq_set_eps2_i_dev(ctx, n, _dev_arg(eps2, (n,), "float64", "eps2"),
+                                    _stream_handle(stream)), ctx)
+
+
+def bhq_set_jp_dev(ctx, adr, x, m, stream=None):
+    n = int(m.shape[0])
+    _check(lib().bhq_set_jp_dev(ctx, int(adr), n, _dev_arg(x, (n, 3), "float64", "x"),
+                                _dev_arg(m, (n,), "float64", "m"), _stream_handle(stream)),
+           ctx)
+
+
+def bhq_set_jc_dev(ctx, adr, x, m, q, trace=None, stream=None):
+    n = int(m.shape[0])
+    _check(lib().bhq_set_jc_dev(ctx, int(adr), n, _dev_arg(x, (n, 3), "float64", "x"),
+                                _dev_arg(m, (n,), "float64", "m"),
+                                _dev_arg(q, (n, 6), "float64", "q"),
+                                _dev_arg(trace, (n,), "float64", "trace"),
+                                _stream_handle(stream)), ctx)
+
+
+def bhq_set_pool_particles_dev(ctx, x, m, stream=None):
+    n = int(m.shape[0])
+    _check(lib().bhq_set_pool_particles_dev(ctx, n, _dev_arg(x, (n, 3), "float64", "x"),
+                                            _dev_arg(m, (n,), "float64", "m"),
+                                            _stream_handle(stream)), ctx)
+
+
+def bhq_set_pool_cells_dev(ctx, x, m, q, trace=None, stream=None):
+    n = int(m.shape[0])
+    _check(lib().bhq_set_pool_cells_dev(ctx, n, _dev_arg(x, (n, 3), "float64", "x"),
+                                        _dev_arg(m, (n,), "float64", "m"),
+                                        _dev_arg(q, (n, 6), "float64", "q"),
+                                        _dev_arg(trace, (n,), "float64", "trace"),
+                                        _stream_handle(stream)), ctx)
+
+
+def bhq_set_jp_idx_dev(ctx, adr, idx, stream=None):
+    n = int(idx.shape[0])
+    _check(lib().bhq_set_jp_idx_dev(ctx, int(adr), n, _dev_arg(idx, (n,), "int32", "idx"),
+                                    _stream_handle(stream)), ctx)
+
+
+def bhq_set_jc_idx_dev(ctx, adr, idx, stream=None):
+    n = int(idx.shape[0])
+    _check(lib().bhq_set_jc_idx_dev(ctx, int(adr), n, _dev_arg(idx, (n,), "int32", "idx"),
+                                    _stream_handle(stream)), ctx)
 
 
 def bhq_build_lists_device(ctx, x, m, theta, ncrit, nleaf=8, box=0.0, rcut=0.0,

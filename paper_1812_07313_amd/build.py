@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libbhq.so")
 ARCH = os.environ.get("BHQ_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["bhq_kernels.hip", "bhq_tree.hip", "bhq_integrate.hip", "bhq_pm.hip",
-           "bhq_order.hip", "bhq_api.cpp", "bhq_lists.cpp"]
+           "bhq_order.hip", "bhq_upload.hip", "bhq_api.cpp", "bhq_lists.cpp"]
 # the tree builders take their floating-point decisions with the same
 # operations on host and device, the leapfrog updates round like plain
 # FP64 arithmetic, and the particle-mesh kernels must find a particle's

@@ -33,7 +33,7 @@ enum Arr {
     A_AX, A_AY, A_AZ, A_POT,
     A_QUEUE,
     A_POOLP, A_POOLC, A_JPIDX, A_JCIDX,
-    A_TORDER, A_ENERGY, A_OSCRATCH, A_SORTSCRATCH, A_PART,
+    A_TORDER, A_ENERGY, A_OSCRATCH, A_SORTSCRATCH, A_PART, A_FLAG,
     A_COUNT
 };
 
@@ -1363,6 +1363,366 @@ static int check_device_range(bhq_ctx *ctx, const void *p, size_t bytes,
     if (q < b || (size_t)(q - b) + bytes > size)
         return ctx->fail(BHQ_E_RANGE, "%s: %zu bytes do not fit its allocation",
                          name, bytes);
+    return BHQ_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Set calls that read caller device memory (bhq_set_*_dev).  Each one waits
+ * for the context's last compute, validates the caller's arrays on the
+ * device, and only then copies them into the context's arrays with device
+ * kernels on `stream`; it returns when the copy is complete.
+ * ------------------------------------------------------------------------ */
+
+// Run the validation kernels queued by checks(flag) on s, wait for them and
+// turn the flag into a return code.
+extern "C++" template <typename F>
+static int dev_check(bhq_ctx *ctx, hipStream_t s, const char *what, F checks)
+{
+    hipError_t e = ctx->arr[A_FLAG].reserve(256);
+    unsigned *flag = ctx->arr[A_FLAG].as<unsigned>();
+    if (e == hipSuccess) e = bhq::launch_clear_flag(flag, s);
+    if (e == hipSuccess) e = checks(flag);
+    unsigned h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return ctx->hip_fail(e, what);
+    if (h & bhq::kBadNonFinite) return ctx->fail(BHQ_E_NONFINITE, "%s: NaN or infinity", what);
+    if (h & bhq::kBadNonPositive) return ctx->fail(BHQ_E_ARG, "%s: a value <= 0", what);
+    if (h & bhq::kBadOrder)
+        return ctx->fail(BHQ_E_RANGE, "%s: offsets not starting at 0 or not monotone", what);
+    if (h & bhq::kBadRange) return ctx->fail(BHQ_E_RANGE, "%s: index outside the pool", what);
+    return BHQ_OK;
+}
+
+static int dev_done(bhq_ctx *ctx, hipError_t e, hipStream_t s, const char *what)
+{
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? BHQ_OK : ctx->hip_fail(e, what);
+}
+
+int bhq_set_groups_dev(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
+                       const double (*center)[3], const int64_t *jp_off,
+                       const int64_t *jc_off, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (ng < 1) return ctx->fail(BHQ_E_ARG, "ng must be >= 1");
+    if (ng > 0x7fffffff) return ctx->fail(BHQ_E_RANGE, "too many groups");
+    if (!i_off || !center || !jp_off || !jc_off)
+        return ctx->fail(BHQ_E_ARG, "set_groups_dev: NULL array");
+    TRY(ctx->select());
+    const size_t ob = ((size_t)ng + 1) * 8;
+    TRY(check_device_range(ctx, i_off, ob, "i_off"));
+    TRY(check_device_range(ctx, jp_off, ob, "jp_off"));
+    TRY(check_device_range(ctx, jc_off, ob, "jc_off"));
+    TRY(check_device_range(ctx, center, (size_t)ng * 24, "center"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ctx->quiesce();
+    TRY(dev_check(ctx, s, "set_groups_dev", [&](unsigned *f) {
+        hipError_t e = bhq::launch_check_offsets(i_off, ng, f, s);
+        if (e == hipSuccess) e = bhq::launch_check_offsets(jp_off, ng, f, s);
+        if (e == hipSuccess) e = bhq::launch_check_offsets(jc_off, ng, f, s);
+        if (e == hipSuccess) e = bhq::launch_check_f64(&center[0][0], 3 * ng, false, f, s);
+        return e;
+    }));
+    int64_t tot[3] = {0, 0, 0};
+    const int64_t *offs[3] = {i_off, jp_off, jc_off};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+        e = hipMemcpyAsync(&tot[k], offs[k] + ng, 8, hipMemcpyDeviceToHost, s);
+    if ((e = (e == hipSuccess ? hipStreamSynchronize(s) : e)) != hipSuccess)
+        return ctx->hip_fail(e, "set_groups_dev: totals");
+    const int64_t ni = tot[0], njp = tot[1], njc = tot[2];
+    const size_t D = sizeof(double);
+    const struct { Arr a; size_t bytes; } need[] = {
+        {A_IOFF, ob}, {A_JPOFF, ob}, {A_JCOFF, ob},
+        {A_GCX, (size_t)ng * D}, {A_GCY, (size_t)ng * D}, {A_GCZ, (size_t)ng * D},
+        {A_XI, (size_t)ni * D}, {A_YI, (size_t)ni * D}, {A_ZI, (size_t)ni * D},
+        {A_E2I, (size_t)ni * D},
+        {A_AX, (size_t)ni * D}, {A_AY, (size_t)ni * D}, {A_AZ, (size_t)ni * D},
+        {A_POT, (size_t)ni * D},
+    };
+    for (auto &q : need) {
+        e = ctx->arr[q.a].reserve(q.bytes);
+        if (e != hipSuccess) {
+            ctx->ng = -1;
+            return ctx->hip_fail(e, "hipMalloc");
+        }
+    }
+    e = hipMemcpyAsync(ctx->arr[A_IOFF].p, i_off, ob, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->arr[A_JPOFF].p, jp_off, ob, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->arr[A_JCOFF].p, jc_off, ob, hipMemcpyDeviceToDevice, s);
+    double *gc[3] = {ctx->arr[A_GCX].as<double>(), ctx->arr[A_GCY].as<double>(),
+                     ctx->arr[A_GCZ].as<double>()};
+    if (e == hipSuccess) e = bhq::launch_unpack(&center[0][0], ng, 3, gc, s);
+    if (dev_done(ctx, e, s, "set_groups_dev: copy") != BHQ_OK) {
+        ctx->ng = -1;
+        return BHQ_E_HIP;
+    }
+    ctx->ng = ng;
+    ctx->ni = ni;
+    ctx->njp = njp;
+    ctx->njc = njc;
+    ctx->off_stale = true;
+    ++ctx->args_version;
+    ctx->have_i = ctx->have_jp = ctx->have_jc = ctx->have_t = false;
+    ctx->have_jp_idx = ctx->have_jc_idx = false;
+    ctx->list_mode = 0;
+    ctx->list_slot_p = ctx->list_slot_c = 0;
+    ctx->tree_order = false;
+    if (ctx->eps_mode == 2) ctx->eps_mode = 0;
+    ctx->nslots = 0;
+    int orc;
+    if (ctx->order_mode == BHQ_ORDER_XCD &&
+        bhq::plan_order_device_supported(ctx->order_window, ctx->order_tail)) {
+        // the offsets are on the device: plan the dispatch order there
+        int64_t ns = 0;
+        std::string msg;
+        orc = bhq::plan_order_device(ng, ctx->arr[A_IOFF].as<int64_t>(),
+                                     ctx->arr[A_JPOFF].as<int64_t>(),
+                                     ctx->arr[A_JCOFF].as<int64_t>(), ctx->order_window,
+                                     ctx->order_tail, BHQ_XCDS, ctx->arr[A_ORDER],
+                                     ctx->arr[A_OSCRATCH], &ns, s, &msg);
+        if (orc == BHQ_OK)
+            ctx->nslots = ns;
+        else
+            ctx->fail(orc, "%s", msg.c_str());
+    } else {
+        orc = ctx->upload_order();
+    }
+    if (orc != BHQ_OK) {
+        ctx->ng = -1;
+        return orc;
+    }
+    if (ctx->eps_mode == 1) TRY(ctx->fill_eps_uniform(s));
+    return BHQ_OK;
+}
+
+int bhq_set_i_dev(bhq_ctx *ctx, int64_t ni, const double (*x)[3], void *stream)
+{
+    CHECK_CTX(ctx);
+    if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "set_i_dev before set_groups");
+    if (ni != ctx->ni)
+        return ctx->fail(BHQ_E_RANGE, "set_i_dev: ni %lld != i_off[ng] %lld",
+                         (long long)ni, (long long)ctx->ni);
+    if (ni == 0) {
+        ctx->have_i = true;
+        return BHQ_OK;
+    }
+    if (!x) return ctx->fail(BHQ_E_ARG, "x is NULL");
+    TRY(ctx->select());
+    TRY(check_device_range(ctx, x, (size_t)ni * 24, "x"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ctx->quiesce();
+    TRY(dev_check(ctx, s, "set_i_dev", [&](unsigned *f) {
+        return bhq::launch_check_f64(&x[0][0], 3 * ni, false, f, s);
+    }));
+    double *out[3] = {ctx->arr[A_XI].as<double>(), ctx->arr[A_YI].as<double>(),
+                      ctx->arr[A_ZI].as<double>()};
+    TRY(dev_done(ctx, bhq::launch_unpack(&x[0][0], ni, 3, out, s), s, "set_i_dev"));
+    ctx->have_i = true;
+    return BHQ_OK;
+}
+
+int bhq_set_eps2_i_dev(bhq_ctx *ctx, int64_t ni, const double *eps2, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "set_eps2_i_dev before set_groups");
+    if (ni != ctx->ni)
+        return ctx->fail(BHQ_E_RANGE, "set_eps2_i_dev: ni %lld != %lld", (long long)ni,
+                         (long long)ctx->ni);
+    if (ni > 0) {
+        if (!eps2) return ctx->fail(BHQ_E_ARG, "eps2 is NULL");
+        TRY(ctx->select());
+        TRY(check_device_range(ctx, eps2, (size_t)ni * 8, "eps2"));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        ctx->quiesce();
+        TRY(dev_check(ctx, s, "set_eps2_i_dev", [&](unsigned *f) {
+            return bhq::launch_check_f64(eps2, ni, true, f, s);
+        }));
+        TRY(dev_done(ctx, hipMemcpyAsync(ctx->arr[A_E2I].p, eps2, (size_t)ni * 8,
+                                         hipMemcpyDeviceToDevice, s),
+                     s, "set_eps2_i_dev"));
+    }
+    ctx->eps_mode = 2;
+    return BHQ_OK;
+}
+
+int bhq_set_jp_dev(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
+                   const double *m, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "set_jp_dev before set_groups");
+    if (adr < 0 || n < 0) return ctx->fail(BHQ_E_ARG, "negative adr or n");
+    if (adr + n > ctx->njp)
+        return ctx->fail(BHQ_E_RANGE, "set_jp_dev: adr + n = %lld > njp = %lld",
+                         (long long)(adr + n), (long long)ctx->njp);
+    if (n > 0 && (!x || !m)) return ctx->fail(BHQ_E_ARG, "x or m is NULL");
+    TRY(ctx->select());
+    if (n > 0) {
+        TRY(check_device_range(ctx, x, (size_t)n * 24, "x"));
+        TRY(check_device_range(ctx, m, (size_t)n * 8, "m"));
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ctx->quiesce();
+    TRY(dev_check(ctx, s, "set_jp_dev", [&](unsigned *f) {
+        hipError_t e = bhq::launch_check_f64(&x[0][0], 3 * n, false, f, s);
+        if (e == hipSuccess) e = bhq::launch_check_f64(m, n, false, f, s);
+        return e;
+    }));
+    TRY(ctx->use_materialised());
+    double *out[3] = {ctx->arr[A_JPX].as<double>() + adr, ctx->arr[A_JPY].as<double>() + adr,
+                      ctx->arr[A_JPZ].as<double>() + adr};
+    hipError_t e = bhq::launch_unpack(&x[0][0], n, 3, out, s);
+    if (e == hipSuccess && n > 0)
+        e = hipMemcpyAsync(ctx->arr[A_JPM].as<double>() + adr, m, (size_t)n * 8,
+                           hipMemcpyDeviceToDevice, s);
+    TRY(dev_done(ctx, e, s, "set_jp_dev"));
+    ctx->have_jp = true;
+    return BHQ_OK;
+}
+
+int bhq_set_jc_dev(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
+                   const double *m, const double (*q)[6], const double *trace, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "set_jc_dev before set_groups");
+    if (adr < 0 || n < 0) return ctx->fail(BHQ_E_ARG, "negative adr or n");
+    if (adr + n > ctx->njc)
+        return ctx->fail(BHQ_E_RANGE, "set_jc_dev: adr + n = %lld > njc = %lld",
+                         (long long)(adr + n), (long long)ctx->njc);
+    if (n > 0 && (!x || !m || !q)) return ctx->fail(BHQ_E_ARG, "x, m or q is NULL");
+    TRY(ctx->select());
+    if (n > 0) {
+        TRY(check_device_range(ctx, x, (size_t)n * 24, "x"));
+        TRY(check_device_range(ctx, m, (size_t)n * 8, "m"));
+        TRY(check_device_range(ctx, q, (size_t)n * 48, "q"));
+        if (trace) TRY(check_device_range(ctx, trace, (size_t)n * 8, "trace"));
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ctx->quiesce();
+    TRY(dev_check(ctx, s, "set_jc_dev", [&](unsigned *f) {
+        hipError_t e = bhq::launch_check_f64(&x[0][0], 3 * n, false, f, s);
+        if (e == hipSuccess) e = bhq::launch_check_f64(m, n, false, f, s);
+        if (e == hipSuccess) e = bhq::launch_check_f64(&q[0][0], 6 * n, false, f, s);
+        if (e == hipSuccess && trace) e = bhq::launch_check_f64(trace, n, false, f, s);
+        return e;
+    }));
+    TRY(ctx->use_materialised());
+    auto col = [&](Arr a) { return ctx->arr[a].as<double>() + adr; };
+    double *xo[3] = {col(A_JCX), col(A_JCY), col(A_JCZ)};
+    double *qo[6] = {col(A_Q00), col(A_Q01), col(A_Q02), col(A_Q11), col(A_Q12), col(A_Q22)};
+    hipError_t e = bhq::launch_unpack(&x[0][0], n, 3, xo, s);
+    if (e == hipSuccess) e = bhq::launch_unpack(&q[0][0], n, 6, qo, s);
+    if (e == hipSuccess && n > 0)
+        e = hipMemcpyAsync(col(A_JCM), m, (size_t)n * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && n > 0)
+        e = trace ? hipMemcpyAsync(col(A_JCT), trace, (size_t)n * 8, hipMemcpyDeviceToDevice, s)
+                  : bhq::launch_fill_f64(col(A_JCT), n, 0.0, s);
+    TRY(dev_done(ctx, e, s, "set_jc_dev"));
+    ctx->have_jc = true;
+    return BHQ_OK;
+}
+
+int bhq_set_pool_particles_dev(bhq_ctx *ctx, int64_t n, const double (*x)[3],
+                               const double *m, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (n < 0 || n > 0x7fffffffLL) return ctx->fail(BHQ_E_ARG, "bad pool size");
+    if (n > 0 && (!x || !m)) return ctx->fail(BHQ_E_ARG, "x or m is NULL");
+    TRY(ctx->select());
+    if (n > 0) {
+        TRY(check_device_range(ctx, x, (size_t)n * 24, "x"));
+        TRY(check_device_range(ctx, m, (size_t)n * 8, "m"));
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ctx->quiesce();
+    TRY(dev_check(ctx, s, "set_pool_particles_dev", [&](unsigned *f) {
+        hipError_t e = bhq::launch_check_f64(&x[0][0], 3 * n, false, f, s);
+        if (e == hipSuccess) e = bhq::launch_check_f64(m, n, false, f, s);
+        return e;
+    }));
+    hipError_t e = ctx->arr[A_POOLP].reserve((size_t)n * sizeof(bhq::PartRec));
+    if (e == hipSuccess)
+        e = bhq::launch_pack_particles(&x[0][0], m, n, ctx->arr[A_POOLP].as<bhq::PartRec>(), s);
+    TRY(dev_done(ctx, e, s, "particle pool upload"));
+    ctx->npool_p = n;
+    ctx->tree_order = false;
+    ctx->have_jp_idx = false;
+    ++ctx->args_version;
+    return BHQ_OK;
+}
+
+int bhq_set_pool_cells_dev(bhq_ctx *ctx, int64_t n, const double (*x)[3], const double *m,
+                           const double (*q)[6], const double *trace, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (n < 0 || n > 0x7fffffffLL) return ctx->fail(BHQ_E_ARG, "bad pool size");
+    if (n > 0 && (!x || !m || !q)) return ctx->fail(BHQ_E_ARG, "x, m or q is NULL");
+    TRY(ctx->select());
+    if (n > 0) {
+        TRY(check_device_range(ctx, x, (size_t)n * 24, "x"));
+        TRY(check_device_range(ctx, m, (size_t)n * 8, "m"));
+        TRY(check_device_range(ctx, q, (size_t)n * 48, "q"));
+        if (trace) TRY(check_device_range(ctx, trace, (size_t)n * 8, "trace"));
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ctx->quiesce();
+    TRY(dev_check(ctx, s, "set_pool_cells_dev", [&](unsigned *f) {
+        hipError_t e = bhq::launch_check_f64(&x[0][0], 3 * n, false, f, s);
+        if (e == hipSuccess) e = bhq::launch_check_f64(m, n, false, f, s);
+        if (e == hipSuccess) e = bhq::launch_check_f64(&q[0][0], 6 * n, false, f, s);
+        if (e == hipSuccess && trace) e = bhq::launch_check_f64(trace, n, false, f, s);
+        return e;
+    }));
+    hipError_t e = ctx->arr[A_POOLC].reserve((size_t)n * sizeof(bhq::CellRec));
+    if (e == hipSuccess)
+        e = bhq::launch_pack_cells(&x[0][0], m, &q[0][0], trace, n,
+                                   ctx->arr[A_POOLC].as<bhq::CellRec>(), s);
+    TRY(dev_done(ctx, e, s, "cell pool upload"));
+    ctx->npool_c = n;
+    ctx->have_jc_idx = false;
+    ++ctx->args_version;
+    return BHQ_OK;
+}
+
+static int set_idx_dev(bhq_ctx *ctx, Arr a, int64_t total, int64_t pool, int64_t adr,
+                       int64_t n, const int32_t *idx, void *stream, const char *what)
+{
+    if (ctx->ng < 0) return ctx->fail(BHQ_E_STATE, "%s before set_groups", what);
+    if (pool < 0) return ctx->fail(BHQ_E_STATE, "%s before its pool is set", what);
+    if (adr < 0 || n < 0) return ctx->fail(BHQ_E_ARG, "negative adr or n");
+    if (adr + n > total)
+        return ctx->fail(BHQ_E_RANGE, "%s: adr + n = %lld > %lld", what, (long long)(adr + n),
+                         (long long)total);
+    if (n > 0 && !idx) return ctx->fail(BHQ_E_ARG, "idx is NULL");
+    TRY(ctx->select());
+    if (n > 0) TRY(check_device_range(ctx, idx, (size_t)n * 4, "idx"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ctx->quiesce();
+    TRY(dev_check(ctx, s, what, [&](unsigned *f) {
+        return bhq::launch_check_idx(idx, n, pool, f, s);
+    }));
+    TRY(ctx->use_indexed());
+    if (n == 0) return BHQ_OK;
+    TRY(ctx->unslot_lists());
+    return dev_done(ctx, hipMemcpyAsync(ctx->arr[a].as<int32_t>() + adr, idx, (size_t)n * 4,
+                                        hipMemcpyDeviceToDevice, s),
+                    s, what);
+}
+
+int bhq_set_jp_idx_dev(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx, void *stream)
+{
+    CHECK_CTX(ctx);
+    TRY(set_idx_dev(ctx, A_JPIDX, ctx->njp, ctx->npool_p, adr, n, idx, stream, "set_jp_idx_dev"));
+    ctx->have_jp_idx = true;
+    return BHQ_OK;
+}
+
+int bhq_set_jc_idx_dev(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx, void *stream)
+{
+    CHECK_CTX(ctx);
+    TRY(set_idx_dev(ctx, A_JCIDX, ctx->njc, ctx->npool_c, adr, n, idx, stream, "set_jc_idx_dev"));
+    ctx->have_jc_idx = true;
     return BHQ_OK;
 }
 

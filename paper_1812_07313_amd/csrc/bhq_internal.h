@@ -175,6 +175,22 @@ hipError_t scratch_init(int device);
 // The address found by scratch_init on `device`, or NULL.
 void *scratch_ptr(int device);
 
+// Device-side uploads (bhq_upload.hip).  The check kernels OR these bits
+// into *flag; launch_clear_flag zeroes it.
+constexpr unsigned kBadNonFinite = 1, kBadNonPositive = 2, kBadOrder = 4, kBadRange = 8;
+hipError_t launch_clear_flag(unsigned *flag, hipStream_t s);
+hipError_t launch_check_f64(const double *v, int64_t n, bool positive, unsigned *flag,
+                            hipStream_t s);
+hipError_t launch_check_offsets(const int64_t *off, int64_t ng, unsigned *flag, hipStream_t s);
+hipError_t launch_check_idx(const int32_t *idx, int64_t n, int64_t pool, unsigned *flag,
+                            hipStream_t s);
+// column c of the AoS array v[n][w] (w <= 6) to out[c] (NULL: skipped)
+hipError_t launch_unpack(const double *v, int64_t n, int w, double *const *out, hipStream_t s);
+hipError_t launch_pack_particles(const double *x, const double *m, int64_t n, PartRec *out,
+                                 hipStream_t s);
+hipError_t launch_pack_cells(const double *x, const double *m, const double *q,
+                             const double *t, int64_t n, CellRec *out, hipStream_t s);
+
 // Launch the force kernel for (kernel, precision) on `stream`.  Returns
 // the launch status.
 hipError_t launch_force(int kernel, int precision, const ForceArgs &args,
