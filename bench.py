@@ -10,13 +10,18 @@ library's builder and are resident in HBM before the timed region.
 
 Prints ONE JSON line (logs go to stderr): throughput in Ginteractions/s
 (particle-particle plus particle-cell interactions per second), the FP32
-VALU roofline of the force kernel, the other variants on the same lists
-(monopole, FP64), the quadrupole-versus-monopole comparison at equal rms
-force error (the paper's Table 2 question), and the FP64 oracle timed on
-the host's cores.
+VALU roofline of the force kernel with the shader clock measured during
+the timed launches, the paper-convention GFLOP/s, the other variants on the
+same lists (monopole, FP64, complete softened quadrupole), the
+quadrupole-versus-monopole comparison at equal rms force error (the paper's
+Table 2 question), the FP64 oracle timed on the host's cores (all of them
+and one), and compact records of the other four configurations (Plummer
+16k, clustered 2^22, 256 batched systems, periodic lattice 2^24 with the
+split kernel priced on its pairs inside the cutoff), each on device-built
+lists with the oracle on sampled groups beside it.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
-        [--no-cpu-baseline] [--no-fixed-error] [--no-variants]
+        [--no-cpu-baseline] [--no-fixed-error] [--no-variants] [--no-configs]
 
 Other workloads (--workload): sphere (the paper's homogeneous sphere,
 N = 4,194,304), plummer16k, clustered, batched, lattice.
@@ -24,6 +29,7 @@ N = 4,194,304), plummer16k, clustered, batched, lattice.
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -43,6 +49,18 @@ from paper_1812_07313_amd import bhq, synth  # noqa: E402
 # radial-function evaluation and are not priced here.
 FLOPS_PP = 20
 FLOPS_PC = {bhq.QUAD: 53, bhq.MONO: 20, bhq.QUAD_SOFT: 55}
+# FP32 split kernels, per term inside the cutoff (FMA = 2, rsqrt and fract 1,
+# the table index conversion 0): particle term 36 (separation 8, rsqrt 1,
+# r 1, table variable and fraction 2, erfc and g by Horner 12, the rest 12);
+# quadrupole cell term 97 (the same start, four Horner functions 24, D1..D3,
+# Q d and d.Q.d, the trace terms and the accumulation); monopole cell 37.
+# Masked terms (beyond the cutoff) do no work of the method and are not
+# counted: the split roofline is priced on the pairs bhq_count_live finds.
+FLOPS_SPLIT_PP = 36
+FLOPS_SPLIT_PC = {bhq.SPLIT_QUAD: 97, bhq.SPLIT_MONO: 37}
+# the paper's convention for one particle-cell quadrupole interaction
+# (rsqrt counted as 20 flops, Sec. 3.3 and Sec. 5.2)
+PAPER_FLOPS_PC = 71
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak
 METRIC = ("Ginteractions/s + s/force-eval at fixed rms error; quad vs mono, "
@@ -120,7 +138,7 @@ def workload(name, n=None):
         return dict(name="perturbed lattice N=%d in the periodic unit box, "
                          "Gaussian split r_s=1.25/256, cutoff 4.5 r_s, "
                          "theta=0.5" % len(c["m"]),
-                    x=c["x"], m=c["m"], theta=0.5, ncrit=64, box=1.0,
+                    x=c["x"], m=c["m"], theta=0.5, ncrit=128, box=1.0,
                     rs=c["rs"], rcut=c["rcut"], kernel=bhq.SPLIT_QUAD)
     raise SystemExit("unknown workload %r" % name)
 
@@ -228,15 +246,22 @@ def upload(ctx, W, L, indexed=False):
     return P, time.perf_counter() - t0
 
 
-def time_variant(torch, ctx, kernel, precision, steps, warmup, stream):
+def time_variant(torch, ctx, kernel, precision, steps, warmup, stream, clock=False):
     """Wall time per step over `steps` back-to-back launches, and the mean
-    and median kernel duration from events recorded on the launch stream."""
+    and median kernel duration from events recorded on the launch stream.
+    clock: also the mean shader clock (MHz) of one CU over the first 80 %
+    of the timed launches (bhq_clock_begin on a stream of its own), else
+    None."""
     bhq.bhq_set_kernel(ctx, kernel, precision)
     for _ in range(warmup):
         bhq.bhq_compute(ctx, stream)
+    est_ms = bhq.bhq_get_kernel_ms(ctx) if warmup else 0.0
     ev = [(torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
+    if clock and est_ms > 0:
+        side = torch.cuda.Stream()
+        bhq.bhq_clock_begin(ctx, min(0.8 * steps * est_ms, 10000.0), side)
     t0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record(stream)
@@ -244,8 +269,9 @@ def time_variant(torch, ctx, kernel, precision, steps, warmup, stream):
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    mhz = bhq.bhq_clock_end(ctx) if (clock and est_ms > 0) else None
     kern_ms = [a.elapsed_time(b) for a, b in ev]
-    return wall / steps * 1e3, float(np.mean(kern_ms)), float(np.median(kern_ms))
+    return wall / steps * 1e3, float(np.mean(kern_ms)), float(np.median(kern_ms)), mhz
 
 
 def result_orig(ctx, P, n):
@@ -369,8 +395,8 @@ def fixed_error_study(torch, ctx, W, ref, stream, steps):
         if timing:
             pp, pc = bhq.bhq_get_counts(ctx)
             for prec in (bhq.FP32_OFS64, bhq.FP64):
-                _, km, _ = time_variant(torch, ctx, kernel, prec, steps, 1,
-                                        stream)
+                _, km, _, _ = time_variant(torch, ctx, kernel, prec, steps, 1,
+                                           stream)
                 out["ms_" + bhq.PRECISION_NAMES[prec]] = round(km, 4)
             out["n_pp"], out["n_pc"] = pp, pc
             out["build_ms"] = round(build_ms(theta), 4)
@@ -417,26 +443,294 @@ def _fixed_error_rows(measure):
 
 # --- CPU baseline -----------------------------------------------------------------
 
-def cpu_baseline(W, a_gpu):
-    """The FP64 oracle (test infrastructure) timed on this host's cores,
-    evaluating the whole workload's lists once; its result also gives the
+def host_info():
+    """The host CPU: model, sockets x cores (lscpu), logical CPUs, and the
+    CPUs this process may run on."""
+    info = {"model": None, "physical_cores": None, "threads_per_core": None,
+            "logical_cpus": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        info["model"] = kv.get("Model name")
+        sockets = int(kv.get("Socket(s)", "0") or 0)
+        per = int(kv.get("Core(s) per socket", "0") or 0)
+        info["physical_cores"] = sockets * per or None
+        info["threads_per_core"] = int(kv.get("Thread(s) per core", "0") or 0) or None
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def _sample_interactions(mat):
+    ni = np.diff(mat["i_off"])
+    return int(np.sum(ni * (np.diff(mat["jp_off"]) + np.diff(mat["jc_off"]))))
+
+
+def cpu_baseline(W, a_gpu, host):
+    """The FP64 oracle (test infrastructure) timed on this host's cores: its
+    own tree, groups and lists (built separately, timed), one evaluation of
+    every particle's lists with all its threads, and one thread on every
+    16th group (the paper's single-core setting).  Its result also gives the
     GPU FP32 path's error against the oracle."""
     import oracle as orc
+    nt = orc.num_threads()
+    t0 = time.perf_counter()
     T = orc.Tree(W["x"], W["m"], W["theta"], W["ncrit"])
+    t_tree = time.perf_counter() - t0
     mat = orc.materialise(T, W["x"], W["m"])
     n_pp, n_pc = T.interaction_counts()
     t0 = time.perf_counter()
     a_o, _ = orc.eval_lists(orc.QUAD, mat, W["x"], W["eps"] ** 2)
     dt = time.perf_counter() - t0
     e = orc.relative_errors(a_gpu, a_o)
+    smat = T.sample_mat(W["x"], W["m"], np.arange(0, T.ngroups, 16))
+    n1 = _sample_interactions(smat)
+    orc.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        orc.eval_lists(orc.QUAD, smat, W["x"], W["eps"] ** 2)
+        dt1 = time.perf_counter() - t0
+    finally:
+        orc.set_threads(nt)
     return {"value": round((n_pp + n_pc) / dt / 1e9, 4),
-            "unit": "Ginteractions/s", "cores": orc.num_threads(),
+            "unit": "Ginteractions/s", "cores": nt,
             "kind": "oracle",
             "sample": "one full FP64 evaluation of all %d particles' lists "
-                      "(%.3g interactions, %.2f s)" % (len(W["m"]), n_pp + n_pc,
-                                                       dt),
+                      "(%.3g interactions, %.2f s, %d threads)" % (len(W["m"]), n_pp + n_pc,
+                                                                  dt, nt),
+            "one_thread": {"value": round(n1 / dt1 / 1e9, 4), "unit": "Ginteractions/s",
+                           "sample": "every 16th group (%.3g interactions, %.2f s)" % (n1, dt1)},
+            "tree_and_lists_s": round(t_tree, 3),
+            "host": host,
             "gpu_fp32_vs_oracle": {"rms": float(np.sqrt(np.mean(e ** 2))),
                                    "max": float(e.max())}}
+
+
+def direct_check(W, ref):
+    """The sampled direct-sum reference of the tree-error study (the
+    library's FP64 kernel over every particle) against the oracle's direct
+    summation of the same targets: the largest relative difference."""
+    import oracle as orc
+    idx, a_lib = ref
+    t0 = time.perf_counter()
+    e2 = W["eps2"] if W.get("eps2") is not None else W["eps"] ** 2
+    a_o, _ = orc.direct(W["x"], W["m"], e2, targets=idx)
+    dt = time.perf_counter() - t0
+    e = orc.relative_errors(a_lib, a_o)
+    return {"targets": int(len(idx)), "max_rel_diff": float(e.max()),
+            "rms_rel_diff": float(np.sqrt(np.mean(e ** 2))), "oracle_s": round(dt, 2)}
+
+
+# --- the other configurations (compact records) ----------------------------------
+
+def _dev_ctx(torch, W, ncrit, kernel):
+    """A context holding device-built lists of the workload."""
+    xt = torch.from_numpy(np.ascontiguousarray(W["x"])).cuda()
+    mt = torch.from_numpy(np.ascontiguousarray(W["m"])).cuda()
+    ctx = bhq.bhq_create(0, kernel, bhq.FP32_OFS64)
+    try:
+        if W.get("sys_off") is not None:
+            e2t = torch.from_numpy(np.ascontiguousarray(W["eps2"])).cuda()
+            bhq.bhq_build_lists_device_batch(ctx, W["sys_off"], xt, mt, W["theta"], ncrit,
+                                             min(8, ncrit), eps2=e2t)
+        else:
+            bhq.bhq_build_lists_device(ctx, xt, mt, W["theta"], ncrit, min(8, ncrit),
+                                       W.get("box", 0.0), W.get("rcut", 0.0))
+            if W.get("eps") is not None:
+                bhq.bhq_set_eps(ctx, W["eps"])
+        if W.get("rs"):
+            bhq.bhq_set_split(ctx, W["rs"], W["rcut"], W.get("box", 0.0))
+    except Exception:
+        bhq.bhq_destroy(ctx)
+        raise
+    return ctx
+
+
+def _result_input_order(torch, ctx, n, stream):
+    a = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    p = torch.empty(n, dtype=torch.float64, device="cuda")
+    bhq.bhq_compute(ctx, stream)
+    bhq.bhq_get_result_device(ctx, a, p, stream)
+    torch.cuda.synchronize()
+    return a.cpu().numpy(), p.cpu().numpy()
+
+
+def _priced(kernel, n_pp, n_pc, ms, peak):
+    if kernel in FLOPS_PC:
+        flops = FLOPS_PP * n_pp + FLOPS_PC[kernel] * n_pc
+    else:
+        flops = FLOPS_SPLIT_PP * n_pp + FLOPS_SPLIT_PC[kernel] * n_pc
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"tflops": round(tf, 3), "frac": round(tf / peak, 4)}
+
+
+def config_record(torch, stream, W, kernel, ncrit, shapes, steps, fp64=True, live=False):
+    """One configuration on device-built lists: the FP32 kernel time for each
+    launch shape (bhq_set_tuning arguments) and the fastest, the FP64 time at
+    that shape, throughput and the FP32 roofline fraction; for the split
+    kernels the pairs inside the cutoff and the roofline priced on them.
+    Returns (record, FP32 result in input order)."""
+    ctx = _dev_ctx(torch, W, ncrit, kernel)
+    n = len(W["m"])
+    try:
+        n_pp, n_pc = bhq.bhq_get_counts(ctx)
+        ng = bhq.bhq_get_lists_sizes(ctx)[0]
+        rows = []
+        for shape in shapes:
+            bhq.bhq_set_tuning(ctx, *shape)
+            _, km, kmed, _ = time_variant(torch, ctx, kernel, bhq.FP32_OFS64, steps, 2, stream)
+            rows.append(dict(shape=list(shape), kernel_ms=round(km, 4),
+                             kernel_ms_median=round(kmed, 4)))
+        best = min(rows, key=lambda r: r["kernel_ms"])
+        bhq.bhq_set_tuning(ctx, *best["shape"])
+        km = best["kernel_ms"]
+        rec = {"workload": W["name"] + ", ncrit=%d" % ncrit, "n": n, "groups": ng,
+               "n_pp": n_pp, "n_pc": n_pc, "kernel": bhq.KERNEL_NAMES[kernel],
+               "launch": dict(zip(("block", "i_per_thread", "blocks_per_cu", "persistent",
+                                   "graph", "jsplit"), best["shape"])),
+               "shapes": rows, "kernel_ms_fp32": km,
+               "Ginteractions_per_s": round((n_pp + n_pc) / km / 1e6, 2),
+               "s_per_force_eval": round(km * 1e-3, 7)}
+        if live:
+            lp, lc = bhq.bhq_count_live(ctx)
+            rec["live_pp"], rec["live_pc"] = lp, lc
+            rec["live_fraction"] = {"pp": round(lp / max(n_pp, 1), 4),
+                                    "pc": round(lc / max(n_pc, 1), 4)}
+            rec["live_Ginteractions_per_s"] = round((lp + lc) / km / 1e6, 2)
+            rec["roofline_fp32"] = dict(_priced(kernel, lp, lc, km, PEAK_FP32_TFLOPS),
+                                        priced_on="pairs inside the cutoff")
+        else:
+            rec["roofline_fp32"] = _priced(kernel, n_pp, n_pc, km, PEAK_FP32_TFLOPS)
+        a32, p32 = _result_input_order(torch, ctx, n, stream)
+        if fp64:
+            _, k64, _, _ = time_variant(torch, ctx, kernel, bhq.FP64, max(3, steps // 4), 1,
+                                        stream)
+            rec["kernel_ms_fp64"] = round(k64, 4)
+            if not live:
+                rec["roofline_fp64"] = _priced(kernel, n_pp, n_pc, k64, PEAK_FP64_TFLOPS)
+            a64, _ = _result_input_order(torch, ctx, n, stream)
+            e = np.linalg.norm(a32 - a64, axis=1) / np.linalg.norm(a64, axis=1)
+            rec["fp32_vs_fp64_rel_err"] = {"rms": float(np.sqrt(np.mean(e ** 2))),
+                                           "max": float(e.max())}
+    finally:
+        bhq.bhq_destroy(ctx)
+    return rec, a32, p32
+
+
+def oracle_leg(W, kernel, ncrit, a_gpu, stride):
+    """The oracle on every stride-th group of its own tree (the same lists as
+    the GPU's): its FP64 rate, its tree and list build time, and the GPU
+    FP32 result's error against it on those groups' particles."""
+    import oracle as orc
+    okind = {bhq.QUAD: orc.QUAD, bhq.SPLIT_QUAD: orc.SPLIT_QUAD}[kernel]
+    t0 = time.perf_counter()
+    T = orc.Tree(W["x"], W["m"], W["theta"], ncrit, nleaf=min(8, ncrit),
+                 box=W.get("box", 0.0), rcut=W.get("rcut", 0.0), walk_stride=stride)
+    t_tree = time.perf_counter() - t0
+    mat = T.sample_mat(W["x"], W["m"], np.arange(0, T.ngroups, stride))
+    nint = _sample_interactions(mat)
+    t0 = time.perf_counter()
+    if kernel == bhq.SPLIT_QUAD:
+        a_o, _ = orc.eval_lists(okind, mat, W["x"], 0.0, box=W["box"], rs=W["rs"],
+                                rcut=W["rcut"], mask=orc.MASK_F64_OFS)
+    else:
+        a_o, _ = orc.eval_lists(okind, mat, W["x"], W["eps"] ** 2)
+    dt = time.perf_counter() - t0
+    sel = mat["i_idx"]
+    e = orc.relative_errors(a_gpu[sel], a_o[sel])
+    return {"value": round(nint / dt / 1e9, 4), "unit": "Ginteractions/s",
+            "cores": orc.num_threads(), "kind": "oracle",
+            "sample": "every %d-th group: %d groups, %d particles, %.3g interactions, %.2f s"
+                      % (stride, len(mat["i_off"]) - 1, len(sel), nint, dt),
+            "tree_and_lists_s": round(t_tree, 3),
+            "gpu_fp32_vs_oracle": {"rms": float(np.sqrt(np.mean(e ** 2))),
+                                   "max": float(e.max()), "particles": int(len(sel))}}
+
+
+def other_configs(torch, stream, steps, cpu=True):
+    """Compact records of the small, clustered, batched and periodic
+    configurations, each on device-built lists, with the oracle on sampled
+    groups beside it."""
+    import oracle as orc
+    recs = {}
+    eager = [(256, 2, 0, 0, 0, 1), (256, 1, 0, 0, 0, 1)]
+
+    W = workload("plummer16k")
+    shapes = [(256, ipt, 0, 0, 0, js) for ipt in (1, 2) for js in (1, 2, 4, 8)]
+    rec, a32, _ = config_record(torch, stream, W, bhq.QUAD, 64, shapes, steps)
+    if cpu:
+        rec["cpu_baseline"] = oracle_leg(W, bhq.QUAD, 64, a32, 1)
+        t0 = time.perf_counter()
+        a_d, _ = orc.direct(W["x"], W["m"], W["eps"] ** 2)
+        e = orc.relative_errors(a32, a_d)
+        rec["tree_error_vs_direct"] = {"rms": float(np.sqrt(np.mean(e ** 2))),
+                                       "p90": float(np.percentile(e, 90)),
+                                       "max": float(e.max()),
+                                       "direct_s": round(time.perf_counter() - t0, 2)}
+    recs["plummer16k"] = rec
+    log("plummer16k: %.4f ms (%s)" % (rec["kernel_ms_fp32"], rec["launch"]))
+
+    W = workload("clustered")
+    rec, a32, _ = config_record(torch, stream, W, bhq.QUAD, 256, eager, steps)
+    if cpu:
+        rec["cpu_baseline"] = oracle_leg(W, bhq.QUAD, 256, a32, 64)
+    recs["clustered"] = rec
+    log("clustered: %.3f ms" % rec["kernel_ms_fp32"])
+    del W
+
+    W = workload("batched")
+    best = None
+    for ncrit in (64, 128):
+        rec, a32, _ = config_record(
+            torch, stream, W, bhq.QUAD, ncrit,
+            eager + [(256, 2, 0, 1, 1, 1), (256, 1, 0, 1, 1, 1)], steps)
+        if best is None or rec["kernel_ms_fp32"] < best[0]["kernel_ms_fp32"]:
+            best = (rec, a32, ncrit)
+    rec, a32, ncrit = best
+    graph = [r for r in rec["shapes"] if r["shape"][3] == 1 and r["shape"][4] == 1]
+    rec["persistent_graph_kernel_ms"] = min(r["kernel_ms"] for r in graph)
+    rec["eager_kernel_ms"] = min(r["kernel_ms"] for r in rec["shapes"] if r["shape"][3] == 0)
+    if cpu:
+        t_all, n_all, errs, t_tree = 0.0, 0, [], 0.0
+        off = W["sys_off"]
+        for sidx in range(0, len(off) - 1, 8):
+            x, m = W["x"][off[sidx]:off[sidx + 1]], W["m"][off[sidx]:off[sidx + 1]]
+            t0 = time.perf_counter()
+            T = orc.Tree(x, m, W["theta"], ncrit, nleaf=min(8, ncrit))
+            t_tree += time.perf_counter() - t0
+            mat = orc.materialise(T, x, m)
+            t0 = time.perf_counter()
+            a_o, _ = orc.eval_lists(orc.QUAD, mat, x, W["eps2"][off[sidx]:off[sidx + 1]])
+            t_all += time.perf_counter() - t0
+            n_all += _sample_interactions(mat)
+            errs.append(orc.relative_errors(a32[off[sidx]:off[sidx + 1]], a_o))
+        e = np.concatenate(errs)
+        rec["cpu_baseline"] = {
+            "value": round(n_all / t_all / 1e9, 4), "unit": "Ginteractions/s",
+            "cores": orc.num_threads(), "kind": "oracle",
+            "sample": "every 8th system (32 of 256, %d particles, %.3g interactions, %.2f s)"
+                      % (len(e), n_all, t_all),
+            "tree_and_lists_s": round(t_tree, 3),
+            "gpu_fp32_vs_oracle": {"rms": float(np.sqrt(np.mean(e ** 2))),
+                                   "max": float(e.max()), "particles": int(len(e))}}
+    recs["batched"] = rec
+    log("batched: ncrit %d, eager %.3f ms, persistent+graph %.3f ms"
+        % (ncrit, rec["eager_kernel_ms"], rec["persistent_graph_kernel_ms"]))
+    del W
+
+    W = workload("lattice")
+    rec, a32, _ = config_record(torch, stream, W, bhq.SPLIT_QUAD, 128,
+                                [(256, 2, 0, 0, 0, 1), (256, 1, 0, 0, 0, 1)],
+                                max(5, steps // 2), live=True)
+    if cpu:
+        rec["cpu_baseline"] = oracle_leg(W, bhq.SPLIT_QUAD, 128, a32, 2000)
+    recs["lattice"] = rec
+    log("lattice: %.3f ms, live pairs %s" % (rec["kernel_ms_fp32"], rec["live_fraction"]))
+    return recs
 
 
 ORDERS = {"xcd": bhq.ORDER_XCD, "cost": bhq.ORDER_COST}
@@ -482,6 +776,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-fixed-error", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the records of the other four configurations")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB "
                          "device-to-device once (a plain copy kernel of known "
@@ -554,9 +850,10 @@ def main():
                                 args.order_tail)
         n_pp, n_pc = bhq.bhq_get_counts(ctx)
         n_int = n_pp + n_pc
+        live = bhq.bhq_count_live(ctx) if kernel not in FLOPS_PC else None
 
-        ms_step, ms_kern, ms_kern_med = time_variant(
-            torch, ctx, kernel, bhq.FP32_OFS64, args.steps, args.warmup, stream)
+        ms_step, ms_kern, ms_kern_med, sclk = time_variant(
+            torch, ctx, kernel, bhq.FP32_OFS64, args.steps, args.warmup, stream, clock=True)
         log("%s fp32: %.3f ms/step (kernel %.3f ms)"
             % (bhq.KERNEL_NAMES[kernel], ms_step, ms_kern))
         bhq.bhq_compute(ctx, stream)
@@ -572,8 +869,8 @@ def main():
                 others = [(bhq.SPLIT_MONO, bhq.FP32_OFS64),
                           (bhq.SPLIT_QUAD, bhq.FP64)]
             for kern, prec in others:
-                vs, vk, _ = time_variant(torch, ctx, kern, prec,
-                                         max(3, args.steps // 4), 1, stream)
+                vs, vk, _, _ = time_variant(torch, ctx, kern, prec,
+                                            max(3, args.steps // 4), 1, stream)
                 v = {"ms_per_eval": round(vs, 4), "kernel_ms": round(vk, 4),
                      "Ginteractions_per_s": round(n_int / vk / 1e6, 2)}
                 if kern in FLOPS_PC:
@@ -596,6 +893,9 @@ def main():
         ref = direct_reference(W, P, nsample=4096 if n <= (1 << 20) else 1024)
         out_extra["tree_error_vs_direct"] = dict(
             sample=len(ref[0]), fp32=tree_error(a32, ref))
+        if not args.no_cpu_baseline and not W.get("rs"):
+            log("checking the direct-sum reference with the oracle ...")
+            out_extra["tree_error_vs_direct"]["reference_vs_oracle_direct"] = direct_check(W, ref)
         if kernel == bhq.QUAD and not args.no_variants:
             # the complete softened quadrupole (with the cells' trace term)
             bhq.bhq_set_kernel(ctx, bhq.QUAD_SOFT, bhq.FP32_OFS64)
@@ -623,17 +923,26 @@ def main():
     roofline = None
     if kernel in FLOPS_PC:
         flops = FLOPS_PP * n_pp + FLOPS_PC[kernel] * n_pc
-        achieved = flops / (ms_kern * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(achieved, 3),
-                    "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                    "traffic": (profiled_traffic() if args.workload == "cube"
-                                and kernel == bhq.QUAD else None)}
+    else:
+        flops = FLOPS_SPLIT_PP * live[0] + FLOPS_SPLIT_PC[kernel] * live[1]
+    achieved = flops / (ms_kern * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": (profiled_traffic() if args.workload == "cube"
+                            and kernel == bhq.QUAD else None)}
+    if kernel not in FLOPS_PC:
+        roofline["priced_on"] = "pairs inside the cutoff (bhq_count_live)"
 
     cpu = None
     if not args.no_cpu_baseline and args.workload == "cube":
         log("timing the oracle on the host ...")
-        cpu = cpu_baseline(W, a32)
+        cpu = cpu_baseline(W, a32, host_info())
+
+    configs = None
+    if not args.no_configs and args.workload == "cube":
+        log("other configurations ...")
+        configs = other_configs(torch, stream, args.steps, cpu=not args.no_cpu_baseline)
 
     out = {
         "metric": METRIC,
@@ -657,12 +966,19 @@ def main():
         "s_per_force_eval": round(ms_step * 1e-3, 6),
         "kernel_ms": round(ms_kern, 4), "kernel_ms_median": round(ms_kern_med, 4),
         "pc_Ginteractions_per_s": round(n_pc / (ms_kern * 1e-3) / 1e9, 3),
+        "paper_convention_gflops": (round(PAPER_FLOPS_PC * n_pc / (ms_kern * 1e-3) / 1e9, 1)
+                                    if kernel == bhq.QUAD else None),
+        "sclk_mhz": round(sclk, 1) if sclk else None,
+        "live_pairs": ({"pp": live[0], "pc": live[1],
+                        "Ginteractions_per_s": round(sum(live) / (ms_kern * 1e-3) / 1e9, 3)}
+                       if live else None),
         "host_list_build_s": round(t_build, 3), "upload_s": round(t_upload, 3),
         "device_list_build": dev_build,
         "treepm": treepm,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,
+        "configs": configs,
     }
     out.update(out_extra)
     print(json.dumps(out), flush=True)

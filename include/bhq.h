@@ -269,6 +269,25 @@ int bhq_get_counts(const bhq_ctx *ctx, int64_t *n_pp, int64_t *n_pc);
  * measured with HIP events on the compute stream.  Waits for it. */
 int bhq_get_kernel_ms(bhq_ctx *ctx, double *ms);
 
+/* For the split kernels (BHQ_SPLIT_QUAD / BHQ_SPLIT_MONO): the number of
+ * (i-particle, list entry) pairs of the context's lists that lie inside the
+ * cutoff, i.e. that the kernels evaluate rather than mask: *pp for the
+ * particle entries, *pc for the cell entries (the decision of the kernels:
+ * FP64 offsets to the group centre, 0 < r^2 < rcut^2).  The list counts of
+ * bhq_get_counts include the masked pairs too.  Synchronous (one counting
+ * kernel).  Errors: BHQ_E_STATE (another kernel, or no lists), BHQ_E_ARG. */
+int bhq_count_live(bhq_ctx *ctx, int64_t *pp, int64_t *pc);
+
+/* The GPU's shader clock during other work (measurement support):
+ * bhq_clock_begin launches one wave on `stream` that reads the shader-clock
+ * counter and the constant-rate counter, waits until wall_ms (in (0, 10000])
+ * of the latter have passed, and reads both again; launch it on a stream of
+ * its own just before the work to be observed.  bhq_clock_end waits for it
+ * and returns the mean clock of the CU it ran on over that window, in MHz.
+ * Errors: BHQ_E_ARG, BHQ_E_STATE (end without begin), BHQ_E_HIP. */
+int bhq_clock_begin(bhq_ctx *ctx, double wall_ms, void *stream);
+int bhq_clock_end(bhq_ctx *ctx, double *mhz);
+
 /* Launch shape: the autotuner's knobs (ncrit, the other knob, shapes the
  * lists; the group size n_crit is the paper's tuning parameter, Sec. 3.4).
  *   block          threads per block, which is also the depth of one LDS

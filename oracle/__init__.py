@@ -8,8 +8,9 @@ shares no code with the GPU library and is never called by it.
 """
 from .oracle import (  # noqa: F401
     MONO, QUAD, SPLIT_QUAD, SPLIT_MONO, QUAD_SOFT, MASK_ABS, MASK_F64_OFS,
-    split_keep, mask_flips,
+    split_keep, mask_flips, count_keep,
     build, lib, Tree, build_tree, eval_lists, direct, moments, pp_plummer,
     pc_quad, pc_quad_soft, pc_mono, pc_split, pp_split, split_derivs, num_threads,
+    set_threads,
     materialise, relative_errors, leapfrog,
 )

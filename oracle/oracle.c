@@ -222,6 +222,30 @@ int64_t orc_mask_flips(int64_t ng, const int64_t *i_idx, const int64_t *i_off,
     return flips;
 }
 
+/* Number of (i, list entry) terms of the lists (arguments as orc_eval)
+ * that the cutoff keeps under decision `mode`: out[0] for the particle
+ * entries, out[1] for the cell entries. */
+void orc_count_keep(int mode, int64_t ng, const int64_t *i_idx, const int64_t *i_off,
+                    const double *x, const int64_t *jp_off, const double *jp_x,
+                    const int64_t *jc_off, const double *jc_x, double box, double rcut,
+                    const double *gcenter, int64_t out[2])
+{
+    int64_t kp = 0, kc = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : kp, kc)
+    for (int64_t g = 0; g < ng; ++g) {
+        const double *c = &gcenter[3 * g];
+        for (int64_t k = i_off[g]; k < i_off[g + 1]; ++k) {
+            const double *xi = &x[3 * i_idx[k]];
+            for (int64_t j = jp_off[g]; j < jp_off[g + 1]; ++j)
+                kp += orc_split_keep(mode, &jp_x[3 * j], xi, c, box, rcut);
+            for (int64_t j = jc_off[g]; j < jc_off[g + 1]; ++j)
+                kc += orc_split_keep(mode, &jc_x[3 * j], xi, c, box, rcut);
+        }
+    }
+    out[0] = kp;
+    out[1] = kc;
+}
+
 /* Short-range point mass without the cutoff test: a = m D1(r) d,
  * phi = m Phi(r). */
 static void split_pair_value(const double d[3], double m, double rs,
@@ -914,4 +938,16 @@ int orc_num_threads(void)
         }
     }
     return nt;
+}
+
+/* Number of OpenMP threads for the oracle's later parallel loops (n >= 1;
+ * it distributes independent groups or particles only, so results do not
+ * depend on it). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }

@@ -55,6 +55,8 @@ def lib():
                                _D, _I64, _D, _D, _I64, _D, _D, _D, _D,
                                ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_int, _D, _D, _D]
+        L.orc_count_keep.argtypes = [ctypes.c_int, ctypes.c_int64, _I64, _I64, _D, _I64, _D,
+                                     _I64, _D, ctypes.c_double, ctypes.c_double, _D, _I64]
         L.orc_mask_flips.restype = ctypes.c_int64
         L.orc_mask_flips.argtypes = [ctypes.c_int64, _I64, _I64, _D, _I64, _D, _I64,
                                      _D, ctypes.c_double, ctypes.c_double, _D]
@@ -79,6 +81,7 @@ def lib():
         L.orc_split_derivs.argtypes = [ctypes.c_double, ctypes.c_double, _D,
                                        _D, _D, _D]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -97,6 +100,11 @@ def _cd(a):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_threads(n):
+    """Threads for the oracle's later parallel loops (results unchanged)."""
+    lib().orc_set_threads(int(n))
 
 
 class Tree:
@@ -247,6 +255,22 @@ def mask_flips(mat, x, box, rcut):
                                     _dp(_cd(mat["jp_x"])), _ip(jc_off),
                                     _dp(_cd(mat["jc_x"])), float(box), float(rcut),
                                     _dp(_cd(mat["gcenter"]))))
+
+
+def count_keep(mat, x, box, rcut, mask=MASK_ABS):
+    """(particle terms, cell terms) of the materialised lists that the
+    cutoff keeps under the given decision."""
+    x = _cd(x).reshape(-1, 3)
+    i_off = np.ascontiguousarray(mat["i_off"], np.int64)
+    out = np.zeros(2, np.int64)
+    lib().orc_count_keep(int(mask), i_off.shape[0] - 1,
+                         _ip(np.ascontiguousarray(mat["i_idx"], np.int64)), _ip(i_off), _dp(x),
+                         _ip(np.ascontiguousarray(mat["jp_off"], np.int64)),
+                         _dp(_cd(mat["jp_x"])),
+                         _ip(np.ascontiguousarray(mat["jc_off"], np.int64)),
+                         _dp(_cd(mat["jc_x"])), float(box), float(rcut),
+                         _dp(_cd(mat["gcenter"])), _ip(out))
+    return int(out[0]), int(out[1])
 
 
 def direct(x, m, eps2=0.0, targets=None, split=False, box=0.0, rs=0.0,

@@ -60,6 +60,9 @@ SIGNATURES = {
     "bhq_set_pool_cells_dev": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, _P, _P]),
     "bhq_set_jp_idx_dev": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
     "bhq_set_jc_idx_dev": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P]),
+    "bhq_count_live": (ctypes.c_int, [_P, _I64, _I64]),
+    "bhq_clock_begin": (ctypes.c_int, [_P, ctypes.c_double, _P]),
+    "bhq_clock_end": (ctypes.c_int, [_P, _D]),
     "bhq_compute": (ctypes.c_int, [_P, _P]),
     "bhq_compute_noalloc": (ctypes.c_int, [_P, _P, _P, _P]),
     "bhq_get_result": (ctypes.c_int, [_P, _D, _D]),
@@ -304,6 +307,24 @@ def bhq_compute_noalloc(ctx, a, pot=None, stream=None):
     pa = _device_ptr(a, (n, 3), "a")
     pp = None if pot is None else _device_ptr(pot, (n,), "pot")
     _check(lib().bhq_compute_noalloc(ctx, pa, pp, _stream_handle(stream)), ctx)
+
+
+def bhq_count_live(ctx):
+    """(particle pairs, cell pairs) of the split kernels' lists inside the
+    cutoff."""
+    pp, pc = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().bhq_count_live(ctx, ctypes.byref(pp), ctypes.byref(pc)), ctx)
+    return pp.value, pc.value
+
+
+def bhq_clock_begin(ctx, wall_ms, stream=None):
+    _check(lib().bhq_clock_begin(ctx, float(wall_ms), _stream_handle(stream)), ctx)
+
+
+def bhq_clock_end(ctx):
+    mhz = ctypes.c_double()
+    _check(lib().bhq_clock_end(ctx, ctypes.byref(mhz)), ctx)
+    return mhz.value
 
 
 def bhq_get_result(ctx, ni):

@@ -33,7 +33,7 @@ enum Arr {
     A_AX, A_AY, A_AZ, A_POT,
     A_QUEUE,
     A_POOLP, A_POOLC, A_JPIDX, A_JCIDX,
-    A_TORDER, A_ENERGY, A_OSCRATCH, A_SORTSCRATCH, A_PART, A_FLAG,
+    A_TORDER, A_ENERGY, A_OSCRATCH, A_SORTSCRATCH, A_PART, A_FLAG, A_LIVE, A_CLOCK,
     A_COUNT
 };
 
@@ -149,6 +149,8 @@ struct bhq_ctx {
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool launched = false;
+    int clock_khz = 0;                  // bhq_clock_begin: constant counter rate
+    hipStream_t clock_stream = nullptr;
     hipStream_t last_stream = nullptr;
 
     bhq::LaunchCfg cfg;
@@ -880,6 +882,64 @@ int bhq_compute_noalloc(bhq_ctx *ctx, double *a, double *pot, void *stream)
     if (e != hipSuccess) return ctx->hip_fail(e, "hipEventRecord");
     ctx->launched = true;
     ctx->last_stream = s;
+    return BHQ_OK;
+}
+
+int bhq_count_live(bhq_ctx *ctx, int64_t *pp, int64_t *pc)
+{
+    CHECK_CTX(ctx);
+    if (!pp || !pc) return ctx->fail(BHQ_E_ARG, "count_live: NULL output");
+    if (ctx->kernel != BHQ_SPLIT_QUAD && ctx->kernel != BHQ_SPLIT_MONO)
+        return ctx->fail(BHQ_E_STATE, "count_live: the context's kernel has no cutoff");
+    bhq::ForceArgs A;
+    TRY(prepare_compute(ctx, A));
+    ctx->quiesce();
+    hipError_t e = ctx->arr[A_LIVE].reserve(256);
+    unsigned long long h[2] = {0, 0};
+    auto *d = ctx->arr[A_LIVE].as<unsigned long long>();
+    if (e == hipSuccess) e = hipMemcpy(d, h, sizeof(h), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = bhq::launch_count_live(A, d, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(h, d, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return ctx->hip_fail(e, "count_live");
+    *pp = (int64_t)h[0];
+    *pc = (int64_t)h[1];
+    return BHQ_OK;
+}
+
+int bhq_clock_begin(bhq_ctx *ctx, double wall_ms, void *stream)
+{
+    CHECK_CTX(ctx);
+    if (!(wall_ms > 0.0) || !(wall_ms <= 10000.0))
+        return ctx->fail(BHQ_E_ARG, "clock_begin: wall_ms must be in (0, 10000]");
+    TRY(ctx->select());
+    int khz = 0;
+    hipError_t e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device);
+    if (e == hipSuccess && khz <= 0) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = ctx->arr[A_CLOCK].reserve(256);
+    if (e == hipSuccess)
+        e = bhq::launch_clock_window((unsigned long long)(wall_ms * (double)khz),
+                                     ctx->arr[A_CLOCK].as<unsigned long long>(),
+                                     static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return ctx->hip_fail(e, "clock_begin");
+    ctx->clock_khz = khz;
+    ctx->clock_stream = static_cast<hipStream_t>(stream);
+    return BHQ_OK;
+}
+
+int bhq_clock_end(bhq_ctx *ctx, double *mhz)
+{
+    CHECK_CTX(ctx);
+    if (!mhz) return ctx->fail(BHQ_E_ARG, "clock_end: NULL output");
+    if (ctx->clock_khz <= 0) return ctx->fail(BHQ_E_STATE, "clock_end before clock_begin");
+    TRY(ctx->select());
+    unsigned long long h[4] = {0, 0, 0, 0};
+    hipError_t e = hipStreamSynchronize(ctx->clock_stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(h, ctx->arr[A_CLOCK].p, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return ctx->hip_fail(e, "clock_end");
+    if (h[3] <= h[1]) return ctx->fail(BHQ_E_STATE, "clock_end: empty window");
+    *mhz = (double)(h[2] - h[0]) / (double)(h[3] - h[1]) * (double)ctx->clock_khz * 1e-3;
+    ctx->clock_khz = 0;
     return BHQ_OK;
 }
 

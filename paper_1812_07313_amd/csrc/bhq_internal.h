@@ -175,6 +175,13 @@ hipError_t scratch_init(int device);
 // The address found by scratch_init on `device`, or NULL.
 void *scratch_ptr(int device);
 
+// Pairs of the split kernels' lists inside the cutoff (FP64 decision),
+// added to out[0] (particles), out[1] (cells); one block per group.
+hipError_t launch_count_live(const ForceArgs &A, unsigned long long *out, hipStream_t s);
+// One wave that records the shader clock over `ticks` of the constant-rate
+// counter: out[0..3] = clock start, real start, clock end, real end.
+hipError_t launch_clock_window(unsigned long long ticks, unsigned long long *out, hipStream_t s);
+
 // Device-side uploads (bhq_upload.hip).  The check kernels OR these bits
 // into *flag; launch_clear_flag zeroes it.
 constexpr unsigned kBadNonFinite = 1, kBadNonPositive = 2, kBadOrder = 4, kBadRange = 8;

@@ -453,6 +453,75 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g, int
 #pragma unroll
         for (int u = 0; u < IB; ++u) ax[u] = ay[u] = az[u] = pt[u] = R(0);
 
+        // Staging of list entries: the FP64 data of entry j (pool record ix
+        // for index lists), then its LDS form relative to the group centre.
+        auto load_p = [&](int64_t j, int32_t ix) -> PartRec {
+            if (indexed) return A.pool_p[ix];
+            return PartRec{A.jpx[j], A.jpy[j], A.jpz[j], A.jpm[j]};
+        };
+        auto stage_p = [&](const PartRec &q, bool real) -> V4<R> {
+            V4<R> v;
+            if (real) {
+                v.x = rel(q.x, cx);
+                v.y = rel(q.y, cy);
+                v.z = rel(q.z, cz);
+                v.w = R(q.m);
+            } else {
+                v.x = v.y = v.z = R(kPadPos);
+                v.w = R(0);
+            }
+            return v;
+        };
+        auto load_c = [&](int64_t j, int32_t ix) -> CellRec {
+            if (indexed) {
+                const CellRec *C = A.pool_c + ix;
+                CellRec c;
+                c.x = C->x, c.y = C->y, c.z = C->z, c.m = C->m;
+                if (kCellQ) {
+                    c.q00 = C->q00, c.q01 = C->q01, c.q02 = C->q02, c.q11 = C->q11;
+                    c.q12 = C->q12, c.q22 = C->q22;
+                    c.t = (KIND == kSplitQuad || KIND == kQuadSoft) ? C->t : 0.0;
+                }
+                return c;
+            }
+            CellRec c;
+            c.x = A.jcx[j], c.y = A.jcy[j], c.z = A.jcz[j], c.m = A.jcm[j];
+            if (kCellQ) {
+                c.q00 = A.q00[j], c.q01 = A.q01[j], c.q02 = A.q02[j], c.q11 = A.q11[j];
+                c.q12 = A.q12[j], c.q22 = A.q22[j];
+                c.t = (KIND == kSplitQuad || KIND == kQuadSoft) ? A.jct[j] : 0.0;
+            }
+            return c;
+        };
+        auto stage_c = [&](const CellRec &c, bool real, int e) {
+            V4<R> v, w, u;
+            if (real) {
+                v.x = rel(c.x, cx);
+                v.y = rel(c.y, cy);
+                v.z = rel(c.z, cz);
+                v.w = R(c.m);
+                if (kCellQ) {
+                    w.x = R(c.q00);
+                    w.y = R(c.q01);
+                    w.z = R(c.q02);
+                    w.w = R(c.q11);
+                    u.x = R(c.q12);
+                    u.y = R(c.q22);
+                    u.z = R(c.t);
+                    u.w = R(0);
+                }
+            } else {
+                v.x = v.y = v.z = R(kPadPos);
+                v.w = R(0);
+                w.x = w.y = w.z = w.w = R(0);
+                u.x = u.y = u.z = u.w = R(0);
+            }
+            sa[e] = v;
+            if (kCellQ) {
+                sb[e] = w;
+                sc[e] = u;
+            }
+        };
         // j-particles
         for (int64_t base = 0; base < np; base += T) {
             const int cnt = (int)(np - base < T ? np - base : T);
@@ -460,29 +529,12 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g, int
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < TD; ++r) {
-              const int te = t + r * BS;
-              if (te < it * S) {
-                V4<R> v;
-                if (te < cnt) {
+                const int te = t + r * BS;
+                if (te < it * S) {
                     const int64_t j = p0 + base + te;
-                    if (indexed) {
-                        const PartRec Pj = A.pool_p[A.jp_idx[j]];
-                        v.x = rel(Pj.x, cx);
-                        v.y = rel(Pj.y, cy);
-                        v.z = rel(Pj.z, cz);
-                        v.w = R(Pj.m);
-                    } else {
-                        v.x = rel(A.jpx[j], cx);
-                        v.y = rel(A.jpy[j], cy);
-                        v.z = rel(A.jpz[j], cz);
-                        v.w = R(A.jpm[j]);
-                    }
-                } else {
-                    v.x = v.y = v.z = R(kPadPos);
-                    v.w = R(0);
+                    sa[te] = te < cnt ? stage_p(load_p(j, indexed ? A.jp_idx[j] : 0), true)
+                                      : stage_p(PartRec{}, false);
                 }
-                sa[te] = v;
-              }
             }
             __syncthreads();
             if (active) {
@@ -543,58 +595,14 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g, int
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < TD; ++r) {
-              const int te = t + r * BS;
-              if (te < it * S) {
-                V4<R> v, w, u;
-                if (te < cnt) {
+                const int te = t + r * BS;
+                if (te < it * S) {
                     const int64_t j = c0 + base + te;
-                    if (indexed) {
-                        const CellRec *C = A.pool_c + A.jc_idx[j];
-                        v.x = rel(C->x, cx);
-                        v.y = rel(C->y, cy);
-                        v.z = rel(C->z, cz);
-                        v.w = R(C->m);
-                        if (kCellQ) {
-                            w.x = R(C->q00);
-                            w.y = R(C->q01);
-                            w.z = R(C->q02);
-                            w.w = R(C->q11);
-                            u.x = R(C->q12);
-                            u.y = R(C->q22);
-                            u.z = (KIND == kSplitQuad || KIND == kQuadSoft) ? R(C->t)
-                                                                            : R(0);
-                            u.w = R(0);
-                        }
-                    } else {
-                        v.x = rel(A.jcx[j], cx);
-                        v.y = rel(A.jcy[j], cy);
-                        v.z = rel(A.jcz[j], cz);
-                        v.w = R(A.jcm[j]);
-                        if (kCellQ) {
-                            w.x = R(A.q00[j]);
-                            w.y = R(A.q01[j]);
-                            w.z = R(A.q02[j]);
-                            w.w = R(A.q11[j]);
-                            u.x = R(A.q12[j]);
-                            u.y = R(A.q22[j]);
-                            u.z = (KIND == kSplitQuad || KIND == kQuadSoft)
-                                      ? R(A.jct[j])
-                                      : R(0);
-                            u.w = R(0);
-                        }
-                    }
-                } else {
-                    v.x = v.y = v.z = R(kPadPos);
-                    v.w = R(0);
-                    w.x = w.y = w.z = w.w = R(0);
-                    u.x = u.y = u.z = u.w = R(0);
+                    if (te < cnt)
+                        stage_c(load_c(j, indexed ? A.jc_idx[j] : 0), true, te);
+                    else
+                        stage_c(CellRec{}, false, te);
                 }
-                sa[te] = v;
-                if (kCellQ) {
-                    sb[te] = w;
-                    sc[te] = u;
-                }
-              }
             }
             __syncthreads();
             if (active) {
@@ -886,6 +894,90 @@ hipError_t launch_prec(int kernel, const ForceArgs &A, const LaunchCfg &cfg,
     }
 }
 
+// Number of (i-particle, list entry) pairs of the split kernels' lists
+// inside the cutoff, with the FP64 decision of the kernels (FP64 offsets to
+// the group centre, 0 < r^2 < rcut^2): one block per group, its threads
+// over the i-particles, every list entry read by all of them.  Adds to
+// out[0] (particles) and out[1] (cells).
+__global__ __launch_bounds__(256) void count_live(const ForceArgs A, unsigned long long *out)
+{
+    __shared__ unsigned long long red[2][4];
+    const int64_t g = blockIdx.x;
+    const int64_t i0 = A.i_off[g], ni = A.i_off[g + 1] - i0;
+    const double cx = A.gcx[g], cy = A.gcy[g], cz = A.gcz[g];
+    const double box = A.box, ibox = box > 0.0 ? 1.0 / box : 0.0;
+    auto rel = [&](double v, double c) { return box > 0.0 ? wrap(v - c, box, ibox) : v - c; };
+    const int64_t np = A.jp_off[g + 1] - A.jp_off[g], nc = A.jc_off[g + 1] - A.jc_off[g];
+    const int64_t p0 = A.jp_slot > 0 ? g * A.jp_slot : A.jp_off[g];
+    const int64_t c0 = A.jc_slot > 0 ? g * A.jc_slot : A.jc_off[g];
+    const bool indexed = A.jp_idx != nullptr;
+    unsigned long long lp = 0, lc = 0;
+    for (int64_t k = threadIdx.x; k < ni; k += 256) {
+        const int64_t i = i0 + k;
+        const double xi = rel(A.xi[i], cx), yi = rel(A.yi[i], cy), zi = rel(A.zi[i], cz);
+        for (int64_t e = 0; e < np; ++e) {
+            const int64_t j = p0 + e;
+            double x, y, z;
+            if (indexed) {
+                const PartRec &q = A.pool_p[A.jp_idx[j]];
+                x = q.x, y = q.y, z = q.z;
+            } else {
+                x = A.jpx[j], y = A.jpy[j], z = A.jpz[j];
+            }
+            lp += keep_f64(rel(x, cx) - xi, rel(y, cy) - yi, rel(z, cz) - zi, A.rcut);
+        }
+        for (int64_t e = 0; e < nc; ++e) {
+            const int64_t j = c0 + e;
+            double x, y, z;
+            if (indexed) {
+                const CellRec &q = A.pool_c[A.jc_idx[j]];
+                x = q.x, y = q.y, z = q.z;
+            } else {
+                x = A.jcx[j], y = A.jcy[j], z = A.jcz[j];
+            }
+            lc += keep_f64(rel(x, cx) - xi, rel(y, cy) - yi, rel(z, cz) - zi, A.rcut);
+        }
+    }
+    // per wave, then per block, then one atomic per block and kind
+    for (int m = 32; m >= 1; m >>= 1) {
+        lp += __shfl_xor(lp, m, 64);
+        lc += __shfl_xor(lc, m, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = lp;
+        red[1][threadIdx.x >> 6] = lc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(out, red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+        atomicAdd(out + 1, red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+    }
+}
+
+// The shader clock of one CU over a wall-clock window: one wave reads the
+// shader-clock counter (s_memtime) and the constant-rate counter
+// (s_memrealtime) at the start, waits until the latter has advanced by
+// `ticks`, and reads both again (out[0..3] = clock start, real start,
+// clock end, real end).
+__global__ __launch_bounds__(64) void clock_window(unsigned long long ticks,
+                                                   unsigned long long *out)
+{
+    const unsigned long long c0 = __builtin_amdgcn_s_memtime();
+    const unsigned long long r0 = __builtin_amdgcn_s_memrealtime();
+    unsigned long long r = r0;
+    while (r - r0 < ticks) {
+        __builtin_amdgcn_s_sleep(2);
+        r = __builtin_amdgcn_s_memrealtime();
+    }
+    const unsigned long long c1 = __builtin_amdgcn_s_memtime();
+    if (threadIdx.x == 0) {
+        out[0] = c0;
+        out[1] = r0;
+        out[2] = c1;
+        out[3] = r;
+    }
+}
+
 // Working memory of bhq_compute_noalloc: queue counters, then j-split
 // parts.  In host code this name is a stand-in, not a device address; the
 // address comes from hipGetSymbolAddress (scratch_init).
@@ -896,6 +988,20 @@ std::mutex g_scratch_mutex;
 void *g_scratch_ptr[kMaxDevices] = {};
 
 }  // namespace
+
+hipError_t launch_count_live(const ForceArgs &A, unsigned long long *out, hipStream_t s)
+{
+    if (A.ng <= 0) return hipSuccess;
+    if (A.ng > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(count_live, dim3((unsigned)A.ng), dim3(256), 0, s, A, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_clock_window(unsigned long long ticks, unsigned long long *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(clock_window, dim3(1), dim3(64), 0, s, ticks, out);
+    return hipGetLastError();
+}
 
 hipError_t scratch_init(int device)
 {

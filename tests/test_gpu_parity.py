@@ -293,6 +293,39 @@ def test_split_kernel_periodic(ctx, nside):
             assert_parity(err, prec, "split %s %s" % (bk, prec))
 
 
+def test_count_live_and_clock(ctx):
+    """bhq_count_live counts the terms the cutoff keeps exactly as the
+    oracle's definition does (materialised and index lists); the clock
+    window reports a shader clock in a physical range."""
+    torch = pytest.importorskip("torch")
+    x, m = synth.perturbed_lattice(24, synth.rng(4))
+    rs = 1.25 / 24
+    rcut = 4.5 * rs
+    T = orc.Tree(x, m, 0.5, 64, box=1.0, rcut=rcut)
+    mat = orc.materialise(T, x, m)
+    want = orc.count_keep(mat, x, 1.0, rcut, mask=orc.MASK_ABS)
+    assert want == orc.count_keep(mat, x, 1.0, rcut, mask=orc.MASK_F64_OFS)
+    upload(ctx, mat, x, split=(rs, rcut, 1.0))
+    bhq.bhq_set_kernel(ctx, bhq.SPLIT_QUAD, bhq.FP32_OFS64)
+    got = bhq.bhq_count_live(ctx)
+    log("  live pairs %s of %s" % (got, bhq.bhq_get_counts(ctx)))
+    assert got == want
+    _upload_indexed(ctx, T, mat, x, m, split=(rs, rcut, 1.0))
+    assert bhq.bhq_count_live(ctx) == want
+    bhq.bhq_set_kernel(ctx, bhq.QUAD, bhq.FP32_OFS64)
+    with pytest.raises(bhq.BhqError) as ei:
+        bhq.bhq_count_live(ctx)
+    assert ei.value.code == bhq.E_STATE
+    s = torch.cuda.Stream()
+    bhq.bhq_clock_begin(ctx, 20.0, s)
+    mhz = bhq.bhq_clock_end(ctx)
+    log("  clock window: %.0f MHz" % mhz)
+    assert 100.0 < mhz < 4000.0
+    with pytest.raises(bhq.BhqError) as ei:
+        bhq.bhq_clock_end(ctx)
+    assert ei.value.code == bhq.E_STATE
+
+
 def _upload_indexed(ctx, T, mat, x, m, eps2=None, split=None):
     x = np.asarray(x, np.float64).reshape(-1, 3)
     bhq.bhq_set_groups(ctx, mat["i_off"], mat["gcenter"], mat["jp_off"],

@@ -276,6 +276,28 @@ def test_mask_flips_counts_disagreements(orc):
     assert orc.mask_flips(mat, x, box, rcut) == 0
 
 
+def test_count_keep_brute_force(orc):
+    """count_keep equals a numpy count of 0 < |d| < rcut over every (i, entry)
+    pair of small lists (minimum image in the unit box)."""
+    g = np.random.default_rng(8)
+    x = g.uniform(0, 1, (3000, 3))
+    m = np.full(3000, 1.0 / 3000)
+    rcut = 0.2
+    T = orc.Tree(x, m, 0.8, 16, box=1.0, rcut=rcut)
+    mat = orc.materialise(T, x, m)
+    want = [0, 0]
+    for gi in range(len(mat["i_off"]) - 1):
+        xi = x[mat["i_idx"][mat["i_off"][gi]:mat["i_off"][gi + 1]]]
+        for k, key in ((0, "jp"), (1, "jc")):
+            xj = mat[key + "_x"][mat[key + "_off"][gi]:mat[key + "_off"][gi + 1]]
+            d = xj[None, :, :] - xi[:, None, :]
+            d -= np.rint(d)
+            r = np.sqrt((d * d).sum(2))
+            want[k] += int(((r > 0) & (r < rcut)).sum())
+    assert orc.count_keep(mat, x, 1.0, rcut) == tuple(want)
+    assert want[0] > 0 and want[1] > 0
+
+
 # --- the complete softened quadrupole (with the trace term) ---------------------
 
 def test_soft_quad_limits(orc):
