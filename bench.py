@@ -71,16 +71,24 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernel_source_digest():
+    """sha256 over the force kernels' source: bhq_kernels.hip followed by the
+    interaction terms it includes (bhq_terms.h)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("bhq_kernels.hip", "bhq_terms.h"):
+        with open(os.path.join(ROOT, "paper_1812_07313_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def profiled_traffic(profile="force_kernel_quad_fp32_cube1m.md"):
     """HBM bytes per launch of the quadrupole FP32 kernel on the default
     workload, from the committed rocprofv3 counter summary (FETCH_SIZE and
     WRITE_SIZE, calibrated against a plain copy).  None when the kernel
     source has changed since those counters were taken."""
-    import hashlib
     try:
-        src = os.path.join(ROOT, "paper_1812_07313_amd", "csrc", "bhq_kernels.hip")
-        with open(src, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        digest = kernel_source_digest()
         with open(os.path.join(ROOT, "profiles", profile)) as f:
             text = f.read()
     except OSError:

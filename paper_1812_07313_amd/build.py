@@ -39,6 +39,27 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+PROBES = ["valu_rates", "interaction_rates"]
+PROBE_DIR = os.path.join(PKG, "probes")
+
+
+def build_probes(cc, verbose=False):
+    """The measurement programs behind the FP32 ceiling of the force
+    kernels (probes/*.cpp, HIP for gfx950), as executables next to their
+    sources."""
+    cmds = []
+    for name in PROBES:
+        cmd = [cc, "-O3", "-std=c++17", "--offload-arch=" + ARCH, "-x", "hip"] + DEVICE_FLAGS + [
+            "-I", CSRC, "-o", os.path.join(PROBE_DIR, name),
+            os.path.join(PROBE_DIR, name + ".cpp")]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        cmds.append(cmd)
+    with concurrent.futures.ThreadPoolExecutor(len(cmds)) as pool:
+        for f in [pool.submit(subprocess.run, c, check=True) for c in cmds]:
+            f.result()
+
+
 def build(verbose=False, extra=()):
     """Compile every source and link libbhq.so (always rebuilds)."""
     cc = hipcc()
@@ -63,6 +84,7 @@ def build(verbose=False, extra=()):
     with concurrent.futures.ThreadPoolExecutor(workers) as pool:
         for f in [pool.submit(subprocess.run, c, check=True) for c in cmds]:
             f.result()
+    build_probes(cc, verbose)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + [
         "-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib", "-lpthread"]

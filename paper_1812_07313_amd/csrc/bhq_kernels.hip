@@ -36,6 +36,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bhq_internal.h"
+#include "bhq_terms.h"
 #include "split_table.h"
 
 #include <mutex>
@@ -44,14 +45,6 @@
 namespace bhq {
 
 namespace {
-
-template <typename R>
-struct alignas(4 * sizeof(R)) V4 {
-    R x, y, z, w;
-};
-
-__device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
-__device__ __forceinline__ double rsq(double v) { return ::rsqrt(v); }
 
 __device__ __forceinline__ double erfc_r(double v) { return ::erfc(v); }
 __device__ __forceinline__ double exp_r(double v) { return ::exp(v); }
@@ -65,55 +58,6 @@ __device__ __forceinline__ double wrap(double v, double box, double ibox)
 }
 
 constexpr int kMono = 0, kQuad = 1, kSplitQuad = 2, kSplitMono = 3, kQuadSoft = 4;
-
-// Plummer-softened particle (also the monopole-only cell).
-template <typename R>
-__device__ __forceinline__ void pp_plummer(const V4<R> &j, R xi, R yi, R zi,
-                                           R e2, R &ax, R &ay, R &az, R &pt)
-{
-    const R dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
-    const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-    const R rinv = rsq(r2);
-    const R mr = j.w * rinv;
-    const R mr3 = mr * (rinv * rinv);
-    pt += mr;
-    ax = fma(mr3, dx, ax);
-    ay = fma(mr3, dy, ay);
-    az = fma(mr3, dz, az);
-}
-
-// Monopole + traceless quadrupole cell (Sec. 3, eqs. 1, 4-7).
-// a: (x, y, z, M), b: (q00, q01, q02, q11), c: (q12, q22, T, 0).
-// SOFT: the complete second-order expansion of the softened potential,
-// which adds T eps^2 / (2 rhat^5) to -phi's quadrupole part with the sign
-// of -d.Q.d: d.Q.d becomes d.Q.d - T eps^2 in both terms (one more FMA).
-template <typename R, bool SOFT>
-__device__ __forceinline__ void pc_quad(const V4<R> &a, const V4<R> &b,
-                                        const V4<R> &c, R xi, R yi, R zi, R e2,
-                                        R &ax, R &ay, R &az, R &pt)
-{
-    const R dx = a.x - xi, dy = a.y - yi, dz = a.z - zi;
-    const R r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
-    const R rinv = rsq(r2);
-    const R rinv2 = rinv * rinv;
-    const R phim = a.w * rinv;
-    const R qx = fma(b.z, dz, fma(b.y, dy, b.x * dx));
-    const R qy = fma(c.x, dz, fma(b.w, dy, b.y * dx));
-    const R qz = fma(c.y, dz, fma(c.x, dy, b.z * dx));
-    R dqd = fma(dz, qz, fma(dy, qy, dx * qx));
-    if (SOFT) dqd = fma(-e2, c.z, dqd);
-    const R rinv5 = (rinv2 * rinv2) * rinv;
-    const R pq = dqd * rinv5;  // 2 phi_quad
-    pt += phim;
-    pt = fma(R(0.5), pq, pt);
-    const R cf = fma(R(2.5), pq, phim) * rinv2;
-    ax = fma(cf, dx, ax);
-    ay = fma(cf, dy, ay);
-    az = fma(cf, dz, az);
-    ax = fma(-rinv5, qx, ax);
-    ay = fma(-rinv5, qy, ay);
-    az = fma(-rinv5, qz, az);
-}
 
 // Constants of the Gaussian split, uniform over a launch: u = r i2rs with
 // i2rs = 1 / (2 r_s); the FP32 table variable is t = r ct = u N / U.
