@@ -11,10 +11,11 @@
 //
 // Small groups (ni < 256) split each tile between S = 256 / ni slices of
 // ni threads.  A tile then holds T = S * floor(256 / S) entries and slice s
-// takes the contiguous chunk [s * it, (s + 1) * it) of it; the last tile is
-// padded to a multiple of S with zero-mass entries, so every thread runs
-// the same trip count.  The slices' partial sums are combined in a fixed
-// order at the end, so results are deterministic run to run.
+// takes the contiguous chunk [s * it, (s + 1) * it) of it (the cell loop
+// of the split kernels: the interleaved entries s, s + S, ...); the last
+// tile is padded to a multiple of S with zero-mass entries, so every thread
+// runs the same trip count.  The slices' partial sums are combined in a
+// fixed order at the end, so results are deterministic run to run.
 //
 // Lists are either materialised (SoA FP64 copies of every entry) or
 // index lists into shared particle and cell pools (AoS FP64 records); the
@@ -555,25 +556,55 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g, int
                 for (int u = 0; u < IB; ++u) bx[u] = by[u] = bz[u] = bp[u] = R(0);
                 const int e0 = slice * it;
                 bool near = false;
-#pragma unroll BHQ_UNROLL
-                for (int k = 0; k < it; ++k) {
-                    const int e = e0 + k;
-                    const V4<R> ja = sa[e];
-                    V4<R> jb, jc;
-                    if (kCellQ) {
-                        jb = sb[e];
-                        jc = sc[e];
-                    }
-                    if constexpr (kSplit) {
-                        Sep<R> sp[IB];
-                        bool keep[IB];
-                        decide(ja, sp, keep, near);
+                if constexpr (kSplit) {
+                    // Most cell terms of a split kernel lie beyond the
+                    // cutoff, and which ones differs from lane to lane.  A
+                    // lane first decides a chunk of up to 32 of its
+                    // entries, keeping the live ones as bits of a mask per
+                    // owned i-particle, and then evaluates only those, in
+                    // list order; the wave loops until its busiest lane is
+                    // done.  Slices take interleaved entries (slice, slice
+                    // + S, ...): consecutive list entries lie close together,
+                    // so a contiguous chunk would be live mostly for the
+                    // lanes on one side of the group.
+                    for (int kc = 0; kc < it; kc += 32) {
+                        const int n = it - kc < 32 ? it - kc : 32;
+                        uint32_t live[IB];
+#pragma unroll
+                        for (int u = 0; u < IB; ++u) live[u] = 0u;
+#pragma unroll BHQ_UNROLL_PP
+                        for (int k = 0; k < n; ++k) {
+                            Sep<R> sp[IB];
+                            bool keep[IB];
+                            decide(sa[slice + (kc + k) * S], sp, keep, near);
+#pragma unroll
+                            for (int u = 0; u < IB; ++u) live[u] |= keep[u] ? 1u << k : 0u;
+                        }
 #pragma unroll
                         for (int u = 0; u < IB; ++u)
-                            if (keep[u])
-                                pc_split<R, KIND == kSplitQuad>(ja, jb, jc, sp[u], K, tab, bx[u],
-                                                                by[u], bz[u], bp[u]);
-                    } else {
+                            for (uint32_t m = live[u]; m != 0u; m &= m - 1u) {
+                                const int e = slice + (kc + __builtin_ctz(m)) * S;
+                                const V4<R> ja = sa[e];
+                                V4<R> jb, jc;
+                                if (kCellQ) {
+                                    jb = sb[e];
+                                    jc = sc[e];
+                                }
+                                pc_split<R, KIND == kSplitQuad>(
+                                    ja, jb, jc, separation(ja, xi[u], yi[u], zi[u]), K, tab, bx[u],
+                                    by[u], bz[u], bp[u]);
+                            }
+                    }
+                } else {
+#pragma unroll BHQ_UNROLL
+                    for (int k = 0; k < it; ++k) {
+                        const int e = e0 + k;
+                        const V4<R> ja = sa[e];
+                        V4<R> jb, jc;
+                        if (kCellQ) {
+                            jb = sb[e];
+                            jc = sc[e];
+                        }
 #pragma unroll
                         for (int u = 0; u < IB; ++u) {
                             if (KIND == kQuad || KIND == kQuadSoft)
@@ -590,7 +621,7 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g, int
                     if (__builtin_expect(near, 0)) {
 #pragma unroll 1
                         for (int k = 0; k < it; ++k) {
-                            const int e = e0 + k;
+                            const int e = slice + k * S;
                             const V4<R> ja = sa[e];
                             V4<R> jb, jc;
                             if (kCellQ) {
