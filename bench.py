@@ -140,14 +140,16 @@ def workload(name, n=None):
                     m=np.concatenate([s[1] for s in systems]),
                     eps2=np.concatenate([np.full(len(s[1]), s[2] ** 2)
                                          for s in systems]),
-                    sys_off=off, theta=0.6, ncrit=64, kernel=bhq.QUAD)
+                    sys_off=off, theta=0.6, ncrit=64, kernel=bhq.QUAD,
+                    tune_ncrits=(64, 128, 256))
     if name == "lattice":
         c = synth.config_lattice(nside=int(round((n or (1 << 24)) ** (1 / 3))))
         return dict(name="perturbed lattice N=%d in the periodic unit box, "
                          "Gaussian split r_s=1.25/256, cutoff 4.5 r_s, "
                          "theta=0.5" % len(c["m"]),
                     x=c["x"], m=c["m"], theta=0.5, ncrit=128, box=1.0,
-                    rs=c["rs"], rcut=c["rcut"], kernel=bhq.SPLIT_QUAD)
+                    rs=c["rs"], rcut=c["rcut"], kernel=bhq.SPLIT_QUAD,
+                    tune_ncrits=(64, 128, 256), waves_per_eu=6)
     raise SystemExit("unknown workload %r" % name)
 
 
@@ -599,7 +601,7 @@ def config_record(torch, stream, W, kernel, ncrit, shapes, steps, fp64=True, liv
         rec = {"workload": W["name"] + ", ncrit=%d" % ncrit, "n": n, "groups": ng,
                "n_pp": n_pp, "n_pc": n_pc, "kernel": bhq.KERNEL_NAMES[kernel],
                "launch": dict(zip(("block", "i_per_thread", "blocks_per_cu", "persistent",
-                                   "graph", "jsplit"), best["shape"])),
+                                   "graph", "jsplit", "waves_per_eu"), best["shape"])),
                "shapes": rows, "kernel_ms_fp32": km,
                "Ginteractions_per_s": round((n_pp + n_pc) / km / 1e6, 2),
                "s_per_force_eval": round(km * 1e-3, 7)}
@@ -665,7 +667,7 @@ def other_configs(torch, stream, steps, cpu=True):
     groups beside it."""
     import oracle as orc
     recs = {}
-    eager = [(256, 2, 0, 0, 0, 1), (256, 1, 0, 0, 0, 1)]
+    eager = [(256, 2, 0, 0, 0, 1), (256, 1, 0, 0, 0, 1), (256, 2, 0, 0, 0, 1, 6)]
 
     W = workload("plummer16k")
     shapes = [(256, ipt, 0, 0, 0, js) for ipt in (1, 2) for js in (1, 2, 4, 8)]
@@ -695,7 +697,8 @@ def other_configs(torch, stream, steps, cpu=True):
     for ncrit in (64, 128):
         rec, a32, _ = config_record(
             torch, stream, W, bhq.QUAD, ncrit,
-            eager + [(256, 2, 0, 1, 1, 1), (256, 1, 0, 1, 1, 1)], steps)
+            eager + [(256, 1, 0, 0, 0, 1, 6), (256, 2, 0, 1, 1, 1), (256, 1, 0, 1, 1, 1),
+                     (256, 1, 0, 1, 1, 1, 6)], steps)
         if best is None or rec["kernel_ms_fp32"] < best[0]["kernel_ms_fp32"]:
             best = (rec, a32, ncrit)
     rec, a32, ncrit = best
@@ -732,7 +735,8 @@ def other_configs(torch, stream, steps, cpu=True):
 
     W = workload("lattice")
     rec, a32, _ = config_record(torch, stream, W, bhq.SPLIT_QUAD, 128,
-                                [(256, 2, 0, 0, 0, 1), (256, 1, 0, 0, 0, 1)],
+                                [(256, 2, 0, 0, 0, 1, 0), (256, 2, 0, 0, 0, 1, 6),
+                                 (256, 2, 0, 1, 0, 1, 6), (256, 1, 0, 0, 0, 1, 0)],
                                 max(5, steps // 2), live=True)
     if cpu:
         rec["cpu_baseline"] = oracle_leg(W, bhq.SPLIT_QUAD, 128, a32, 2000)
@@ -762,6 +766,9 @@ def main():
                     help="i-particles per thread (1 or 2)")
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--waves-per-eu", type=int, default=None,
+                    help="register cap for 6 or 8 waves per SIMD (0: compiler's choice; "
+                         "default: 6 for the lattice, where the autotuner picks it, else 0)")
     ap.add_argument("--jsplit", type=int, default=1,
                     help="parts each group's lists are cut into (1, 2, 4, 8)")
     ap.add_argument("--order", default="xcd", choices=["xcd", "cost"],
@@ -817,12 +824,17 @@ def main():
         W["ncrit"] = args.ncrit
     kernel = W["kernel"]
     n = len(W["m"])
+    if args.waves_per_eu is None:
+        args.waves_per_eu = W.get("waves_per_eu", 0)
     tuned = None
     if args.autotune is None:
         args.autotune = 1 if args.workload == "batched" else 0
     if args.autotune:
         from paper_1812_07313_amd import tune
-        log("autotuning ncrit and launch shape ...")
+        # the configurations that name a group size keep it; the others
+        # search ncrit too
+        log("autotuning %s and launch shape ..." % ("ncrit" if "tune_ncrits" in W else
+                                                    "ncrit=%d fixed:" % W["ncrit"]))
         tctx = bhq.bhq_create(0, kernel, bhq.FP32_OFS64)
         try:
             r = tune.autotune(tctx, W["x"], W["m"], W["theta"], args.workload,
@@ -830,7 +842,7 @@ def main():
                               eps2_per_particle=W.get("eps2"),
                               sys_off=W.get("sys_off"), box=W.get("box", 0.0),
                               rcut=W.get("rcut", 0.0), rs=W.get("rs", 0.0),
-                              force=True)
+                              ncrits=W.get("tune_ncrits", (W["ncrit"],)), force=True)
         finally:
             bhq.bhq_destroy(tctx)
         tuned = r["best"]
@@ -838,6 +850,7 @@ def main():
         args.block, args.persistent = tuned["block"], tuned["persistent"]
         args.ipt = tuned["i_per_thread"]
         args.graph, args.jsplit = tuned["use_graph"], tuned["jsplit"]
+        args.waves_per_eu = tuned["waves_per_eu"]
         args.order = {v: k for k, v in ORDERS.items()}[tuned["order"]]
         log("autotuned: %s" % tuned)
     L, t_build = build_lists(W, W["theta"], W["ncrit"])
@@ -853,7 +866,7 @@ def main():
         bhq.bhq_lists_free(L)
         bhq.bhq_set_tuning(ctx, args.block, args.ipt,
                            tuned["blocks_per_cu"] if tuned else 0,
-                           args.persistent, args.graph, args.jsplit)
+                           args.persistent, args.graph, args.jsplit, args.waves_per_eu)
         bhq.bhq_set_group_order(ctx, ORDERS[args.order], args.order_window,
                                 args.order_tail)
         n_pp, n_pc = bhq.bhq_get_counts(ctx)
@@ -968,6 +981,7 @@ def main():
                    "launch": {"block": args.block, "i_per_thread": args.ipt,
                               "persistent": args.persistent,
                               "graph": args.graph, "jsplit": args.jsplit,
+                              "waves_per_eu": args.waves_per_eu,
                               "order": args.order,
                               "order_window": args.order_window,
                               "order_tail": args.order_tail}},

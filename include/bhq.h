@@ -311,16 +311,21 @@ int bhq_clock_end(bhq_ctx *ctx, double *mhz);
  *                  in part order (for inputs with too few groups to fill the
  *                  GPU, the small-N regime of Sec. 5.2); the context keeps a
  *                  buffer of 32 jsplit ni bytes for the parts
- * The persistent queue and graph replay do not change results (bitwise).
- * block, i_per_thread and jsplit change how a group's lists are split
- * across threads and blocks and so the order of the FP32/FP64 sums (results
- * agree to rounding).  Errors: BHQ_E_ARG for values outside these sets. */
-int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread,
-                   int blocks_per_cu, int persistent, int use_graph, int jsplit);
+ *   waves_per_eu   0: the compiler's register allocation; 6 or 8: kernel
+ *                  instances whose registers are capped so that at least that
+ *                  many waves fit on each SIMD (FP32 kernels at block 256;
+ *                  FP64 kernels run the compiler's choice)
+ * The persistent queue, graph replay and waves_per_eu do not change results
+ * (bitwise).  block, i_per_thread and jsplit change how a group's lists are
+ * split across threads and blocks and so the order of the FP32/FP64 sums
+ * (results agree to rounding).  Errors: BHQ_E_ARG for values outside these
+ * sets, or waves_per_eu != 0 with block 128. */
+int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread, int blocks_per_cu,
+                   int persistent, int use_graph, int jsplit, int waves_per_eu);
 
-/* Current launch shape: out[0..5] = block, i_per_thread, blocks_per_cu,
- * persistent, use_graph, jsplit. */
-int bhq_get_tuning(const bhq_ctx *ctx, int out[6]);
+/* Current launch shape: out[0..6] = block, i_per_thread, blocks_per_cu,
+ * persistent, use_graph, jsplit, waves_per_eu. */
+int bhq_get_tuning(const bhq_ctx *ctx, int out[7]);
 
 /* Order in which groups are handed to blocks.  Group g costs
  * c_g = ni_g (100 njp_g + 265 njc_g + 100), in 64-bit integers (a cell term

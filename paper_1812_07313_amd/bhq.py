@@ -71,7 +71,7 @@ SIGNATURES = {
     "bhq_last_error": (ctypes.c_char_p, [_P]),
     "bhq_set_tuning": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                      ctypes.c_int]),
+                                      ctypes.c_int, ctypes.c_int]),
     "bhq_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
     "bhq_set_group_order": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int]),
@@ -347,17 +347,18 @@ def bhq_get_kernel_ms(ctx):
 
 
 def bhq_set_tuning(ctx, block=256, i_per_thread=2, blocks_per_cu=0,
-                   persistent=0, use_graph=0, jsplit=1):
+                   persistent=0, use_graph=0, jsplit=1, waves_per_eu=0):
     _check(lib().bhq_set_tuning(ctx, int(block), int(i_per_thread),
                                 int(blocks_per_cu), int(persistent),
-                                int(use_graph), int(jsplit)), ctx)
+                                int(use_graph), int(jsplit), int(waves_per_eu)), ctx)
 
 
 def bhq_get_tuning(ctx):
-    out = (ctypes.c_int * 6)()
+    out = (ctypes.c_int * 7)()
     _check(lib().bhq_get_tuning(ctx, out), ctx)
     return dict(block=out[0], i_per_thread=out[1], blocks_per_cu=out[2],
-                persistent=out[3], use_graph=out[4], jsplit=out[5])
+                persistent=out[3], use_graph=out[4], jsplit=out[5],
+                waves_per_eu=out[6])
 
 
 def bhq_set_group_order(ctx, mode=ORDER_XCD, window=ORDER_WINDOW,

@@ -170,7 +170,8 @@ struct bhq_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     struct {
-        int kernel, precision, block, i_per_thread, persistent, blocks_per_cu, jsplit;
+        int kernel, precision, block, i_per_thread, persistent, blocks_per_cu, jsplit,
+            waves_per_eu;
         uint64_t version;
     } graph_key{};
 
@@ -795,6 +796,7 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
             ctx->graph_key.persistent == ctx->cfg.persistent &&
             ctx->graph_key.blocks_per_cu == ctx->cfg.blocks_per_cu &&
             ctx->graph_key.jsplit == ctx->cfg.jsplit &&
+            ctx->graph_key.waves_per_eu == ctx->cfg.waves_per_eu &&
             ctx->graph_key.version == ctx->args_version;
         if (!same) {
             if (ctx->launched) (void)hipEventSynchronize(ctx->ev1);
@@ -826,6 +828,7 @@ int bhq_compute(bhq_ctx *ctx, void *stream)
             ctx->graph_key.persistent = ctx->cfg.persistent;
             ctx->graph_key.blocks_per_cu = ctx->cfg.blocks_per_cu;
             ctx->graph_key.jsplit = ctx->cfg.jsplit;
+            ctx->graph_key.waves_per_eu = ctx->cfg.waves_per_eu;
             ctx->graph_key.version = ctx->args_version;
         }
         e = hipEventRecord(ctx->ev0, s);
@@ -943,8 +946,8 @@ int bhq_clock_end(bhq_ctx *ctx, double *mhz)
     return BHQ_OK;
 }
 
-int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread,
-                   int blocks_per_cu, int persistent, int use_graph, int jsplit)
+int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread, int blocks_per_cu,
+                   int persistent, int use_graph, int jsplit, int waves_per_eu)
 {
     CHECK_CTX(ctx);
     if (block == 0) block = 256;
@@ -960,7 +963,12 @@ int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread,
         return ctx->fail(BHQ_E_ARG, "blocks_per_cu must be in [0, 64]");
     if ((persistent != 0 && persistent != 1) || (use_graph != 0 && use_graph != 1))
         return ctx->fail(BHQ_E_ARG, "persistent and use_graph are 0 or 1");
+    if (waves_per_eu != 0 && waves_per_eu != 6 && waves_per_eu != 8)
+        return ctx->fail(BHQ_E_ARG, "waves_per_eu must be 0, 6 or 8");
+    if (waves_per_eu != 0 && block != 256)
+        return ctx->fail(BHQ_E_ARG, "waves_per_eu 6 and 8 exist for block 256 only");
     ctx->cfg.block = block;
+    ctx->cfg.waves_per_eu = waves_per_eu;
     ctx->cfg.i_per_thread = i_per_thread;
     ctx->cfg.blocks_per_cu = blocks_per_cu;
     ctx->cfg.persistent = persistent;
@@ -969,7 +977,7 @@ int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread,
     return BHQ_OK;
 }
 
-int bhq_get_tuning(const bhq_ctx *ctx, int out[6])
+int bhq_get_tuning(const bhq_ctx *ctx, int out[7])
 {
     if (!ctx || !out) return BHQ_E_ARG;
     out[0] = ctx->cfg.block;
@@ -978,6 +986,7 @@ int bhq_get_tuning(const bhq_ctx *ctx, int out[6])
     out[3] = ctx->cfg.persistent;
     out[4] = ctx->use_graph;
     out[5] = ctx->cfg.jsplit;
+    out[6] = ctx->cfg.waves_per_eu;
     return BHQ_OK;
 }
 

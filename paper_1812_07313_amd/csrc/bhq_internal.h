@@ -159,6 +159,7 @@ struct LaunchCfg {
     int blocks_per_cu = 0;
     int num_cu = 0;
     int jsplit = 1;        // parts of each group's lists (1, 2, 4 or 8)
+    int waves_per_eu = 0;  // 0: compiler's choice; 6 or 8 (FP32, block 256)
 };
 
 constexpr int kMaxJsplit = 8;

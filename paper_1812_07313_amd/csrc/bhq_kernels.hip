@@ -253,9 +253,11 @@ __device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b, const V
 
 // Compile-time tuning: unroll depth of the cell loop and of the particle
 // loop (whose shorter body leaves more room for independent work: 4 measured
-// 3 % faster than 2 on the quadrupole kernel), list entries staged per thread
-// per tile (2 doubles the LDS tile; slower for the split kernels), and the
-// occupancy (waves per SIMD) the register allocator must allow.
+// 3 % faster than 2 on the quadrupole kernel) and list entries staged per
+// thread per tile (2 doubles the LDS tile; slower for the split kernels).
+// The occupancy (waves per SIMD) the register allocator must allow is a
+// launch knob: kernel instances for 6 and 8 waves besides the compiler's
+// own choice.
 #ifndef BHQ_UNROLL
 #define BHQ_UNROLL 2
 #endif
@@ -264,14 +266,6 @@ __device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b, const V
 #endif
 #ifndef BHQ_TILE_DEPTH
 #define BHQ_TILE_DEPTH 1
-#endif
-#ifndef BHQ_WAVES_PER_EU
-#define BHQ_WAVES_PER_EU 0
-#endif
-#if BHQ_WAVES_PER_EU > 0
-#define BHQ_OCCUPANCY __attribute__((amdgpu_waves_per_eu(BHQ_WAVES_PER_EU)))
-#else
-#define BHQ_OCCUPANCY
 #endif
 
 // Far position for padding entries: zero mass (and zero moments) at a
@@ -711,8 +705,11 @@ __device__ __forceinline__ void load_split_tab(V4<float> *tab)
     }
 }
 
-template <typename R, int KIND, bool PERIODIC, int BS, int IB>
-__global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel(const ForceArgs A)
+// WPE > 0: at least WPE waves per SIMD (registers capped to fit); a
+// minimum of 1 leaves the compiler's choice.
+template <typename R, int KIND, bool PERIODIC, int BS, int IB, int WPE>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void force_kernel(const ForceArgs A)
 {
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
     __shared__ V4<R> sa[BHQ_TILE_DEPTH * BS];
@@ -744,9 +741,9 @@ __device__ __forceinline__ int xcd_id()
 // then the others' in turn.  Every counter only grows, and a block leaves a
 // counter once it has passed that counter's slot count, so every block
 // exits.
-template <typename R, int KIND, bool PERIODIC, int BS, int IB>
-__global__ __launch_bounds__(BS) BHQ_OCCUPANCY void force_kernel_persistent(const ForceArgs A,
-                                                                           int nj)
+template <typename R, int KIND, bool PERIODIC, int BS, int IB, int WPE>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void force_kernel_persistent(const ForceArgs A, int nj)
 {
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
     __shared__ V4<R> sa[BHQ_TILE_DEPTH * BS];
@@ -804,7 +801,7 @@ __global__ void reset_queue(unsigned int *q)
     if (blockIdx.x == 0 && threadIdx.x < kQueueWords) q[threadIdx.x] = 0u;
 }
 
-template <typename R, int KIND, bool P, int BS, int IB>
+template <typename R, int KIND, bool P, int BS, int IB, int WPE>
 hipError_t launch_one(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
 {
     const int nj = cfg.jsplit;
@@ -816,16 +813,16 @@ hipError_t launch_one(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
         int per_cu = cfg.blocks_per_cu;
         if (per_cu <= 0) {
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, force_kernel_persistent<R, KIND, P, BS, IB>, BS, 0);
+                &per_cu, force_kernel_persistent<R, KIND, P, BS, IB, WPE>, BS, 0);
             if (e != hipSuccess) return e;
             if (per_cu < 1) per_cu = 1;
         }
         const int64_t want = (int64_t)per_cu * cfg.num_cu;
         const unsigned grid = (unsigned)(want < items ? want : items);
-        hipLaunchKernelGGL((force_kernel_persistent<R, KIND, P, BS, IB>),
+        hipLaunchKernelGGL((force_kernel_persistent<R, KIND, P, BS, IB, WPE>),
                            dim3(grid), dim3(BS), 0, s, A, nj);
     } else {
-        hipLaunchKernelGGL((force_kernel<R, KIND, P, BS, IB>),
+        hipLaunchKernelGGL((force_kernel<R, KIND, P, BS, IB, WPE>),
                            dim3((unsigned)items), dim3(BS), 0, s, A);
     }
     hipError_t e = hipGetLastError();
@@ -835,14 +832,26 @@ hipError_t launch_one(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
     return hipGetLastError();
 }
 
+// Block 256 in FP32 has instances for 6 and 8 waves per SIMD; the other
+// shapes and FP64 run the compiler's choice whatever cfg.waves_per_eu says.
+template <typename R, int KIND, bool P, int IB>
+hipError_t launch_wpe(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
+{
+    if constexpr (std::is_same<R, float>::value) {
+        if (cfg.waves_per_eu == 6) return launch_one<R, KIND, P, 256, IB, 6>(A, cfg, s);
+        if (cfg.waves_per_eu == 8) return launch_one<R, KIND, P, 256, IB, 8>(A, cfg, s);
+    }
+    return launch_one<R, KIND, P, 256, IB, 0>(A, cfg, s);
+}
+
 template <typename R, int KIND, bool P>
 hipError_t launch_bs(const ForceArgs &A, const LaunchCfg &cfg, hipStream_t s)
 {
     if (cfg.i_per_thread == 2)
-        return cfg.block == 128 ? launch_one<R, KIND, P, 128, 2>(A, cfg, s)
-                                : launch_one<R, KIND, P, 256, 2>(A, cfg, s);
-    return cfg.block == 128 ? launch_one<R, KIND, P, 128, 1>(A, cfg, s)
-                            : launch_one<R, KIND, P, 256, 1>(A, cfg, s);
+        return cfg.block == 128 ? launch_one<R, KIND, P, 128, 2, 0>(A, cfg, s)
+                                : launch_wpe<R, KIND, P, 2>(A, cfg, s);
+    return cfg.block == 128 ? launch_one<R, KIND, P, 128, 1, 0>(A, cfg, s)
+                            : launch_wpe<R, KIND, P, 1>(A, cfg, s);
 }
 
 template <typename R>

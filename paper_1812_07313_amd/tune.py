@@ -1,9 +1,11 @@
 """Autotuner for the force evaluation: chooses the group size bound ncrit
 (which changes the interaction lists; the paper's n_crit, Sec. 3.4), the
 launch shape (block size = LDS tile depth, i-particles per thread, persistent
-queue and its grid size = resident blocks per CU, HIP graph replay, and the
-cross-block j-split for inputs with too few groups to fill the GPU) and the
-group dispatch order that minimise the time of one force evaluation.
+queue and its grid size = resident blocks per CU, HIP graph replay, the
+cross-block j-split for inputs with too few groups to fill the GPU, and the
+occupancy: kernel instances whose registers are capped for 6 or 8 waves per
+SIMD) and the group dispatch order that minimise the time of one force
+evaluation.
 Interactions per second alone would reward larger ncrit (more, cheaper
 interactions), so the objective is seconds per evaluation.
 
@@ -27,6 +29,9 @@ NCRITS = (64, 128, 256)
 SHAPES = ((256, 1, 0, 0, 0), (256, 2, 0, 0, 0), (128, 1, 0, 0, 0), (128, 2, 0, 0, 0),
           (256, 1, 0, 1, 0), (256, 2, 0, 1, 0), (128, 2, 4, 1, 0),
           (256, 1, 0, 1, 1), (256, 2, 0, 1, 1), (256, 2, 0, 0, 1))
+# waves per SIMD the registers must allow (0: the compiler's choice); the
+# capped instances exist for block 256
+WAVES = (0, 6, 8)
 JSPLITS = (1,)
 SMALL_JSPLITS = (1, 2, 4, 8)   # for inputs of a few hundred groups
 ORDERS = (bhq.ORDER_XCD, bhq.ORDER_COST)
@@ -55,18 +60,21 @@ def cache_key(arch, workload, kernel, precision, theta):
                                         bhq.PRECISION_NAMES[precision], theta)
 
 
-def search(measure, ncrits=NCRITS, shapes=SHAPES, orders=ORDERS, jsplits=JSPLITS):
+def search(measure, ncrits=NCRITS, shapes=SHAPES, orders=ORDERS, jsplits=JSPLITS,
+           waves=WAVES):
     """Exhaustive search.  measure(ncrit, cfg) with cfg a dict of the launch
     knobs (block, i_per_thread, blocks_per_cu, persistent, use_graph, jsplit,
-    order) returns seconds per evaluation.  Returns (best, table)."""
+    waves_per_eu, order) returns seconds per evaluation; waves_per_eu other
+    than 0 is tried for block 256 only.  Returns (best, table)."""
     table = []
     for nc in ncrits:
         for shape in shapes:
-            for js in jsplits:
-                for order in orders:
-                    cfg = dict(zip(KNOBS, shape), jsplit=js, order=order)
-                    t = measure(nc, cfg)
-                    table.append(dict(cfg, ncrit=nc, seconds=t))
+            for w in (waves if shape[0] == 256 else (0,)):
+                for js in jsplits:
+                    for order in orders:
+                        cfg = dict(zip(KNOBS, shape), jsplit=js, waves_per_eu=w, order=order)
+                        t = measure(nc, cfg)
+                        table.append(dict(cfg, ncrit=nc, seconds=t))
     best = min(table, key=lambda r: r["seconds"])
     return dict(best), table
 
@@ -74,7 +82,8 @@ def search(measure, ncrits=NCRITS, shapes=SHAPES, orders=ORDERS, jsplits=JSPLITS
 def apply(ctx, cfg):
     """Set a configuration's launch knobs and order on ctx."""
     bhq.bhq_set_tuning(ctx, cfg["block"], cfg["i_per_thread"], cfg["blocks_per_cu"],
-                       cfg["persistent"], cfg.get("use_graph", 0), cfg.get("jsplit", 1))
+                       cfg["persistent"], cfg.get("use_graph", 0), cfg.get("jsplit", 1),
+                       cfg.get("waves_per_eu", 0))
     bhq.bhq_set_group_order(ctx, cfg["order"])
 
 
@@ -124,19 +133,20 @@ def gpu_measure(ctx, x, m, theta, kernel=bhq.QUAD, precision=bhq.FP32_OFS64,
 
 def autotune(ctx, x, m, theta, workload, arch="gfx950", kernel=bhq.QUAD,
              precision=bhq.FP32_OFS64, cache=DEFAULT_CACHE, ncrits=NCRITS,
-             shapes=SHAPES, orders=ORDERS, jsplits=JSPLITS, force=False, **kw):
+             shapes=SHAPES, orders=ORDERS, jsplits=JSPLITS, waves=WAVES, force=False,
+             **kw):
     """Tune (or read from the cache) and leave ctx holding the best lists
     and launch shape.  Returns dict(best=..., table=..., cached=bool)."""
     key = cache_key(arch, workload, kernel, precision, theta)
     db = _load(cache)
     measure = gpu_measure(ctx, x, m, theta, kernel=kernel, precision=precision,
                           **kw)
-    if not force and key in db and "jsplit" in db[key]["best"]:
+    if not force and key in db and "waves_per_eu" in db[key]["best"]:
         best = db[key]["best"]
         measure(best["ncrit"], best)
         return dict(best=best, table=db[key]["table"], cached=True)
     t0 = time.perf_counter()
-    best, table = search(measure, ncrits, shapes, orders, jsplits)
+    best, table = search(measure, ncrits, shapes, orders, jsplits, waves)
     db = _load(cache)
     db[key] = dict(best=best, table=table, seconds_spent=time.perf_counter() - t0)
     _store(cache, db)

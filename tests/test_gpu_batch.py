@@ -47,6 +47,16 @@ def test_launch_shapes(ctx, cube_case):
                     bhq.bhq_set_tuning(ctx, block, ipt, bpc, 1)
                     a1, p1 = run(ctx, mat, len(m), bhq.QUAD, prec)
                     assert np.array_equal(a0, a1) and np.array_equal(p0, p1)
+                if block == 256:
+                    # capped register allocation: the same arithmetic
+                    for w in (6, 8):
+                        log("  waves_per_eu=%d" % w)
+                        bhq.bhq_set_tuning(ctx, block, ipt, 0, 0, 0, 1, w)
+                        aw, pw = run(ctx, mat, len(m), bhq.QUAD, prec)
+                        assert np.array_equal(a0, aw) and np.array_equal(p0, pw)
+                        bhq.bhq_set_tuning(ctx, block, ipt, 0, 1, 0, 1, w)
+                        aw, pw = run(ctx, mat, len(m), bhq.QUAD, prec)
+                        assert np.array_equal(a0, aw) and np.array_equal(p0, pw)
                 for js in (2, 4, 8):
                     # cross-block j-split: parts of the lists in different
                     # blocks, added in part order; the persistent queue
@@ -61,6 +71,7 @@ def test_launch_shapes(ctx, cube_case):
                     assert np.array_equal(a2, a3) and np.array_equal(p2, p3)
         t = bhq.bhq_get_tuning(ctx)
         assert t["persistent"] == 1 and t["i_per_thread"] == 2 and t["jsplit"] == 8
+        assert t["waves_per_eu"] == 0
     bhq.bhq_set_tuning(ctx)
 
 
@@ -98,7 +109,8 @@ def test_group_orders_bitwise(ctx, cube_case):
 def test_tuning_argument_errors(ctx):
     for args in ((64, 1, 0, 0, 0), (256, 3, 0, 0, 0), (256, 1, -1, 0, 0),
                  (256, 1, 0, 2, 0), (256, 1, 0, 0, 3), (256, 1, 0, 0, 0, 3),
-                 (256, 1, 0, 0, 0, 16), (256, 1, 0, 0, 0, -1)):
+                 (256, 1, 0, 0, 0, 16), (256, 1, 0, 0, 0, -1), (256, 1, 0, 0, 0, 1, 4),
+                 (256, 1, 0, 0, 0, 1, 7), (128, 1, 0, 0, 0, 1, 6)):
         with pytest.raises(bhq.BhqError) as ei:
             bhq.bhq_set_tuning(ctx, *args)
         assert ei.value.code == bhq.E_ARG

@@ -291,6 +291,14 @@ def test_split_kernel_periodic(ctx, nside):
             err = errors(a, p, a_ref, p_ref)
             log("    %s" % err)
             assert_parity(err, prec, "split %s %s" % (bk, prec))
+            # instances with capped registers (6 and 8 waves per SIMD),
+            # eager and persistent: the same arithmetic, the same bits
+            for w in (6, 8):
+                for pers in (0, 1):
+                    bhq.bhq_set_tuning(ctx, 256, 2, 0, pers, 0, 1, w)
+                    aw, pw = run(ctx, mat, len(m), bk, prec)
+                    bhq.bhq_set_tuning(ctx)
+                    assert np.array_equal(a, aw) and np.array_equal(p, pw), (w, pers)
 
 
 def test_count_live_and_clock(ctx):
@@ -452,6 +460,10 @@ def test_split_cutoff_band_pairs(ctx, ncrit, nleaf):
                    int(np.any(a != 0.0, axis=1).sum()), len(m)))
             assert np.array_equal(np.any(a != 0.0, axis=1), kept), (bk, prec)
             assert np.array_equal(p != 0.0, kept), (bk, prec)
+            bhq.bhq_set_tuning(ctx, 256, 2, 0, 0, 0, 1, 6)
+            aw, pw = run(ctx, mat, len(m), bk, prec)
+            bhq.bhq_set_tuning(ctx)
+            assert np.array_equal(a, aw) and np.array_equal(p, pw)
             ea = orc.relative_errors(a[kept], a_ref[kept])
             ep = np.abs(p[kept] - p_ref[kept]) / np.abs(p_ref[kept])
             tol = 1e-5 if prec == bhq.FP32_OFS64 else 1e-12

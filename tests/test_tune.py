@@ -15,14 +15,17 @@ def test_search_picks_minimum_and_cache_roundtrip(tmp_path):
     def measure(nc, c):
         return (cost[nc] + (0.1 if c["block"] == 128 else 0.0) - 0.05 * c["persistent"]
                 - 0.01 * c["i_per_thread"] - 0.001 * (c["order"] == bhq.ORDER_COST)
-                - 0.002 * c["use_graph"] + 0.0001 * c["jsplit"])
+                - 0.002 * c["use_graph"] + 0.0001 * c["jsplit"]
+                - 0.0003 * (c["waves_per_eu"] == 6))
 
     best, table = tune.search(measure, jsplits=tune.SMALL_JSPLITS)
-    assert len(table) == (len(tune.NCRITS) * len(tune.SHAPES) * len(tune.ORDERS)
-                          * len(tune.SMALL_JSPLITS))
+    n256 = sum(1 for s in tune.SHAPES if s[0] == 256)
+    assert len(table) == (len(tune.NCRITS) * (n256 * len(tune.WAVES) + len(tune.SHAPES) - n256)
+                          * len(tune.ORDERS) * len(tune.SMALL_JSPLITS))
+    assert all(r["waves_per_eu"] == 0 for r in table if r["block"] == 128)
     assert best["ncrit"] == 128 and best["block"] == 256 and best["persistent"] == 1
     assert best["i_per_thread"] == 2 and best["order"] == bhq.ORDER_COST
-    assert best["use_graph"] == 1 and best["jsplit"] == 1
+    assert best["use_graph"] == 1 and best["jsplit"] == 1 and best["waves_per_eu"] == 6
     assert best["seconds"] == min(r["seconds"] for r in table)
     path = str(tmp_path / "tune.json")
     key = tune.cache_key("gfx950", "w", bhq.QUAD, bhq.FP32_OFS64, 0.6)
