@@ -90,16 +90,22 @@ typedef struct bhq_lists bhq_lists;
 #define BHQ_XCDS 8 /* accelerator complex dies (own L2 each) of one gfx950 */
 
 /* Create a context on HIP device `device` for the given kernel and
- * precision.  *out receives the context (NULL on failure).
+ * precision (the counterpart of opening the force library, g5_open in the
+ * paper's driver, Sec. 3.4, List 4).  *out receives the context (NULL on
+ * failure).
  * Errors: BHQ_E_ARG (null out, bad enum), BHQ_E_NODEV (no GPU, or device
  * out of range), BHQ_E_HIP, BHQ_E_NOMEM. */
 int bhq_create(bhq_ctx **out, int device, int kernel, int precision);
 
 /* Wait for outstanding work, free all device and host memory of the
- * context.  NULL is accepted and ignored. */
+ * context (g5_close, List 4).  NULL is accepted and ignored. */
 int bhq_destroy(bhq_ctx *ctx);
 
-/* Switch kernel and/or precision for later computes on the same data. */
+/* Switch kernel and/or precision for later computes on the same data:
+ * quadrupole cells (Sec. 3, eqs. 1, 4-7), monopole cells (the monopole
+ * program of Secs. 4-5), the complete softened quadrupole, or the split
+ * kinds (no counterpart in the paper); FP32 with FP64 offsets or FP64.
+ * Errors: BHQ_E_ARG for an unknown kernel or precision. */
 int bhq_set_kernel(bhq_ctx *ctx, int kernel, int precision);
 
 /* One softening length for every i-particle: eps^2 = eps * eps (the
@@ -115,7 +121,9 @@ int bhq_set_eps(bhq_ctx *ctx, double eps);
  * BHQ_E_NONFINITE otherwise). */
 int bhq_set_eps2_i(bhq_ctx *ctx, int64_t ni, const double *eps2);
 
-/* Short-range split parameters for the SPLIT kernels: r_s > 0, cutoff
+/* Short-range split parameters for the SPLIT kernels (no counterpart in
+ * the paper; the short-range part of the TreePM force that Sec. 1 names
+ * as the setting of tree codes in cosmology): r_s > 0, cutoff
  * rcut > 0; box > 0 selects a periodic cube of that side (minimum-image
  * separations), box == 0 an open boundary.  The FP32 split kernels take
  * erfc and the related radial functions from a table that covers
@@ -125,7 +133,9 @@ int bhq_set_eps2_i(bhq_ctx *ctx, int64_t ni, const double *eps2);
 int bhq_set_split(bhq_ctx *ctx, double rs, double rcut, double box);
 
 /* Define the groups and the list sizes; must precede set_i / set_jp /
- * set_jc.  ng >= 1 groups.
+ * set_jc.  A group is the set of i-particles that share one interaction
+ * list: the particles of a cell with at most n_crit of them (the modified
+ * tree algorithm, Sec. 3.4, List 4).  ng >= 1 groups.
  *   i_off[ng+1]   i_off[0] == 0, non-decreasing; ni = i_off[ng]
  *   center[ng]    FP64 reference point of each group (its cell centre);
  *                 FP32 kernels form all positions relative to it
@@ -137,22 +147,30 @@ int bhq_set_groups(bhq_ctx *ctx, int64_t ng, const int64_t *i_off,
                    const double (*center)[3], const int64_t *jp_off,
                    const int64_t *jc_off);
 
-/* i-particle positions, ni == i_off[ng], in group order. */
+/* i-particle positions, ni == i_off[ng], in group order (the coordinates
+ * that g5c_calculate_force_on_xMC transmits, Sec. 3.4, List 3).  Errors:
+ * BHQ_E_STATE before bhq_set_groups, BHQ_E_ARG for ni != i_off[ng],
+ * BHQ_E_NONFINITE, BHQ_E_NOMEM. */
 int bhq_set_i(bhq_ctx *ctx, int64_t ni, const double (*x)[3]);
 
 /* j-particles: entries adr .. adr+n-1 of the materialised list arrays
- * (chunked filling allowed; adr + n <= njp). */
+ * (chunked filling allowed; adr + n <= njp): positions and masses, as
+ * g5_set_xmjMC sets them (List 4).  Errors: BHQ_E_STATE before
+ * bhq_set_groups, BHQ_E_RANGE past njp, BHQ_E_NONFINITE, BHQ_E_NOMEM. */
 int bhq_set_jp(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
                const double *m);
 
-/* j-cells: entries adr .. adr+n-1 (adr + n <= njc): centre of mass x,
+/* j-cells: entries adr .. adr+n-1 (adr + n <= njc), as g5c_set_xmjMC
+ * sets them (Sec. 3.4, List 3): centre of mass x,
  * total mass m, quadrupole q (List 1 order), and the trace
  * T = sum m |x - com|^2 used by the SPLIT_QUAD kernel (may be NULL for the
  * other kernels; then T = 0). */
 int bhq_set_jc(bhq_ctx *ctx, int64_t adr, int64_t n, const double (*x)[3],
                const double *m, const double (*q)[6], const double *trace);
 
-/* Index-mode lists (alternative to bhq_set_jp / bhq_set_jc): the j-data
+/* Index-mode lists (alternative to bhq_set_jp / bhq_set_jc; the same
+ * j-particles and j-cells as List 3's set calls, without a copy per list
+ * entry): the j-data
  * live once in two pools and each list entry is an int32 index into them,
  * so neighbouring groups share the data (4 bytes per entry instead of a
  * copy).  After bhq_set_groups the lists are given either materialised or
@@ -237,7 +255,10 @@ int bhq_set_jc_idx_dev(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx,
                        void *stream);
 
 /* Launch the force evaluation on HIP stream `stream` (NULL: the null
- * stream).  Asynchronous.  Errors: BHQ_E_STATE if groups, i-particles or
+ * stream): the forces and potentials of every group's list on its
+ * i-particles, as g5_calculate_force_on_xMC and then
+ * g5c_calculate_force_on_xMC compute them for one group (Sec. 3.4, Lists 3
+ * and 4), for all groups in one launch.  Asynchronous.  Errors: BHQ_E_STATE if groups, i-particles or
  * softening are missing; BHQ_E_HIP on a launch failure. */
 int bhq_compute(bhq_ctx *ctx, void *stream);
 
@@ -258,18 +279,22 @@ int bhq_compute(bhq_ctx *ctx, void *stream);
 int bhq_compute_noalloc(bhq_ctx *ctx, double *a, double *pot, void *stream);
 
 /* Wait for the last compute and copy out a[ni][3] and pot[ni] (FP64, group
- * order).  Either pointer may be NULL. */
+ * order; the arrays ai and pi of List 3).  Either pointer may be NULL.
+ * Errors: BHQ_E_STATE before a compute, BHQ_E_HIP. */
 int bhq_get_result(bhq_ctx *ctx, double (*a)[3], double *pot);
 
 /* Interaction counts of the current lists: n_pp = sum_g ni_g * njp_g,
- * n_pc = sum_g ni_g * njc_g. */
+ * n_pc = sum_g ni_g * njc_g (the interactions that the paper's throughput
+ * counts, Sec. 5.2).  Errors: BHQ_E_ARG, BHQ_E_STATE before bhq_set_groups. */
 int bhq_get_counts(const bhq_ctx *ctx, int64_t *n_pp, int64_t *n_pc);
 
 /* Duration in milliseconds of the force kernel(s) of the last compute,
- * measured with HIP events on the compute stream.  Waits for it. */
+ * measured with HIP events on the compute stream (the force-calculation
+ * time of Sec. 5).  Waits for it.  Errors: BHQ_E_STATE before a compute. */
 int bhq_get_kernel_ms(bhq_ctx *ctx, double *ms);
 
-/* For the split kernels (BHQ_SPLIT_QUAD / BHQ_SPLIT_MONO): the number of
+/* Measurement support, no counterpart in the paper.
+ * For the split kernels (BHQ_SPLIT_QUAD / BHQ_SPLIT_MONO): the number of
  * (i-particle, list entry) pairs of the context's lists that lie inside the
  * cutoff, i.e. that the kernels evaluate rather than mask: *pp for the
  * particle entries, *pc for the cell entries (the decision of the kernels:
@@ -278,7 +303,8 @@ int bhq_get_kernel_ms(bhq_ctx *ctx, double *ms);
  * kernel).  Errors: BHQ_E_STATE (another kernel, or no lists), BHQ_E_ARG. */
 int bhq_count_live(bhq_ctx *ctx, int64_t *pp, int64_t *pc);
 
-/* The GPU's shader clock during other work (measurement support):
+/* The GPU's shader clock during other work (measurement support, no
+ * counterpart in the paper):
  * bhq_clock_begin launches one wave on `stream` that reads the shader-clock
  * counter and the constant-rate counter, waits until wall_ms (in (0, 10000])
  * of the latter have passed, and reads both again; launch it on a stream of
@@ -327,7 +353,8 @@ int bhq_set_tuning(bhq_ctx *ctx, int block, int i_per_thread, int blocks_per_cu,
  * persistent, use_graph, jsplit, waves_per_eu. */
 int bhq_get_tuning(const bhq_ctx *ctx, int out[7]);
 
-/* Order in which groups are handed to blocks.  Group g costs
+/* Order in which groups are handed to blocks (no counterpart in the paper,
+ * whose driver evaluates one group per call, List 4).  Group g costs
  * c_g = ni_g (100 njp_g + 265 njc_g + 100), in 64-bit integers (a cell term
  * costs about 53/20 of a particle term; the last term stands for loading
  * and storing the i-particles).  Group g of the XCD order goes to piece
@@ -358,10 +385,12 @@ int bhq_get_tuning(const bhq_ctx *ctx, int out[7]);
  * after which the groups must be set again. */
 int bhq_set_group_order(bhq_ctx *ctx, int mode, int window, int tail);
 
-/* Current group order: out[0..2] = mode, window, tail. */
+/* Current group order: out[0..2] = mode, window, tail.  Errors:
+ * BHQ_E_ARG for NULL. */
 int bhq_get_group_order(const bhq_ctx *ctx, int out[3]);
 
-/* What the last bhq_build_lists_device(_batch) on ctx did: out[0] = 1 if
+/* (No counterpart in the paper.)
+ * What the last bhq_build_lists_device(_batch) on ctx did: out[0] = 1 if
  * it walked the tree once (a rebuild: each group's entries went into a slot
  * of 1.25 times an earlier device build's longest list plus 32 entries, and
  * were compacted; the slot size is kept from build to build while that
@@ -373,7 +402,8 @@ int bhq_get_group_order(const bhq_ctx *ctx, int out[3]);
  * either way.  All zero before the first device build. */
 int bhq_get_build_info(const bhq_ctx *ctx, int64_t out[3]);
 
-/* The launch slot table in use (the order above applied to the current
+/* (No counterpart in the paper: how one launch hands groups to blocks.)
+ * The launch slot table in use (the order above applied to the current
  * groups): order[b] is the group of slot b or -1.  Lists built on the
  * device get their table computed on the device (for windows and tails up
  * to 1024), equal entry for entry to bhq_plan_order on their offsets.
@@ -395,7 +425,8 @@ int bhq_plan_order(int64_t ng, const int64_t *i_off, const int64_t *jp_off,
                    const int64_t *jc_off, int mode, int window, int tail,
                    int xcds, int32_t *order, int64_t cap, int64_t *nslots);
 
-/* Message for the last error on ctx (never NULL; "" when none).  With
+/* (No counterpart in the paper.)
+ * Message for the last error on ctx (never NULL; "" when none).  With
  * ctx == NULL: the message of the last failed bhq_create on this thread. */
 const char *bhq_last_error(const bhq_ctx *ctx);
 
@@ -422,7 +453,7 @@ int bhq_build_lists(int64_t n, const double (*x)[3], const double *m,
                     double rcut, int nthreads, bhq_lists **out);
 
 /* Build lists for nsys independent systems in one object (for one batched
- * launch): system s is particles sys_off[s] .. sys_off[s+1]-1 of x and m
+ * launch; no counterpart in the paper, which evaluates one system): system s is particles sys_off[s] .. sys_off[s+1]-1 of x and m
  * (sys_off[0] == 0, strictly increasing), open boundaries, one theta and
  * ncrit for all.  Each system gets its own tree; groups, i-particles and
  * list entries of system s follow those of system s-1, and every index in
