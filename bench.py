@@ -671,6 +671,7 @@ def other_configs(torch, stream, steps, cpu=True):
 
     W = workload("plummer16k")
     shapes = [(256, ipt, 0, 0, 0, js) for ipt in (1, 2) for js in (1, 2, 4, 8)]
+    shapes += [(256, 1, 0, 0, 0, js, w) for js in (2, 4) for w in (6, 8)]
     rec, a32, _ = config_record(torch, stream, W, bhq.QUAD, 64, shapes, steps)
     if cpu:
         rec["cpu_baseline"] = oracle_leg(W, bhq.QUAD, 64, a32, 1)
@@ -685,7 +686,8 @@ def other_configs(torch, stream, steps, cpu=True):
     log("plummer16k: %.4f ms (%s)" % (rec["kernel_ms_fp32"], rec["launch"]))
 
     W = workload("clustered")
-    rec, a32, _ = config_record(torch, stream, W, bhq.QUAD, 256, eager, steps)
+    rec, a32, _ = config_record(torch, stream, W, bhq.QUAD, 256,
+                                eager + [(256, 2, 0, 1, 0, 1)], steps)
     if cpu:
         rec["cpu_baseline"] = oracle_leg(W, bhq.QUAD, 256, a32, 64)
     recs["clustered"] = rec
