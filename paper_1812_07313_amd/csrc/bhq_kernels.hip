@@ -490,8 +490,25 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g, int
                         bool keep[IB];
                         decide(jv, sp, keep, near);
 #pragma unroll
-                        for (int u = 0; u < IB; ++u)
-                            if (keep[u]) pp_split(jv, sp[u], K, tab, bx[u], by[u], bz[u], bp[u]);
+                        for (int u = 0; u < IB; ++u) {
+                            if constexpr (std::is_same<R, double>::value) {
+                                // FP64: every lane evaluates the term, and a
+                                // dropped one gets a separation inside the
+                                // cutoff and zero mass, adding exactly zero.
+                                // The unrolled entries then form one block
+                                // whose library erfc and exp calls overlap:
+                                // 72 ms instead of 84 on the 2^24 lattice,
+                                // with the same bits.  FP32 keeps the branch
+                                // (its table form is faster with it).
+                                Sep<R> s = sp[u];
+                                V4<R> jk = jv;
+                                s.r2 = keep[u] ? s.r2 : R(0.25) * rcut2;
+                                jk.w = keep[u] ? jv.w : R(0);
+                                pp_split(jk, s, K, tab, bx[u], by[u], bz[u], bp[u]);
+                            } else if (keep[u]) {
+                                pp_split(jv, sp[u], K, tab, bx[u], by[u], bz[u], bp[u]);
+                            }
+                        }
                     } else {
 #pragma unroll
                         for (int u = 0; u < IB; ++u)
