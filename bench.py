@@ -23,8 +23,9 @@ lists with the oracle on sampled groups beside it.
     python bench.py [--steps K] [--warmup W] [--workload NAME]
         [--no-cpu-baseline] [--no-fixed-error] [--no-variants] [--no-configs]
 
-Other workloads (--workload): sphere (the paper's homogeneous sphere,
-N = 4,194,304), plummer16k, clustered, batched, lattice.
+Other workloads (--workload): sphere and plummer4m (the paper's homogeneous
+sphere and Plummer model, N = 4,194,304), plummer16k, clustered, batched,
+lattice.
 """
 import argparse
 import json
@@ -119,6 +120,13 @@ def workload(name, n=None):
                          "theta=0.5" % nn,
                     x=x, m=m, eps=2.0 ** -8, theta=0.5, ncrit=256,
                     kernel=bhq.QUAD)
+    if name == "plummer4m":
+        # the paper's Plummer model at its Table 2 size (softening as for the
+        # homogeneous sphere: the paper gives none for these runs)
+        nn = n or 4194304
+        x, m = synth.plummer(nn, synth.rng(6))
+        return dict(name="Plummer sphere (scale radius 1) N=%d, eps=2^-8, theta=0.5" % nn,
+                    x=x, m=m, eps=2.0 ** -8, theta=0.5, ncrit=256, kernel=bhq.QUAD)
     if name == "plummer16k":
         c = synth.config_plummer_16k()
         return dict(name="Plummer sphere N=16384, eps=1/64, theta=0.5",
@@ -758,7 +766,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cube",
-                    choices=["cube", "sphere", "plummer16k", "clustered",
+                    choices=["cube", "sphere", "plummer4m", "plummer16k", "clustered",
                              "batched", "lattice"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--ncrit", type=int, default=None,
@@ -926,7 +934,7 @@ def main():
             a_soft, _ = result_orig(ctx, P, n)
             out_extra["tree_error_vs_direct"]["fp32_quad_soft"] = tree_error(a_soft, ref)
             bhq.bhq_set_kernel(ctx, kernel, bhq.FP32_OFS64)
-        if not args.no_fixed_error and args.workload in ("cube", "sphere"):
+        if not args.no_fixed_error and args.workload in ("cube", "sphere", "plummer4m"):
             W["indexed"] = args.lists == "indexed"
             log("fixed-error study ...")
             out_extra["fixed_error"] = fixed_error_study(
