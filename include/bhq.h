@@ -109,16 +109,17 @@ int bhq_destroy(bhq_ctx *ctx);
 int bhq_set_kernel(bhq_ctx *ctx, int kernel, int precision);
 
 /* One softening length for every i-particle: eps^2 = eps * eps (the
- * paper's set-eps-to-all call, List 4).  eps > 0: the softened kernels
- * include each particle's self pair (d = 0), which needs eps^2 > 0
- * (BHQ_E_ARG otherwise).  Overrides earlier per-particle values.  The
- * split kernels do not use eps. */
+ * paper's set-eps-to-all call, List 4).  The softened kernels include each
+ * particle's self pair (d = 0, r^2 = eps^2), which needs eps^2 >= 2^-126, a
+ * normal FP32 number (eps >= about 1.1e-19; BHQ_E_ARG otherwise).
+ * Overrides earlier per-particle values.  The split kernels do not use
+ * eps. */
 int bhq_set_eps(bhq_ctx *ctx, double eps);
 
 /* Per-i-particle squared softening (the i-particle structure carries eps^2
  * per particle, List 2), in group order; ni must equal i_off[ng] of the
- * last bhq_set_groups.  Every value finite and > 0 (BHQ_E_ARG / 
- * BHQ_E_NONFINITE otherwise). */
+ * last bhq_set_groups.  Every value finite and >= 2^-126, as for bhq_set_eps
+ * (BHQ_E_ARG / BHQ_E_NONFINITE otherwise). */
 int bhq_set_eps2_i(bhq_ctx *ctx, int64_t ni, const double *eps2);
 
 /* Short-range split parameters for the SPLIT kernels (no counterpart in
@@ -204,7 +205,7 @@ int bhq_set_jc_idx(bhq_ctx *ctx, int64_t adr, int64_t n, const int32_t *idx);
  * (Sec. 3.4, List 3); these copy device data the same way, without a host
  * round trip.  Each call waits for the context's last compute, checks the
  * caller's arrays on the device (the same checks as the host twin: finite
- * values, eps2 > 0, offsets from 0 and monotone, indices inside the pool),
+ * values, eps2 >= 2^-126, offsets from 0 and monotone, indices inside the pool),
  * and only then copies them into the context with kernels on `stream`
  * (NULL: the null stream).  It returns when the copy is complete: the
  * caller's memory is borrowed for the duration of the call, and may be
@@ -526,7 +527,7 @@ int bhq_build_lists_device(bhq_ctx *ctx, int64_t n, const double *x,
  * system from its own bounding box; cells are numbered system by system.
  * eps2 (device, may be NULL) gives each particle's squared softening in
  * input order: the context then holds it in group order, as bhq_set_eps2_i
- * would (values must be finite and > 0: BHQ_E_ARG otherwise).
+ * would (values must be finite and >= 2^-126: BHQ_E_ARG otherwise).
  * Errors as bhq_build_lists_device, BHQ_E_RANGE for bad offsets. */
 int bhq_build_lists_device_batch(bhq_ctx *ctx, int64_t nsys,
                                  const int64_t *sys_off, const double *x,

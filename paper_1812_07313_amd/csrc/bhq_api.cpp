@@ -488,9 +488,9 @@ int bhq_set_eps(bhq_ctx *ctx, double eps)
 {
     CHECK_CTX(ctx);
     if (!std::isfinite(eps)) return ctx->fail(BHQ_E_NONFINITE, "eps not finite");
-    if (!(eps > 0.0))
-        return ctx->fail(BHQ_E_ARG, "eps must be > 0: the softened kernels "
-                                    "include each particle's self pair");
+    if (!(eps > 0.0) || !(eps * eps >= bhq::kMinEps2))
+        return ctx->fail(BHQ_E_ARG, "eps^2 must be >= 2^-126 (a normal FP32 number): the "
+                                    "softened kernels include each particle's self pair");
     ctx->eps2_all = eps * eps;
     ctx->eps_mode = 1;
     if (ctx->ng >= 0) {
@@ -512,8 +512,8 @@ int bhq_set_eps2_i(bhq_ctx *ctx, int64_t ni, const double *eps2)
         if (!std::isfinite(eps2[k]))
             return ctx->fail(BHQ_E_NONFINITE, "eps2[%lld] not finite",
                              (long long)k);
-        if (!(eps2[k] > 0.0))
-            return ctx->fail(BHQ_E_ARG, "eps2[%lld] must be > 0 (the softened "
+        if (!(eps2[k] >= bhq::kMinEps2))
+            return ctx->fail(BHQ_E_ARG, "eps2[%lld] must be >= 2^-126 (the softened "
                              "kernels include the self pair)", (long long)k);
     }
     TRY(ctx->select());
@@ -1456,7 +1456,7 @@ static int dev_check(bhq_ctx *ctx, hipStream_t s, const char *what, F checks)
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return ctx->hip_fail(e, what);
     if (h & bhq::kBadNonFinite) return ctx->fail(BHQ_E_NONFINITE, "%s: NaN or infinity", what);
-    if (h & bhq::kBadNonPositive) return ctx->fail(BHQ_E_ARG, "%s: a value <= 0", what);
+    if (h & bhq::kBadNonPositive) return ctx->fail(BHQ_E_ARG, "%s: a value below 2^-126", what);
     if (h & bhq::kBadOrder)
         return ctx->fail(BHQ_E_RANGE, "%s: offsets not starting at 0 or not monotone", what);
     if (h & bhq::kBadRange) return ctx->fail(BHQ_E_RANGE, "%s: index outside the pool", what);

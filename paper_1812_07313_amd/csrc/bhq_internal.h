@@ -186,6 +186,13 @@ hipError_t launch_clock_window(unsigned long long ticks, unsigned long long *out
 // Device-side uploads (bhq_upload.hip).  The check kernels OR these bits
 // into *flag; launch_clear_flag zeroes it.
 constexpr unsigned kBadNonFinite = 1, kBadNonPositive = 2, kBadOrder = 4, kBadRange = 8;
+
+// Smallest accepted squared softening: the smallest normal FP32 number,
+// 2^-126.  The softened kernels include each particle's self pair, where r^2
+// = eps^2, and its reciprocal square root must be finite in FP32 (a smaller
+// eps^2 flushes to zero there) and in the FP64 kernels' rsqrt, which handles
+// only normal positive arguments.
+constexpr double kMinEps2 = 0x1p-126;
 hipError_t launch_clear_flag(unsigned *flag, hipStream_t s);
 hipError_t launch_check_f64(const double *v, int64_t n, bool positive, unsigned *flag,
                             hipStream_t s);

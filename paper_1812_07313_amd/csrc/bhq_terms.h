@@ -14,7 +14,19 @@ struct alignas(4 * sizeof(R)) V4 {
 };
 
 __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
-__device__ __forceinline__ double rsq(double v) { return ::rsqrt(v); }
+
+// FP64 1/sqrt(v) for finite v > 0 (every argument here: softened r^2 >= eps^2
+// > 0, or a split pair's r^2 > 0): the hardware estimate y, then one step of
+// the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ... with e = 1 - v y^2, which
+// takes the estimate's relative error d to O(d^3).  No special-value handling
+// (zero, infinity, denormals), which the library function spends three more
+// operations on.
+__device__ __forceinline__ double rsq(double v)
+{
+    const double y = __builtin_amdgcn_rsq(v);
+    const double e = fma(-v * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
 
 // Plummer-softened particle (also the monopole-only cell).
 template <typename R>

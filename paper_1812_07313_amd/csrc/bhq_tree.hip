@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(const double *x, const 
     if (!isfinite(x[3 * p]) || !isfinite(x[3 * p + 1]) || !isfinite(x[3 * p + 2]) ||
         !isfinite(m[p]))
         flag[0] = 1;
-    if (eps2 && !(isfinite(eps2[p]) && eps2[p] > 0.0)) flag[1] = 1;
+    if (eps2 && !(isfinite(eps2[p]) && eps2[p] >= kMinEps2)) flag[1] = 1;
 }
 
 // Bounding box of each system of a batch: one block per system.
@@ -1009,7 +1009,7 @@ int build_tree_lists(const TreeParams &P, TreeOut &O, hipStream_t s, std::string
     }
     if (hflag2[1]) {
         code = BHQ_E_ARG;
-        what = "eps2 must be finite and > 0";
+        what = "eps2 must be finite and >= 2^-126";
         return fail();
     }
     STEP(B[T_SYSOFF].reserve((size_t)(nsys + 1) * 8), "allocation");

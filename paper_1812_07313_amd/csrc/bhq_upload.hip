@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kBlock) void k_check_f64(const double *v, int64_t n
          k += (int64_t)gridDim.x * kBlock) {
         const double x = v[k];
         if (!isfinite(x)) bad |= kBadNonFinite;
-        else if (positive && !(x > 0.0)) bad |= kBadNonPositive;
+        else if (positive && !(x >= kMinEps2)) bad |= kBadNonPositive;
     }
     if (bad) atomicOr(flag, bad);
 }

@@ -117,9 +117,10 @@ def test_dev_upload_errors_leave_context(case):
         xb = x[i_idx].copy()
         xb[7, 1] = np.nan
         expect(bhq.E_NONFINITE, bhq.bhq_set_i_dev, _t(torch, xb))
-        eb = e2[i_idx].copy()
-        eb[3] = 0.0
-        expect(bhq.E_ARG, bhq.bhq_set_eps2_i_dev, _t(torch, eb))
+        for bad in (0.0, 2.0 ** -127):
+            eb = e2[i_idx].copy()
+            eb[3] = bad
+            expect(bhq.E_ARG, bhq.bhq_set_eps2_i_dev, _t(torch, eb))
         qb = mat["jc_q"].copy()
         qb[5, 2] = np.inf
         expect(bhq.E_NONFINITE, bhq.bhq_set_jc_dev, 0, _t(torch, mat["jc_x"]),

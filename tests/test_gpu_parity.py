@@ -248,13 +248,15 @@ def test_state_errors(ctx):
         with pytest.raises(bhq.BhqError) as ei:
             bhq.bhq_compute(c2)  # no softening yet
         assert ei.value.code == bhq.E_STATE
-        for bad in (0.0, -1.0):
+        for bad in (0.0, -1.0, 1e-20):
             with pytest.raises(bhq.BhqError) as ei:
-                bhq.bhq_set_eps(c2, bad)   # the self pair needs eps > 0
+                bhq.bhq_set_eps(c2, bad)   # the self pair needs eps^2 >= 2^-126
             assert ei.value.code == bhq.E_ARG
-        with pytest.raises(bhq.BhqError) as ei:
-            bhq.bhq_set_eps2_i(c2, [1.0, 0.0])
-        assert ei.value.code == bhq.E_ARG
+        for bad in (0.0, 2.0 ** -127):
+            with pytest.raises(bhq.BhqError) as ei:
+                bhq.bhq_set_eps2_i(c2, [1.0, bad])
+            assert ei.value.code == bhq.E_ARG
+        bhq.bhq_set_eps2_i(c2, [1.0, 2.0 ** -126])  # the smallest accepted value
         bhq.bhq_set_eps(c2, 1.0)
         bhq.bhq_compute(c2)
         a, p = bhq.bhq_get_result(c2, 2)

@@ -392,8 +392,9 @@ def test_device_batch_forces_with_softening():
             ar, pr = orc.eval_lists(orc.QUAD, orc.materialise(T, x, m), x, eps * eps)
             sl = slice(off[s], off[s + 1])
             assert_parity(errors(a[sl], p[sl], ar, pr), bhq.FP32_OFS64, "batch system %d" % s)
-        # a zero softening is refused, and the context then holds no lists
-        e2t[5] = 0.0
+        # a softening below 2^-126 in eps^2 is refused, and the context then
+        # holds no lists
+        e2t[5] = 2.0 ** -127
         with pytest.raises(bhq.BhqError) as ei:
             bhq.bhq_build_lists_device_batch(ctx_d, off, xt, mt, 0.6, 64, eps2=e2t)
         assert ei.value.code == bhq.E_ARG
