@@ -86,6 +86,34 @@ def test_theta_zero_single_group_and_tiny(ctx):
         assert p[0] == pytest.approx(-8.0, rel=1e-6 if prec == 0 else 1e-15)
 
 
+@pytest.mark.parametrize("js", [2, 4, 8])
+def test_jsplit_short_lists(ctx, js):
+    """Cross-block j-split on lists shorter than the part count: most parts
+    of a group hold no entry and add exact zeros in the part sum.  The
+    persistent queue hands out the same parts (bitwise the same sums)."""
+    x1 = np.array([[0.25, -0.5, 2.0]])
+    m1 = np.array([1.0])
+    x, m = synth.plummer(40, synth.rng(7))
+    try:
+        for pers in (0, 1):
+            bhq.bhq_set_tuning(ctx, 256, 2, 2 if pers else 0, pers, 0, js)
+            log("case jsplit=%d persistent=%d" % (js, pers))
+            _, _, out = _check_case(ctx, "single js%d" % js, x1, m1, 0.125, 0.5, 8)
+            for (bk, prec), (a, p) in out.items():
+                assert np.all(a == 0.0)
+                assert p[0] == pytest.approx(-8.0, rel=1e-6 if prec == 0 else 1e-15)
+            T, _, out = _check_case(ctx, "short js%d" % js, x, m, 0.05, 0.7, 4)
+            assert T.ngroups > 1
+            if pers == 0:
+                eager = out
+            else:
+                for key, (a, p) in out.items():
+                    assert np.array_equal(a, eager[key][0])
+                    assert np.array_equal(p, eager[key][1])
+    finally:
+        bhq.bhq_set_tuning(ctx)
+
+
 def test_per_particle_softening(ctx):
     """Several independent Plummer systems, each with its own eps, in one
     launch (per-i eps^2; the batched configuration in miniature)."""
