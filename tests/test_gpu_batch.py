@@ -161,6 +161,49 @@ def test_graph_replays_match_eager(ctx, cube_case):
     bhq.bhq_set_tuning(ctx)
 
 
+def test_jsplit_across_launches(ctx, cube_case):
+    """Cross-block j-split over repeated launches: eager launches, graph
+    replays (the force kernel and the parts' reduction recorded together)
+    and the persistent queue give the first launch's bits, also after an
+    input with more groups and particles has grown the parts buffer, and
+    back."""
+    torch = pytest.importorskip("torch")
+    x, m, mat, (a_ref, p_ref) = cube_case
+    x2, m2 = synth.uniform_cube(1 << 15, synth.rng(13))
+    T2 = orc.Tree(x2, m2, 0.5, 16)
+    mat2 = orc.materialise(T2, x2, m2)
+    assert len(mat2["i_off"]) > len(mat["i_off"])
+    ref2 = orc.eval_lists(orc.QUAD, mat2, x2, 1e-6)
+    try:
+        for prec in PRECS:
+            for js in (2, 8):
+                upload(ctx, mat, x, eps2=1e-6)
+                bhq.bhq_set_tuning(ctx, 256, 2, 0, 0, 0, js)
+                a0, p0 = run(ctx, mat, len(m), bhq.QUAD, prec)
+                assert_parity(errors(a0, p0, a_ref, p_ref), prec, "jsplit %d" % js)
+                for pers, graph in ((0, 0), (0, 1), (1, 0), (1, 1)):
+                    bhq.bhq_set_tuning(ctx, 256, 2, 2 if pers else 0, pers, graph, js)
+                    for rep in range(3):
+                        log("case jsplit launches precision=%s jsplit=%d persistent=%d graph=%d "
+                            "launch %d" % (bhq.PRECISION_NAMES[prec], js, pers, graph, rep))
+                        a, p = run(ctx, mat, len(m), bhq.QUAD, prec)
+                        assert np.array_equal(a, a0) and np.array_equal(p, p0)
+                        y = torch.ones(1 << 16, device="cuda")
+                        torch.cuda.synchronize()
+                        assert float(y.sum()) == float(1 << 16)
+                # more groups, then the first input again
+                log("case jsplit launches: %d groups, then %d"
+                    % (len(mat2["i_off"]) - 1, len(mat["i_off"]) - 1))
+                upload(ctx, mat2, x2, eps2=1e-6)
+                a2, p2 = run(ctx, mat2, len(m2), bhq.QUAD, prec)
+                assert_parity(errors(a2, p2, *ref2), prec, "jsplit %d, more groups" % js)
+                upload(ctx, mat, x, eps2=1e-6)
+                a, p = run(ctx, mat, len(m), bhq.QUAD, prec)
+                assert np.array_equal(a, a0) and np.array_equal(p, p0)
+    finally:
+        bhq.bhq_set_tuning(ctx)
+
+
 @pytest.mark.parametrize("persistent", [0, 1])
 def test_batched_systems_one_launch(ctx, persistent):
     """Independent Plummer systems (sizes log-uniform in [2^10, 2^13] here),
