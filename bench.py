@@ -47,7 +47,7 @@ from paper_1812_07313_amd import bhq, synth  # noqa: E402
 # flops; quadrupole cell term 34 operations and 53 flops; a monopole cell is
 # a particle term; the complete softened quadrupole adds one FMA to the
 # cell term (35 operations, 55 flops).  The split kernels add their
-# radial-function evaluation and are not priced here.
+# radial-function evaluation; their counts follow.
 FLOPS_PP = 20
 FLOPS_PC = {bhq.QUAD: 53, bhq.MONO: 20, bhq.QUAD_SOFT: 55}
 # FP32 split kernels, per term inside the cutoff (FMA = 2, rsqrt and fract 1,
@@ -362,6 +362,34 @@ def direct_reference(W, P, nsample=4096, seed=7):
     finally:
         bhq.bhq_destroy(ctx)
     return i_idx, a
+
+
+def lane_slot_fraction(i_off, jp_off, jc_off, block, ipt, ops_pp=14, ops_pc=34):
+    """Fraction of the lane-slots the force kernel's term loops issue that
+    hold a real (i-particle, list entry) pair, from the group sizes and the
+    kernel's slicing: a pass over nic <= block * ipt i-particles of a group
+    gives each slice P = ceil(nic / ipt) threads and runs S = floor(block / P)
+    slices; every wave holding an active thread issues (ipt slots per lane);
+    a tile of T = S floor(block / S) list entries takes ceil(cnt / S) steps.
+    Particle and cell terms are weighted by their VALU operation counts."""
+    ni = np.diff(np.asarray(i_off, np.int64))
+    lists = ((np.diff(np.asarray(jp_off, np.int64)), ops_pp),
+             (np.diff(np.asarray(jc_off, np.int64)), ops_pc))
+    issued = useful = 0.0
+    for ib in range(0, int(ni.max()) if len(ni) else 0, block * ipt):
+        nic = np.clip(ni - ib, 0, block * ipt)
+        on = nic > 0
+        nic = nic[on]
+        P = -(-nic // ipt)
+        S = block // P
+        waves = -(-(S * P) // 64)
+        T = S * (block // S)
+        for n, ops in lists:
+            n = n[on]
+            steps = (n // T) * (T // S) + -(-(n % T) // S)
+            issued += float(np.sum(waves * 64 * ipt * steps)) * ops
+            useful += float(np.sum(nic * n)) * ops
+    return useful / issued if issued else 1.0
 
 
 def tree_error(a_tree, ref):
@@ -882,6 +910,10 @@ def main():
         n_pp, n_pc = bhq.bhq_get_counts(ctx)
         n_int = n_pp + n_pc
         live = bhq.bhq_count_live(ctx) if kernel not in FLOPS_PC else None
+        # the term loops' lane-slots that hold a pair (all list pairs, as
+        # the non-split kernels evaluate them)
+        lane_slots = lane_slot_fraction(P["i_off"], P["jp_off"], P["jc_off"], args.block,
+                                        args.ipt)
 
         ms_step, ms_kern, ms_kern_med, sclk = time_variant(
             torch, ctx, kernel, bhq.FP32_OFS64, args.steps, args.warmup, stream, clock=True)
@@ -1004,6 +1036,7 @@ def main():
         "live_pairs": ({"pp": live[0], "pc": live[1],
                         "Ginteractions_per_s": round(sum(live) / (ms_kern * 1e-3) / 1e9, 3)}
                        if live else None),
+        "lane_slot_fraction": round(lane_slots, 4),
         "host_list_build_s": round(t_build, 3), "upload_s": round(t_upload, 3),
         "device_list_build": dev_build,
         "treepm": treepm,

@@ -88,3 +88,27 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
+
+
+def test_bench_lane_slot_fraction():
+    """The slicing model behind bench.py's lane_slot_fraction, on cases
+    counted by hand."""
+    import bench
+    # 64 i-particles, 2 per thread: 32 threads a slice, 8 slices fill the
+    # 256 threads; 256 entries are 32 steps of every slice: no empty slot
+    assert bench.lane_slot_fraction([0, 64], [0, 256], [0, 0], 256, 2) == 1.0
+    # 3 i-particles: 2 threads a slice, 128 slices (4 waves, 512 slots a
+    # step); 5 particle entries take one step: 15 of 512 slots
+    assert bench.lane_slot_fraction([0, 3], [0, 5], [0, 0], 256, 2) == 15 / 512
+    # cells weigh 34 operations against 14: 64 i-particles over 256 entries
+    # of each kind (1.0) plus a group of 3 with 5 cells (15 / 512)
+    f = bench.lane_slot_fraction([0, 64, 67], [0, 256, 256], [0, 256, 261], 256, 2)
+    useful = 64 * 256 * 14 + 64 * 256 * 34 + 3 * 5 * 34
+    issued = 64 * 256 * 14 + 64 * 256 * 34 + 512 * 34
+    assert f == pytest.approx(useful / issued, rel=1e-15)
+    # 600 i-particles in two passes: 512 (256 threads, one slice, 256-entry
+    # tiles of 256 steps) and 88 (44 threads a slice, 5 slices in 4 waves,
+    # 255-entry tiles of 51 steps); 300 entries: 256 + 44 steps in the
+    # first pass, 51 + 9 in the second
+    f = bench.lane_slot_fraction([0, 600], [0, 300], [0, 0], 256, 2)
+    assert f == pytest.approx(600 * 300 / (512 * (256 + 44) + 512 * (51 + 9)), rel=1e-15)
