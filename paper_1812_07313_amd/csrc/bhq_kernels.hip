@@ -39,6 +39,7 @@
 #include "bhq_internal.h"
 #include "bhq_terms.h"
 #include "split_table.h"
+#include "split_table64.h"
 
 #include <mutex>
 #include <type_traits>
@@ -97,11 +98,42 @@ constexpr SplitTab make_split_tab()
 
 __device__ const SplitTab kSplitTabDev = make_split_tab();
 
+// The FP64 kernels' table of erfcx (split_table64.h), likewise copied to
+// LDS by each block of an FP64 split kernel.
+struct ErfcxTab {
+    double v[kErfcxIntervals * (kErfcxDegree + 1)];
+};
+
+constexpr ErfcxTab make_erfcx_tab()
+{
+    ErfcxTab t{};
+    for (int q = 0; q < kErfcxIntervals; ++q)
+        for (int k = 0; k <= kErfcxDegree; ++k) t.v[q * (kErfcxDegree + 1) + k] = kErfcxTable[q][k];
+    return t;
+}
+
+__device__ const ErfcxTab kErfcxTabDev = make_erfcx_tab();
+
+// Element type of the LDS table of a precision.
+template <typename R>
+struct SplitTabT {
+    using type = V4<float>;
+};
+template <>
+struct SplitTabT<double> {
+    using type = double;
+};
+template <typename R>
+using TabT = typename SplitTabT<R>::type;
+
 // Gaussian-split radial functions at r (r2 = r^2), u = r / (2 r_s):
 //   ec = erfc(u), g = erfc(u) + (2u/sqrt(pi)) e^{-u^2},
 //   G2 = 3g + h, G3 = 15g + 5h + k, with h = (4u^3/sqrt(pi)) e^{-u^2} and
 //   k = 2 u^2 h (G2, G3 only for cells with the quadrupole).
-// FP64 evaluates them from the library's erfc and exp.  FP32 reads the
+// FP64 takes E = exp(-u^2) from the library and erfc(u) = E erfcx(u) from
+// the degree-9 polynomials of split_table64.h (interval q = floor(t), t =
+// u 32 / 4, f = t - q, Horner's rule; the library's erfc past u = 4, that is
+// for cutoffs beyond 8 r_s).  FP32 reads the
 // piecewise cubics of the table at t = r ct: interval q = floor(t), local
 // variable f = t - q, Horner's rule (valid for u up to kSplitDomain and one
 // interval beyond; the host refuses FP32 split kernels with a longer
@@ -117,7 +149,7 @@ __device__ __forceinline__ float horner(const V4<float> &c, float f)
 }
 
 template <typename R, bool CELL>
-__device__ __forceinline__ SplitG<R> split_g(R r, const SplitK<R> &K, const V4<float> *tab)
+__device__ __forceinline__ SplitG<R> split_g(R r, const SplitK<R> &K, const TabT<R> *tab)
 {
     SplitG<R> s;
     if constexpr (std::is_same<R, float>::value) {
@@ -134,8 +166,21 @@ __device__ __forceinline__ SplitG<R> split_g(R r, const SplitK<R> &K, const V4<f
         const R rsqpi = R(0.56418958354775628694807945156);
         const R u = r * K.i2rs;
         const R u2 = u * u;
-        const R e = exp_r(-u2) * rsqpi;
-        s.ec = erfc_r(u);
+        const R E = exp_r(-u2);
+        if (u < R(kErfcxDomain)) {
+            // t < 32 exactly: the scale 32 / 4 is a power of two
+            const R t = u * R(kErfcxIntervals / kErfcxDomain);
+            const int q = (int)t;
+            const R f = t - R(q);
+            const double *c = tab + q * (kErfcxDegree + 1);
+            R x = c[kErfcxDegree];
+#pragma unroll
+            for (int k = kErfcxDegree - 1; k >= 0; --k) x = fma(x, f, c[k]);
+            s.ec = E * x;
+        } else {
+            s.ec = erfc_r(u);
+        }
+        const R e = E * rsqpi;
         s.g = fma(R(2) * u, e, s.ec);
         if (CELL) {
             const R h = R(4) * u * u2 * e;
@@ -196,7 +241,7 @@ __device__ __forceinline__ Sep<R> separation(const V4<R> &j, R xi, R yi, R zi)
 // a += m g/r^3 d, -phi += m erfc(u)/r.
 template <typename R>
 __device__ __forceinline__ void pp_split(const V4<R> &j, const Sep<R> &s, const SplitK<R> &K,
-                                         const V4<float> *tab, R &ax, R &ay, R &az, R &pt)
+                                         const TabT<R> *tab, R &ax, R &ay, R &az, R &pt)
 {
     const R rinv = rsq(s.r2);
     const R r = s.r2 * rinv;
@@ -217,7 +262,7 @@ __device__ __forceinline__ void pp_split(const V4<R> &j, const Sep<R> &s, const 
 template <typename R, bool QUAD>
 __device__ __forceinline__ void pc_split(const V4<R> &a, const V4<R> &b, const V4<R> &c,
                                          const Sep<R> &s, const SplitK<R> &K,
-                                         const V4<float> *tab, R &ax, R &ay, R &az, R &pt)
+                                         const TabT<R> *tab, R &ax, R &ay, R &az, R &pt)
 {
     const R dx = s.dx, dy = s.dy, dz = s.dz, r2 = s.r2;
     const R rinv = rsq(r2);
@@ -285,7 +330,7 @@ struct Smem {
 template <typename R, int KIND, bool PERIODIC, int BS, int IB>
 __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g, int js, int nj,
                                               V4<R> *sa, V4<R> *sb, V4<R> *sc,
-                                              const V4<float> *tab)
+                                              const TabT<R> *tab)
 {
     constexpr bool kSplit = (KIND == kSplitQuad || KIND == kSplitMono);
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
@@ -490,25 +535,8 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g, int
                         bool keep[IB];
                         decide(jv, sp, keep, near);
 #pragma unroll
-                        for (int u = 0; u < IB; ++u) {
-                            if constexpr (std::is_same<R, double>::value) {
-                                // FP64: every lane evaluates the term, and a
-                                // dropped one gets a separation inside the
-                                // cutoff and zero mass, adding exactly zero.
-                                // The unrolled entries then form one block
-                                // whose library erfc and exp calls overlap:
-                                // 72 ms instead of 84 on the 2^24 lattice,
-                                // with the same bits.  FP32 keeps the branch
-                                // (its table form is faster with it).
-                                Sep<R> s = sp[u];
-                                V4<R> jk = jv;
-                                s.r2 = keep[u] ? s.r2 : R(0.25) * rcut2;
-                                jk.w = keep[u] ? jv.w : R(0);
-                                pp_split(jk, s, K, tab, bx[u], by[u], bz[u], bp[u]);
-                            } else if (keep[u]) {
-                                pp_split(jv, sp[u], K, tab, bx[u], by[u], bz[u], bp[u]);
-                            }
-                        }
+                        for (int u = 0; u < IB; ++u)
+                            if (keep[u]) pp_split(jv, sp[u], K, tab, bx[u], by[u], bz[u], bp[u]);
                     } else {
 #pragma unroll
                         for (int u = 0; u < IB; ++u)
@@ -703,36 +731,54 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g, int
     }
 }
 
-// The FP32 split kinds keep the table of their radial functions in LDS.
+// The split kinds keep the table of their radial functions in LDS (FP32:
+// split_table.h; FP64: the erfcx polynomials of split_table64.h).
 template <typename R, int KIND>
 constexpr int split_tab_size()
 {
-    return std::is_same<R, float>::value && (KIND == kSplitQuad || KIND == kSplitMono)
-               ? kSplitFuncs * kSplitEntries
-               : 1;
+    return KIND != kSplitQuad && KIND != kSplitMono ? 1
+           : std::is_same<R, float>::value          ? kSplitFuncs * kSplitEntries
+                                                    : kErfcxIntervals * (kErfcxDegree + 1);
 }
 
 template <typename R, int KIND, int BS>
-__device__ __forceinline__ void load_split_tab(V4<float> *tab)
+__device__ __forceinline__ void load_split_tab(TabT<R> *tab)
 {
-    if (split_tab_size<R, KIND>() > 1) {
-        for (int k = threadIdx.x; k < kSplitFuncs * kSplitEntries; k += BS)
-            tab[k] = kSplitTabDev.v[k];
+    if constexpr (split_tab_size<R, KIND>() > 1) {
+        if constexpr (std::is_same<R, float>::value) {
+            for (int k = threadIdx.x; k < kSplitFuncs * kSplitEntries; k += BS)
+                tab[k] = kSplitTabDev.v[k];
+        } else {
+            for (int k = threadIdx.x; k < kErfcxIntervals * (kErfcxDegree + 1); k += BS)
+                tab[k] = kErfcxTabDev.v[k];
+        }
         __syncthreads();
     }
 }
 
-// WPE > 0: at least WPE waves per SIMD (registers capped to fit); a
-// minimum of 1 leaves the compiler's choice.
+// Waves per SIMD the register allocation must allow: WPE > 0 asks for at
+// least WPE (registers capped to fit).  Otherwise the FP64 split kinds ask
+// for 3: left alone the compiler takes 192 VGPRs (2 waves), and 3 waves
+// (168, some spilled to scratch) ran the 2^24 lattice in 52 ms instead of
+// 57.  A minimum of 1 leaves the compiler's choice.
+template <typename R, int KIND, int WPE>
+constexpr int min_waves()
+{
+    return WPE > 0 ? WPE
+                   : (std::is_same<R, double>::value && (KIND == kSplitQuad || KIND == kSplitMono)
+                          ? 3
+                          : 1);
+}
+
 template <typename R, int KIND, bool PERIODIC, int BS, int IB, int WPE>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(min_waves<R, KIND, WPE>())))
 void force_kernel(const ForceArgs A)
 {
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
     __shared__ V4<R> sa[BHQ_TILE_DEPTH * BS];
     __shared__ V4<R> sb[kCellQ ? BHQ_TILE_DEPTH * BS : 1];
     __shared__ V4<R> sc[kCellQ ? BHQ_TILE_DEPTH * BS : 1];
-    __shared__ V4<float> st[split_tab_size<R, KIND>()];
+    __shared__ __align__(16) TabT<R> st[split_tab_size<R, KIND>()];
     // block b: slot b % nslots, part b / nslots of its group's lists (the
     // slot of a block keeps its XCD, b % 8, when nslots is a multiple of 8)
     const int nj = (int)(gridDim.x / A.nslots);
@@ -759,14 +805,14 @@ __device__ __forceinline__ int xcd_id()
 // counter once it has passed that counter's slot count, so every block
 // exits.
 template <typename R, int KIND, bool PERIODIC, int BS, int IB, int WPE>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(min_waves<R, KIND, WPE>())))
 void force_kernel_persistent(const ForceArgs A, int nj)
 {
     constexpr bool kCellQ = Smem<R, KIND>::kCellQ;
     __shared__ V4<R> sa[BHQ_TILE_DEPTH * BS];
     __shared__ V4<R> sb[kCellQ ? BHQ_TILE_DEPTH * BS : 1];
     __shared__ V4<R> sc[kCellQ ? BHQ_TILE_DEPTH * BS : 1];
-    __shared__ V4<float> st[split_tab_size<R, KIND>()];
+    __shared__ __align__(16) TabT<R> st[split_tab_size<R, KIND>()];
     __shared__ int64_t next;
     load_split_tab<R, KIND, BS>(st);
     const int nq = A.xcds > 0 ? A.xcds : 1;

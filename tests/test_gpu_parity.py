@@ -3,7 +3,8 @@ interaction lists, element by element, through the C ABI.
 
 Bars (per-particle relative error of the acceleration, and of the
 potential): FP32 with FP64 group offsets <= 2e-6 rms and <= 1e-4 max;
-FP64 <= 1e-12 rms and <= 1e-10 max (summation order only).
+FP64 <= 1e-12 rms and <= 1e-10 max (summation order and the last bits of
+rsqrt and erfc).
 """
 import numpy as np
 import pytest
@@ -407,10 +408,12 @@ def test_split_fp32_cutoff_range(ctx):
     """FP32 split kernels take erfc and the related functions from a table
     of r / 2r_s in [0, 2.5] (plus one interval for the rounding of r at the
     cutoff): a cutoff of 5 r_s is accepted and evaluated to the FP32 bar,
-    5.2 r_s and 7.5 r_s are refused for FP32 and accepted for FP64."""
+    5.2 r_s, 7.5 r_s and 9 r_s are refused for FP32 and accepted for FP64.
+    FP64 takes erfc from its erfcx table up to u = 4 (8 r_s) and from the
+    library beyond, so 9 r_s runs both forms side by side."""
     x, m = synth.perturbed_lattice(8, synth.rng(4))
     rs = 0.04
-    for rcut in (0.3, 5.2 * rs):
+    for rcut in (0.3, 5.2 * rs, 9.0 * rs):
         T = orc.Tree(x, m, 0.5, 64, box=1.0, rcut=rcut)
         mat = orc.materialise(T, x, m)
         upload(ctx, mat, x, split=(rs, rcut, 1.0))
