@@ -758,15 +758,16 @@ __device__ __forceinline__ void load_split_tab(TabT<R> *tab)
 
 // Waves per SIMD the register allocation must allow: WPE > 0 asks for at
 // least WPE (registers capped to fit).  Otherwise the FP64 split kinds ask
-// for 3: left alone the compiler takes 192 VGPRs (2 waves), and 3 waves
-// (168, some spilled to scratch) ran the 2^24 lattice in 52 ms instead of
-// 57.  A minimum of 1 leaves the compiler's choice.
+// for 4: left alone the compiler takes 192 VGPRs (2 waves); capped for 3,
+// 4 and 5 waves (registers spilled to scratch) they ran the 2^24 lattice in
+// 49.2, 47.5 and 50.8 ms against 56.7.  A minimum of 1 leaves the
+// compiler's choice.
 template <typename R, int KIND, int WPE>
 constexpr int min_waves()
 {
     return WPE > 0 ? WPE
                    : (std::is_same<R, double>::value && (KIND == kSplitQuad || KIND == kSplitMono)
-                          ? 3
+                          ? 4
                           : 1);
 }
 
