@@ -330,6 +330,19 @@ def test_split_kernel_periodic(ctx, nside):
                     aw, pw = run(ctx, mat, len(m), bk, prec)
                     bhq.bhq_set_tuning(ctx)
                     assert np.array_equal(a, aw) and np.array_equal(p, pw), (w, pers)
+            # cross-block j-split: the parts' cutoff decisions (and the FP32
+            # band's FP64 re-decisions) read the entries of their own part
+            for js in (2, 4):
+                try:
+                    bhq.bhq_set_tuning(ctx, 256, 2, 0, 0, 0, js)
+                    aj, pj = run(ctx, mat, len(m), bk, prec)
+                    assert_parity(errors(aj, pj, a_ref, p_ref), prec,
+                                  "split %s %s jsplit %d" % (bk, prec, js))
+                    bhq.bhq_set_tuning(ctx, 256, 2, 2, 1, 0, js)
+                    ap, pp = run(ctx, mat, len(m), bk, prec)
+                finally:
+                    bhq.bhq_set_tuning(ctx)
+                assert np.array_equal(aj, ap) and np.array_equal(pj, pp), js
 
 
 def test_count_live_and_clock(ctx):
@@ -501,6 +514,15 @@ def test_split_cutoff_band_pairs(ctx, ncrit, nleaf):
             ep = np.abs(p[kept] - p_ref[kept]) / np.abs(p_ref[kept])
             tol = 1e-5 if prec == bhq.FP32_OFS64 else 1e-12
             assert ea.max() <= tol and ep.max() <= tol, (bk, prec, ea.max(), ep.max())
+            # the same decisions with the lists cut into parts
+            try:
+                bhq.bhq_set_tuning(ctx, 256, 2, 0, 0, 0, 4)
+                aj, pj = run(ctx, mat, len(m), bk, prec)
+            finally:
+                bhq.bhq_set_tuning(ctx)
+            assert np.array_equal(np.any(aj != 0.0, axis=1), kept), (bk, prec, "jsplit")
+            ea = orc.relative_errors(aj[kept], a_ref[kept])
+            assert ea.max() <= tol, (bk, prec, "jsplit", ea.max())
 
 
 def test_index_lists_split_periodic(ctx):
@@ -518,6 +540,12 @@ def test_index_lists_split_periodic(ctx):
         err = errors(a, p, a_ref, p_ref)
         log("  precision=%s %s" % (bhq.PRECISION_NAMES[prec], err))
         assert_parity(err, prec, "indexed split")
+        try:
+            bhq.bhq_set_tuning(ctx, 256, 2, 0, 0, 0, 4)
+            a, p = run(ctx, mat, len(m), bhq.SPLIT_QUAD, prec)
+        finally:
+            bhq.bhq_set_tuning(ctx)
+        assert_parity(errors(a, p, a_ref, p_ref), prec, "indexed split jsplit 4")
 
 
 def test_index_list_errors(ctx):
