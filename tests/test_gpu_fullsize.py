@@ -92,6 +92,23 @@ def test_uniform_cube_1m():
         _check("cube %s" % bhq.KERNEL_NAMES[bk], gpu, lambda prec: ref, sel)
 
 
+def test_plummer_16k_bench_shapes():
+    """Plummer sphere N = 16384, eps = 1/64, theta = 0.5, ncrit = 64, at
+    every launch shape the bench times for it (1 or 2 i-particles per
+    thread, cross-block j-split 1 to 8, registers capped for 6 or 8 waves):
+    every particle against the oracle."""
+    c = synth.config_plummer_16k()
+    x, m, eps = c["x"], c["m"], c["eps"]
+    T = orc.Tree(x, m, 0.5, 64)
+    ref = orc.eval_lists(orc.QUAD, orc.materialise(T, x, m), x, eps * eps)
+    shapes = [(256, ipt, 0, 0, 0, js) for ipt in (1, 2) for js in (1, 2, 4, 8)]
+    shapes += [(256, 1, 0, 0, 0, js, w) for js in (2, 4) for w in (6, 8)]
+    for shape in shapes:
+        log("case plummer16k shape %s" % (shape,))
+        gpu = _gpu_product(x, m, 0.5, 64, bhq.QUAD, eps=eps, tuning=shape)
+        _check("plummer16k %s" % (shape,), gpu, lambda prec: ref, np.arange(len(m)))
+
+
 def test_clustered_4m_sampled():
     """512 Plummer clusters + background, N = 2^22, eps = 2e-4,
     theta = 0.5, ncrit = 256: the particles of every 64th group."""
@@ -99,6 +116,11 @@ def test_clustered_4m_sampled():
     x, m, eps = c["x"], c["m"], c["eps"]
     log("case clustered 2^22 (sampled groups)")
     gpu = _gpu_product(x, m, 0.5, 256, bhq.QUAD, eps=eps)
+    log("  persistent per-XCD queues (a launch the bench times)")
+    gpu_p = _gpu_product(x, m, 0.5, 256, bhq.QUAD, eps=eps, tuning=(256, 2, 0, 1, 0, 1))
+    for prec in gpu:
+        assert np.array_equal(gpu[prec][0], gpu_p[prec][0])
+        assert np.array_equal(gpu[prec][1], gpu_p[prec][1])
     T = orc.Tree(x, m, 0.5, 256, walk_stride=64)
     groups = np.arange(0, T.ngroups, 64)
     mat = T.sample_mat(x, m, groups)
@@ -133,6 +155,23 @@ def test_batched_256_systems():
         a_ref[off[s]:off[s + 1]] = a
         p_ref[off[s]:off[s + 1]] = p
     _check("batched", gpu, lambda prec: (a_ref, p_ref), np.arange(len(M)))
+    # ncrit 128 (the bench's choice among 64 and 128), one i-particle per
+    # thread with registers capped for 6 waves, eager and from a replayed
+    # persistent graph
+    log("  ncrit 128, 1 i/thread, 6 waves: eager and persistent graph")
+    gpu = _gpu_product(X, M, 0.6, 128, bhq.QUAD, eps2=E2, sys_off=off,
+                       tuning=(256, 1, 0, 0, 0, 1, 6))
+    gpu_graph = _gpu_product(X, M, 0.6, 128, bhq.QUAD, eps2=E2, sys_off=off,
+                             tuning=(256, 1, 0, 1, 1, 1, 6), replays=3)
+    for prec in gpu:
+        assert np.array_equal(gpu[prec][0], gpu_graph[prec][0])
+        assert np.array_equal(gpu[prec][1], gpu_graph[prec][1])
+    for s, (x, m, eps) in enumerate(systems):
+        T = orc.Tree(x, m, 0.6, 128)
+        a, p = orc.eval_lists(orc.QUAD, orc.materialise(T, x, m), x, eps * eps)
+        a_ref[off[s]:off[s + 1]] = a
+        p_ref[off[s]:off[s + 1]] = p
+    _check("batched ncrit 128", gpu, lambda prec: (a_ref, p_ref), np.arange(len(M)))
 
 
 def test_periodic_lattice_16m_sampled():
@@ -153,6 +192,17 @@ def test_periodic_lattice_16m_sampled():
     ref = orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=1.0, rs=rs, rcut=rcut,
                          mask=orc.MASK_F64_OFS)
     _check("lattice", gpu, lambda prec: ref, mat["i_idx"])
+    # the configuration the bench times: ncrit 128, registers capped for 6
+    # waves (FP64 runs its own instance)
+    log("case lattice 2^24 at ncrit 128, 6 waves (sampled groups)")
+    gpu = _gpu_product(x, m, 0.5, 128, bhq.SPLIT_QUAD, box=1.0, rcut=rcut, rs=rs,
+                       tuning=(256, 2, 0, 0, 0, 1, 6))
+    T = orc.Tree(x, m, 0.5, 128, box=1.0, rcut=rcut, walk_stride=2000)
+    mat = T.sample_mat(x, m, np.arange(0, T.ngroups, 2000))
+    assert orc.mask_flips(mat, x, 1.0, rcut) == 0
+    ref = orc.eval_lists(orc.SPLIT_QUAD, mat, x, 0.0, box=1.0, rs=rs, rcut=rcut,
+                         mask=orc.MASK_F64_OFS)
+    _check("lattice ncrit 128", gpu, lambda prec: ref, mat["i_idx"])
 
 
 @pytest.mark.parametrize("which", ["cube", "clustered", "lattice", "batched"])
