@@ -43,7 +43,7 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-PROBES = ["valu_rates", "interaction_rates"]
+PROBES = ["valu_rates", "interaction_rates", "mfma_cell_term"]
 PROBE_DIR = os.path.join(PKG, "probes")
 
 
