@@ -345,6 +345,35 @@ def test_split_kernel_periodic(ctx, nside):
                 assert np.array_equal(aj, ap) and np.array_equal(pj, pp), js
 
 
+def test_split_multipass_groups(ctx):
+    """Split kernels on groups larger than one pass of the block (up to 539
+    i-particles: two passes at two i-particles per thread, three at one):
+    the cutoff decisions and the FP32 band's FP64 re-decisions index the
+    i-particles of the current pass."""
+    x, m = synth.perturbed_lattice(32, synth.rng(9))
+    rs = 1.25 / 32
+    rcut = 4.5 * rs
+    T = orc.Tree(x, m, 0.5, 600, box=1.0, rcut=rcut)
+    assert np.diff(T.i_off).max() > 512
+    mat = orc.materialise(T, x, m)
+    assert orc.mask_flips(mat, x, 1.0, rcut) == 0
+    upload(ctx, mat, x, split=(rs, rcut, 1.0))
+    try:
+        for bk, ok in ((bhq.SPLIT_QUAD, orc.SPLIT_QUAD), (bhq.SPLIT_MONO, orc.SPLIT_MONO)):
+            a_ref, p_ref = orc.eval_lists(ok, mat, x, 0.0, box=1.0, rs=rs, rcut=rcut,
+                                          mask=orc.MASK_F64_OFS)
+            for prec in PRECS:
+                for shape in ((256, 2, 0, 0, 0, 1), (256, 1, 0, 0, 0, 1), (256, 2, 0, 0, 0, 2)):
+                    bhq.bhq_set_tuning(ctx, *shape)
+                    a, p = run(ctx, mat, len(m), bk, prec)
+                    err = errors(a, p, a_ref, p_ref)
+                    log("case split multipass kernel=%s precision=%s shape=%s %s"
+                        % (bhq.KERNEL_NAMES[bk], bhq.PRECISION_NAMES[prec], shape, err))
+                    assert_parity(err, prec, "split multipass %s %s %s" % (bk, prec, shape))
+    finally:
+        bhq.bhq_set_tuning(ctx)
+
+
 def test_count_live_and_clock(ctx):
     """bhq_count_live counts the terms the cutoff keeps exactly as the
     oracle's definition does (materialised and index lists); the clock
