@@ -137,6 +137,20 @@ def test_forces_from_device_lists(prec):
         err = errors(a, p, a_ref, p_ref)
         log("case device-list forces %s: %s" % (bhq.PRECISION_NAMES[prec], err))
         assert_parity(err, prec, "device lists")
+        # a rebuild leaves each group's entries in a slot of its own; the
+        # j-split parts and the persistent queue read them there, and give
+        # the host-built lists' bits at the same launch shape
+        bhq.bhq_build_lists_device(ctx_d, xt, mt, 0.5, 64)
+        bhq.bhq_set_eps(ctx_d, eps)
+        for shape in ((256, 2, 0, 0, 0, 1), (256, 1, 0, 0, 0, 2, 6), (256, 2, 2, 1, 0, 4)):
+            log("case device-list rebuild %s shape %s" % (bhq.PRECISION_NAMES[prec], shape))
+            out = []
+            for ctx in (ctx_d, ctx_h):
+                bhq.bhq_set_tuning(ctx, *shape)
+                bhq.bhq_compute(ctx)
+                out.append(bhq.bhq_get_result(ctx, len(m)))
+                bhq.bhq_set_tuning(ctx)
+            assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
     finally:
         bhq.bhq_destroy(ctx_d)
         bhq.bhq_destroy(ctx_h)
