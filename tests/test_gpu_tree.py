@@ -175,6 +175,23 @@ def test_split_forces_from_device_lists():
             bhq.bhq_compute(ctx)
             res.append(bhq.bhq_get_result(ctx, len(m)))
         assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+        # after a rebuild (entries in per-group slots), in both precisions and
+        # the launch shapes the bench times for the lattice, plus the j-split
+        bhq.bhq_build_lists_device(ctx_d, xt, mt, 0.5, 64, 8, 1.0, rcut)
+        bhq.bhq_set_split(ctx_d, rs, rcut, 1.0)
+        for prec in (bhq.FP32_OFS64, bhq.FP64):
+            for shape in ((256, 2, 0, 0, 0, 1, 6), (256, 2, 0, 1, 0, 1, 6), (256, 2, 0, 0, 0, 4)):
+                log("case split device-list rebuild %s shape %s"
+                    % (bhq.PRECISION_NAMES[prec], shape))
+                out = []
+                for ctx in (ctx_d, ctx_h):
+                    bhq.bhq_set_kernel(ctx, bhq.SPLIT_QUAD, prec)
+                    bhq.bhq_set_tuning(ctx, *shape)
+                    bhq.bhq_compute(ctx)
+                    out.append(bhq.bhq_get_result(ctx, len(m)))
+                    bhq.bhq_set_tuning(ctx)
+                assert np.array_equal(out[0][0], out[1][0])
+                assert np.array_equal(out[0][1], out[1][1])
     finally:
         bhq.bhq_destroy(ctx_d)
         bhq.bhq_destroy(ctx_h)

@@ -81,3 +81,39 @@ def test_noalloc_refuses_parts_beyond_its_memory():
         assert bhq.lib().bhq_compute_noalloc(ctx, None, None, None) == bhq.E_ARG
     finally:
         bhq.bhq_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [bhq.FP32_OFS64, bhq.FP64])
+def test_noalloc_split_kernel(precision):
+    """The periodic split kernel through bhq_compute_noalloc equals
+    bhq_compute, whole lists and cut into parts, for two inputs in a row
+    (the second smaller)."""
+    torch = pytest.importorskip("torch")
+    ctx = bhq.bhq_create(0, bhq.SPLIT_QUAD, precision)
+    try:
+        for nside in (24, 16):
+            x, m = synth.perturbed_lattice(nside, synth.rng(50 + nside))
+            rs = 1.25 / nside
+            rcut = 4.5 * rs
+            L = bhq.bhq_build_lists(x, m, 0.5, 64, box=1.0, rcut=rcut)
+            try:
+                bhq.bhq_set_lists_indexed(ctx, L, x, m)
+            finally:
+                bhq.bhq_lists_free(L)
+            bhq.bhq_set_split(ctx, rs, rcut, 1.0)
+            n = len(m)
+            for shape in ((256, 2, 0, 0, 0, 1), (256, 2, 0, 1, 0, 4)):
+                log("case noalloc split n=%d precision=%s shape=%s"
+                    % (n, bhq.PRECISION_NAMES[precision], shape))
+                bhq.bhq_set_tuning(ctx, *shape)
+                bhq.bhq_set_kernel(ctx, bhq.SPLIT_QUAD, precision)
+                bhq.bhq_compute(ctx)
+                a_ref, p_ref = bhq.bhq_get_result(ctx, n)
+                a = torch.full((n, 3), float("nan"), dtype=torch.float64, device="cuda")
+                p = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+                bhq.bhq_compute_noalloc(ctx, a, p)
+                torch.cuda.synchronize()
+                assert np.array_equal(a.cpu().numpy(), a_ref), shape
+                assert np.array_equal(p.cpu().numpy(), p_ref), shape
+    finally:
+        bhq.bhq_destroy(ctx)
