@@ -10,8 +10,8 @@ library's builder and are resident in HBM before the timed region.
 
 Prints ONE JSON line (logs go to stderr): throughput in Ginteractions/s
 (particle-particle plus particle-cell interactions per second), the FP32
-VALU roofline of the force kernel with the shader clock measured during
-the timed launches, the paper-convention GFLOP/s, the other variants on the
+VALU roofline of the force kernel with the shader clock measured beside as
+many launches right after the timed ones, the paper-convention GFLOP/s, the other variants on the
 same lists (monopole, FP64, complete softened quadrupole), the
 quadrupole-versus-monopole comparison at equal rms force error (the paper's
 Table 2 question), the FP64 oracle timed on the host's cores (all of them
@@ -267,19 +267,16 @@ def upload(ctx, W, L, indexed=False):
 def time_variant(torch, ctx, kernel, precision, steps, warmup, stream, clock=False):
     """Wall time per step over `steps` back-to-back launches, and the mean
     and median kernel duration from events recorded on the launch stream.
-    clock: also the mean shader clock (MHz) of one CU over the first 80 %
-    of the timed launches (bhq_clock_begin on a stream of its own), else
-    None."""
+    clock: also the mean shader clock (MHz) of one CU over `steps` more
+    launches right after the timed ones (bhq_clock_begin on a stream of its
+    own, over their first 80 %), else None.  The clock reader runs beside
+    untimed launches because beside the timed ones it slowed them by 3 %."""
     bhq.bhq_set_kernel(ctx, kernel, precision)
     for _ in range(warmup):
         bhq.bhq_compute(ctx, stream)
-    est_ms = bhq.bhq_get_kernel_ms(ctx) if warmup else 0.0
     ev = [(torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
-    if clock and est_ms > 0:
-        side = torch.cuda.Stream()
-        bhq.bhq_clock_begin(ctx, min(0.8 * steps * est_ms, 10000.0), side)
     t0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record(stream)
@@ -287,8 +284,15 @@ def time_variant(torch, ctx, kernel, precision, steps, warmup, stream, clock=Fal
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    mhz = bhq.bhq_clock_end(ctx) if (clock and est_ms > 0) else None
     kern_ms = [a.elapsed_time(b) for a, b in ev]
+    mhz = None
+    if clock and steps > 0:
+        side = torch.cuda.Stream()
+        bhq.bhq_clock_begin(ctx, min(0.8 * steps * float(np.mean(kern_ms)), 10000.0), side)
+        for _ in range(steps):
+            bhq.bhq_compute(ctx, stream)
+        torch.cuda.synchronize()
+        mhz = bhq.bhq_clock_end(ctx)
     return wall / steps * 1e3, float(np.mean(kern_ms)), float(np.median(kern_ms)), mhz
 
 
