@@ -758,7 +758,7 @@ __device__ __forceinline__ void load_split_tab(TabT<R> *tab)
 
 // Waves per SIMD the register allocation must allow: WPE > 0 asks for at
 // least WPE (registers capped to fit).  Otherwise the FP64 split kinds ask
-// for 4: left alone the compiler takes 192 VGPRs (2 waves); capped for 3,
+// for 4: left alone the compiler takes 188 VGPRs (2 waves); capped for 3,
 // 4 and 5 waves (registers spilled to scratch) they ran the 2^24 lattice in
 // 49.2, 47.5 and 50.8 ms against 56.7.  A minimum of 1 leaves the
 // compiler's choice.
