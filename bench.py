@@ -623,7 +623,7 @@ def config_record(torch, stream, W, kernel, ncrit, shapes, steps, fp64=True, liv
     launch shape (bhq_set_tuning arguments) and the fastest, the FP64 time at
     that shape, throughput and the FP32 roofline fraction; for the split
     kernels the pairs inside the cutoff and the roofline priced on them.
-    Returns (record, FP32 result in input order)."""
+    Returns (record, FP32 accelerations, FP32 potentials), in input order."""
     ctx = _dev_ctx(torch, W, ncrit, kernel)
     n = len(W["m"])
     try:
