@@ -98,21 +98,21 @@ constexpr SplitTab make_split_tab()
 
 __device__ const SplitTab kSplitTabDev = make_split_tab();
 
-// The FP64 kernels' table of erfcx (split_table64.h), likewise copied to
-// LDS by each block of an FP64 split kernel.
-struct ErfcxTab {
-    double v[kErfcxIntervals * (kErfcxDegree + 1)];
+// The FP64 kernels' table of exp(-u^2) and erfcx (split_table64.h),
+// likewise copied to LDS by each block of an FP64 split kernel.
+struct Tab64 {
+    double v[kTab64Intervals * kTab64Stride];
 };
 
-constexpr ErfcxTab make_erfcx_tab()
+constexpr Tab64 make_tab64()
 {
-    ErfcxTab t{};
-    for (int q = 0; q < kErfcxIntervals; ++q)
-        for (int k = 0; k <= kErfcxDegree; ++k) t.v[q * (kErfcxDegree + 1) + k] = kErfcxTable[q][k];
+    Tab64 t{};
+    for (int q = 0; q < kTab64Intervals; ++q)
+        for (int k = 0; k < kTab64Stride; ++k) t.v[q * kTab64Stride + k] = kTab64[q][k];
     return t;
 }
 
-__device__ const ErfcxTab kErfcxTabDev = make_erfcx_tab();
+__device__ const Tab64 kTab64Dev = make_tab64();
 
 // Element type of the LDS table of a precision.
 template <typename R>
@@ -130,10 +130,11 @@ using TabT = typename SplitTabT<R>::type;
 //   ec = erfc(u), g = erfc(u) + (2u/sqrt(pi)) e^{-u^2},
 //   G2 = 3g + h, G3 = 15g + 5h + k, with h = (4u^3/sqrt(pi)) e^{-u^2} and
 //   k = 2 u^2 h (G2, G3 only for cells with the quadrupole).
-// FP64 takes E = exp(-u^2) from the library and erfc(u) = E erfcx(u) from
-// the degree-9 polynomials of split_table64.h (interval q = floor(t), t =
-// u 32 / 4, f = t - q, Horner's rule; the library's erfc past u = 4, that is
-// for cutoffs beyond 8 r_s).  FP32 reads the
+// FP64 takes E = exp(-u^2) and erfcx(u) from the polynomials of
+// split_table64.h (interval q = floor(t), t = u 64 / 4, f = t - q, Horner's
+// rule; degree 9 for E, 7 for erfcx) and forms erfc(u) = E erfcx(u); past
+// u = 4, that is for cutoffs beyond 8 r_s, it calls the library's exp and
+// erfc.  FP32 reads the
 // piecewise cubics of the table at t = r ct: interval q = floor(t), local
 // variable f = t - q, Horner's rule (valid for u up to kSplitDomain and one
 // interval beyond; the host refuses FP32 split kernels with a longer
@@ -166,18 +167,23 @@ __device__ __forceinline__ SplitG<R> split_g(R r, const SplitK<R> &K, const TabT
         const R rsqpi = R(0.56418958354775628694807945156);
         const R u = r * K.i2rs;
         const R u2 = u * u;
-        const R E = exp_r(-u2);
-        if (u < R(kErfcxDomain)) {
-            // t < 32 exactly: the scale 32 / 4 is a power of two
-            const R t = u * R(kErfcxIntervals / kErfcxDomain);
+        R E;
+        if (u < R(kTab64Domain)) {
+            // t < 64 exactly: the scale 64 / 4 is a power of two
+            const R t = u * R(kTab64Intervals / kTab64Domain);
             const int q = (int)t;
             const R f = t - R(q);
-            const double *c = tab + q * (kErfcxDegree + 1);
-            R x = c[kErfcxDegree];
+            const double *c = tab + q * kTab64Stride;
+            E = c[kExpDegree];
 #pragma unroll
-            for (int k = kErfcxDegree - 1; k >= 0; --k) x = fma(x, f, c[k]);
+            for (int k = kExpDegree - 1; k >= 0; --k) E = fma(E, f, c[k]);
+            const double *cx = c + kExpDegree + 1;
+            R x = cx[kErfcxDegree];
+#pragma unroll
+            for (int k = kErfcxDegree - 1; k >= 0; --k) x = fma(x, f, cx[k]);
             s.ec = E * x;
         } else {
+            E = exp_r(-u2);
             s.ec = erfc_r(u);
         }
         const R e = E * rsqpi;
@@ -732,13 +738,14 @@ __device__ __forceinline__ void process_group(const ForceArgs &A, int64_t g, int
 }
 
 // The split kinds keep the table of their radial functions in LDS (FP32:
-// split_table.h; FP64: the erfcx polynomials of split_table64.h).
+// split_table.h; FP64: the exp(-u^2) and erfcx polynomials of
+// split_table64.h).
 template <typename R, int KIND>
 constexpr int split_tab_size()
 {
     return KIND != kSplitQuad && KIND != kSplitMono ? 1
            : std::is_same<R, float>::value          ? kSplitFuncs * kSplitEntries
-                                                    : kErfcxIntervals * (kErfcxDegree + 1);
+                                                    : kTab64Intervals * kTab64Stride;
 }
 
 template <typename R, int KIND, int BS>
@@ -749,8 +756,8 @@ __device__ __forceinline__ void load_split_tab(TabT<R> *tab)
             for (int k = threadIdx.x; k < kSplitFuncs * kSplitEntries; k += BS)
                 tab[k] = kSplitTabDev.v[k];
         } else {
-            for (int k = threadIdx.x; k < kErfcxIntervals * (kErfcxDegree + 1); k += BS)
-                tab[k] = kErfcxTabDev.v[k];
+            for (int k = threadIdx.x; k < kTab64Intervals * kTab64Stride; k += BS)
+                tab[k] = kTab64Dev.v[k];
         }
         __syncthreads();
     }
@@ -758,16 +765,19 @@ __device__ __forceinline__ void load_split_tab(TabT<R> *tab)
 
 // Waves per SIMD the register allocation must allow: WPE > 0 asks for at
 // least WPE (registers capped to fit).  Otherwise the FP64 split kinds ask
-// for 4: left alone the compiler takes 188 VGPRs (2 waves); capped for 3,
-// 4 and 5 waves (registers spilled to scratch) they ran the 2^24 lattice in
-// 49.2, 47.5 and 50.8 ms against 56.7.  A minimum of 1 leaves the
-// compiler's choice.
+// for BHQ_F64_SPLIT_WAVES: left alone the compiler takes 188 VGPRs (2
+// waves); capped for 3, 4 and 5 waves (registers spilled to scratch) they
+// ran the 2^24 lattice in 49.2, 47.5 and 50.8 ms against 56.7, with exp
+// from the library.  A minimum of 1 leaves the compiler's choice.
+#ifndef BHQ_F64_SPLIT_WAVES
+#define BHQ_F64_SPLIT_WAVES 4
+#endif
 template <typename R, int KIND, int WPE>
 constexpr int min_waves()
 {
     return WPE > 0 ? WPE
                    : (std::is_same<R, double>::value && (KIND == kSplitQuad || KIND == kSplitMono)
-                          ? 4
+                          ? BHQ_F64_SPLIT_WAVES
                           : 1);
 }
 

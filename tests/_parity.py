@@ -11,8 +11,8 @@ from paper_1812_07313_amd import bhq
 # Parity bars.  FP32 bulk arithmetic with FP64 group offsets: per-particle
 # relative acceleration error <= 2e-6 rms and <= 1e-4 max.  FP64: the two
 # sides differ in summation order, the kernels' rsqrt (a hardware estimate
-# and one series step) and, in the split kernels, erfc from a table of
-# erfcx (within 1.2e-15 relative), all far below 1e-12.
+# and one series step) and, in the split kernels, exp(-u^2) and erfc from
+# tables (within 5e-16 relative), all far below 1e-12.
 TOL = {
     bhq.FP32_OFS64: dict(rms=2e-6, max=1e-4, pot_rms=2e-6, pot_max=1e-4),
     bhq.FP64: dict(rms=1e-12, max=1e-10, pot_rms=1e-12, pot_max=1e-10),

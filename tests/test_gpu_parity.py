@@ -451,8 +451,8 @@ def test_split_fp32_cutoff_range(ctx):
     of r / 2r_s in [0, 2.5] (plus one interval for the rounding of r at the
     cutoff): a cutoff of 5 r_s is accepted and evaluated to the FP32 bar,
     5.2 r_s, 7.5 r_s and 9 r_s are refused for FP32 and accepted for FP64.
-    FP64 takes erfc from its erfcx table up to u = 4 (8 r_s) and from the
-    library beyond, so 9 r_s runs both forms side by side."""
+    FP64 takes exp(-u^2) and erfc from its table up to u = 4 (8 r_s) and
+    from the library beyond, so 9 r_s runs both forms side by side."""
     x, m = synth.perturbed_lattice(8, synth.rng(4))
     rs = 0.04
     for rcut in (0.3, 5.2 * rs, 9.0 * rs):

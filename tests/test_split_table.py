@@ -4,9 +4,10 @@ the kernels do (interval q = floor(t), f = t - q, Horner's rule with fused
 multiply-adds emulated exactly), match the functions computed from scipy's
 erfc and numpy's exp to 3e-7 relative on 0 <= u <= 2.5, its first entries
 reproduce erfc(0) = 1, g(0) = 1, G2(0) = 3, G3(0) = 15, and the header
-matches its generator.  The FP64 kernels' table of erfcx(u) = exp(u^2)
-erfc(u) (csrc/split_table64.h), evaluated as they evaluate it, matches
-erfcx and erfc computed with 30 significant digits to a few 1e-16."""
+matches its generator.  The FP64 kernels' table of exp(-u^2) and
+erfcx(u) = exp(u^2) erfc(u) (csrc/split_table64.h), evaluated as they
+evaluate it, matches both functions, and their product erfc, computed with
+30 significant digits to a few 1e-16."""
 import importlib.util
 import os
 import re
@@ -109,48 +110,59 @@ def test_generator_derivatives():
 def _header64():
     with open(os.path.join(CSRC, "split_table64.h")) as f:
         text = f.read()
-    dom = float(re.search(r"kErfcxDomain = ([0-9.]+);", text).group(1))
-    n = int(re.search(r"kErfcxIntervals = (\d+);", text).group(1))
-    deg = int(re.search(r"kErfcxDegree = (\d+);", text).group(1))
-    body = text[text.index("kErfcxTable["):]
+    dom = float(re.search(r"kTab64Domain = ([0-9.]+);", text).group(1))
+    n = int(re.search(r"kTab64Intervals = (\d+);", text).group(1))
+    de = int(re.search(r"kExpDegree = (\d+);", text).group(1))
+    dx = int(re.search(r"kErfcxDegree = (\d+);", text).group(1))
+    stride = int(re.search(r"kTab64Stride = (\d+);", text).group(1))
+    assert stride == de + dx + 2
+    body = text[text.index("kTab64["):]
     body = body[body.index("= {"):]
     vals = [float(v) for v in re.findall(r"([-+0-9.]+e[-+0-9]+)", body)]
-    return dom, n, deg, np.array(vals).reshape(n, deg + 1)
+    return dom, n, de, dx, np.array(vals).reshape(n, stride)
 
 
-def _erfcx_kernel(u, dom, n, deg, tab):
-    """The FP64 kernels' evaluation: t = u n / dom (exact: a power-of-two
-    scale), q = floor(t), f = t - q, Horner's rule with fused multiply-adds
-    (emulated exactly: the rational result rounded once)."""
+def _horner_fma(c, f):
+    """Horner's rule with fused multiply-adds (emulated exactly: the
+    rational result rounded once)."""
     from fractions import Fraction
-    t = u * (n / dom)
-    q = int(t)
-    f = t - q
-    c = tab[q]
-    x = float(c[deg])
-    for k in range(deg - 1, -1, -1):
+    x = float(c[-1])
+    for k in range(len(c) - 2, -1, -1):
         x = float(Fraction(x) * Fraction(f) + Fraction(float(c[k])))
     return x
 
 
-def test_fp64_erfcx_table():
+def _tab64_kernel(u, dom, n, de, tab):
+    """The FP64 kernels' evaluation: t = u n / dom (exact: a power-of-two
+    scale), q = floor(t), f = t - q; exp(-u^2) and erfcx(u) from row q."""
+    t = u * (n / dom)
+    q = int(t)
+    f = t - q
+    return _horner_fma(tab[q, :de + 1], f), _horner_fma(tab[q, de + 1:], f)
+
+
+def test_fp64_exp_erfcx_table():
     import mpmath as mp
-    dom, n, deg, tab = _header64()
-    assert (dom, n, deg) == (4.0, 32, 9)
-    assert tab[0, 0] == 1.0   # erfcx(0) = 1
+    dom, n, de, dx, tab = _header64()
+    assert (dom, n, de, dx) == (4.0, 64, 9, 7)
+    # exp(0) = 1 exactly; erfcx(0) = 1 within one unit in the last place (the
+    # degree-7 interpolant's error at the interval's end)
+    assert tab[0, 0] == 1.0
+    assert abs(tab[0, de + 1] - 1.0) <= 2.0 ** -52
     u = np.concatenate([np.linspace(0.0, dom, 1601, endpoint=False),
                         np.nextafter(np.arange(1, n + 1) * (dom / n), 0.0)])
-    worst_x = worst_c = 0.0
+    worst_e = worst_x = worst_c = 0.0
     with mp.workdps(30):
         for v in u:
-            x = _erfcx_kernel(float(v), dom, n, deg, tab)
-            ref = mp.exp(mp.mpf(v) ** 2) * mp.erfc(mp.mpf(v))
-            worst_x = max(worst_x, abs(float(x / ref - 1)))
-            # the kernels' erfc: exp(-u^2) from the library times the table
-            ec = float(np.exp(-v * v)) * x
-            worst_c = max(worst_c, abs(float(ec / mp.erfc(mp.mpf(v)) - 1)))
+            e, x = _tab64_kernel(float(v), dom, n, de, tab)
+            w = mp.mpf(float(v))
+            worst_e = max(worst_e, abs(float(e / mp.exp(-w * w) - 1)))
+            worst_x = max(worst_x, abs(float(x / (mp.exp(w * w) * mp.erfc(w)) - 1)))
+            # the kernels' erfc: the two table values multiplied in FP64
+            worst_c = max(worst_c, abs(float((e * x) / mp.erfc(w) - 1)))
+    assert worst_e < 1e-15, worst_e
     assert worst_x < 1e-15, worst_x
-    assert worst_c < 4e-15, worst_c
+    assert worst_c < 2e-15, worst_c
 
 
 def test_fp64_header_matches_generator():
@@ -158,5 +170,5 @@ def test_fp64_header_matches_generator():
         "gen64", os.path.join(CSRC, "gen_split_table64.py"))
     gen = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(gen)
-    _, _, _, tab = _header64()
+    _, _, _, _, tab = _header64()
     assert np.array_equal(tab, np.array(gen.table()))
