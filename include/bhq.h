@@ -129,9 +129,9 @@ int bhq_set_eps2_i(bhq_ctx *ctx, int64_t ni, const double *eps2);
  * separations), box == 0 an open boundary.  The FP32 split kernels take
  * erfc and the related radial functions from a table that covers
  * r / (2 r_s) <= 2.5 only, so bhq_compute returns BHQ_E_ARG for FP32 with
- * rcut > 5 r_s (FP64 has no such limit: it evaluates erfc as exp(-u^2)
- * times a table of exp(u^2) erfc(u) up to u = 4, and calls the library's
- * erfc beyond).  In a periodic box every
+ * rcut > 5 r_s (FP64 has no such limit: it takes exp(-u^2) and
+ * exp(u^2) erfc(u) from polynomial tables up to u = 4, forms erfc as their
+ * product, and calls the library's exp and erfc beyond).  In a periodic box every
  * group cell plus 2 rcut must stay below half the box. */
 int bhq_set_split(bhq_ctx *ctx, double rs, double rcut, double box);
 
