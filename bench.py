@@ -264,16 +264,26 @@ def upload(ctx, W, L, indexed=False):
     return P, time.perf_counter() - t0
 
 
-def time_variant(torch, ctx, kernel, precision, steps, warmup, stream, clock=False):
+def time_variant(torch, ctx, kernel, precision, steps, warmup, stream, clock=False,
+                 warm_ms=30.0):
     """Wall time per step over `steps` back-to-back launches, and the mean
     and median kernel duration from events recorded on the launch stream.
+    Untimed launches first: `warmup` of them, and more until `warm_ms` of
+    wall time has passed (the shader clock drops while the GPU idles, for
+    instance while the host rebuilds lists, and takes tens of ms of work to
+    come back: launches timed right after such a gap ran up to 15 % slow).
     clock: also the mean shader clock (MHz) of one CU over `steps` more
     launches right after the timed ones (bhq_clock_begin on a stream of its
     own, over their first 80 %), else None.  The clock reader runs beside
     untimed launches because beside the timed ones it slowed them by 3 %."""
     bhq.bhq_set_kernel(ctx, kernel, precision)
-    for _ in range(warmup):
+    t_w = time.perf_counter()
+    k = 0
+    while k < warmup or (time.perf_counter() - t_w) * 1e3 < warm_ms:
         bhq.bhq_compute(ctx, stream)
+        k += 1
+        if k >= warmup:
+            torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
@@ -657,7 +667,7 @@ def config_record(torch, stream, W, kernel, ncrit, shapes, steps, fp64=True, liv
             rec["roofline_fp32"] = _priced(kernel, n_pp, n_pc, km, PEAK_FP32_TFLOPS)
         a32, p32 = _result_input_order(torch, ctx, n, stream)
         if fp64:
-            _, k64, _, _ = time_variant(torch, ctx, kernel, bhq.FP64, max(3, steps // 4), 1,
+            _, k64, _, _ = time_variant(torch, ctx, kernel, bhq.FP64, max(5, steps // 2), 1,
                                         stream)
             rec["kernel_ms_fp64"] = round(k64, 4)
             if not live:
@@ -935,7 +945,7 @@ def main():
                           (bhq.SPLIT_QUAD, bhq.FP64)]
             for kern, prec in others:
                 vs, vk, _, _ = time_variant(torch, ctx, kern, prec,
-                                            max(3, args.steps // 4), 1, stream)
+                                            max(5, args.steps // 2), 1, stream)
                 v = {"ms_per_eval": round(vs, 4), "kernel_ms": round(vk, 4),
                      "Ginteractions_per_s": round(n_int / vk / 1e6, 2)}
                 if kern in FLOPS_PC:
@@ -949,8 +959,11 @@ def main():
                 log("%s_%s: kernel %.3f ms" % (bhq.KERNEL_NAMES[kern],
                                                 bhq.PRECISION_NAMES[prec], vk))
 
+        # exactly args.warmup untimed launches: the variants just ran, so the
+        # GPU is busy up to here
         ms_step, ms_kern, ms_kern_med, sclk = time_variant(
-            torch, ctx, kernel, bhq.FP32_OFS64, args.steps, args.warmup, stream, clock=True)
+            torch, ctx, kernel, bhq.FP32_OFS64, args.steps, args.warmup, stream, clock=True,
+            warm_ms=0.0)
         log("%s fp32: %.3f ms/step (kernel %.3f ms)"
             % (bhq.KERNEL_NAMES[kernel], ms_step, ms_kern))
         bhq.bhq_compute(ctx, stream)
