@@ -59,6 +59,14 @@ FLOPS_PC = {bhq.QUAD: 53, bhq.MONO: 20, bhq.QUAD_SOFT: 55}
 # counted: the split roofline is priced on the pairs bhq_count_live finds.
 FLOPS_SPLIT_PP = 36
 FLOPS_SPLIT_PC = {bhq.SPLIT_QUAD: 97, bhq.SPLIT_MONO: 37}
+# FP64 split kernels: the same terms with the radial functions from degree-9
+# (exp(-u^2)) and degree-7 (erfcx) polynomials instead of cubics.  Particle
+# term 62 (u, table variable and fraction 3, Horner 18 + 14, erfc, the
+# e^{-u^2}/sqrt(pi) factor and g 5, the rest as in FP32); quadrupole cell
+# term 123 (the particle term's radial part plus u^2, h, k, G2 and G3 12,
+# and the FP32 cell term's other 71); monopole cell 63.
+FLOPS_SPLIT64_PP = 62
+FLOPS_SPLIT64_PC = {bhq.SPLIT_QUAD: 123, bhq.SPLIT_MONO: 63}
 # the paper's convention for one particle-cell quadrupole interaction
 # (rsqrt counted as 20 flops, Sec. 3.3 and Sec. 5.2)
 PAPER_FLOPS_PC = 71
@@ -619,9 +627,11 @@ def _result_input_order(torch, ctx, n, stream):
     return a.cpu().numpy(), p.cpu().numpy()
 
 
-def _priced(kernel, n_pp, n_pc, ms, peak):
+def _priced(kernel, n_pp, n_pc, ms, peak, fp64=False):
     if kernel in FLOPS_PC:
         flops = FLOPS_PP * n_pp + FLOPS_PC[kernel] * n_pc
+    elif fp64:
+        flops = FLOPS_SPLIT64_PP * n_pp + FLOPS_SPLIT64_PC[kernel] * n_pc
     else:
         flops = FLOPS_SPLIT_PP * n_pp + FLOPS_SPLIT_PC[kernel] * n_pc
     tf = flops / (ms * 1e-3) / 1e12
@@ -670,7 +680,11 @@ def config_record(torch, stream, W, kernel, ncrit, shapes, steps, fp64=True, liv
             _, k64, _, _ = time_variant(torch, ctx, kernel, bhq.FP64, max(5, steps // 2), 1,
                                         stream)
             rec["kernel_ms_fp64"] = round(k64, 4)
-            if not live:
+            if live:
+                rec["roofline_fp64"] = dict(_priced(kernel, lp, lc, k64, PEAK_FP64_TFLOPS,
+                                                    fp64=True),
+                                            priced_on="pairs inside the cutoff")
+            else:
                 rec["roofline_fp64"] = _priced(kernel, n_pp, n_pc, k64, PEAK_FP64_TFLOPS)
             a64, _ = _result_input_order(torch, ctx, n, stream)
             e = np.linalg.norm(a32 - a64, axis=1) / np.linalg.norm(a64, axis=1)
@@ -948,12 +962,18 @@ def main():
                                             max(5, args.steps // 2), 1, stream)
                 v = {"ms_per_eval": round(vs, 4), "kernel_ms": round(vk, 4),
                      "Ginteractions_per_s": round(n_int / vk / 1e6, 2)}
+                peak = (PEAK_FP64_TFLOPS if prec == bhq.FP64
+                        else PEAK_FP32_TFLOPS)
                 if kern in FLOPS_PC:
                     flops = FLOPS_PP * n_pp + FLOPS_PC[kern] * n_pc
-                    peak = (PEAK_FP64_TFLOPS if prec == bhq.FP64
-                            else PEAK_FP32_TFLOPS)
                     v["tflops"] = round(flops / vk / 1e9, 2)
                     v["frac_of_peak"] = round(flops / vk / 1e9 / peak, 4)
+                elif live is not None:
+                    # the split variants decide the cutoff as the headline
+                    # kernel does, so the same pairs are live
+                    pr = _priced(kern, live[0], live[1], vk, peak, fp64=prec == bhq.FP64)
+                    v["tflops"], v["frac_of_peak"] = pr["tflops"], pr["frac"]
+                    v["priced_on"] = "pairs inside the cutoff"
                 variants["%s_%s" % (bhq.KERNEL_NAMES[kern],
                                     bhq.PRECISION_NAMES[prec])] = v
                 log("%s_%s: kernel %.3f ms" % (bhq.KERNEL_NAMES[kern],

@@ -112,3 +112,17 @@ def test_bench_lane_slot_fraction():
     # first pass, 51 + 9 in the second
     f = bench.lane_slot_fraction([0, 600], [0, 300], [0, 0], 256, 2)
     assert f == pytest.approx(600 * 300 / (512 * (256 + 44) + 512 * (51 + 9)), rel=1e-15)
+
+
+def test_bench_split_pricing():
+    """The split kernels are priced per term inside the cutoff with the
+    counts of their own precision (FP32 cubics, FP64 polynomials)."""
+    import bench
+    n_pp, n_pc = 10 ** 12, 10 ** 11
+    r32 = bench._priced(bhq.SPLIT_QUAD, n_pp, n_pc, 1000.0, 100.0)
+    r64 = bench._priced(bhq.SPLIT_QUAD, n_pp, n_pc, 1000.0, 100.0, fp64=True)
+    assert r32["tflops"] == round((36 * n_pp + 97 * n_pc) / 1e12, 3)
+    assert r64["tflops"] == round((62 * n_pp + 123 * n_pc) / 1e12, 3)
+    # the non-split kernels ignore the flag
+    assert bench._priced(bhq.QUAD, n_pp, n_pc, 1000.0, 100.0, fp64=True) == \
+        bench._priced(bhq.QUAD, n_pp, n_pc, 1000.0, 100.0)
